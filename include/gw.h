@@ -1,0 +1,172 @@
+/* gw.h - C-ABI of libgw: the contour-deformation G0W0 hot path on one
+ * MI355X (gfx950) GPU.
+ *
+ * Method: Mejia-Rodriguez, Kunitsa, Apra, Govind, "Scalable Molecular GW
+ * Calculations: Valence and Core Spectra" (JCTC 2021).  Sections cited:
+ *   [CD-theory]  Theory - Contour Deformation (Sigma = R - I, the residue
+ *                term R and the imaginary-axis term I)
+ *   [CD-impl]    Implementation - Contour Deformation (W in the fitted
+ *                auxiliary basis, Pi_PQ(omega), the dielectric matrix 1 - Pi,
+ *                the imaginary-axis integral I_nn on a modified Gauss-Legendre
+ *                grid, the residue term R_nn solved with MINRES and the
+ *                explicit-build fallback)
+ *   [Alg1]       Algorithm 1 (CD-GW)
+ *   [QP]         Implementation - Solution of the Quasiparticle Equations
+ *                (QP equation, Z, the step-selection tree figure)
+ *   [RVF]        Implementation - Variational Fitting Approximation (the
+ *                orthonormalised three-index integrals (P|pq))
+ *
+ * Conventions (all entry points):
+ *   - Hartree atomic units, closed shell.  Orbitals 0..n_occ-1 are occupied,
+ *     n_occ..n_mo-1 virtual; eps must be strictly ascending.
+ *   - Every pointer argument is a HOST pointer unless stated otherwise.  The
+ *     caller owns all input and output arrays; inputs are copied to device
+ *     memory before the call returns and are not retained.
+ *   - Arrays are row-major float64 unless stated otherwise.
+ *   - Return value: 0 on success, a negative GW_E* code on a hard error (the
+ *     context is left unchanged where possible; gw_last_error() describes it).
+ *   - A context is not thread-safe; distinct contexts may be used from
+ *     different threads.  All device work of a context runs on its stream.
+ *   - Every entry point computes on the GPU; there is no host fallback.
+ */
+#ifndef GW_H
+#define GW_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hard errors */
+#define GW_OK 0
+#define GW_EINVAL (-1)   /* bad sizes, unsorted/non-finite eps, unknown state, bad grid */
+#define GW_ENOMEM (-2)   /* device allocation failed or the memory budget is exceeded */
+#define GW_EDEVICE (-3)  /* a HIP runtime call or kernel launch failed */
+#define GW_ENOTSPD (-4)  /* 1 - Pi(i xi) was not positive definite (cannot happen for real B) */
+
+/* per-state soft status bits returned by gw_qp */
+#define GW_ST_MAXITER 1   /* the QP iteration limit was reached */
+#define GW_ST_SMALL_Z 2   /* Z < 0.1 at the returned point */
+#define GW_ST_FALLBACK 4  /* at least one residue used the dense fallback */
+
+/* precision of the Pi(i xi) build only; Cholesky, MINRES and the QP step
+ * are always float64 */
+#define GW_PI_FP64 0
+#define GW_PI_FP32 1    /* FP32 operands, FP32 MFMA accumulation, FP64 split-K sum */
+#define GW_PI_BF16X3 2  /* bf16 hi/lo split, 3 MFMA products, FP32 accumulation */
+
+typedef struct gw_ctx gw_ctx;
+
+/* Options; a zero-initialised struct means the defaults. */
+typedef struct gw_opts {
+  int pi_prec;              /* GW_PI_*                                   (0: FP64)  */
+  int minres_max_iter;      /* MINRES iteration cap before the fallback  (0: 200)   */
+  double minres_rtol;       /* MINRES relative residual target           (0: 1e-12) */
+  double qp_tol;            /* |f| < qp_tol ends the QP iteration, Ha    (0: 1e-10) */
+  int qp_max_iter;          /* QP iteration cap                          (0: 100)   */
+  const double* dsig_x;     /* optional [n_mo]: Sigma^x_nn - V^xc_nn; NULL means 0.
+                               Copied at setup. */
+  void* stream;             /* hipStream_t to run on; NULL: the context creates one */
+  size_t mem_budget_bytes;  /* cap on device memory of this context (0: no cap) */
+  size_t work_budget_bytes; /* cap on the stage-A workspace (0: 16 GiB); grid points
+                               are factored in chunks that fit */
+} gw_opts;
+
+/* Imaginary-frequency quadrature: nodes xi[n] > 0 and d-xi weights w[n]
+ * (no 1/pi), so that sum_g w_g h(xi_g) approximates int_0^inf h(xi) d xi. */
+typedef struct gw_grid {
+  int n;
+  const double* xi;
+  const double* w;
+} gw_grid;
+
+/* Modified Gauss-Legendre grid [CD-impl]: Gauss-Legendre nodes t_g, weights
+ * u_g on [-1, 1] mapped by xi = x0 (1 + t)/(1 - t), w = u 2 x0/(1 - t)^2.
+ * xi, w: caller arrays of length n.  Returns GW_EINVAL for n < 1 or
+ * x0 <= 0.  (Host arithmetic only; no device needed.) */
+int gw_grid_gauss_legendre(int n, double x0, double* xi, double* w);
+
+/* Create a context holding one molecule on the current HIP device.
+ *   n_mo, n_occ, n_aux: sizes (0 < n_occ < n_mo, n_aux >= 1)
+ *   eps    [n_mo]                        Kohn-Sham levels, strictly ascending
+ *   B_ov   [n_aux][n_occ*(n_mo-n_occ)]   (P|ia), column ia = i*n_virt + a   [RVF]
+ *   row_ids[n_rows]                      states n whose rows are supplied (distinct)
+ *   B_rows [n_rows][n_mo][n_aux]         (P|nm) for n = row_ids[r], every m
+ *   opts   may be NULL (defaults)
+ * On success *ctx owns device copies of everything it needs.
+ * Errors: GW_EINVAL (sizes, ordering, non-finite values, duplicate rows),
+ * GW_ENOMEM, GW_EDEVICE. */
+int gw_setup(gw_ctx** ctx, int n_mo, int n_occ, int n_aux, const double* eps,
+             const double* B_ov, int n_rows, const int* row_ids, const double* B_rows,
+             const gw_opts* opts);
+
+/* G0W0 quasiparticle energies [QP], [Alg1] with maxeviter = 0:
+ * for each state n solves eps_QP = eps_n + dsig_x_n + Re Sigma^c_nn(eps_QP)
+ * with Sigma^c = R - I [CD-theory]: the imaginary-axis term from the W^c
+ * table on `grid` (Pi build -> Cholesky of 1 - Pi -> W^c, computed once per
+ * grid and cached in the context) and the residue term from batched MINRES
+ * at real frequencies, using the step-selection tree of [QP].
+ *   states[n_states]: each must be one of the setup's row_ids
+ *   outputs (caller arrays of length n_states): E_qp, sigma_c = Re Sigma^c at
+ *   E_qp, Z = 1/(1 - dRe Sigma^c/d omega) at E_qp; status may be NULL.
+ * Errors: GW_EINVAL, GW_ENOMEM, GW_EDEVICE, GW_ENOTSPD. */
+int gw_qp(gw_ctx* ctx, int n_states, const int* states, const gw_grid* grid, double* E_qp,
+          double* sigma_c, double* Z, int* status);
+
+/* Release the context and all of its device memory.  NULL is ignored. */
+void gw_free(gw_ctx* ctx);
+
+/* Text describing the last nonzero return of this thread ("" if none). */
+const char* gw_last_error(void);
+
+/* Select the precision of subsequent Pi builds (GW_PI_*); invalidates the
+ * cached W^c table.  GW_EINVAL for an unknown value. */
+int gw_set_pi_prec(gw_ctx* ctx, int pi_prec);
+
+/* ---- stage entry points (the same kernels gw_qp runs; for parity checks
+ *      and tooling) ------------------------------------------------------- */
+
+/* The dielectric matrices 1 - Pi(i xi_g) [CD-impl], Pi = -4 sum_ia
+ * (P|ia) D_ia/(D_ia^2 + xi^2) (ia|Q) (closed-shell spin sum, eta -> 0+), in
+ * the context's Pi precision.  out: [n_xi][n_aux][n_aux], lower triangle
+ * written (the strict upper triangle is set to 0). */
+int gw_dielectric(gw_ctx* ctx, int n_xi, const double* xi, double* out);
+
+/* Cholesky factors L_g of 1 - Pi(i xi_g): out [n_xi][n_aux][n_aux] lower
+ * triangular (upper set to 0). */
+int gw_cholesky(gw_ctx* ctx, int n_xi, const double* xi, double* out);
+
+/* The screened-interaction table W^c_nm(i xi_g) = b^T[(1 - Pi)^-1 - 1]b,
+ * b = (P|nm) [CD-impl], [Alg1], for every supplied row n and every m:
+ * out [n_rows][n_mo][grid->n].  Also fills the context's cache. */
+int gw_wtable(gw_ctx* ctx, const gw_grid* grid, double* out);
+
+/* Re Sigma^c_nn(omega) and its omega-derivative at fixed real frequencies
+ * (one omega per entry; states may repeat) [CD-theory], [Alg1]:
+ *   sigma, dsigma: [n] outputs; n_res (nullable): residues used per entry.
+ * The residue term uses batched MINRES (with the dense fallback). */
+int gw_sigma(gw_ctx* ctx, int n, const int* states, const double* omega, const gw_grid* grid,
+             double* sigma, double* dsigma, int* n_res);
+
+/* Batched residue solves [CD-impl]: for j < k, x_j solves
+ * (1 - Pi(w_j)) x_j = b_j with b_j = (P|n_j m_j), Pi(w) = -4 sum_ia (P|ia)
+ * D/(D^2 - w^2) (ia|Q).  Outputs (nullable each):
+ *   x [k][n_aux], wc [k] = b^T x - b^T b, dwc [k] = x^T (dPi/dw) x,
+ *   iters [k] = MINRES iterations (negative: did not converge; the dense
+ *   fallback was used when use_fallback != 0). */
+int gw_residues(gw_ctx* ctx, int k, const int* states, const int* m, const double* w,
+                int use_fallback, double* x, double* wc, double* dwc, int* iters);
+
+/* Per-context timing of the last gw_qp / gw_wtable call, milliseconds,
+ * measured with HIP events on the context stream. */
+typedef struct gw_timing {
+  double pi_ms, chol_ms, wtab_ms, quad_ms, minres_ms, fallback_ms, total_ms;
+  int qp_rounds, minres_iters, minres_systems, fallback_systems, wtab_cached;
+} gw_timing;
+int gw_get_timing(gw_ctx* ctx, gw_timing* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GW_H */

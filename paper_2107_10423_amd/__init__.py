@@ -1,0 +1,244 @@
+"""Python binding of libgw (include/gw.h): argument marshalling only.
+
+Every computation happens inside libgw.so on the GPU.  The library must have
+been built (``python -m paper_2107_10423_amd.build`` or
+``__graft_entry__.build()``); importing this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgw.so")
+
+GW_PI_FP64, GW_PI_FP32, GW_PI_BF16X3 = 0, 1, 2
+PREC = {"fp64": GW_PI_FP64, "fp32": GW_PI_FP32, "bf16x3": GW_PI_BF16X3}
+ST_MAXITER, ST_SMALL_Z, ST_FALLBACK = 1, 2, 4
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2107_10423_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("pi_prec", ctypes.c_int), ("minres_max_iter", ctypes.c_int),
+                ("minres_rtol", ctypes.c_double), ("qp_tol", ctypes.c_double),
+                ("qp_max_iter", ctypes.c_int), ("dsig_x", _dp), ("stream", ctypes.c_void_p),
+                ("mem_budget_bytes", ctypes.c_size_t), ("work_budget_bytes", ctypes.c_size_t)]
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("xi", _dp), ("w", _dp)]
+
+
+class Timing(ctypes.Structure):
+    _fields_ = [("pi_ms", ctypes.c_double), ("chol_ms", ctypes.c_double),
+                ("wtab_ms", ctypes.c_double), ("quad_ms", ctypes.c_double),
+                ("minres_ms", ctypes.c_double), ("fallback_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double), ("qp_rounds", ctypes.c_int),
+                ("minres_iters", ctypes.c_int), ("minres_systems", ctypes.c_int),
+                ("fallback_systems", ctypes.c_int), ("wtab_cached", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_ctxp = ctypes.c_void_p
+_sig = {
+    "gw_last_error": (ctypes.c_char_p, []),
+    "gw_grid_gauss_legendre": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _dp, _dp]),
+    "gw_setup": (ctypes.c_int, [ctypes.POINTER(_ctxp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                _dp, _dp, ctypes.c_int, _ip, _dp, ctypes.POINTER(_Opts)]),
+    "gw_qp": (ctypes.c_int, [_ctxp, ctypes.c_int, _ip, ctypes.POINTER(_Grid), _dp, _dp, _dp, _ip]),
+    "gw_free": (None, [_ctxp]),
+    "gw_set_pi_prec": (ctypes.c_int, [_ctxp, ctypes.c_int]),
+    "gw_dielectric": (ctypes.c_int, [_ctxp, ctypes.c_int, _dp, _dp]),
+    "gw_cholesky": (ctypes.c_int, [_ctxp, ctypes.c_int, _dp, _dp]),
+    "gw_wtable": (ctypes.c_int, [_ctxp, ctypes.POINTER(_Grid), _dp]),
+    "gw_sigma": (ctypes.c_int, [_ctxp, ctypes.c_int, _ip, _dp, ctypes.POINTER(_Grid), _dp, _dp, _ip]),
+    "gw_residues": (ctypes.c_int, [_ctxp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_int, _dp, _dp,
+                                   _dp, _ip]),
+    "gw_get_timing": (ctypes.c_int, [_ctxp, ctypes.POINTER(Timing)]),
+    "gw_audit_enable": (ctypes.c_int, []),
+    "gw_audit_launch_count": (ctypes.c_long, []),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class GWError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libgw error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        raise GWError(rc, _lib.gw_last_error().decode())
+
+
+def _d(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _pd(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+def _pi(a):
+    return a.ctypes.data_as(_ip) if a is not None else None
+
+
+def grid_gauss_legendre(n: int, x0: float = 0.5):
+    xi = np.empty(n)
+    w = np.empty(n)
+    _check(_lib.gw_grid_gauss_legendre(int(n), float(x0), _pd(xi), _pd(w)))
+    return xi, w
+
+
+class Grid:
+    def __init__(self, xi, w):
+        self.xi = _d(xi)
+        self.w = _d(w)
+        if self.xi.shape != self.w.shape or self.xi.ndim != 1:
+            raise ValueError("grid arrays must be 1-D and of equal length")
+        self._g = _Grid(len(self.xi), _pd(self.xi), _pd(self.w))
+
+    @classmethod
+    def gauss_legendre(cls, n, x0=0.5):
+        return cls(*grid_gauss_legendre(n, x0))
+
+    @property
+    def n(self):
+        return len(self.xi)
+
+
+class Context:
+    """One molecule resident on the GPU (wraps gw_setup / gw_free)."""
+
+    def __init__(self, eps, n_occ, B_ov, row_ids, B_rows, pi_prec="fp64", minres_max_iter=0,
+                 minres_rtol=0.0, qp_tol=0.0, qp_max_iter=0, dsig_x=None, stream=None,
+                 mem_budget_bytes=0, work_budget_bytes=0):
+        eps = _d(eps)
+        B_ov = _d(B_ov)
+        rows = _i(row_ids)
+        B_rows = _d(B_rows)
+        n_mo = eps.size
+        n_aux = B_ov.shape[0]
+        if B_ov.shape != (n_aux, n_occ * (n_mo - n_occ)):
+            raise ValueError("B_ov must be [n_aux][n_occ*n_virt]")
+        if B_rows.shape != (rows.size, n_mo, n_aux):
+            raise ValueError("B_rows must be [n_rows][n_mo][n_aux]")
+        self._dsx = _d(dsig_x) if dsig_x is not None else None
+        o = _Opts(PREC[pi_prec] if isinstance(pi_prec, str) else int(pi_prec),
+                  int(minres_max_iter), float(minres_rtol), float(qp_tol), int(qp_max_iter),
+                  _pd(self._dsx), ctypes.c_void_p(stream) if stream else None,
+                  int(mem_budget_bytes), int(work_budget_bytes))
+        h = _ctxp()
+        _check(_lib.gw_setup(ctypes.byref(h), n_mo, int(n_occ), n_aux, _pd(eps), _pd(B_ov),
+                             rows.size, _pi(rows), _pd(B_rows), ctypes.byref(o)))
+        self._h = h
+        self.n_mo, self.n_occ, self.n_aux = n_mo, int(n_occ), n_aux
+        self.row_ids = rows.copy()
+
+    @classmethod
+    def from_inputs(cls, inp, **kw):
+        return cls(inp.eps, inp.n_occ, inp.B_ov, inp.row_ids, inp.B_rows, **kw)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.gw_free(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_pi_prec(self, prec):
+        _check(_lib.gw_set_pi_prec(self._h, PREC[prec] if isinstance(prec, str) else int(prec)))
+
+    def qp(self, states: Sequence[int], grid: Grid):
+        st = _i(states)
+        n = st.size
+        E, S, Z = np.empty(n), np.empty(n), np.empty(n)
+        status = np.empty(n, dtype=np.int32)
+        _check(_lib.gw_qp(self._h, n, _pi(st), ctypes.byref(grid._g), _pd(E), _pd(S), _pd(Z),
+                          _pi(status)))
+        return E, S, Z, status
+
+    def wtable(self, grid: Grid):
+        out = np.empty((self.row_ids.size, self.n_mo, grid.n))
+        _check(_lib.gw_wtable(self._h, ctypes.byref(grid._g), _pd(out)))
+        return out
+
+    def dielectric(self, xi):
+        xi = _d(np.atleast_1d(xi))
+        out = np.empty((xi.size, self.n_aux, self.n_aux))
+        _check(_lib.gw_dielectric(self._h, xi.size, _pd(xi), _pd(out)))
+        return out
+
+    def cholesky(self, xi):
+        xi = _d(np.atleast_1d(xi))
+        out = np.empty((xi.size, self.n_aux, self.n_aux))
+        _check(_lib.gw_cholesky(self._h, xi.size, _pd(xi), _pd(out)))
+        return out
+
+    def sigma(self, states, omega, grid: Grid):
+        st = _i(states)
+        om = _d(omega)
+        n = st.size
+        s, ds = np.empty(n), np.empty(n)
+        nres = np.empty(n, dtype=np.int32)
+        _check(_lib.gw_sigma(self._h, n, _pi(st), _pd(om), ctypes.byref(grid._g), _pd(s), _pd(ds),
+                             _pi(nres)))
+        return s, ds, nres
+
+    def residues(self, states, m, w, use_fallback=True):
+        st, mm, ww = _i(states), _i(m), _d(w)
+        k = st.size
+        x = np.empty((k, self.n_aux))
+        wc, dwc = np.empty(k), np.empty(k)
+        it = np.empty(k, dtype=np.int32)
+        _check(_lib.gw_residues(self._h, k, _pi(st), _pi(mm), _pd(ww), int(bool(use_fallback)),
+                                _pd(x), _pd(wc), _pd(dwc), _pi(it)))
+        return x, wc, dwc, it
+
+    def timing(self):
+        t = Timing()
+        _check(_lib.gw_get_timing(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+
+GW_EAUDIT = -5
+
+
+def audit_enable():
+    """Irreversibly switch this process into launch-audit mode (include/gw_audit.h)."""
+    _check(_lib.gw_audit_enable())
+
+
+def audit_launch_count():
+    return int(_lib.gw_audit_launch_count())
+
+
+def exported_symbols():
+    """Names declared in include/gw.h that the loaded library exports."""
+    return sorted(n for n in _sig if hasattr(_lib, n))

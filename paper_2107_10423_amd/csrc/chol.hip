@@ -1,0 +1,216 @@
+// Blocked Cholesky pieces for the dielectric matrices 1 - Pi(i xi_g) and the
+// screened-interaction reduction.
+//
+// The matrix of grid point g is stored augmented: rows [0, Np) hold 1 - Pi
+// (lower triangle), rows [Np, Np + nR) hold the vectors b = (P|nm) of every
+// requested state n and every m.  A right-looking blocked Cholesky (panel
+// width 64) run over all rows factors 1 - Pi = L L^T and, because the
+// appended rows are treated like the rows below the diagonal, leaves
+// y^T = (L^-1 b)^T in them.  Then b^T (1 - Pi)^-1 b = |y|^2.
+#include "gw_internal.h"
+
+namespace gw {
+
+constexpr int NB = 64;
+
+// Factor the 64x64 diagonal block at (k, k) of every batch item in LDS, write
+// L back (strict upper part zeroed) and L^-1 to Linv[g][64][64].
+__global__ __launch_bounds__(256) void k_chol_diag(double* A, long ldA, long sA, double* Linv,
+                                                   int k, int* info) {
+  __shared__ double L[NB][NB + 1];
+  __shared__ double X[NB][NB + 1];
+  __shared__ double part[4][NB];
+  const int g = blockIdx.x;
+  const int t = threadIdx.x;
+  double* Ag = A + (long)g * sA + (long)k * ldA + k;
+  for (int idx = t; idx < NB * NB; idx += 256) {
+    int i = idx / NB, c = idx % NB;
+    L[i][c] = (c <= i) ? Ag[(long)i * ldA + c] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    if (t == 0) {
+      double d = L[j][j];
+      if (!(d > 0.0)) {  // not positive definite (or NaN): record, keep going with 1
+        if (info[g] == 0) info[g] = k + j + 1;
+        d = 1.0;
+      }
+      L[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    for (int i = j + 1 + t; i < NB; i += 256) L[i][j] /= L[j][j];
+    __syncthreads();
+    for (int idx = t; idx < NB * NB; idx += 256) {
+      int i = idx / NB, c = idx % NB;
+      if (c > j && c <= i) L[i][c] -= L[i][j] * L[c][j];
+    }
+    __syncthreads();
+  }
+  // X = L^-1 by forward substitution, row by row; 4 threads per column split
+  // the inner product.
+  const int col = t & 63, q = t >> 6;
+  for (int i = 0; i < NB; ++i) {
+    double s = 0.0;
+    for (int j = q; j < i; j += 4) s += L[i][j] * X[j][col];
+    part[q][col] = s;
+    __syncthreads();
+    if (q == 0) {
+      double tot = part[0][col] + part[1][col] + part[2][col] + part[3][col];
+      double rhs = (i == col) ? 1.0 : 0.0;
+      X[i][col] = (col <= i) ? (rhs - tot) / L[i][i] : 0.0;
+    }
+    __syncthreads();
+  }
+  double* Li = Linv + (long)g * NB * NB;
+  for (int idx = t; idx < NB * NB; idx += 256) {
+    int i = idx / NB, c = idx % NB;
+    Ag[(long)i * ldA + c] = (c <= i) ? L[i][c] : 0.0;
+    Li[idx] = X[i][c];
+  }
+}
+
+hipError_t chol_diag(double* A, long ldA, long sA, double* Linv, int k, int G, int* info,
+                     long nA, long nLinv, long nInfo, hipStream_t st) {
+  if (G <= 0) return hipSuccess;
+  GW_GUARD("chol_diag", "A", (long)(G - 1) * sA + (long)(k + NB - 1) * ldA + k + NB - 1, nA);
+  GW_GUARD("chol_diag", "Linv", (long)G * NB * NB - 1, nLinv);
+  GW_GUARD("chol_diag", "info", G - 1, nInfo);
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_chol_diag, dim3(G), dim3(256), 0, st, A, ldA, sA, Linv, k, info);
+  return hipGetLastError();
+}
+
+// rows [row0, row0 + nR) of every batch item <- R[nR][Np] (already padded)
+__global__ void k_copy_rows(double* A, long ldA, long sA, int row0, const double* R, int nR,
+                            int Np) {
+  const int g = blockIdx.y;
+  const long n = (long)nR * Np;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+       idx += (long)gridDim.x * blockDim.x) {
+    long r = idx / Np, c = idx % Np;
+    A[(long)g * sA + (row0 + r) * ldA + c] = R[idx];
+  }
+}
+
+hipError_t copy_rows_into(double* A, long ldA, long sA, int row0, const double* R, int nR,
+                          int Np, int G, long nA, long nR_ext, hipStream_t st) {
+  long n = (long)nR * Np;
+  if (n <= 0 || G <= 0) return hipSuccess;
+  GW_GUARD("copy_rows", "A", (long)(G - 1) * sA + (long)(row0 + nR - 1) * ldA + Np - 1, nA);
+  GW_GUARD("copy_rows", "R", n - 1, nR_ext);
+  GW_AUDIT_RETURN();
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_copy_rows, dim3(blocks, G), dim3(256), 0, st, A, ldA, sA, row0, R, nR, Np);
+  return hipGetLastError();
+}
+
+// wtab[q][g0 + g] = |row (row0 + q) of item g|^2 - bnorm2[q]; one wavefront per (q, g)
+__global__ __launch_bounds__(256) void k_wc_reduce(const double* A, long ldA, long sA, int row0,
+                                                   const double* bnorm2, int nR, int Np, int G,
+                                                   int Gtot, int g0, double* wtab) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const long item = (long)blockIdx.x * 4 + wave;
+  if (item >= (long)nR * G) return;
+  const int q = (int)(item / G), g = (int)(item % G);
+  const double* row = A + (long)g * sA + (long)(row0 + q) * ldA;
+  double s = 0.0;
+  for (int c = lane; c < Np; c += 64) s += row[c] * row[c];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) wtab[(long)q * Gtot + g0 + g] = s - bnorm2[q];
+}
+
+hipError_t wc_reduce_chunk(const double* A, long ldA, long sA, int row0, const double* bnorm2,
+                           int nR, int Np, int G, int Gtot, int g0, double* wtab, long nA,
+                           long nBn, long nW, hipStream_t st) {
+  long items = (long)nR * G;
+  int blocks = (int)((items + 3) / 4);
+  if (blocks < 1) return hipSuccess;
+  GW_GUARD("wc_reduce", "A", (long)(G - 1) * sA + (long)(row0 + nR - 1) * ldA + Np - 1, nA);
+  GW_GUARD("wc_reduce", "bnorm2", nR - 1, nBn);
+  GW_GUARD("wc_reduce", "wtab", (long)(nR - 1) * Gtot + g0 + G - 1, nW);
+  if (g0 + G > Gtot) return refuse("wc_reduce", "grid chunk beyond the table");
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_wc_reduce, dim3(blocks), dim3(256), 0, st, A, ldA, sA, row0, bnorm2, nR,
+                     Np, G, Gtot, g0, wtab);
+  return hipGetLastError();
+}
+
+// s[g][k] = D_k / (D_k^2 + xi_g^2) for k < Kov, 0 for the padding
+__global__ void k_scale_imag(const double* D, int Kov, int Kp, const double* xi, double* s) {
+  const int g = blockIdx.y;
+  const double x2 = xi[g] * xi[g];
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < Kp; k += gridDim.x * blockDim.x) {
+    double d = D[k];
+    s[(long)g * Kp + k] = (k < Kov) ? d / (d * d + x2) : 0.0;
+  }
+}
+
+hipError_t make_scale_imag(const double* D, int Kov, int Kp, const double* xi, int G, double* s,
+                           long nD, long nXi, long nS, hipStream_t st) {
+  if (G <= 0 || Kp <= 0) return hipSuccess;
+  GW_GUARD("scale_imag", "D", Kp - 1, nD);
+  GW_GUARD("scale_imag", "xi", G - 1, nXi);
+  GW_GUARD("scale_imag", "s", (long)G * Kp - 1, nS);
+  if (Kov > Kp) return refuse("scale_imag", "Kov > Kp");
+  GW_AUDIT_RETURN();
+  int blocks = (Kp + 255) / 256;
+  if (blocks > 256) blocks = 256;
+  hipLaunchKernelGGL(k_scale_imag, dim3(blocks, G), dim3(256), 0, st, D, Kov, Kp, xi, s);
+  return hipGetLastError();
+}
+
+// Imaginary-axis part of Re Sigma^c and its omega-derivative for n states.
+// sig_j = -(1/pi) sum_m sum_g W[r_j][m][g] z_g a/(a^2 + xi_g^2), a = omega_j - eps_m.
+__global__ __launch_bounds__(256) void k_sigma_quad(const double* wtab, int n_mo, int G,
+                                                    const int* rowsel, const double* omega,
+                                                    const double* eps, const double* xi,
+                                                    const double* z, double* sig,
+                                                    double* dsig) {
+  __shared__ double rs[256], rd[256];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const int r = rowsel[j];
+  const double w = omega[j];
+  const double* W = wtab + (long)r * n_mo * G;
+  double s = 0.0, d = 0.0;
+  const long n = (long)n_mo * G;
+  for (long idx = t; idx < n; idx += 256) {
+    int m = (int)(idx / G), g = (int)(idx % G);
+    double a = w - eps[m];
+    double x2 = xi[g] * xi[g];
+    double den = a * a + x2;
+    double wz = W[idx] * z[g];
+    s += wz * a / den;
+    d += wz * (x2 - a * a) / (den * den);
+  }
+  rs[t] = s;
+  rd[t] = d;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (t < off) {
+      rs[t] += rs[t + off];
+      rd[t] += rd[t + off];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    const double inv_pi = 0.31830988618379067154;
+    sig[j] = -inv_pi * rs[0];
+    dsig[j] = -inv_pi * rd[0];
+  }
+}
+
+hipError_t sigma_quad(const double* wtab, int n_mo, int G, const int* rowsel, const double* omega,
+                      const double* eps, const double* xi, const double* z, int n, double* sig,
+                      double* dsig, int n_rows, long nW, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  // row indices come from the context's validated state -> row map (< n_rows)
+  GW_GUARD("sigma_quad", "wtab", (long)n_rows * n_mo * G - 1, nW);
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_sigma_quad, dim3(n), dim3(256), 0, st, wtab, n_mo, G, rowsel, omega, eps,
+                     xi, z, sig, dsig);
+  return hipGetLastError();
+}
+
+}  // namespace gw

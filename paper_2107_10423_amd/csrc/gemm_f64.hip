@@ -1,0 +1,321 @@
+// FP64 MFMA GEMM used by the Pi build, the blocked Cholesky of the augmented
+// dielectric matrix and the MINRES matrix-vector products.
+//
+// Work tile: BM x BN outputs per 256-thread workgroup (4 wavefronts), staged
+// through LDS in K-steps of 16 with double buffering; each wavefront owns
+// TM x TN blocks of 16x16 and issues v_mfma_f64_16x16x4_f64.  Operands are
+// either k-contiguous ([row][k]) or k-major ([k][row]) in HBM; LDS always
+// holds [k][row] so that the 16 lanes of an MFMA row group read 16
+// consecutive doubles.  All extents handed to the kernel are padded to the
+// tile, so the inner loop carries no bounds checks.
+//
+// Workgroups are swizzled so that each XCD (workgroups are dealt round-robin
+// to the 8 XCDs) receives a contiguous range of the work list; with the batch
+// index fastest (Pi build) the 64-128 grid points of one output tile run on
+// one XCD at the same time and stream the same B rows through its L2.
+#include "gw_internal.h"
+
+namespace gw {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BK = 16;
+
+__device__ __forceinline__ int xcd_swizzle(int wid, int total) {
+  const int nx = 8;
+  int q = total / nx, r = total % nx;
+  int x = wid % nx, l = wid / nx;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
+}
+
+template <int BM, int BN>
+__device__ __forceinline__ void decode_tile(const GemmArgs& p, int tile, int& I, int& J) {
+  if (p.map == MAP_FULL) {
+    I = tile / p.tiles_n;
+    J = tile % p.tiles_n;
+    return;
+  }
+  // lower map: row tile I holds columns J <= ((I+1)*BM - 1) / BN
+  int acc = 0;
+  for (I = 0; I < p.tiles_m; ++I) {
+    int cnt = ((I + 1) * BM - 1) / BN + 1;
+    if (cnt > p.tiles_n) cnt = p.tiles_n;
+    if (tile < acc + cnt) { J = tile - acc; return; }
+    acc += cnt;
+  }
+  I = p.tiles_m; J = 0;  // unreachable when n_tiles is consistent
+}
+
+template <int BR, int LAYOUT, bool SCALED>
+struct Stager {
+  // number of double2 items per thread for a BR x 16 tile
+  static constexpr int NITEM = BR * BK / 2 / 256;
+  double2 v[NITEM];
+  __device__ __forceinline__ void load(const double* X, long ld, int r0, int kk0,
+                                       const double* s, int t) {
+#pragma unroll
+    for (int u = 0; u < NITEM; ++u) {
+      int q = t + 256 * u;
+      if (LAYOUT == KC) {
+        int row = q / 8, k = (q % 8) * 2;
+        v[u] = *reinterpret_cast<const double2*>(X + (long)(r0 + row) * ld + kk0 + k);
+        if (SCALED) {
+          double2 sv = *reinterpret_cast<const double2*>(s + kk0 + k);
+          v[u].x *= sv.x;
+          v[u].y *= sv.y;
+        }
+      } else {
+        int k = q / (BR / 2), rp = (q % (BR / 2)) * 2;
+        v[u] = *reinterpret_cast<const double2*>(X + (long)(kk0 + k) * ld + r0 + rp);
+        if (SCALED) {
+          double sk = s[kk0 + k];
+          v[u].x *= sk;
+          v[u].y *= sk;
+        }
+      }
+    }
+  }
+  __device__ __forceinline__ void store(double (*Xs)[BR], int t) {
+#pragma unroll
+    for (int u = 0; u < NITEM; ++u) {
+      int q = t + 256 * u;
+      if (LAYOUT == KC) {
+        int row = q / 8, k = (q % 8) * 2;
+        Xs[k][row] = v[u].x;
+        Xs[k + 1][row] = v[u].y;
+      } else {
+        int k = q / (BR / 2), rp = (q % (BR / 2)) * 2;
+        *reinterpret_cast<double2*>(&Xs[k][rp]) = v[u];
+      }
+    }
+  }
+};
+
+template <int WAVES_M, int TM, int TN, int LA, int LB, int EPI, bool SCALED, bool BATCH_FAST>
+__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
+  constexpr int WAVES_N = 4 / WAVES_M;
+  constexpr int BM = WAVES_M * TM * 16;
+  constexpr int BN = WAVES_N * TN * 16;
+  __shared__ double As[2][BK][BM];
+  __shared__ double Bs[2][BK][BN];
+  __shared__ double red[WAVES_N][BM];
+
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+
+  const int total = p.n_tiles * p.batch * p.splitk;
+  const int id = xcd_swizzle(blockIdx.x, total);
+  int tile, b, split;
+  if (BATCH_FAST) {
+    b = id % p.batch;
+    int rest = id / p.batch;
+    split = rest % p.splitk;
+    tile = rest / p.splitk;
+  } else {
+    tile = id % p.n_tiles;
+    int rest = id / p.n_tiles;
+    split = rest % p.splitk;
+    b = rest / p.splitk;
+  }
+  int I, J;
+  decode_tile<BM, BN>(p, tile, I, J);
+
+  const double* A = p.A + (long)b * p.sA;
+  const double* Bm = p.B + (long)b * p.sB;
+  const double* S = SCALED ? p.scale + (long)b * p.sS : nullptr;
+  const int arow0 = p.row0 + I * BM;
+  const int brow0 = p.col0 + J * BN;
+
+  int kchunk = ((p.K / BK + p.splitk - 1) / p.splitk) * BK;
+  int kbeg = split * kchunk;
+  int kend = kbeg + kchunk;
+  if (kend > p.K) kend = p.K;
+  const int nk = kend > kbeg ? (kend - kbeg) / BK : 0;
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  Stager<BM, LA, false> sa;
+  Stager<BN, LB, SCALED> sb;
+  if (nk > 0) {
+    sa.load(A, p.lda, arow0, p.k0 + kbeg, nullptr, t);
+    sb.load(Bm, p.ldb, brow0, p.kb0 + kbeg, S, t);
+    sa.store(As[0], t);
+    sb.store(Bs[0], t);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) {
+      const int kstep = kbeg + (kt + 1) * BK;
+      sa.load(A, p.lda, arow0, p.k0 + kstep, nullptr, t);
+      sb.load(Bm, p.ldb, brow0, p.kb0 + kstep, S, t);
+    }
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kr = ks * 4 + (lane >> 4);
+      double av[TM], bv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) av[i] = As[cur][kr][wm * TM * 16 + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bv[j] = Bs[cur][kr][wn * TN * 16 + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) {
+      sa.store(As[cur ^ 1], t);
+      sb.store(Bs[cur ^ 1], t);
+    }
+    __syncthreads();
+  }
+
+  // Epilogue.  f64 16x16x4 output layout: lane l, register r holds
+  // row (l / 16) + 4 r, column l % 16 of the 16x16 block.
+  double* C = p.C + (long)b * p.sC + (long)split * p.sSplit;
+  if (EPI == EPI_RES_DERIV) {
+    // per-row sum over this tile's columns of acc^2 * 2 D w / (D^2 - w^2)^2
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int lrow = wm * TM * 16 + i * 16 + (lane >> 4) + 4 * r;
+        const double w = p.wrow[arow0 + lrow];
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int gcol = brow0 + wn * TN * 16 + j * 16 + (lane & 15);
+          const double D = p.Dvec[gcol];
+          const double den = D * D - w * w;
+          const double u = acc[i][j][r];
+          s += u * u * (2.0 * D * w / (den * den));
+        }
+        // reduce over the 16 lanes sharing this row
+        for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+        if ((lane & 15) == 0) red[wn][lrow] = s;
+      }
+    }
+    __syncthreads();
+    if (t < BM) {
+      double s = 0.0;
+#pragma unroll
+      for (int q = 0; q < WAVES_N; ++q) s += red[q][t];
+      C[(long)J * p.ldc + arow0 + t] = s;
+    }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int grow = arow0 + wm * TM * 16 + i * 16 + (lane >> 4) + 4 * r;
+        const int gcol = brow0 + wn * TN * 16 + j * 16 + (lane & 15);
+        double* c = C + (long)grow * p.ldc + gcol;
+        const double v = acc[i][j][r];
+        if (EPI == EPI_ONE_PLUS_4) {
+          *c = (grow == gcol ? 1.0 : 0.0) + 4.0 * v;
+        } else if (EPI == EPI_AXPBY) {
+          *c = (p.beta == 0.0) ? p.alpha * v : p.alpha * v + p.beta * (*c);
+        } else if (EPI == EPI_RES_SCALE) {
+          const double w = p.wrow[grow];
+          const double D = p.Dvec[gcol];
+          *c = v * (D / (D * D - w * w));
+        } else {
+          *c = v;
+        }
+      }
+    }
+  }
+}
+
+template <int WAVES_M, int TM, int TN, int LA, int LB, int EPI, bool SCALED, bool BF>
+static hipError_t launch(const GemmArgs& a, hipStream_t st) {
+  const long total = (long)a.n_tiles * a.batch * a.splitk;
+  if (total <= 0) return hipSuccess;
+  if (total > 0x7fffffffL) return hipErrorInvalidValue;
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL((k_gemm_f64<WAVES_M, TM, TN, LA, LB, EPI, SCALED, BF>), dim3((unsigned)total),
+                     dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+// Largest element index each operand of a launch can touch (see the kernel's
+// index arithmetic above), checked against the extents carried in GemmArgs.
+static hipError_t check_gemm(const GemmArgs& a, int tile_kind, int la, int lb, int epi) {
+  const int BM = tile_kind == 2 ? 64 : 128;
+  const int BN = tile_kind == 1 ? 64 : 128;
+  const char* kn = "gemm_f64";
+  if (a.K <= 0 || a.K % BK != 0 || a.tiles_m <= 0 || a.tiles_n <= 0 || a.batch <= 0 ||
+      a.splitk <= 0 || a.row0 < 0 || a.col0 < 0 || a.k0 < 0 || a.kb0 < 0)
+    return refuse(kn, "shape");
+  long want = a.map == MAP_FULL ? (long)a.tiles_m * a.tiles_n : 0;
+  if (a.map == MAP_LOWER)
+    for (int I = 0; I < a.tiles_m; ++I) {
+      int c = ((I + 1) * BM - 1) / BN + 1;
+      want += c < a.tiles_n ? c : a.tiles_n;
+    }
+  if (want != a.n_tiles) return refuse(kn, "tile count");
+  // 16-byte vector loads: even leading dimensions and offsets, aligned bases
+  if ((a.lda | a.ldb | a.k0 | a.kb0 | a.row0 | a.col0) & 1)
+    return refuse(kn, "odd leading dimension or offset");
+  if (((uintptr_t)a.A | (uintptr_t)a.B) & 15)
+    return refuse(kn, "operand pointer not 16-byte aligned");
+  const long rmax = a.row0 + (long)a.tiles_m * BM - 1;
+  const long cmax = a.col0 + (long)a.tiles_n * BN - 1;
+  const long b1 = a.batch - 1;
+  long maxA = la == KC ? b1 * a.sA + rmax * a.lda + a.k0 + a.K - 1
+                       : b1 * a.sA + (long)(a.k0 + a.K - 1) * a.lda + rmax;
+  long maxB = lb == KC ? b1 * a.sB + cmax * a.ldb + a.kb0 + a.K - 1
+                       : b1 * a.sB + (long)(a.kb0 + a.K - 1) * a.ldb + cmax;
+  if (!guard(kn, "A", maxA, a.nA)) return hipErrorInvalidValue;
+  if (!guard(kn, "B", maxB, a.nB)) return hipErrorInvalidValue;
+  if (a.scale && !guard(kn, "scale", b1 * a.sS + a.kb0 + a.K - 1, a.nS)) return hipErrorInvalidValue;
+  long maxC = b1 * a.sC + (long)(a.splitk - 1) * a.sSplit +
+              (epi == EPI_RES_DERIV ? (long)(a.tiles_n - 1) * a.ldc + rmax : rmax * a.ldc + cmax);
+  if (!guard(kn, "C", maxC, a.nC)) return hipErrorInvalidValue;
+  if (epi == EPI_RES_SCALE || epi == EPI_RES_DERIV) {
+    if (!guard(kn, "D", cmax, a.nD)) return hipErrorInvalidValue;
+    if (!guard(kn, "w", rmax, a.nW)) return hipErrorInvalidValue;
+  }
+  return hipSuccess;
+}
+
+// Instantiations used by the library.  tile_kind: 0 = 128x128, 1 = 128x64, 2 = 64x128.
+hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, hipStream_t st) {
+  {
+    hipError_t e = check_gemm(a, tile_kind, la, lb, epi);
+    if (e != hipSuccess) return e;
+  }
+  const bool scaled = a.scale != nullptr;
+  // Pi build: KC x KC, scaled, 1 + 4 acc, batch-fastest
+  if (tile_kind == 0 && la == KC && lb == KC && epi == EPI_ONE_PLUS_4 && scaled)
+    return launch<2, 4, 4, KC, KC, EPI_ONE_PLUS_4, true, true>(a, st);
+  // Cholesky trailing update: KC x KC, axpby
+  if (tile_kind == 0 && la == KC && lb == KC && epi == EPI_AXPBY && !scaled)
+    return launch<2, 4, 4, KC, KC, EPI_AXPBY, false, false>(a, st);
+  // Cholesky panel solve (A_panel Linv^T): 128 x 64, axpby
+  if (tile_kind == 1 && la == KC && lb == KC && epi == EPI_AXPBY && !scaled)
+    return launch<2, 4, 2, KC, KC, EPI_AXPBY, false, false>(a, st);
+  // MINRES: V = scale(X B) with X [sys][P] (KC) and B_ov [P][ia] (KM): 64 x 128 tiles
+  if (tile_kind == 2 && la == KC && lb == KM && epi == EPI_RES_SCALE && !scaled)
+    return launch<1, 4, 2, KC, KM, EPI_RES_SCALE, false, false>(a, st);
+  if (tile_kind == 2 && la == KC && lb == KM && epi == EPI_RES_DERIV && !scaled)
+    return launch<1, 4, 2, KC, KM, EPI_RES_DERIV, false, false>(a, st);
+  // MINRES: part[s][sys][P] = sum_ia V[sys][ia] B_ov[P][ia], split-K partials, 64 x 128 tiles
+  if (tile_kind == 2 && la == KC && lb == KC && epi == EPI_STORE && !scaled)
+    return launch<1, 4, 2, KC, KC, EPI_STORE, false, false>(a, st);
+  // generic full 128x128 store / axpby (tests, dense fallback build)
+  if (tile_kind == 0 && la == KC && lb == KC && epi == EPI_STORE && scaled)
+    return launch<2, 4, 4, KC, KC, EPI_STORE, true, false>(a, st);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace gw

@@ -1,0 +1,1222 @@
+// Host side of libgw: the C-ABI of include/gw.h, the per-molecule context,
+// the stage-A pipeline (Pi build -> blocked Cholesky -> W^c table), the
+// batched residue solver driver and the quasiparticle step tree.
+//
+// Method: Mejia-Rodriguez et al., "Scalable Molecular GW Calculations:
+// Valence and Core Spectra", Implementation - Contour Deformation, Algorithm 1
+// and Implementation - Solution of the Quasiparticle Equations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gw.h"
+#include "../../include/gw_audit.h"
+#include "gw_internal.h"
+
+using namespace gw;
+
+namespace {
+
+thread_local std::string g_err;
+bool g_contexts_created = false;
+
+// Host-side trace of every stage, to stderr, when GW_TRACE is set.
+bool trace_on() {
+  static const bool on = getenv("GW_TRACE") != nullptr;
+  return on;
+}
+void trace(const char* fmt, ...) {
+  if (!trace_on()) return;
+  va_list ap;
+  va_start(ap, fmt);
+  fprintf(stderr, "[gw] ");
+  vfprintf(stderr, fmt, ap);
+  fprintf(stderr, "\n");
+  fflush(stderr);
+  va_end(ap);
+}
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(GW_EDEVICE, "%s failed: %s [%s] (%s:%d)", #expr, hipGetErrorString(e_),    \
+                  gw::launch_error(), __FILE__, __LINE__);                                   \
+  } while (0)
+
+#define RCHK(expr)            \
+  do {                        \
+    int r_ = (expr);          \
+    if (r_ != 0) return r_;   \
+  } while (0)
+
+// Runtime calls go through these wrappers.  In launch-audit mode (see
+// include/gw_audit.h) device buffers are host memory, copies are memcpy and
+// nothing is launched; the kernel wrappers only run their bounds guards.
+hipError_t rt_malloc(void** p, size_t bytes) {
+  if (audit_mode()) {
+    size_t b = (bytes + 255) / 256 * 256;
+    *p = aligned_alloc(256, b);
+    if (!*p) return hipErrorOutOfMemory;
+    memset(*p, 0, b);
+    return hipSuccess;
+  }
+  return hipMalloc(p, bytes);
+}
+void rt_free(void* p) {
+  if (audit_mode()) free(p);
+  else hipFree(p);
+}
+hipError_t rt_memcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t st) {
+  if (audit_mode()) {
+    if (bytes) memcpy(dst, src, bytes);
+    return hipSuccess;
+  }
+  return hipMemcpyAsync(dst, src, bytes, kind, st);
+}
+hipError_t rt_memcpy2d(void* dst, size_t dpitch, const void* src, size_t spitch, size_t width,
+                       size_t height, hipMemcpyKind kind, hipStream_t st) {
+  if (audit_mode()) {
+    for (size_t r = 0; r < height; ++r)
+      memcpy((char*)dst + r * dpitch, (const char*)src + r * spitch, width);
+    return hipSuccess;
+  }
+  return hipMemcpy2DAsync(dst, dpitch, src, spitch, width, height, kind, st);
+}
+hipError_t rt_memset(void* p, int v, size_t bytes, hipStream_t st) {
+  if (audit_mode()) {
+    memset(p, v, bytes);
+    return hipSuccess;
+  }
+  return hipMemsetAsync(p, v, bytes, st);
+}
+hipError_t rt_sync(hipStream_t st) { return audit_mode() ? hipSuccess : hipStreamSynchronize(st); }
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+inline long round_up_l(long x, long m) { return (x + m - 1) / m * m; }
+
+constexpr int PANEL = 64;  // Cholesky panel width (matches chol.hip)
+
+long lower_tile_count(int tiles_m, int tiles_n, int BM, int BN) {
+  long n = 0;
+  for (int I = 0; I < tiles_m; ++I) {
+    int c = ((I + 1) * BM - 1) / BN + 1;
+    n += std::min(c, tiles_n);
+  }
+  return n;
+}
+
+// Residue system of one Sigma evaluation
+struct System {
+  int q;        // row of the right-hand side in the padded R buffer (r * n_mo + m)
+  double w;     // real frequency eps_m - omega
+};
+
+struct Timer {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t st = nullptr;
+  void start(hipStream_t s) {
+    st = s;
+    if (!audit_mode()) hipEventRecord(a, st);
+  }
+  double stop() {
+    if (audit_mode()) return 0.0;
+    hipEventRecord(b, st);
+    hipEventSynchronize(b);
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, a, b);
+    return ms;
+  }
+};
+
+}  // namespace
+
+struct gw_ctx {
+  // sizes
+  int n_mo = 0, n_occ = 0, n_virt = 0, n_aux = 0, n_rows = 0;
+  int Np = 0;      // n_aux padded to 128
+  int Kov = 0;     // n_occ * n_virt
+  int Kp = 0;      // Kov padded to 128
+  int nR = 0;      // n_rows * n_mo
+  int Rp = 0;      // nR padded to 64
+  // options
+  int pi_prec = GW_PI_FP64;
+  int minres_max_iter = 200;
+  double minres_rtol = 1e-12;
+  double qp_tol = 1e-10;
+  int qp_max_iter = 100;
+  size_t mem_budget = 0, work_budget = 16ull << 30;
+  size_t mem_used = 0;
+  // host copies
+  std::vector<double> eps, dsig_x;
+  std::vector<int> row_ids;
+  std::map<int, int> row_of;
+  // stream
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;    // stage timers
+  hipEvent_t ev0b = nullptr, ev1b = nullptr;  // whole-call timer
+  // device data
+  double* d_eps = nullptr;
+  double* d_D = nullptr;       // [Kp]
+  double* d_Bov = nullptr;     // [Np][Kp]
+  double* d_R = nullptr;       // [Rp][Np]
+  double* d_bn = nullptr;      // [Rp]
+  // mixed-precision copies of B_ov (lazily built)
+  float* d_B32 = nullptr;
+  uint16_t* d_Bhi = nullptr;
+  uint16_t* d_Blo = nullptr;
+  // stage-A workspace
+  double* d_work = nullptr;
+  size_t work_bytes = 0;
+  int chunk = 0;
+  double* d_Linv = nullptr;
+  int* d_info = nullptr;
+  double* d_scale = nullptr;   // [chunk][Kp]
+  double* d_grid = nullptr;    // [2][Gmax]
+  int grid_cap = 0;
+  // W^c table cache
+  double* d_wtab = nullptr;    // [nR][G]
+  int wtab_G = 0;
+  bool wtab_valid = false;
+  std::vector<double> wtab_xi, wtab_w;
+  int wtab_prec = -1;
+  // Sigma quadrature buffers
+  int* d_rowsel = nullptr;
+  double* d_omega = nullptr;
+  double* d_sig = nullptr;
+  double* d_dsig = nullptr;
+  int sig_cap = 0;
+  // MINRES workspace
+  MinresBufs mr{};
+  int mr_cap = 0;       // kp capacity
+  int mr_splitk = 1;
+  size_t part_cap = 0;  // doubles
+  int* d_rhs_idx = nullptr;
+  double* d_wc = nullptr;
+  double* d_dwc = nullptr;
+  int* d_conv = nullptr;
+  // dense fallback workspace
+  double* d_dense = nullptr;
+  double* d_dscale = nullptr;
+  double* d_db = nullptr;
+  int* d_dinfo = nullptr;
+  gw_timing timing{};
+
+  std::vector<void*> allocs;
+
+  int alloc(void** p, size_t bytes) {
+    if (bytes == 0) bytes = 8;
+    if (mem_budget && mem_used + bytes > mem_budget)
+      return fail(GW_ENOMEM, "device memory budget exceeded: need %zu more bytes, %zu of %zu used",
+                  bytes, mem_used, mem_budget);
+    hipError_t e = rt_malloc(p, bytes);
+    if (e != hipSuccess) return fail(GW_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    allocs.push_back(*p);
+    mem_used += bytes;
+    alloc_sizes[*p] = bytes;
+    return 0;
+  }
+  void release(void* p) {
+    if (!p) return;
+    auto it = alloc_sizes.find(p);
+    if (it != alloc_sizes.end()) {
+      mem_used -= it->second;
+      alloc_sizes.erase(it);
+    }
+    allocs.erase(std::remove(allocs.begin(), allocs.end(), p), allocs.end());
+    rt_free(p);
+  }
+  // elements of size `elem` reachable from p inside its allocation (0 if none)
+  long ext(const void* p, size_t elem) const {
+    if (!p) return 0;
+    auto it = alloc_sizes.upper_bound(const_cast<void*>(p));
+    if (it == alloc_sizes.begin()) return 0;
+    --it;
+    const char* base = (const char*)it->first;
+    const char* q = (const char*)p;
+    if (q < base || q >= base + it->second) return 0;
+    return (long)((size_t)(base + it->second - q) / elem);
+  }
+  std::map<void*, size_t> alloc_sizes;
+
+  ~gw_ctx() {
+    if (st) hipStreamSynchronize(st);
+    for (void* p : allocs) rt_free(p);
+    for (hipEvent_t e : {ev0, ev1, ev0b, ev1b})
+      if (e) hipEventDestroy(e);
+    if (own_stream && st) hipStreamDestroy(st);
+  }
+};
+
+namespace {
+
+template <class T>
+int ensure(gw_ctx* c, T** p, size_t count, size_t* cap_bytes = nullptr) {
+  size_t bytes = count * sizeof(T);
+  if (*p && cap_bytes && *cap_bytes >= bytes) return 0;
+  if (*p) c->release(*p);
+  *p = nullptr;
+  RCHK(c->alloc(reinterpret_cast<void**>(p), bytes));
+  if (cap_bytes) *cap_bytes = bytes;
+  return 0;
+}
+
+// GEMM launch with operand extents taken from the context's allocation map
+int run_gemm(gw_ctx* c, GemmArgs a, int kind, int la, int lb, int epi) {
+  trace("gemm kind=%d la=%d lb=%d epi=%d tiles=%dx%d n=%d batch=%d split=%d K=%d", kind, la, lb,
+        epi, a.tiles_m, a.tiles_n, a.n_tiles, a.batch, a.splitk, a.K);
+  a.nA = c->ext(a.A, sizeof(double));
+  a.nB = c->ext(a.B, sizeof(double));
+  a.nS = c->ext(a.scale, sizeof(double));
+  a.nC = c->ext(a.C, sizeof(double));
+  a.nD = c->ext(a.Dvec, sizeof(double));
+  a.nW = c->ext(a.wrow, sizeof(double));
+  HIPCHK(gemm_f64(a, kind, la, lb, epi, c->st));
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Stage A: W^c table for a grid
+
+int ensure_mixed_operands(gw_ctx* c);
+int pi_build_chunk(gw_ctx* c, int G, long per_g, long ldA);
+
+int setup_work(gw_ctx* c, int G) {
+  const long ldA = c->Np + 128;
+  const long rows = (long)c->Np + c->Rp + 128;
+  const long per_g = rows * ldA;
+  size_t per_bytes = (size_t)per_g * sizeof(double) + (size_t)c->Kp * sizeof(double) +
+                     PANEL * PANEL * sizeof(double);
+  int chunk = (int)std::max<size_t>(1, c->work_budget / per_bytes);
+  if (chunk > G) chunk = G;
+  if (c->d_work && c->chunk >= chunk) return 0;
+  if (c->d_work) c->release(c->d_work);
+  if (c->d_Linv) c->release(c->d_Linv);
+  if (c->d_info) c->release(c->d_info);
+  if (c->d_scale) c->release(c->d_scale);
+  c->d_work = nullptr;
+  c->d_Linv = nullptr;
+  c->d_info = nullptr;
+  c->d_scale = nullptr;
+  RCHK(c->alloc((void**)&c->d_work, (size_t)per_g * chunk * sizeof(double)));
+  HIPCHK(rt_memset(c->d_work, 0, (size_t)per_g * chunk * sizeof(double), c->st));
+  RCHK(c->alloc((void**)&c->d_Linv, (size_t)chunk * PANEL * PANEL * sizeof(double)));
+  RCHK(c->alloc((void**)&c->d_info, (size_t)chunk * sizeof(int)));
+  RCHK(c->alloc((void**)&c->d_scale, (size_t)chunk * c->Kp * sizeof(double)));
+  c->chunk = chunk;
+  return 0;
+}
+
+int upload_grid(gw_ctx* c, int n, const double* xi, const double* w) {
+  if (n > c->grid_cap) {
+    if (c->d_grid) c->release(c->d_grid);
+    c->d_grid = nullptr;
+    RCHK(c->alloc((void**)&c->d_grid, 2 * (size_t)n * sizeof(double)));
+    c->grid_cap = n;
+  }
+  HIPCHK(rt_memcpy(c->d_grid, xi, n * sizeof(double), hipMemcpyHostToDevice, c->st));
+  HIPCHK(rt_memcpy(c->d_grid + c->grid_cap, w, n * sizeof(double), hipMemcpyHostToDevice,
+                        c->st));
+  return 0;
+}
+
+int check_grid(const gw_grid* grid) {
+  if (!grid || grid->n < 1 || !grid->xi || !grid->w)
+    return fail(GW_EINVAL, "grid must have n >= 1 and non-NULL xi, w");
+  for (int g = 0; g < grid->n; ++g)
+    if (!(std::isfinite(grid->xi[g]) && std::isfinite(grid->w[g]) && grid->xi[g] >= 0.0))
+      return fail(GW_EINVAL, "grid point %d is not finite and non-negative", g);
+  return 0;
+}
+
+// Pi build of `G` grid points (scales already in d_scale) into the work buffer
+int pi_build_chunk(gw_ctx* c, int G, long per_g, long ldA) {
+  if (c->pi_prec == GW_PI_FP64) {
+    GemmArgs a{};
+    a.A = c->d_Bov; a.lda = c->Kp; a.sA = 0;
+    a.B = c->d_Bov; a.ldb = c->Kp; a.sB = 0;
+    a.scale = c->d_scale; a.sS = c->Kp;
+    a.C = c->d_work; a.ldc = ldA; a.sC = per_g;
+    a.M = c->Np; a.N = c->Np; a.K = c->Kp;
+    a.row0 = 0; a.col0 = 0; a.k0 = 0;
+    a.map = MAP_LOWER;
+    a.tiles_m = c->Np / 128; a.tiles_n = c->Np / 128;
+    a.n_tiles = (int)lower_tile_count(a.tiles_m, a.tiles_n, 128, 128);
+    a.batch = G; a.splitk = 1; a.sSplit = 0;
+    RCHK(run_gemm(c, a, 0, KC, KC, EPI_ONE_PLUS_4));
+    return 0;
+  }
+  RCHK(ensure_mixed_operands(c));
+  if (c->pi_prec == GW_PI_FP32) {
+    HIPCHK(pi_build_f32(c->d_B32, c->Kp, c->d_scale, c->Kp, c->d_work, ldA, per_g, c->Np, c->Kp,
+                        G, c->ext(c->d_B32, 4), c->ext(c->d_scale, 8), c->ext(c->d_work, 8),
+                        c->st));
+    return 0;
+  }
+  const long nB = std::min({c->ext(c->d_Bhi, 2), c->ext(c->d_Blo, 2), c->ext(c->d_B32, 4)});
+  HIPCHK(pi_build_bf16x3(c->d_Bhi, c->d_Blo, c->Kp, c->d_B32, c->d_scale, c->Kp, c->d_work, ldA,
+                         per_g, c->Np, c->Kp, G, nB, c->ext(c->d_scale, 8), c->ext(c->d_work, 8),
+                         c->st));
+  return 0;
+}
+
+int ensure_mixed_operands(gw_ctx* c) {
+  const size_t n = (size_t)c->Np * c->Kp;
+  if (!c->d_B32) {
+    RCHK(c->alloc((void**)&c->d_B32, n * sizeof(float)));
+    RCHK(c->alloc((void**)&c->d_Bhi, n * sizeof(uint16_t)));
+    RCHK(c->alloc((void**)&c->d_Blo, n * sizeof(uint16_t)));
+    HIPCHK(split_bf16(c->d_Bov, c->d_Bhi, c->d_Blo, c->d_B32, (long)n, c->st));
+  }
+  return 0;
+}
+
+// Blocked right-looking Cholesky of every item of the chunk, over the
+// augmented rows [0, Np + Rp).
+int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
+  const int Mrows = c->Np + c->Rp;
+  HIPCHK(rt_memset(c->d_info, 0, G * sizeof(int), c->st));
+  for (int k = 0; k < c->Np; k += PANEL) {
+    trace("cholesky panel k=%d", k);
+    HIPCHK(chol_diag(c->d_work, ldA, per_g, c->d_Linv, k, G, c->d_info, c->ext(c->d_work, 8),
+                     c->ext(c->d_Linv, 8), c->ext(c->d_info, 4), c->st));
+    const int rows_below = Mrows - (k + PANEL);
+    if (rows_below <= 0) continue;
+    {  // panel solve: L[i][k:k+64] = A[i][k:k+64] Linv^T
+      GemmArgs a{};
+      a.A = c->d_work; a.lda = ldA; a.sA = per_g;
+      a.B = c->d_Linv; a.ldb = PANEL; a.sB = PANEL * PANEL;
+      a.C = c->d_work + k; a.ldc = ldA; a.sC = per_g;
+      a.K = PANEL; a.row0 = k + PANEL; a.col0 = 0; a.k0 = k; a.kb0 = 0;
+      a.map = MAP_FULL;
+      a.tiles_m = (rows_below + 127) / 128; a.tiles_n = 1;
+      a.M = a.tiles_m * 128; a.N = PANEL;
+      a.n_tiles = a.tiles_m; a.batch = G; a.splitk = 1;
+      a.alpha = 1.0; a.beta = 0.0;
+      RCHK(run_gemm(c, a, 1, KC, KC, EPI_AXPBY));
+    }
+    const int cols_right = c->Np - (k + PANEL);
+    if (cols_right <= 0) continue;
+    {  // trailing update of the lower trapezoid: A -= L_panel L_panel^T
+      GemmArgs a{};
+      a.A = c->d_work; a.lda = ldA; a.sA = per_g;
+      a.B = c->d_work; a.ldb = ldA; a.sB = per_g;
+      a.C = c->d_work; a.ldc = ldA; a.sC = per_g;
+      a.K = PANEL; a.row0 = k + PANEL; a.col0 = k + PANEL; a.k0 = k; a.kb0 = k;
+      a.map = MAP_LOWER;
+      a.tiles_m = (rows_below + 127) / 128; a.tiles_n = (cols_right + 127) / 128;
+      a.M = a.tiles_m * 128; a.N = a.tiles_n * 128;
+      a.n_tiles = (int)lower_tile_count(a.tiles_m, a.tiles_n, 128, 128);
+      a.batch = G; a.splitk = 1;
+      a.alpha = -1.0; a.beta = 1.0;
+      RCHK(run_gemm(c, a, 0, KC, KC, EPI_AXPBY));
+    }
+  }
+  std::vector<int> info(G);
+  HIPCHK(rt_memcpy(info.data(), c->d_info, G * sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(rt_sync(c->st));
+  for (int g = 0; g < G; ++g)
+    if (info[g] != 0)
+      return fail(GW_ENOTSPD, "1 - Pi(i xi) is not positive definite (item %d, pivot %d)", g,
+                  info[g]);
+  return 0;
+}
+
+// Copy the leading n_aux x n_aux block of each chunk item to host memory and
+// zero its strict upper triangle (only the lower triangle is maintained).
+int copy_out_blocks(gw_ctx* c, double* dst, int Gc, long per_g, long ldA) {
+  const int n = c->n_aux;
+  for (int g = 0; g < Gc; ++g)
+    HIPCHK(rt_memcpy2d(dst + (size_t)g * n * n, n * sizeof(double), c->d_work + g * per_g,
+                            ldA * sizeof(double), n * sizeof(double), n, hipMemcpyDeviceToHost,
+                            c->st));
+  HIPCHK(rt_sync(c->st));
+  for (int g = 0; g < Gc; ++g)
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) dst[(size_t)g * n * n + (size_t)i * n + j] = 0.0;
+  return 0;
+}
+
+// Build the W^c table for `grid` unless cached.  mode: 0 normal; 1/2 write
+// the dielectric matrix / Cholesky factor of each point to `dbg_out`.
+int build_wtable(gw_ctx* c, const gw_grid* grid, int mode = 0, double* dbg_out = nullptr) {
+  RCHK(check_grid(grid));
+  const int G = grid->n;
+  if (mode == 0 && c->wtab_valid && c->wtab_G == G && c->wtab_prec == c->pi_prec &&
+      std::equal(grid->xi, grid->xi + G, c->wtab_xi.begin()) &&
+      std::equal(grid->w, grid->w + G, c->wtab_w.begin())) {
+    c->timing.wtab_cached = 1;
+    return 0;
+  }
+  c->timing.wtab_cached = 0;
+  RCHK(setup_work(c, G));
+  RCHK(upload_grid(c, G, grid->xi, grid->w));
+  if (mode == 0) {
+    if (c->d_wtab && c->wtab_G < G) {
+      c->release(c->d_wtab);
+      c->d_wtab = nullptr;
+    }
+    if (!c->d_wtab) {
+      RCHK(c->alloc((void**)&c->d_wtab, (size_t)std::max(c->nR, 1) * G * sizeof(double)));
+    }
+    c->wtab_valid = false;
+  }
+  const long ldA = c->Np + 128;
+  const long per_g = ((long)c->Np + c->Rp + 128) * ldA;
+  Timer tm;
+  tm.a = c->ev0; tm.b = c->ev1;
+  double pi_ms = 0, chol_ms = 0, wt_ms = 0;
+  for (int g0 = 0; g0 < G; g0 += c->chunk) {
+    const int Gc = std::min(c->chunk, G - g0);
+    trace("stage A mode=%d g0=%d Gc=%d prec=%d Np=%d Kp=%d Rp=%d", mode, g0, Gc, c->pi_prec, c->Np,
+          c->Kp, c->Rp);
+    tm.start(c->st);
+    HIPCHK(make_scale_imag(c->d_D, c->Kov, c->Kp, c->d_grid + g0, Gc, c->d_scale,
+                           c->ext(c->d_D, 8), G - g0, c->ext(c->d_scale, 8), c->st));
+    RCHK(pi_build_chunk(c, Gc, per_g, ldA));
+    pi_ms += tm.stop();
+    if (mode == 1) {
+      RCHK(copy_out_blocks(c, dbg_out + (size_t)g0 * c->n_aux * c->n_aux, Gc, per_g, ldA));
+      continue;
+    }
+    tm.start(c->st);
+    if (c->nR > 0) {
+      HIPCHK(copy_rows_into(c->d_work, ldA, per_g, c->Np, c->d_R, c->Rp, c->Np, Gc,
+                            c->ext(c->d_work, 8), c->ext(c->d_R, 8), c->st));
+    }
+    RCHK(cholesky_chunk(c, Gc, per_g, ldA));
+    chol_ms += tm.stop();
+    if (mode == 2) {
+      RCHK(copy_out_blocks(c, dbg_out + (size_t)g0 * c->n_aux * c->n_aux, Gc, per_g, ldA));
+      continue;
+    }
+    tm.start(c->st);
+    if (c->nR > 0) {
+      HIPCHK(wc_reduce_chunk(c->d_work, ldA, per_g, c->Np, c->d_bn, c->nR, c->Np, Gc, G, g0,
+                             c->d_wtab, c->ext(c->d_work, 8), c->ext(c->d_bn, 8),
+                             c->ext(c->d_wtab, 8), c->st));
+    }
+    wt_ms += tm.stop();
+  }
+  c->timing.pi_ms = pi_ms;
+  c->timing.chol_ms = chol_ms;
+  c->timing.wtab_ms = wt_ms;
+  if (mode == 0) {
+    c->wtab_valid = true;
+    c->wtab_G = G;
+    c->wtab_prec = c->pi_prec;
+    c->wtab_xi.assign(grid->xi, grid->xi + G);
+    c->wtab_w.assign(grid->w, grid->w + G);
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Residues: batched MINRES with dense fallback
+
+int ensure_minres(gw_ctx* c, int kp) {
+  if (kp <= c->mr_cap) return 0;
+  MinresBufs& m = c->mr;
+  void* olds[] = {m.x, m.w, m.w2, m.r1, m.r2, m.y, m.v, m.scal, m.V, m.part, m.omega, m.active,
+                  c->d_rhs_idx, c->d_wc, c->d_dwc, c->d_conv};
+  for (void* p : olds) c->release(p);
+  const size_t vec = (size_t)kp * c->Np;
+  double** vecs[] = {&m.x, &m.w, &m.w2, &m.r1, &m.r2, &m.y, &m.v};
+  for (double** p : vecs) RCHK(c->alloc((void**)p, vec * sizeof(double)));
+  RCHK(c->alloc((void**)&m.scal, (size_t)kp * 16 * sizeof(double)));
+  RCHK(c->alloc((void**)&m.V, (size_t)kp * c->Kp * sizeof(double)));
+  // split-K partials for B_ov V^T: aim for >= 512 workgroups
+  const int tiles = (kp / 64) * (c->Np / 128);
+  int splitk = std::max(1, std::min(512 / std::max(tiles, 1) + 1, c->Kp / 128));
+  c->mr_splitk = splitk;
+  size_t part = std::max((size_t)splitk * kp * c->Np, (size_t)(c->Kp / 128) * kp);
+  RCHK(c->alloc((void**)&m.part, part * sizeof(double)));
+  c->part_cap = part;
+  RCHK(c->alloc((void**)&m.omega, (size_t)kp * sizeof(double)));
+  RCHK(c->alloc((void**)&m.active, sizeof(int)));
+  RCHK(c->alloc((void**)&c->d_rhs_idx, (size_t)kp * sizeof(int)));
+  RCHK(c->alloc((void**)&c->d_wc, (size_t)kp * sizeof(double)));
+  RCHK(c->alloc((void**)&c->d_dwc, (size_t)kp * sizeof(double)));
+  RCHK(c->alloc((void**)&c->d_conv, (size_t)kp * sizeof(int)));
+  c->mr_cap = kp;
+  return 0;
+}
+
+int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long ldc) {
+  // out = scale(X B_ov): rows = systems, cols = ia
+  GemmArgs a{};
+  a.A = X; a.lda = c->Np; a.sA = 0;
+  a.B = c->d_Bov; a.ldb = c->Kp; a.sB = 0;
+  a.C = out; a.ldc = ldc; a.sC = 0;
+  a.M = kp; a.N = c->Kp; a.K = c->Np;
+  a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Kp / 128;
+  a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
+  a.Dvec = c->d_D; a.wrow = c->mr.omega;
+  RCHK(run_gemm(c, a, 2, KC, KM, epi));
+  return 0;
+}
+
+int backproject_pass(gw_ctx* c, int kp) {
+  // part[s][sys][P] = sum_{ia in split s} V[sys][ia] B_ov[P][ia]
+  GemmArgs a{};
+  a.A = c->mr.V; a.lda = c->Kp; a.sA = 0;
+  a.B = c->d_Bov; a.ldb = c->Kp; a.sB = 0;
+  a.C = c->mr.part; a.ldc = c->Np; a.sC = 0;
+  a.M = kp; a.N = c->Np; a.K = c->Kp;
+  a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Np / 128;
+  a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1;
+  a.splitk = c->mr_splitk; a.sSplit = (long)kp * c->Np;
+  RCHK(run_gemm(c, a, 2, KC, KC, EPI_STORE));
+  return 0;
+}
+
+// Solve all systems; fills wc, dwc (host) and iteration counts (negative if
+// not converged by MINRES; fallback marks them solved when enabled).
+int solve_residues(gw_ctx* c, const std::vector<System>& sys, bool use_fallback,
+                   std::vector<double>& wc, std::vector<double>& dwc, std::vector<int>& iters,
+                   std::vector<double>* x_out = nullptr) {
+  const int k = (int)sys.size();
+  wc.assign(k, 0.0);
+  dwc.assign(k, 0.0);
+  iters.assign(k, 0);
+  if (k == 0) return 0;
+  const int kp = round_up(k, 64);
+  RCHK(ensure_minres(c, kp));
+  MinresBufs& m = c->mr;
+  m.k = k; m.kp = kp; m.Np = c->Np; m.Kp = c->Kp;
+  m.n_vec = std::min({c->ext(m.x, 8), c->ext(m.w, 8), c->ext(m.w2, 8), c->ext(m.r1, 8),
+                      c->ext(m.r2, 8), c->ext(m.y, 8), c->ext(m.v, 8)});
+  m.n_scal = c->ext(m.scal, 8);
+  m.n_part = c->ext(m.part, 8);
+  m.n_V = c->ext(m.V, 8);
+  std::vector<int> idx(kp, 0);
+  std::vector<double> om(kp, 0.0);
+  for (int j = 0; j < k; ++j) {
+    idx[j] = sys[j].q;
+    om[j] = sys[j].w;
+  }
+  Timer tm;
+  tm.a = c->ev0; tm.b = c->ev1;
+  tm.start(c->st);
+  HIPCHK(rt_memcpy(c->d_rhs_idx, idx.data(), kp * sizeof(int), hipMemcpyHostToDevice, c->st));
+  HIPCHK(rt_memcpy(m.omega, om.data(), kp * sizeof(double), hipMemcpyHostToDevice, c->st));
+  trace("minres k=%d kp=%d splitk=%d", k, kp, c->mr_splitk);
+  HIPCHK(minres_init(m, c->d_R, c->d_rhs_idx, idx.data(), c->Rp, c->st));
+  int active = k;
+  int itn = 0;
+  for (itn = 1; itn <= c->minres_max_iter; ++itn) {
+    RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp));
+    RCHK(backproject_pass(c, kp));
+    HIPCHK(rt_memset(m.active, 0, sizeof(int), c->st));
+    HIPCHK(minres_finish_step(m, c->mr_splitk, itn, c->minres_rtol, c->st));
+    HIPCHK(rt_memcpy(&active, m.active, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(rt_sync(c->st));
+    if (active == 0) break;
+  }
+  c->timing.minres_iters += std::min(itn, c->minres_max_iter);
+  c->timing.minres_systems += k;
+  // derivative partials: sum over ia of (B^T x)^2 * 2 D w/(D^2 - w^2)^2
+  const int nparts = c->Kp / 128;
+  RCHK(matvec_pass(c, m.x, kp, EPI_RES_DERIV, m.part, kp));
+  HIPCHK(minres_results(m, c->d_R, c->d_rhs_idx, c->Rp, nparts, c->d_wc, c->d_dwc, c->d_conv,
+                        c->ext(c->d_wc, 8), c->st));
+  HIPCHK(rt_memcpy(wc.data(), c->d_wc, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(rt_memcpy(dwc.data(), c->d_dwc, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(rt_memcpy(iters.data(), c->d_conv, k * sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(rt_sync(c->st));
+  c->timing.minres_ms += tm.stop();
+
+  if (audit_mode())  // no results exist; walk the fallback launches for every system
+    for (int j = 0; j < k; ++j) iters[j] = -1;
+  std::vector<int> bad;
+  for (int j = 0; j < k; ++j)
+    if (iters[j] < 0) bad.push_back(j);
+  if (!bad.empty() && use_fallback) {
+    tm.start(c->st);
+    const long ld = c->Np;
+    if (!c->d_dense) {
+      RCHK(c->alloc((void**)&c->d_dense, (size_t)c->Np * c->Np * sizeof(double)));
+      RCHK(c->alloc((void**)&c->d_dscale, (size_t)c->Kp * sizeof(double)));
+      RCHK(c->alloc((void**)&c->d_db, (size_t)c->Np * sizeof(double)));
+      RCHK(c->alloc((void**)&c->d_dinfo, sizeof(int)));
+    }
+    for (int j : bad) {
+      HIPCHK(make_scale_real(c->d_D, c->Kov, c->Kp, sys[j].w, c->d_dscale, c->ext(c->d_D, 8),
+                             c->ext(c->d_dscale, 8), c->st));
+      GemmArgs a{};
+      a.A = c->d_Bov; a.lda = c->Kp;
+      a.B = c->d_Bov; a.ldb = c->Kp;
+      a.scale = c->d_dscale; a.sS = 0;
+      a.C = c->d_dense; a.ldc = ld;
+      a.M = c->Np; a.N = c->Np; a.K = c->Kp;
+      a.map = MAP_FULL; a.tiles_m = c->Np / 128; a.tiles_n = c->Np / 128;
+      a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
+      RCHK(run_gemm(c, a, 0, KC, KC, EPI_ONE_PLUS_4));
+      HIPCHK(copy_vec(c->d_R + (long)sys[j].q * c->Np, c->d_db, c->Np,
+                      c->ext(c->d_R + (long)sys[j].q * c->Np, 8), c->ext(c->d_db, 8), c->st));
+      HIPCHK(rt_memset(c->d_dinfo, 0, sizeof(int), c->st));
+      HIPCHK(dense_solve(c->d_dense, ld, c->Np, c->d_db, c->d_dinfo, c->ext(c->d_dense, 8),
+                         c->ext(c->d_db, 8), c->st));
+      HIPCHK(copy_vec(c->d_db, m.x + (long)j * c->Np, c->Np, c->ext(c->d_db, 8),
+                      c->ext(m.x + (long)j * c->Np, 8), c->st));
+      int dinfo = 0;
+      HIPCHK(rt_memcpy(&dinfo, c->d_dinfo, sizeof(int), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(rt_sync(c->st));
+      if (dinfo != 0)
+        return fail(GW_EDEVICE, "dense fallback: singular dielectric matrix at w = %.17g",
+                    sys[j].w);
+    }
+    RCHK(matvec_pass(c, m.x, kp, EPI_RES_DERIV, m.part, kp));
+    HIPCHK(minres_results(m, c->d_R, c->d_rhs_idx, c->Rp, nparts, c->d_wc, c->d_dwc, c->d_conv,
+                        c->ext(c->d_wc, 8), c->st));
+    HIPCHK(rt_memcpy(wc.data(), c->d_wc, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(rt_memcpy(dwc.data(), c->d_dwc, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(rt_sync(c->st));
+    c->timing.fallback_ms += tm.stop();
+    c->timing.fallback_systems += (int)bad.size();
+  }
+  if (x_out) {
+    x_out->assign((size_t)k * c->n_aux, 0.0);
+    for (int j = 0; j < k; ++j)
+      HIPCHK(rt_memcpy(x_out->data() + (size_t)j * c->n_aux, m.x + (long)j * c->Np,
+                            c->n_aux * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(rt_sync(c->st));
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Sigma^c at a batch of (state, omega)
+
+// Residue weight of the residue term R_nn: occupied m carry -theta(eps_m - w),
+// virtual m carry +theta(w - eps_m), with theta(0) = 1/2.
+double residue_weight(const gw_ctx* c, int m, double w) {
+  const double e = c->eps[m];
+  if (m < c->n_occ) {
+    double x = e - w;
+    return x > 0 ? -1.0 : (x == 0 ? -0.5 : 0.0);
+  }
+  double x = w - e;
+  return x > 0 ? 1.0 : (x == 0 ? 0.5 : 0.0);
+}
+
+int ensure_sig(gw_ctx* c, int n) {
+  if (n <= c->sig_cap) return 0;
+  c->release(c->d_rowsel);
+  c->release(c->d_omega);
+  c->release(c->d_sig);
+  c->release(c->d_dsig);
+  RCHK(c->alloc((void**)&c->d_rowsel, n * sizeof(int)));
+  RCHK(c->alloc((void**)&c->d_omega, n * sizeof(double)));
+  RCHK(c->alloc((void**)&c->d_sig, n * sizeof(double)));
+  RCHK(c->alloc((void**)&c->d_dsig, n * sizeof(double)));
+  c->sig_cap = n;
+  return 0;
+}
+
+// Requires a valid W^c table for the grid in the context.
+int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<double>& omega,
+               std::vector<double>& sig, std::vector<double>& dsig, std::vector<int>& nres,
+               std::vector<int>& flags) {
+  const int n = (int)states.size();
+  sig.assign(n, 0.0);
+  dsig.assign(n, 0.0);
+  nres.assign(n, 0);
+  flags.assign(n, 0);
+  if (n == 0) return 0;
+  RCHK(ensure_sig(c, n));
+  std::vector<int> rows(n);
+  for (int j = 0; j < n; ++j) rows[j] = c->row_of[states[j]];
+  Timer tm;
+  tm.a = c->ev0; tm.b = c->ev1;
+  tm.start(c->st);
+  HIPCHK(rt_memcpy(c->d_rowsel, rows.data(), n * sizeof(int), hipMemcpyHostToDevice, c->st));
+  HIPCHK(rt_memcpy(c->d_omega, omega.data(), n * sizeof(double), hipMemcpyHostToDevice, c->st));
+  HIPCHK(sigma_quad(c->d_wtab, c->n_mo, c->wtab_G, c->d_rowsel, c->d_omega, c->d_eps, c->d_grid,
+                    c->d_grid + c->grid_cap, n, c->d_sig, c->d_dsig, c->n_rows,
+                    c->ext(c->d_wtab, 8), c->st));
+  HIPCHK(rt_memcpy(sig.data(), c->d_sig, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(rt_memcpy(dsig.data(), c->d_dsig, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(rt_sync(c->st));
+  c->timing.quad_ms += tm.stop();
+  // residue systems of every entry
+  std::vector<System> sys;
+  std::vector<int> owner;
+  std::vector<double> weight;
+  for (int j = 0; j < n; ++j) {
+    for (int m = 0; m < c->n_mo; ++m) {
+      double f = residue_weight(c, m, omega[j]);
+      if (f == 0.0) continue;
+      sys.push_back(System{rows[j] * c->n_mo + m, c->eps[m] - omega[j]});
+      owner.push_back(j);
+      weight.push_back(f);
+      nres[j]++;
+    }
+  }
+  std::vector<double> wc, dwc;
+  std::vector<int> it;
+  RCHK(solve_residues(c, sys, true, wc, dwc, it));
+  for (size_t s = 0; s < sys.size(); ++s) {
+    const int j = owner[s];
+    sig[j] += weight[s] * wc[s];
+    // the residue frequency eps_m - omega moves opposite to omega
+    dsig[j] -= weight[s] * dwc[s];
+    if (it[s] < 0) flags[j] |= GW_ST_FALLBACK;
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Quasiparticle step tree (Implementation - Solution of the Quasiparticle
+// Equations, step-selection tree figure).  f(w) = eps_n + dsig_x_n +
+// Re Sigma^c(w) - w, Z = -1/f'(w).
+//   iteration 0: scaled residual, dw = a f with a = min(0.1, 0.1/|f|)
+//   Z >= 0.3: Newton, dw = Z f
+//   else bracketed: golden section, next = s + 0.381966 (e - s) with s the
+//       bracket end of smaller |f|
+//   else Z >= 0.1: scaled Newton, dw = 0.7 Z f
+//   else: scaled residual
+// Brackets come from consecutive points: a sign change with f > 0 on the
+// left end, or the same sign with growing |f| after a step taken along the
+// residual (a pole was crossed and a root skipped).  A point inside an
+// existing bracket replaces one of its ends.  Converged when |f| < qp_tol.
+
+struct QPState {
+  int n;
+  double w;
+  bool done = false;
+  int iter = 0;
+  bool has_prev = false;
+  double wp = 0, fp = 0;
+  bool has_br = false;
+  double s = 0, fs = 0, e = 0, fe = 0;
+  double E = 0, sig = 0, Z = 0;
+  int status = 0;
+};
+
+inline int sgn(double x) { return (x > 0) - (x < 0); }
+
+void order_bracket(QPState& q) {
+  if (std::fabs(q.fe) < std::fabs(q.fs)) {
+    std::swap(q.s, q.e);
+    std::swap(q.fs, q.fe);
+  }
+}
+
+void update_bracket(QPState& q, double w, double f) {
+  if (!q.has_prev) return;
+  if (q.has_br && std::min(q.s, q.e) < w && w < std::max(q.s, q.e)) {
+    if (sgn(q.fs) != sgn(q.fe)) {
+      if (sgn(f) == sgn(q.fs)) { q.s = w; q.fs = f; }
+      else { q.e = w; q.fe = f; }
+    } else {
+      if (sgn(f) == sgn(q.fs) && std::fabs(f) < std::fabs(q.fs)) { q.s = w; q.fs = f; }
+      else { q.e = w; q.fe = f; }
+    }
+    order_bracket(q);
+    return;
+  }
+  const double wp = q.wp, fp = q.fp;
+  if (fp * f < 0) {
+    double lo = wp, flo = fp, hi = w, fhi = f;
+    if (w < wp) { lo = w; flo = f; hi = wp; fhi = fp; }
+    if (flo > 0 && fhi < 0) {
+      q.has_br = true;
+      q.s = lo; q.fs = flo; q.e = hi; q.fe = fhi;
+      order_bracket(q);
+    }
+  } else if (fp * f > 0 && std::fabs(f) > std::fabs(fp) && sgn(w - wp) == sgn(fp)) {
+    q.has_br = true;
+    q.s = wp; q.fs = fp; q.e = w; q.fe = f;
+    order_bracket(q);
+  }
+}
+
+double alpha_of(double f) { return f != 0.0 ? std::min(0.1, 0.1 / std::fabs(f)) : 0.1; }
+
+// One step-tree decision for a state that has just been evaluated.
+void qp_step(gw_ctx* c, QPState& q, double sigma, double dsigma) {
+  const double f = c->eps[q.n] + c->dsig_x[q.n] + sigma - q.w;
+  const double fprime = dsigma - 1.0;
+  const double Z = (fprime != 0.0) ? -1.0 / fprime : INFINITY;
+  update_bracket(q, q.w, f);
+  if (std::fabs(f) < c->qp_tol) {
+    q.done = true;
+    q.E = q.w;
+    q.sig = sigma;
+    q.Z = Z;
+    if (Z < 0.1) q.status |= GW_ST_SMALL_Z;
+    return;
+  }
+  double wn;
+  if (q.iter == 0) wn = q.w + alpha_of(f) * f;
+  else if (Z >= 0.3) wn = q.w + Z * f;
+  else if (q.has_br) wn = q.s + 0.3819660112501051 * (q.e - q.s);
+  else if (Z >= 0.1) wn = q.w + 0.7 * Z * f;
+  else wn = q.w + alpha_of(f) * f;
+  q.has_prev = true;
+  q.wp = q.w;
+  q.fp = f;
+  q.w = wn;
+  q.iter++;
+  if (q.iter >= c->qp_max_iter) {
+    q.status |= GW_ST_MAXITER;
+  }
+}
+
+// Result-returning entry points end here: in launch-audit mode nothing was
+// computed, so they report GW_EAUDIT instead of success.
+int finish() {
+  if (audit_mode()) return fail(GW_EAUDIT, "launch audit: every launch was checked, none was run");
+  return 0;
+}
+
+int validate_states(gw_ctx* c, int n, const int* states) {
+  if (n < 0 || (n > 0 && !states)) return fail(GW_EINVAL, "bad state list");
+  for (int j = 0; j < n; ++j)
+    if (!c->row_of.count(states[j]))
+      return fail(GW_EINVAL, "state %d was not among the rows given to gw_setup", states[j]);
+  return 0;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+
+extern "C" {
+
+const char* gw_last_error(void) { return g_err.c_str(); }
+
+int gw_grid_gauss_legendre(int n, double x0, double* xi, double* w) {
+  if (n < 1 || !(x0 > 0.0) || !xi || !w) return fail(GW_EINVAL, "need n >= 1, x0 > 0");
+  // Gauss-Legendre nodes by Newton's method on P_n (three-term recurrence)
+  std::vector<double> t(n), u(n);
+  for (int i = 0; i < n; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int j = 2; j <= n; ++j) {
+        double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) { p1 = x; p0 = 1.0; }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      double dx = p1 / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    // final derivative at the converged node
+    double p0 = 1.0, p1 = x;
+    for (int j = 2; j <= n; ++j) {
+      double p2 = ((2.0 * j - 1.0) * x * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (n == 1) { p1 = x; p0 = 1.0; }
+    dp = n * (x * p1 - p0) / (x * x - 1.0);
+    t[i] = x;
+    u[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  // ascending t
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int a, int b) { return t[a] < t[b]; });
+  for (int i = 0; i < n; ++i) {
+    double tt = t[ord[i]], uu = u[ord[i]];
+    xi[i] = x0 * (1.0 + tt) / (1.0 - tt);
+    w[i] = uu * 2.0 * x0 / ((1.0 - tt) * (1.0 - tt));
+  }
+  return 0;
+}
+
+int gw_setup(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps, const double* B_ov,
+             int n_rows, const int* row_ids, const double* B_rows, const gw_opts* opts) {
+  if (!out) return fail(GW_EINVAL, "ctx pointer is NULL");
+  *out = nullptr;
+  if (n_mo < 2 || n_occ < 1 || n_occ >= n_mo || n_aux < 1 || n_rows < 0)
+    return fail(GW_EINVAL, "bad sizes: n_mo=%d n_occ=%d n_aux=%d n_rows=%d", n_mo, n_occ, n_aux,
+                n_rows);
+  if (!eps || !B_ov || (n_rows > 0 && (!row_ids || !B_rows)))
+    return fail(GW_EINVAL, "NULL input array");
+  for (int i = 0; i < n_mo; ++i) {
+    if (!std::isfinite(eps[i])) return fail(GW_EINVAL, "eps[%d] is not finite", i);
+    if (i > 0 && !(eps[i] > eps[i - 1])) return fail(GW_EINVAL, "eps is not strictly ascending at %d", i);
+  }
+  const long Kov = (long)n_occ * (n_mo - n_occ);
+  if (Kov > 0x3fffffffL || (long)n_aux * n_mo > 0x3fffffffL)
+    return fail(GW_EINVAL, "sizes too large");
+  for (long i = 0; i < (long)n_aux * Kov; ++i)
+    if (!std::isfinite(B_ov[i])) return fail(GW_EINVAL, "B_ov has a non-finite entry at %ld", i);
+  for (long i = 0; i < (long)n_rows * n_mo * n_aux; ++i)
+    if (!std::isfinite(B_rows[i])) return fail(GW_EINVAL, "B_rows has a non-finite entry at %ld", i);
+  gw_opts o{};
+  if (opts) o = *opts;
+  if (o.pi_prec < 0 || o.pi_prec > 2) return fail(GW_EINVAL, "unknown pi_prec %d", o.pi_prec);
+  if (o.minres_max_iter < 0 || o.qp_max_iter < 0 || o.minres_rtol < 0 || o.qp_tol < 0)
+    return fail(GW_EINVAL, "negative option");
+
+  gw_ctx* c = new gw_ctx();
+  g_contexts_created = true;
+  c->n_mo = n_mo; c->n_occ = n_occ; c->n_virt = n_mo - n_occ; c->n_aux = n_aux;
+  c->n_rows = n_rows;
+  c->Np = round_up(n_aux, 128);
+  c->Kov = (int)Kov;
+  c->Kp = round_up((int)Kov, 128);
+  c->nR = n_rows * n_mo;
+  c->Rp = round_up(std::max(c->nR, 1), 64);
+  c->pi_prec = o.pi_prec;
+  if (o.minres_max_iter > 0) c->minres_max_iter = o.minres_max_iter;
+  if (o.minres_rtol > 0) c->minres_rtol = o.minres_rtol;
+  if (o.qp_tol > 0) c->qp_tol = o.qp_tol;
+  if (o.qp_max_iter > 0) c->qp_max_iter = o.qp_max_iter;
+  c->mem_budget = o.mem_budget_bytes;
+  if (o.work_budget_bytes > 0) c->work_budget = o.work_budget_bytes;
+  c->eps.assign(eps, eps + n_mo);
+  c->dsig_x.assign(n_mo, 0.0);
+  if (o.dsig_x) {
+    for (int i = 0; i < n_mo; ++i) {
+      if (!std::isfinite(o.dsig_x[i])) {
+        delete c;
+        return fail(GW_EINVAL, "dsig_x[%d] is not finite", i);
+      }
+      c->dsig_x[i] = o.dsig_x[i];
+    }
+  }
+  for (int r = 0; r < n_rows; ++r) {
+    if (row_ids[r] < 0 || row_ids[r] >= n_mo || c->row_of.count(row_ids[r])) {
+      delete c;
+      return fail(GW_EINVAL, "row_ids[%d] = %d is out of range or repeated", r, row_ids[r]);
+    }
+    c->row_of[row_ids[r]] = r;
+    c->row_ids.push_back(row_ids[r]);
+  }
+  int rc = 0;
+  auto cleanup = [&](int code) {
+    std::string keep = g_err;
+    delete c;
+    g_err = keep;
+    return code;
+  };
+  if (audit_mode()) {
+    c->st = nullptr;
+  } else if (o.stream) {
+    c->st = (hipStream_t)o.stream;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->st, hipStreamNonBlocking);
+    if (e != hipSuccess) return cleanup(fail(GW_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)));
+    c->own_stream = true;
+  }
+  if (!audit_mode() &&
+      (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+       hipEventCreate(&c->ev0b) != hipSuccess || hipEventCreate(&c->ev1b) != hipSuccess))
+    return cleanup(fail(GW_EDEVICE, "hipEventCreate failed"));
+  if ((rc = c->alloc((void**)&c->d_eps, n_mo * sizeof(double)))) return cleanup(rc);
+  if ((rc = c->alloc((void**)&c->d_D, (size_t)c->Kp * sizeof(double)))) return cleanup(rc);
+  if ((rc = c->alloc((void**)&c->d_Bov, (size_t)c->Np * c->Kp * sizeof(double)))) return cleanup(rc);
+  if ((rc = c->alloc((void**)&c->d_R, (size_t)c->Rp * c->Np * sizeof(double)))) return cleanup(rc);
+  if ((rc = c->alloc((void**)&c->d_bn, (size_t)c->Rp * sizeof(double)))) return cleanup(rc);
+  hipStream_t st = c->st;
+#define SETUP_CHK(expr)                                                                     \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return cleanup(fail(GW_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)));      \
+  } while (0)
+  SETUP_CHK(rt_memcpy(c->d_eps, eps, n_mo * sizeof(double), hipMemcpyHostToDevice, st));
+  SETUP_CHK(transition_energies(c->d_eps, n_occ, c->n_virt, c->Kp, c->d_D, c->ext(c->d_eps, 8),
+                                c->ext(c->d_D, 8), st));
+  SETUP_CHK(rt_memset(c->d_Bov, 0, (size_t)c->Np * c->Kp * sizeof(double), st));
+  SETUP_CHK(rt_memcpy2d(c->d_Bov, (size_t)c->Kp * sizeof(double), B_ov, (size_t)Kov * sizeof(double),
+                             (size_t)Kov * sizeof(double), n_aux, hipMemcpyHostToDevice, st));
+  SETUP_CHK(rt_memset(c->d_R, 0, (size_t)c->Rp * c->Np * sizeof(double), st));
+  if (c->nR > 0) {
+    SETUP_CHK(rt_memcpy2d(c->d_R, (size_t)c->Np * sizeof(double), B_rows,
+                               (size_t)n_aux * sizeof(double), (size_t)n_aux * sizeof(double),
+                               c->nR, hipMemcpyHostToDevice, st));
+  }
+  SETUP_CHK(row_norm2(c->d_R, c->Rp, c->Np, c->d_bn, c->ext(c->d_R, 8), c->ext(c->d_bn, 8), st));
+  SETUP_CHK(rt_sync(st));
+#undef SETUP_CHK
+  *out = c;
+  return 0;
+}
+
+void gw_free(gw_ctx* ctx) { delete ctx; }
+
+int gw_set_pi_prec(gw_ctx* c, int prec) {
+  if (!c) return fail(GW_EINVAL, "NULL ctx");
+  if (prec < 0 || prec > 2) return fail(GW_EINVAL, "unknown pi_prec %d", prec);
+  if (prec != c->pi_prec) c->wtab_valid = false;
+  c->pi_prec = prec;
+  return 0;
+}
+
+int gw_get_timing(gw_ctx* c, gw_timing* out) {
+  if (!c || !out) return fail(GW_EINVAL, "NULL argument");
+  *out = c->timing;
+  return 0;
+}
+
+int gw_dielectric(gw_ctx* c, int n_xi, const double* xi, double* out) {
+  if (!c || n_xi < 1 || !xi || !out) return fail(GW_EINVAL, "bad arguments");
+  std::vector<double> w(n_xi, 1.0);
+  gw_grid g{n_xi, xi, w.data()};
+  RCHK(build_wtable(c, &g, 1, out));
+  return finish();
+}
+
+int gw_cholesky(gw_ctx* c, int n_xi, const double* xi, double* out) {
+  if (!c || n_xi < 1 || !xi || !out) return fail(GW_EINVAL, "bad arguments");
+  std::vector<double> w(n_xi, 1.0);
+  gw_grid g{n_xi, xi, w.data()};
+  RCHK(build_wtable(c, &g, 2, out));
+  return finish();
+}
+
+int gw_wtable(gw_ctx* c, const gw_grid* grid, double* out) {
+  if (!c) return fail(GW_EINVAL, "NULL ctx");
+  c->timing = gw_timing{};
+  RCHK(build_wtable(c, grid, 0));
+  if (out && c->nR > 0) {
+    HIPCHK(rt_memcpy(out, c->d_wtab, (size_t)c->nR * grid->n * sizeof(double),
+                          hipMemcpyDeviceToHost, c->st));
+    HIPCHK(rt_sync(c->st));
+  }
+  return finish();
+}
+
+int gw_sigma(gw_ctx* c, int n, const int* states, const double* omega, const gw_grid* grid,
+             double* sigma, double* dsigma, int* n_res) {
+  if (!c || n < 0 || (n > 0 && (!omega || !sigma || !dsigma)))
+    return fail(GW_EINVAL, "bad arguments");
+  RCHK(validate_states(c, n, states));
+  for (int j = 0; j < n; ++j)
+    if (!std::isfinite(omega[j])) return fail(GW_EINVAL, "omega[%d] is not finite", j);
+  c->timing = gw_timing{};
+  RCHK(build_wtable(c, grid, 0));
+  std::vector<int> st(states, states + n), nres, flags;
+  std::vector<double> om(omega, omega + n), sg, dsg;
+  RCHK(eval_sigma(c, st, om, sg, dsg, nres, flags));
+  for (int j = 0; j < n; ++j) {
+    sigma[j] = sg[j];
+    dsigma[j] = dsg[j];
+    if (n_res) n_res[j] = nres[j];
+  }
+  return finish();
+}
+
+int gw_residues(gw_ctx* c, int k, const int* states, const int* m, const double* w,
+                int use_fallback, double* x, double* wc, double* dwc, int* iters) {
+  if (!c || k < 0 || (k > 0 && (!states || !m || !w))) return fail(GW_EINVAL, "bad arguments");
+  RCHK(validate_states(c, k, states));
+  std::vector<System> sys(k);
+  for (int j = 0; j < k; ++j) {
+    if (m[j] < 0 || m[j] >= c->n_mo || !std::isfinite(w[j]))
+      return fail(GW_EINVAL, "bad system %d", j);
+    sys[j] = System{c->row_of[states[j]] * c->n_mo + m[j], w[j]};
+  }
+  c->timing = gw_timing{};
+  std::vector<double> a, b, xs;
+  std::vector<int> it;
+  RCHK(solve_residues(c, sys, use_fallback != 0, a, b, it, x ? &xs : nullptr));
+  for (int j = 0; j < k; ++j) {
+    if (wc) wc[j] = a[j];
+    if (dwc) dwc[j] = b[j];
+    if (iters) iters[j] = it[j];
+  }
+  if (x) std::copy(xs.begin(), xs.end(), x);
+  return finish();
+}
+
+int gw_qp(gw_ctx* c, int n_states, const int* states, const gw_grid* grid, double* E_qp,
+          double* sigma_c, double* Z, int* status) {
+  if (!c || n_states < 0 || (n_states > 0 && (!E_qp || !sigma_c || !Z)))
+    return fail(GW_EINVAL, "bad arguments");
+  RCHK(validate_states(c, n_states, states));
+  c->timing = gw_timing{};
+  Timer total;
+  total.a = c->ev0b;
+  total.b = c->ev1b;
+  total.start(c->st);
+  int rc = build_wtable(c, grid, 0);
+  if (rc) return rc;
+  std::vector<QPState> qs(n_states);
+  for (int j = 0; j < n_states; ++j) {
+    qs[j].n = states[j];
+    qs[j].w = c->eps[states[j]];
+  }
+  int rounds = 0;
+  while (true) {
+    std::vector<int> act, st;
+    std::vector<double> om;
+    for (int j = 0; j < n_states; ++j)
+      if (!qs[j].done) {
+        act.push_back(j);
+        st.push_back(qs[j].n);
+        om.push_back(qs[j].w);
+      }
+    if (act.empty()) break;
+    std::vector<double> sg, dsg;
+    std::vector<int> nres, flags;
+    rc = eval_sigma(c, st, om, sg, dsg, nres, flags);
+    if (rc) break;
+    rounds++;
+    for (size_t a = 0; a < act.size(); ++a) {
+      QPState& q = qs[act[a]];
+      q.status |= flags[a];
+      qp_step(c, q, sg[a], dsg[a]);
+      if (!q.done && q.iter >= c->qp_max_iter) {
+        // report the last evaluated point
+        q.done = true;
+        q.E = q.wp;
+        q.sig = sg[a];
+        const double fprime = dsg[a] - 1.0;
+        q.Z = fprime != 0.0 ? -1.0 / fprime : INFINITY;
+      }
+    }
+  }
+  const double ms = total.stop();
+  if (rc) return rc;
+  c->timing.total_ms = ms;
+  c->timing.qp_rounds = rounds;
+  for (int j = 0; j < n_states; ++j) {
+    E_qp[j] = qs[j].E;
+    sigma_c[j] = qs[j].sig;
+    Z[j] = qs[j].Z;
+    if (status) status[j] = qs[j].status;
+  }
+  return finish();
+}
+
+// ---- launch audit (include/gw_audit.h)
+
+int gw_audit_enable(void) {
+  if (g_contexts_created) return fail(GW_EINVAL, "launch audit must be enabled before any context exists");
+  set_audit_mode(true);
+  return 0;
+}
+
+long gw_audit_launch_count(void) { return audit_count(); }
+
+}  // extern "C"

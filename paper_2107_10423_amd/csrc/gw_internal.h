@@ -1,0 +1,137 @@
+// Internal declarations shared by the HIP translation units of libgw.
+// Not part of the public C-ABI (see include/gw.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace gw {
+
+// ---------------------------------------------------------------------------
+// Launch guards.  Every kernel wrapper computes, on the host, the largest
+// element index its launch can touch in each buffer and compares it with the
+// buffer's extent (elements available from the pointer handed in); a launch
+// that could leave a buffer is refused with hipErrorInvalidValue and the
+// reason is kept in launch_error().  In audit mode the wrappers stop after
+// the check and launch nothing (see include/gw_audit.h).
+bool audit_mode();
+void set_audit_mode(bool on);
+const char* launch_error();
+bool guard(const char* kernel, const char* buffer, long max_index, long extent);
+hipError_t refuse(const char* kernel, const char* why);  // records why, returns an error
+#define GW_GUARD(kernel, buffer, max_index, extent) \
+  do {                                              \
+    if (!::gw::guard(kernel, buffer, (long)(max_index), (long)(extent))) return hipErrorInvalidValue; \
+  } while (0)
+long audit_count();
+void audit_note();
+#define GW_AUDIT_RETURN()      \
+  do {                         \
+    if (::gw::audit_mode()) {  \
+      ::gw::audit_note();      \
+      return hipSuccess;       \
+    }                          \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// FP64 MFMA GEMM.  C_tile = epilogue( sum_k A(i,k) * s(k) * B(j,k) ).
+// Operand layouts: KC = row-major [row][k] (k contiguous), KM = [k][row].
+enum OpLayout { KC = 0, KM = 1 };
+
+enum Epilogue {
+  EPI_ONE_PLUS_4 = 0,   // C = delta_ij + 4 acc           (1 - Pi(i xi) from B d B^T)
+  EPI_AXPBY = 1,        // C = alpha acc + beta C
+  EPI_RES_SCALE = 2,    // C = acc * D/(D^2 - w_row^2)    (MINRES: scaled B^T v, rows = systems)
+  EPI_RES_DERIV = 3,    // part[colTile][row] = sum_col acc^2 * 2 D w/(D^2 - w^2)^2
+  EPI_STORE = 4,        // C = acc (split-K partials)
+};
+
+enum TileMap {
+  MAP_FULL = 0,   // every (I, J) tile
+  MAP_LOWER = 1,  // tiles holding some element with row >= col (both offset by `diag_off`)
+};
+
+struct GemmArgs {
+  const double* A; long lda; long sA;   // sA: batch stride (elements)
+  const double* B; long ldb; long sB;
+  const double* scale; long sS;         // per-k scale of B, or nullptr
+  double* C; long ldc; long sC;
+  int M, N, K;                          // M, N multiples of the tile; K multiple of 16
+  int row0, col0;                       // offsets of the first A row / B row
+  int k0, kb0;                          // k offsets of A and of B (and of the scale)
+  int map;                              // TileMap
+  int tiles_m, tiles_n;
+  int n_tiles;                          // tiles per batch item
+  int batch;
+  int splitk;                           // >= 1; split s covers k in [s*K/splitk, (s+1)*K/splitk)
+  long sSplit;                          // C offset between split-K slabs
+  double alpha, beta;
+  const double* Dvec;                   // transition energies (EPI_RES_*)
+  const double* wrow;                   // per-row real frequency (EPI_RES_*)
+  // extents (elements reachable from each pointer), checked before launch
+  long nA, nB, nS, nC, nD, nW;
+};
+
+hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, hipStream_t st);
+// tile_kind 0: 128x128, 1: 128x64, 2: 64x128
+
+// Mixed-precision Pi builds (write 1 - Pi lower tiles in FP64)
+// nB: elements of each B copy, nS: of scale, nA: of the output
+hipError_t pi_build_f32(const float* B32, long ld, const double* scale, long sS, double* A,
+                        long ldA, long sA, int Np, int Kp, int G, long nB, long nS, long nA,
+                        hipStream_t st);
+hipError_t pi_build_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, long ld, const float* B32,
+                           const double* scale, long sS, double* A, long ldA, long sA, int Np,
+                           int Kp, int G, long nB, long nS, long nA, hipStream_t st);
+hipError_t split_bf16(const double* B, uint16_t* hi, uint16_t* lo, float* b32, long n, hipStream_t st);
+
+// Cholesky pieces
+hipError_t chol_diag(double* A, long ldA, long sA, double* Linv, int k, int G, int* info,
+                     long nA, long nLinv, long nInfo, hipStream_t st);
+hipError_t copy_rows_into(double* A, long ldA, long sA, int row0, const double* R, int nR,
+                          int Np, int G, long nA, long nR_ext, hipStream_t st);
+hipError_t wc_reduce_chunk(const double* A, long ldA, long sA, int row0, const double* bnorm2,
+                           int nR, int Np, int G, int Gtot, int g0, double* wtab, long nA,
+                           long nBn, long nW, hipStream_t st);
+
+// prep
+hipError_t transition_energies(const double* eps, int n_occ, int n_virt, int Kp, double* D,
+                               long nEps, long nD, hipStream_t st);
+hipError_t row_norm2(const double* R, int nR, int Np, double* bn, long nRext, long nBn,
+                     hipStream_t st);
+hipError_t make_scale_real(const double* D, int Kov, int Kp, double w, double* s, long nD,
+                           long nS, hipStream_t st);
+hipError_t copy_vec(const double* src, double* dst, int n, long nSrc, long nDst, hipStream_t st);
+hipError_t make_scale_imag(const double* D, int Kov, int Kp, const double* xi, int G, double* s,
+                           long nD, long nXi, long nS, hipStream_t st);
+
+// Sigma quadrature: per state j: sum_m sum_g W[row_j][m][g] z_g a/(a^2+xi^2) and derivative
+hipError_t sigma_quad(const double* wtab, int n_mo, int G, const int* rowsel, const double* omega,
+                      const double* eps, const double* xi, const double* z, int n,
+                      double* sig, double* dsig, int n_rows, long nW, hipStream_t st);
+
+// MINRES
+struct MinresBufs {
+  int k, kp, Np, Kp;       // systems, padded systems, padded aux, padded ov
+  double *x, *w, *w2, *r1, *r2, *y, *v;     // [kp][Np] each
+  double *scal;            // [kp][16] per-system scalars
+  double *V;               // [kp][Kp] scaled B^T v
+  double *part;            // split-K partials [splitk][kp][Np] (reused for deriv partials)
+  double *omega;           // [kp] real frequencies
+  int *active;             // [1] count of unconverged systems
+  long n_vec, n_scal, n_part, n_V;   // extents in elements (per array)
+};
+// rhs_idx values must be < n_rhs_rows (rows of rhs_base, each Np long); the host
+// passes the index array it uploaded so the guard can check it
+hipError_t minres_init(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
+                       const int* host_idx, int n_rhs_rows, hipStream_t st);
+hipError_t minres_finish_step(MinresBufs& m, int splitk, int itn, double rtol, hipStream_t st);
+hipError_t minres_results(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
+                          int n_rhs_rows, int n_deriv_parts, double* wc, double* dwc, int* conv,
+                          long n_out, hipStream_t st);
+
+// dense fallback: solve A x = b for one system with partial pivoting (A overwritten)
+hipError_t dense_solve(double* A, long ldA, int n, double* b, int* info, long nA, long nb,
+                       hipStream_t st);
+
+}  // namespace gw

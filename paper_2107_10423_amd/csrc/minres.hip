@@ -1,0 +1,198 @@
+// Batched MINRES (Paige and Saunders) for the residue systems
+// (1 - Pi(w_j)) x_j = b_j, one system per real frequency w_j.  The matrix is
+// never formed: A v = v + 4 B_ov diag(D/(D^2 - w^2)) B_ov^T v is applied as
+// two MFMA GEMM passes over B_ov (see gemm_f64.hip) for all systems at once.
+// This file holds the per-system Lanczos / Givens recurrences, one
+// workgroup per system.
+#include "gw_internal.h"
+
+namespace gw {
+
+enum { S_BETA1 = 0, S_BETA, S_OLDB, S_DBAR, S_EPS, S_PHIBAR, S_CS, S_SN, S_DONE, S_ITERS, S_RATIO };
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  const int t = threadIdx.x;
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __syncthreads();
+  if ((t & 63) == 0) red[t >> 6] = v;
+  __syncthreads();
+  double s = red[0] + red[1] + red[2] + red[3];
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_minres_init(MinresBufs m, const double* rhs_base,
+                                                     const int* rhs_idx) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const long o = (long)j * m.Np;
+  const double* b = (j < m.k) ? rhs_base + (long)rhs_idx[j] * m.Np : nullptr;
+  double s = 0.0;
+  for (int p = t; p < m.Np; p += 256) {
+    double bv = b ? b[p] : 0.0;
+    m.r1[o + p] = bv;
+    m.r2[o + p] = bv;
+    m.y[o + p] = bv;
+    m.x[o + p] = 0.0;
+    m.w[o + p] = 0.0;
+    m.w2[o + p] = 0.0;
+    s += bv * bv;
+  }
+  const double beta1 = sqrt(block_sum(s, red));
+  const double inv = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
+  for (int p = t; p < m.Np; p += 256) m.v[o + p] = m.y[o + p] * inv;
+  if (t == 0) {
+    double* sc = m.scal + j * 16;
+    sc[S_BETA1] = beta1;
+    sc[S_BETA] = beta1;
+    sc[S_OLDB] = 0.0;
+    sc[S_DBAR] = 0.0;
+    sc[S_EPS] = 0.0;
+    sc[S_PHIBAR] = beta1;
+    sc[S_CS] = -1.0;
+    sc[S_SN] = 0.0;
+    sc[S_DONE] = (j < m.k && beta1 > 0.0) ? 0.0 : 1.0;
+    sc[S_ITERS] = 0.0;
+    sc[S_RATIO] = 0.0;
+  }
+}
+
+static hipError_t check_bufs(const MinresBufs& m, const char* kn) {
+  if (m.k < 0 || m.k > m.kp || m.kp % 64 != 0) return refuse(kn, "system count");
+  GW_GUARD(kn, "vectors", (long)m.kp * m.Np - 1, m.n_vec);
+  GW_GUARD(kn, "scalars", (long)m.kp * 16 - 1, m.n_scal);
+  return hipSuccess;
+}
+
+hipError_t minres_init(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
+                       const int* host_idx, int n_rhs_rows, hipStream_t st) {
+  if (hipError_t e = check_bufs(m, "minres_init")) return e;
+  for (int j = 0; j < m.k; ++j)
+    if (host_idx[j] < 0 || host_idx[j] >= n_rhs_rows) return refuse("minres_init", "rhs index");
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_minres_init, dim3(m.kp), dim3(256), 0, st, m, rhs_base, rhs_idx);
+  return hipGetLastError();
+}
+
+// One MINRES iteration for every unconverged system, given the split-K
+// partials part[s][j][:] of B_ov V^T (V = scaled B_ov^T v).
+__global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int splitk, int itn,
+                                                     double rtol) {
+  __shared__ double red[4];
+  __shared__ double bc[5];
+  const int j = blockIdx.x, t = threadIdx.x;
+  double* sc = m.scal + j * 16;
+  if (sc[S_DONE] != 0.0) return;
+  const long o = (long)j * m.Np;
+  const long slab = (long)m.kp * m.Np;
+  const double beta = sc[S_BETA], oldb = sc[S_OLDB];
+  // y = A v (- (beta/oldb) r1 from the second iteration on)
+  const double c1 = (itn >= 2) ? beta / oldb : 0.0;
+  double sa = 0.0;
+  for (int p = t; p < m.Np; p += 256) {
+    double av = 0.0;
+    for (int s = 0; s < splitk; ++s) av += m.part[s * slab + o + p];
+    double yv = m.v[o + p] + 4.0 * av - c1 * m.r1[o + p];
+    m.y[o + p] = yv;
+    sa += m.v[o + p] * yv;
+  }
+  const double alpha = block_sum(sa, red);
+  double sb = 0.0;
+  for (int p = t; p < m.Np; p += 256) {
+    double yv = m.y[o + p] - (alpha / beta) * m.r2[o + p];
+    m.r1[o + p] = m.r2[o + p];
+    m.r2[o + p] = yv;
+    m.y[o + p] = yv;
+    sb += yv * yv;
+  }
+  const double beta_new = sqrt(block_sum(sb, red));
+  if (t == 0) {
+    const double oldeps = sc[S_EPS];
+    const double cs = sc[S_CS], sn = sc[S_SN], dbar = sc[S_DBAR];
+    const double delta = cs * dbar + sn * alpha;
+    const double gbar = sn * dbar - cs * alpha;
+    const double epsln = sn * beta_new;
+    const double dbar_n = -cs * beta_new;
+    double gamma = sqrt(gbar * gbar + beta_new * beta_new);
+    if (gamma < 1e-300) gamma = 1e-300;
+    const double cs_n = gbar / gamma, sn_n = beta_new / gamma;
+    const double phi = cs_n * sc[S_PHIBAR];
+    const double phibar = sn_n * sc[S_PHIBAR];
+    sc[S_OLDB] = beta;
+    sc[S_BETA] = beta_new;
+    sc[S_EPS] = epsln;
+    sc[S_DBAR] = dbar_n;
+    sc[S_CS] = cs_n;
+    sc[S_SN] = sn_n;
+    sc[S_PHIBAR] = phibar;
+    sc[S_ITERS] = (double)itn;
+    const double ratio = phibar / sc[S_BETA1];
+    sc[S_RATIO] = ratio;
+    const bool done = (ratio <= rtol) || (beta_new <= 1e-300);
+    if (done) sc[S_DONE] = 1.0;
+    bc[0] = oldeps;
+    bc[1] = delta;
+    bc[2] = 1.0 / gamma;
+    bc[3] = phi;
+    bc[4] = done ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const double oldeps = bc[0], delta = bc[1], ginv = bc[2], phi = bc[3];
+  const bool done = bc[4] != 0.0;
+  const double inv_b = (beta_new > 1e-300) ? 1.0 / beta_new : 0.0;
+  for (int p = t; p < m.Np; p += 256) {
+    double w1 = m.w2[o + p];
+    double w2 = m.w[o + p];
+    double wn = (m.v[o + p] - oldeps * w1 - delta * w2) * ginv;
+    m.w2[o + p] = w2;
+    m.w[o + p] = wn;
+    m.x[o + p] += phi * wn;
+    m.v[o + p] = done ? 0.0 : m.y[o + p] * inv_b;
+  }
+  if (t == 0 && !done) atomicAdd(m.active, 1);
+}
+
+hipError_t minres_finish_step(MinresBufs& m, int splitk, int itn, double rtol, hipStream_t st) {
+  if (hipError_t e = check_bufs(m, "minres_step")) return e;
+  GW_GUARD("minres_step", "part", (long)splitk * m.kp * m.Np - 1, m.n_part);
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_minres_step, dim3(m.kp), dim3(256), 0, st, m, splitk, itn, rtol);
+  return hipGetLastError();
+}
+
+// W^c = b.x - b.b and dW^c/dw = -4 sum of the derivative partials
+__global__ __launch_bounds__(256) void k_minres_results(MinresBufs m, const double* rhs_base,
+                                                        const int* rhs_idx, int nparts,
+                                                        double* wc, double* dwc, int* conv) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const double* b = rhs_base + (long)rhs_idx[j] * m.Np;
+  const long o = (long)j * m.Np;
+  double s = 0.0;
+  for (int p = t; p < m.Np; p += 256) s += b[p] * (m.x[o + p] - b[p]);
+  const double bx = block_sum(s, red);
+  double d = 0.0;
+  for (int q = t; q < nparts; q += 256) d += m.part[(long)q * m.kp + j];
+  const double dd = block_sum(d, red);
+  if (t == 0) {
+    wc[j] = bx;
+    dwc[j] = -4.0 * dd;
+    const double* sc = m.scal + j * 16;
+    conv[j] = (sc[S_DONE] != 0.0) ? (int)sc[S_ITERS] : -(int)sc[S_ITERS] - 1;
+  }
+}
+
+hipError_t minres_results(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
+                          int n_rhs_rows, int n_deriv_parts, double* wc, double* dwc, int* conv,
+                          long n_out, hipStream_t st) {
+  if (m.k <= 0) return hipSuccess;
+  (void)n_rhs_rows;  // indices were checked by minres_init for this batch
+  if (hipError_t e = check_bufs(m, "minres_results")) return e;
+  GW_GUARD("minres_results", "part", (long)n_deriv_parts * m.kp - 1, m.n_part);
+  GW_GUARD("minres_results", "outputs", m.k - 1, n_out);
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_minres_results, dim3(m.k), dim3(256), 0, st, m, rhs_base, rhs_idx,
+                     n_deriv_parts, wc, dwc, conv);
+  return hipGetLastError();
+}
+
+}  // namespace gw

@@ -1,0 +1,68 @@
+"""Walk every launch of the HIP path in launch-audit mode (no GPU needed).
+
+Run as a separate process (audit mode is irreversible):
+    python tests/audit_walk.py
+Prints one line per case and exits non-zero if any launch guard refused a
+launch or any entry point failed for another reason.
+"""
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import gwgen  # noqa: E402
+import paper_2107_10423_amd as gwl  # noqa: E402
+
+CASES = [
+    # n_occ, n_virt, n_aux, rows, G, work_budget, minres cap
+    (7, 45, 200, (4, 5, 6, 7, 8), 8, 0, 0),
+    (5, 38, 112, (4, 5), 64, 0, 0),            # monomer shape
+    (3, 20, 64, (1, 2), 5, 0, 0),              # n_aux = 64 < one Pi tile
+    (1, 1, 1, (0, 1), 3, 0, 0),                # smallest possible
+    (2, 3, 130, (1,), 4, 0, 1),                # N_aux just past a tile, fallback forced
+    (11, 60, 300, tuple(range(0, 71)), 6, 0, 0),  # many rows (nR > 4000)
+    (12, 70, 220, (0, 11), 32, 2 << 20, 0),    # chunked stage A
+    (50, 380, 1120, tuple(range(45, 55)), 64, 0, 0),  # (H2O)10 shape
+    (17, 63, 129, (16, 17, 40), 7, 0, 2),
+]
+
+
+def run_case(n_occ, n_virt, n_aux, rows, G, wb, cap):
+    shape = gwgen.custom_shape(n_occ, n_virt, n_aux, n_core=1 if n_occ > 1 else 0)
+    inp = gwgen.make_inputs(shape, 1, rows)
+    g = gwl.Grid.gauss_legendre(G)
+    for prec in ("fp64", "fp32", "bf16x3"):
+        kw = dict(pi_prec=prec, work_budget_bytes=wb, minres_max_iter=cap)
+        with gwl.Context.from_inputs(inp, **kw) as c:
+            before = gwl.audit_launch_count()
+            for call in (lambda: c.dielectric([0.1, 2.0]), lambda: c.cholesky([0.3]),
+                         lambda: c.wtable(g),
+                         lambda: c.sigma([rows[0]] * 3, [inp.eps[rows[0]], -21.0, 0.7], g),
+                         lambda: c.residues([rows[0]] * 70, list(range(70 % (n_occ + n_virt))) *
+                                            0 + [m % (n_occ + n_virt) for m in range(70)],
+                                            np.linspace(-1, 22, 70)),
+                         lambda: c.qp(list(rows), g)):
+                try:
+                    call()
+                except gwl.GWError as e:
+                    if e.code != gwl.GW_EAUDIT:
+                        raise
+                else:
+                    raise AssertionError("audit mode returned results")
+            n = gwl.audit_launch_count() - before
+        print(f"case {n_occ}/{n_virt}/{n_aux} rows={len(rows)} G={G} {prec}: {n} launches checked",
+              flush=True)
+
+
+def main():
+    gwl.audit_enable()
+    for case in CASES:
+        run_case(*case)
+    print("audit ok")
+
+
+if __name__ == "__main__":
+    main()
