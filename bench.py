@@ -1,0 +1,179 @@
+"""Benchmark of the contour-deformation G0W0 hot path on one MI355X.
+
+Workload: the (H2O)10-shaped G0W0 problem (n_occ=50, n_virt=380, N_aux=1120,
+64-point modified Gauss-Legendre grid, QP energies of HOMO-4..LUMO+4),
+synthetic seeded inputs resident in HBM before timing starts.
+
+One step = one gw_qp call with the W^c table cache dropped first, i.e. the
+whole hot path: Pi(i xi) build on every grid point, Cholesky of 1 - Pi,
+W^c table, imaginary-axis Sigma quadrature, batched MINRES residues and the
+QP step tree, for all 10 states.  The headline value is the mixed-precision
+(BF16x3 Pi build) path; the plain FP64 path and the FP32 Pi path are timed
+the same way and reported beside it, each with its error against the FP64
+oracle's stored QP energies.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+MEV = 1e-3 / 27.211386245988
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def pi_flops(n_aux, n_ov, G):
+    """Algorithmic flops of the Pi build: N_aux (N_aux + 1) N_ov per grid point
+    (the symmetric product counted once, multiply and add each one flop)."""
+    return n_aux * (n_aux + 1) * n_ov * G
+
+
+def time_path(gwl, inp, states, grid, prec, steps, warmup):
+    import numpy as np
+    import torch
+    with gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=1e-10) as c:
+        for _ in range(warmup):
+            c.reset_cache()
+            out = c.qp(states, grid)
+        torch.cuda.synchronize()
+        pi_ms, tot_ms, stages = [], [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            c.reset_cache()
+            out = c.qp(states, grid)
+            t = c.timing()
+            pi_ms.append(t["pi_ms"])
+            tot_ms.append(t["total_ms"])
+            stages.append(t)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    E = out[0]
+    return dict(E=E, Z=out[2], status=out[3], wall_s=wall, ms_per_step=1e3 * wall / steps,
+                pi_ms=float(np.mean(pi_ms)), total_ms=float(np.mean(tot_ms)),
+                stages={k: float(np.mean([s[k] for s in stages])) for k in stages[0]})
+
+
+def cpu_baseline(inp, states, G, gold):
+    """Oracle timed on a bounded sample of the same workload: the W^c table on
+    one grid point and one Sigma^c evaluation (with its residues) of the HOMO,
+    scaled to the whole workload with the oracle's own iteration counts."""
+    import numpy as np
+    from oracle import cd, grid as ogrid
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max((i.get("num_threads", 1) for i in threadpool_info()), default=os.cpu_count())
+    except Exception:
+        cores = os.cpu_count()
+    xi, z = ogrid.gauss_legendre(G)
+    t0 = time.perf_counter()
+    cd.w_table(inp.eps, inp.n_occ, inp.B_ov, inp.B_rows, xi[:1])
+    t_g = time.perf_counter() - t0
+    homo = inp.n_occ - 1
+    r = list(inp.row_ids).index(homo)
+    wt = np.zeros((inp.shape.n_mo, G))
+    w = gold["results"][states.index(homo)]["E"]
+    t0 = time.perf_counter()
+    _, _, nres = cd.sigma_c(inp.eps, inp.n_occ, inp.B_ov, inp.B_rows[r], wt, xi, z, w)
+    t_eval = time.perf_counter() - t0
+    n_evals = sum(x["iters"] for x in gold["results"])
+    total = G * t_g + n_evals * t_eval
+    return {"value": len(states) / total, "unit": "QP energies/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": (f"W^c table on 1 of {G} grid points ({t_g:.1f} s) + one Sigma^c evaluation "
+                       f"of the HOMO at its QP energy with {nres} residues ({t_eval:.1f} s); "
+                       f"scaled to {G} grid points and {n_evals} evaluations"),
+            "est_total_s": total}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default=None, help="time only this Pi precision (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the work would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    import gwgen
+    import paper_2107_10423_amd as gwl
+
+    name = "h2o10"
+    cfg = gwgen.CONFIGS[name]
+    states = list(cfg.states)
+    log(f"bench: generating {name} inputs")
+    inp = gwgen.make_config(name)
+    grid = gwl.Grid.gauss_legendre(cfg.grid_points)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", f"{name}.json")))
+    E_ref = np.array([r["E"] for r in gold["results"]])
+    n_aux, n_ov = cfg.shape.n_aux, cfg.shape.n_ov
+    flops = pi_flops(n_aux, n_ov, cfg.grid_points)
+
+    precs = [args.only] if args.only else ["bf16x3", "fp64", "fp32"]
+    res = {}
+    for prec in precs:
+        log(f"bench: timing {prec} path, {args.warmup} warmup + {args.steps} steps")
+        r = time_path(gwl, inp, states, grid, prec, args.steps, args.warmup)
+        r["err_mev"] = float(np.max(np.abs(r["E"] - E_ref)) / MEV)
+        r["qp_per_s"] = len(states) / (r["ms_per_step"] / 1e3)
+        r["pi_tflops"] = flops / (r["pi_ms"] / 1e3) / 1e12
+        res[prec] = r
+        log(f"bench: {prec}: {r['ms_per_step']:.2f} ms/step, Pi {r['pi_ms']:.2f} ms "
+            f"({r['pi_tflops']:.1f} TFLOP/s), max |E - oracle| = {r['err_mev']:.2e} meV, "
+            f"stages {json.dumps({k: round(v, 3) for k, v in r['stages'].items()})}")
+
+    head = precs[0]
+    h = res[head]
+    # dominant kernel: the Pi build (one launch per step at this size)
+    roof = {"kernel": f"pi_build_{head}", "bound": "mfma", "achieved": round(h["pi_tflops"], 2),
+            "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
+            "frac": round(h["pi_tflops"] / PEAK_TFLOPS[head], 4), "traffic": None,
+            "flops_per_launch": flops, "launch_ms": round(h["pi_ms"], 4)}
+    out = {
+        "metric": "QP energies/sec (mixed-precision Pi vs FP64, <= 1 meV vs FP64 oracle)",
+        "value": round(h["qp_per_s"], 3), "unit": "QP energies/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(h["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"bf16x3": "bf16x3 Pi (fp32 acc) + f64", "fp64": "f64",
+                  "fp32": "f32 Pi + f64"}[head],
+        "data": "synthetic",
+        "config": {"workload": "(H2O)10-shaped G0W0: n_occ=50, n_virt=380, N_aux=1120, "
+                               "64-point grid, HOMO-4..LUMO+4 (10 states), seed 2",
+                   "n_occ": 50, "n_virt": 380, "n_aux": 1120, "grid_points": 64, "states": 10},
+        "roofline": roof,
+        "paths": {p: {"qp_per_s": round(r["qp_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
+                      "pi_ms": round(r["pi_ms"], 3), "pi_tflops": round(r["pi_tflops"], 2),
+                      "pi_frac_of_peak": round(r["pi_tflops"] / PEAK_TFLOPS[p], 4),
+                      "max_err_mev_vs_oracle": r["err_mev"],
+                      "stages_ms": {k: round(v, 3) for k, v in r["stages"].items()}}
+                  for p, r in res.items()},
+    }
+    if "fp64" in res and head != "fp64":
+        out["mixed_over_fp64"] = {"qp_per_s": round(h["qp_per_s"] / res["fp64"]["qp_per_s"], 3),
+                                  "pi_tflops": round(h["pi_tflops"] / res["fp64"]["pi_tflops"], 3)}
+    if not args.no_cpu_baseline:
+        log("bench: timing the oracle on a bounded sample")
+        out["cpu_baseline"] = cpu_baseline(inp, states, cfg.grid_points, gold)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -124,6 +124,10 @@ const char* gw_last_error(void);
  * cached W^c table.  GW_EINVAL for an unknown value. */
 int gw_set_pi_prec(gw_ctx* ctx, int pi_prec);
 
+/* Drop the cached W^c table: the next gw_qp / gw_sigma / gw_wtable call
+ * rebuilds it (Pi build, Cholesky, reduction) from the resident inputs. */
+int gw_reset_cache(gw_ctx* ctx);
+
 /* ---- stage entry points (the same kernels gw_qp runs; for parity checks
  *      and tooling) ------------------------------------------------------- */
 

@@ -67,6 +67,7 @@ _sig = {
     "gw_residues": (ctypes.c_int, [_ctxp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_int, _dp, _dp,
                                    _dp, _ip]),
     "gw_get_timing": (ctypes.c_int, [_ctxp, ctypes.POINTER(Timing)]),
+    "gw_reset_cache": (ctypes.c_int, [_ctxp]),
     "gw_audit_enable": (ctypes.c_int, []),
     "gw_audit_launch_count": (ctypes.c_long, []),
 }
@@ -220,6 +221,9 @@ class Context:
         _check(_lib.gw_residues(self._h, k, _pi(st), _pi(mm), _pd(ww), int(bool(use_fallback)),
                                 _pd(x), _pd(wc), _pd(dwc), _pi(it)))
         return x, wc, dwc, it
+
+    def reset_cache(self):
+        _check(_lib.gw_reset_cache(self._h))
 
     def timing(self):
         t = Timing()

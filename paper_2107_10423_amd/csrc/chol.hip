@@ -2,11 +2,17 @@
 // screened-interaction reduction.
 //
 // The matrix of grid point g is stored augmented: rows [0, Np) hold 1 - Pi
-// (lower triangle), rows [Np, Np + nR) hold the vectors b = (P|nm) of every
-// requested state n and every m.  A right-looking blocked Cholesky (panel
-// width 64) run over all rows factors 1 - Pi = L L^T and, because the
-// appended rows are treated like the rows below the diagonal, leaves
-// y^T = (L^-1 b)^T in them.  Then b^T (1 - Pi)^-1 b = |y|^2.
+// (lower triangle), rows [Np, 2 Np) start as the identity.  A right-looking
+// blocked Cholesky (panel width 64) run over the rows factors 1 - Pi = L L^T
+// and, because the appended rows are treated like rows below the diagonal,
+// leaves (L^-1 I)^T = L^-T in them (row Np + s holds column s of L^-1).
+// Identity row s is untouched until the panel that contains column s, so each
+// panel only carries the appended rows up to its own end, which makes the
+// inverse cost N^3/3.  The screened interaction then needs
+// b^T (1 - Pi)^-1 b = |L^-1 b|^2 for every b = (P|nm), one triangular GEMM
+// with the squared-norm reduction in its epilogue.
+#include <algorithm>
+
 #include "gw_internal.h"
 
 namespace gw {
@@ -80,60 +86,51 @@ hipError_t chol_diag(double* A, long ldA, long sA, double* Linv, int k, int G, i
   return hipGetLastError();
 }
 
-// rows [row0, row0 + nR) of every batch item <- R[nR][Np] (already padded)
-__global__ void k_copy_rows(double* A, long ldA, long sA, int row0, const double* R, int nR,
-                            int Np) {
+// rows [row0, row0 + n) of every batch item <- e_0 .. e_{n-1} over columns [0, ncol)
+__global__ void k_set_identity(double* A, long ldA, long sA, int row0, int n, int ncol) {
   const int g = blockIdx.y;
-  const long n = (long)nR * Np;
-  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < n;
+  const long cnt = (long)n * ncol;
+  for (long idx = (long)blockIdx.x * blockDim.x + threadIdx.x; idx < cnt;
        idx += (long)gridDim.x * blockDim.x) {
-    long r = idx / Np, c = idx % Np;
-    A[(long)g * sA + (row0 + r) * ldA + c] = R[idx];
+    int r = (int)(idx / ncol), c = (int)(idx % ncol);
+    A[(long)g * sA + (long)(row0 + r) * ldA + c] = (r == c) ? 1.0 : 0.0;
   }
 }
 
-hipError_t copy_rows_into(double* A, long ldA, long sA, int row0, const double* R, int nR,
-                          int Np, int G, long nA, long nR_ext, hipStream_t st) {
-  long n = (long)nR * Np;
-  if (n <= 0 || G <= 0) return hipSuccess;
-  GW_GUARD("copy_rows", "A", (long)(G - 1) * sA + (long)(row0 + nR - 1) * ldA + Np - 1, nA);
-  GW_GUARD("copy_rows", "R", n - 1, nR_ext);
+hipError_t set_identity_rows(double* A, long ldA, long sA, int row0, int n, int ncol, int G,
+                             long nA, hipStream_t st) {
+  const long cnt = (long)n * ncol;
+  if (cnt <= 0 || G <= 0) return hipSuccess;
+  GW_GUARD("set_identity", "A", (long)(G - 1) * sA + (long)(row0 + n - 1) * ldA + ncol - 1, nA);
   GW_AUDIT_RETURN();
-  int blocks = (int)((n + 255) / 256);
-  if (blocks > 1024) blocks = 1024;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(k_copy_rows, dim3(blocks, G), dim3(256), 0, st, A, ldA, sA, row0, R, nR, Np);
+  int blocks = (int)std::min<long>((cnt + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_set_identity, dim3(blocks, G), dim3(256), 0, st, A, ldA, sA, row0, n, ncol);
   return hipGetLastError();
 }
 
-// wtab[q][g0 + g] = |row (row0 + q) of item g|^2 - bnorm2[q]; one wavefront per (q, g)
-__global__ __launch_bounds__(256) void k_wc_reduce(const double* A, long ldA, long sA, int row0,
-                                                   const double* bnorm2, int nR, int Np, int G,
-                                                   int Gtot, int g0, double* wtab) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const long item = (long)blockIdx.x * 4 + wave;
-  if (item >= (long)nR * G) return;
-  const int q = (int)(item / G), g = (int)(item % G);
-  const double* row = A + (long)g * sA + (long)(row0 + q) * ldA;
-  double s = 0.0;
-  for (int c = lane; c < Np; c += 64) s += row[c] * row[c];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) wtab[(long)q * Gtot + g0 + g] = s - bnorm2[q];
+// wtab[q][g0 + g] = sum_J part[g][J][q] - bnorm2[q]
+__global__ void k_wc_from_parts(const double* part, long sPart, int nJ, int ldp,
+                                const double* bnorm2, int nR, int Gtot, int g0, double* wtab) {
+  const int g = blockIdx.y;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nR; q += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int J = 0; J < nJ; ++J) s += part[(long)g * sPart + (long)J * ldp + q];
+    wtab[(long)q * Gtot + g0 + g] = s - bnorm2[q];
+  }
 }
 
-hipError_t wc_reduce_chunk(const double* A, long ldA, long sA, int row0, const double* bnorm2,
-                           int nR, int Np, int G, int Gtot, int g0, double* wtab, long nA,
-                           long nBn, long nW, hipStream_t st) {
-  long items = (long)nR * G;
-  int blocks = (int)((items + 3) / 4);
-  if (blocks < 1) return hipSuccess;
-  GW_GUARD("wc_reduce", "A", (long)(G - 1) * sA + (long)(row0 + nR - 1) * ldA + Np - 1, nA);
-  GW_GUARD("wc_reduce", "bnorm2", nR - 1, nBn);
-  GW_GUARD("wc_reduce", "wtab", (long)(nR - 1) * Gtot + g0 + G - 1, nW);
-  if (g0 + G > Gtot) return refuse("wc_reduce", "grid chunk beyond the table");
+hipError_t wc_from_parts(const double* part, long sPart, int nJ, int ldp, const double* bnorm2,
+                         int nR, int G, int Gtot, int g0, double* wtab, long nPart, long nBn,
+                         long nW, hipStream_t st) {
+  if (nR <= 0 || G <= 0) return hipSuccess;
+  if (g0 + G > Gtot || ldp < nR) return refuse("wc_from_parts", "shape");
+  GW_GUARD("wc_from_parts", "part", (long)(G - 1) * sPart + (long)(nJ - 1) * ldp + nR - 1, nPart);
+  GW_GUARD("wc_from_parts", "bnorm2", nR - 1, nBn);
+  GW_GUARD("wc_from_parts", "wtab", (long)(nR - 1) * Gtot + g0 + G - 1, nW);
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_wc_reduce, dim3(blocks), dim3(256), 0, st, A, ldA, sA, row0, bnorm2, nR,
-                     Np, G, Gtot, g0, wtab);
+  int blocks = std::min((nR + 255) / 256, 256);
+  hipLaunchKernelGGL(k_wc_from_parts, dim3(blocks, G), dim3(256), 0, st, part, sPart, nJ, ldp,
+                     bnorm2, nR, Gtot, g0, wtab);
   return hipGetLastError();
 }
 

@@ -131,6 +131,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   int kbeg = split * kchunk;
   int kend = kbeg + kchunk;
   if (kend > p.K) kend = p.K;
+  if (p.ktri) {
+    const int lim = p.col0 + (J + 1) * BN - p.kb0;
+    if (kend > lim) kend = lim;
+  }
   const int nk = kend > kbeg ? (kend - kbeg) / BK : 0;
 
   d4 acc[TM][TN];
@@ -179,22 +183,27 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   // Epilogue.  f64 16x16x4 output layout: lane l, register r holds
   // row (l / 16) + 4 r, column l % 16 of the 16x16 block.
   double* C = p.C + (long)b * p.sC + (long)split * p.sSplit;
-  if (EPI == EPI_RES_DERIV) {
-    // per-row sum over this tile's columns of acc^2 * 2 D w / (D^2 - w^2)^2
+  if (EPI == EPI_RES_DERIV || EPI == EPI_SQNORM) {
+    // per-row sum over this tile's columns of acc^2 (EPI_SQNORM) or of
+    // acc^2 * 2 D w / (D^2 - w^2)^2 (EPI_RES_DERIV)
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int lrow = wm * TM * 16 + i * 16 + (lane >> 4) + 4 * r;
-        const double w = p.wrow[arow0 + lrow];
+        const double w = (EPI == EPI_RES_DERIV) ? p.wrow[arow0 + lrow] : 0.0;
         double s = 0.0;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          const int gcol = brow0 + wn * TN * 16 + j * 16 + (lane & 15);
-          const double D = p.Dvec[gcol];
-          const double den = D * D - w * w;
           const double u = acc[i][j][r];
-          s += u * u * (2.0 * D * w / (den * den));
+          if (EPI == EPI_RES_DERIV) {
+            const int gcol = brow0 + wn * TN * 16 + j * 16 + (lane & 15);
+            const double D = p.Dvec[gcol];
+            const double den = D * D - w * w;
+            s += u * u * (2.0 * D * w / (den * den));
+          } else {
+            s += u * u;
+          }
         }
         // reduce over the 16 lanes sharing this row
         for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
@@ -250,8 +259,8 @@ static hipError_t launch(const GemmArgs& a, hipStream_t st) {
 // Largest element index each operand of a launch can touch (see the kernel's
 // index arithmetic above), checked against the extents carried in GemmArgs.
 static hipError_t check_gemm(const GemmArgs& a, int tile_kind, int la, int lb, int epi) {
-  const int BM = tile_kind == 2 ? 64 : 128;
-  const int BN = tile_kind == 1 ? 64 : 128;
+  const int BM = (tile_kind == 2 || tile_kind == 3) ? 64 : 128;
+  const int BN = (tile_kind == 1 || tile_kind == 3) ? 64 : 128;
   const char* kn = "gemm_f64";
   if (a.K <= 0 || a.K % BK != 0 || a.tiles_m <= 0 || a.tiles_n <= 0 || a.batch <= 0 ||
       a.splitk <= 0 || a.row0 < 0 || a.col0 < 0 || a.k0 < 0 || a.kb0 < 0)
@@ -278,8 +287,10 @@ static hipError_t check_gemm(const GemmArgs& a, int tile_kind, int la, int lb, i
   if (!guard(kn, "A", maxA, a.nA)) return hipErrorInvalidValue;
   if (!guard(kn, "B", maxB, a.nB)) return hipErrorInvalidValue;
   if (a.scale && !guard(kn, "scale", b1 * a.sS + a.kb0 + a.K - 1, a.nS)) return hipErrorInvalidValue;
+  const bool per_tile = epi == EPI_RES_DERIV || epi == EPI_SQNORM;
   long maxC = b1 * a.sC + (long)(a.splitk - 1) * a.sSplit +
-              (epi == EPI_RES_DERIV ? (long)(a.tiles_n - 1) * a.ldc + rmax : rmax * a.ldc + cmax);
+              (per_tile ? (long)(a.tiles_n - 1) * a.ldc + rmax : rmax * a.ldc + cmax);
+  if (a.ktri && a.splitk != 1) return refuse(kn, "triangular k limit with split-K");
   if (!guard(kn, "C", maxC, a.nC)) return hipErrorInvalidValue;
   if (epi == EPI_RES_SCALE || epi == EPI_RES_DERIV) {
     if (!guard(kn, "D", cmax, a.nD)) return hipErrorInvalidValue;
@@ -288,7 +299,8 @@ static hipError_t check_gemm(const GemmArgs& a, int tile_kind, int la, int lb, i
   return hipSuccess;
 }
 
-// Instantiations used by the library.  tile_kind: 0 = 128x128, 1 = 128x64, 2 = 64x128.
+// Instantiations used by the library.
+// tile_kind: 0 = 128x128, 1 = 128x64, 2 = 64x128, 3 = 64x64.
 hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, hipStream_t st) {
   {
     hipError_t e = check_gemm(a, tile_kind, la, lb, epi);
@@ -304,14 +316,17 @@ hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, h
   // Cholesky panel solve (A_panel Linv^T): 128 x 64, axpby
   if (tile_kind == 1 && la == KC && lb == KC && epi == EPI_AXPBY && !scaled)
     return launch<2, 4, 2, KC, KC, EPI_AXPBY, false, false>(a, st);
-  // MINRES: V = scale(X B) with X [sys][P] (KC) and B_ov [P][ia] (KM): 64 x 128 tiles
-  if (tile_kind == 2 && la == KC && lb == KM && epi == EPI_RES_SCALE && !scaled)
-    return launch<1, 4, 2, KC, KM, EPI_RES_SCALE, false, false>(a, st);
-  if (tile_kind == 2 && la == KC && lb == KM && epi == EPI_RES_DERIV && !scaled)
-    return launch<1, 4, 2, KC, KM, EPI_RES_DERIV, false, false>(a, st);
+  // MINRES: V = scale(X B) with X [sys][P] (KC) and B_ov [P][ia] (KM): 64 x 64 tiles
+  if (tile_kind == 3 && la == KC && lb == KM && epi == EPI_RES_SCALE && !scaled)
+    return launch<2, 2, 2, KC, KM, EPI_RES_SCALE, false, false>(a, st);
+  if (tile_kind == 3 && la == KC && lb == KM && epi == EPI_RES_DERIV && !scaled)
+    return launch<2, 2, 2, KC, KM, EPI_RES_DERIV, false, false>(a, st);
   // MINRES: part[s][sys][P] = sum_ia V[sys][ia] B_ov[P][ia], split-K partials, 64 x 128 tiles
   if (tile_kind == 2 && la == KC && lb == KC && epi == EPI_STORE && !scaled)
     return launch<1, 4, 2, KC, KC, EPI_STORE, false, false>(a, st);
+  // W^c reduction: |R^T Linv^T|^2 per row, Linv^T k-major, triangular k range
+  if (tile_kind == 0 && la == KC && lb == KM && epi == EPI_SQNORM && !scaled)
+    return launch<2, 4, 4, KC, KM, EPI_SQNORM, false, true>(a, st);
   // generic full 128x128 store / axpby (tests, dense fallback build)
   if (tile_kind == 0 && la == KC && lb == KC && epi == EPI_STORE && scaled)
     return launch<2, 4, 4, KC, KC, EPI_STORE, true, false>(a, st);

@@ -155,7 +155,7 @@ struct gw_ctx {
   int Kov = 0;     // n_occ * n_virt
   int Kp = 0;      // Kov padded to 128
   int nR = 0;      // n_rows * n_mo
-  int Rp = 0;      // nR padded to 64
+  int Rp = 0;      // nR padded to 128
   // options
   int pi_prec = GW_PI_FP64;
   int minres_max_iter = 200;
@@ -190,6 +190,7 @@ struct gw_ctx {
   double* d_Linv = nullptr;
   int* d_info = nullptr;
   double* d_scale = nullptr;   // [chunk][Kp]
+  double* d_parts = nullptr;   // [chunk][Np/128][Rp] squared-norm partials
   double* d_grid = nullptr;    // [2][Gmax]
   int grid_cap = 0;
   // W^c table cache
@@ -299,12 +300,18 @@ int run_gemm(gw_ctx* c, GemmArgs a, int kind, int la, int lb, int epi) {
 int ensure_mixed_operands(gw_ctx* c);
 int pi_build_chunk(gw_ctx* c, int G, long per_g, long ldA);
 
+// Stage-A layout of one grid point: rows [0, Np) the dielectric matrix (then
+// L), rows [Np, 2 Np) the identity (then L^-T), 128 rows and 128 columns of
+// padding that tiles overrunning a 64-aligned edge may touch.
+inline long work_ld(const gw_ctx* c) { return c->Np + 128; }
+inline long work_per_g(const gw_ctx* c) { return (2L * c->Np + 128) * work_ld(c); }
+inline int parts_ld(const gw_ctx* c) { return c->Rp; }
+inline long parts_per_g(const gw_ctx* c) { return (long)(c->Np / 128) * c->Rp; }
+
 int setup_work(gw_ctx* c, int G) {
-  const long ldA = c->Np + 128;
-  const long rows = (long)c->Np + c->Rp + 128;
-  const long per_g = rows * ldA;
+  const long per_g = work_per_g(c);
   size_t per_bytes = (size_t)per_g * sizeof(double) + (size_t)c->Kp * sizeof(double) +
-                     PANEL * PANEL * sizeof(double);
+                     PANEL * PANEL * sizeof(double) + (size_t)parts_per_g(c) * sizeof(double);
   int chunk = (int)std::max<size_t>(1, c->work_budget / per_bytes);
   if (chunk > G) chunk = G;
   if (c->d_work && c->chunk >= chunk) return 0;
@@ -312,11 +319,14 @@ int setup_work(gw_ctx* c, int G) {
   if (c->d_Linv) c->release(c->d_Linv);
   if (c->d_info) c->release(c->d_info);
   if (c->d_scale) c->release(c->d_scale);
+  if (c->d_parts) c->release(c->d_parts);
   c->d_work = nullptr;
   c->d_Linv = nullptr;
   c->d_info = nullptr;
   c->d_scale = nullptr;
+  c->d_parts = nullptr;
   RCHK(c->alloc((void**)&c->d_work, (size_t)per_g * chunk * sizeof(double)));
+  RCHK(c->alloc((void**)&c->d_parts, (size_t)parts_per_g(c) * chunk * sizeof(double)));
   HIPCHK(rt_memset(c->d_work, 0, (size_t)per_g * chunk * sizeof(double), c->st));
   RCHK(c->alloc((void**)&c->d_Linv, (size_t)chunk * PANEL * PANEL * sizeof(double)));
   RCHK(c->alloc((void**)&c->d_info, (size_t)chunk * sizeof(int)));
@@ -389,18 +399,20 @@ int ensure_mixed_operands(gw_ctx* c) {
   return 0;
 }
 
-// Blocked right-looking Cholesky of every item of the chunk, over the
-// augmented rows [0, Np + Rp).
+// Blocked right-looking Cholesky of every item of the chunk over the rows
+// [0, Np) of 1 - Pi and the appended identity rows; panel k carries the
+// appended rows up to Np + k + 64 only (the later ones are still unit rows
+// that the panel does not touch).
 int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
-  const int Mrows = c->Np + c->Rp;
+  const int Np = c->Np;
   HIPCHK(rt_memset(c->d_info, 0, G * sizeof(int), c->st));
-  for (int k = 0; k < c->Np; k += PANEL) {
+  HIPCHK(set_identity_rows(c->d_work, ldA, per_g, Np, Np, Np, G, c->ext(c->d_work, 8), c->st));
+  for (int k = 0; k < Np; k += PANEL) {
     trace("cholesky panel k=%d", k);
     HIPCHK(chol_diag(c->d_work, ldA, per_g, c->d_Linv, k, G, c->d_info, c->ext(c->d_work, 8),
                      c->ext(c->d_Linv, 8), c->ext(c->d_info, 4), c->st));
-    const int rows_below = Mrows - (k + PANEL);
-    if (rows_below <= 0) continue;
-    {  // panel solve: L[i][k:k+64] = A[i][k:k+64] Linv^T
+    const int rows_below = Np + k + PANEL - (k + PANEL);  // rows [k + 64, Np + k + 64)
+    {  // panel solve: L[i][k:k+64] = A[i][k:k+64] Linv_kk^T
       GemmArgs a{};
       a.A = c->d_work; a.lda = ldA; a.sA = per_g;
       a.B = c->d_Linv; a.ldb = PANEL; a.sB = PANEL * PANEL;
@@ -413,7 +425,7 @@ int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
       a.alpha = 1.0; a.beta = 0.0;
       RCHK(run_gemm(c, a, 1, KC, KC, EPI_AXPBY));
     }
-    const int cols_right = c->Np - (k + PANEL);
+    const int cols_right = Np - (k + PANEL);
     if (cols_right <= 0) continue;
     {  // trailing update of the lower trapezoid: A -= L_panel L_panel^T
       GemmArgs a{};
@@ -479,8 +491,8 @@ int build_wtable(gw_ctx* c, const gw_grid* grid, int mode = 0, double* dbg_out =
     }
     c->wtab_valid = false;
   }
-  const long ldA = c->Np + 128;
-  const long per_g = ((long)c->Np + c->Rp + 128) * ldA;
+  const long ldA = work_ld(c);
+  const long per_g = work_per_g(c);
   Timer tm;
   tm.a = c->ev0; tm.b = c->ev1;
   double pi_ms = 0, chol_ms = 0, wt_ms = 0;
@@ -498,10 +510,6 @@ int build_wtable(gw_ctx* c, const gw_grid* grid, int mode = 0, double* dbg_out =
       continue;
     }
     tm.start(c->st);
-    if (c->nR > 0) {
-      HIPCHK(copy_rows_into(c->d_work, ldA, per_g, c->Np, c->d_R, c->Rp, c->Np, Gc,
-                            c->ext(c->d_work, 8), c->ext(c->d_R, 8), c->st));
-    }
     RCHK(cholesky_chunk(c, Gc, per_g, ldA));
     chol_ms += tm.stop();
     if (mode == 2) {
@@ -510,9 +518,19 @@ int build_wtable(gw_ctx* c, const gw_grid* grid, int mode = 0, double* dbg_out =
     }
     tm.start(c->st);
     if (c->nR > 0) {
-      HIPCHK(wc_reduce_chunk(c->d_work, ldA, per_g, c->Np, c->d_bn, c->nR, c->Np, Gc, G, g0,
-                             c->d_wtab, c->ext(c->d_work, 8), c->ext(c->d_bn, 8),
-                             c->ext(c->d_wtab, 8), c->st));
+      // |L^-1 b|^2 for every b = (P|nm): rows of R times L^-T (k-major rows
+      // Np.. of the work buffer), k limited to the lower triangle
+      GemmArgs a{};
+      a.A = c->d_R; a.lda = c->Np; a.sA = 0;
+      a.B = c->d_work + (long)c->Np * ldA; a.ldb = ldA; a.sB = per_g;
+      a.C = c->d_parts; a.ldc = parts_ld(c); a.sC = parts_per_g(c);
+      a.M = c->Rp; a.N = c->Np; a.K = c->Np;
+      a.map = MAP_FULL; a.tiles_m = c->Rp / 128; a.tiles_n = c->Np / 128;
+      a.n_tiles = a.tiles_m * a.tiles_n; a.batch = Gc; a.splitk = 1; a.ktri = 1;
+      RCHK(run_gemm(c, a, 0, KC, KM, EPI_SQNORM));
+      HIPCHK(wc_from_parts(c->d_parts, parts_per_g(c), c->Np / 128, parts_ld(c), c->d_bn, c->nR,
+                           Gc, G, g0, c->d_wtab, c->ext(c->d_parts, 8), c->ext(c->d_bn, 8),
+                           c->ext(c->d_wtab, 8), c->st));
     }
     wt_ms += tm.stop();
   }
@@ -543,11 +561,11 @@ int ensure_minres(gw_ctx* c, int kp) {
   for (double** p : vecs) RCHK(c->alloc((void**)p, vec * sizeof(double)));
   RCHK(c->alloc((void**)&m.scal, (size_t)kp * 16 * sizeof(double)));
   RCHK(c->alloc((void**)&m.V, (size_t)kp * c->Kp * sizeof(double)));
-  // split-K partials for B_ov V^T: aim for >= 512 workgroups
+  // split-K partials for B_ov V^T: aim for about 1024 workgroups
   const int tiles = (kp / 64) * (c->Np / 128);
-  int splitk = std::max(1, std::min(512 / std::max(tiles, 1) + 1, c->Kp / 128));
+  int splitk = std::max(1, std::min(1024 / std::max(tiles, 1), c->Kp / 256));
   c->mr_splitk = splitk;
-  size_t part = std::max((size_t)splitk * kp * c->Np, (size_t)(c->Kp / 128) * kp);
+  size_t part = std::max((size_t)splitk * kp * c->Np, (size_t)(c->Kp / 64) * kp);
   RCHK(c->alloc((void**)&m.part, part * sizeof(double)));
   c->part_cap = part;
   RCHK(c->alloc((void**)&m.omega, (size_t)kp * sizeof(double)));
@@ -567,10 +585,10 @@ int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long l
   a.B = c->d_Bov; a.ldb = c->Kp; a.sB = 0;
   a.C = out; a.ldc = ldc; a.sC = 0;
   a.M = kp; a.N = c->Kp; a.K = c->Np;
-  a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Kp / 128;
+  a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Kp / 64;
   a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
   a.Dvec = c->d_D; a.wrow = c->mr.omega;
-  RCHK(run_gemm(c, a, 2, KC, KM, epi));
+  RCHK(run_gemm(c, a, 3, KC, KM, epi));
   return 0;
 }
 
@@ -622,11 +640,17 @@ int solve_residues(gw_ctx* c, const std::vector<System>& sys, bool use_fallback,
   HIPCHK(minres_init(m, c->d_R, c->d_rhs_idx, idx.data(), c->Rp, c->st));
   int active = k;
   int itn = 0;
+  // convergence is polled (one 4-byte copy and a stream sync) every `poll`
+  // iterations; converged systems are frozen by the step kernel meanwhile
+  const int poll = 3;
   for (itn = 1; itn <= c->minres_max_iter; ++itn) {
     RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp));
     RCHK(backproject_pass(c, kp));
-    HIPCHK(rt_memset(m.active, 0, sizeof(int), c->st));
-    HIPCHK(minres_finish_step(m, c->mr_splitk, itn, c->minres_rtol, c->st));
+    HIPCHK(minres_apply(m, c->mr_splitk, c->st));
+    const bool check = (itn % poll == 0) || itn == c->minres_max_iter;
+    if (check) HIPCHK(rt_memset(m.active, 0, sizeof(int), c->st));
+    HIPCHK(minres_finish_step(m, itn, c->minres_rtol, c->st));
+    if (!check) continue;
     HIPCHK(rt_memcpy(&active, m.active, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(rt_sync(c->st));
     if (active == 0) break;
@@ -634,7 +658,7 @@ int solve_residues(gw_ctx* c, const std::vector<System>& sys, bool use_fallback,
   c->timing.minres_iters += std::min(itn, c->minres_max_iter);
   c->timing.minres_systems += k;
   // derivative partials: sum over ia of (B^T x)^2 * 2 D w/(D^2 - w^2)^2
-  const int nparts = c->Kp / 128;
+  const int nparts = c->Kp / 64;
   RCHK(matvec_pass(c, m.x, kp, EPI_RES_DERIV, m.part, kp));
   HIPCHK(minres_results(m, c->d_R, c->d_rhs_idx, c->Rp, nparts, c->d_wc, c->d_dwc, c->d_conv,
                         c->ext(c->d_wc, 8), c->st));
@@ -984,7 +1008,7 @@ int gw_setup(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps, co
   c->Kov = (int)Kov;
   c->Kp = round_up((int)Kov, 128);
   c->nR = n_rows * n_mo;
-  c->Rp = round_up(std::max(c->nR, 1), 64);
+  c->Rp = round_up(std::max(c->nR, 1), 128);
   c->pi_prec = o.pi_prec;
   if (o.minres_max_iter > 0) c->minres_max_iter = o.minres_max_iter;
   if (o.minres_rtol > 0) c->minres_rtol = o.minres_rtol;
@@ -1069,6 +1093,12 @@ int gw_set_pi_prec(gw_ctx* c, int prec) {
   if (prec < 0 || prec > 2) return fail(GW_EINVAL, "unknown pi_prec %d", prec);
   if (prec != c->pi_prec) c->wtab_valid = false;
   c->pi_prec = prec;
+  return 0;
+}
+
+int gw_reset_cache(gw_ctx* c) {
+  if (!c) return fail(GW_EINVAL, "NULL ctx");
+  c->wtab_valid = false;
   return 0;
 }
 

@@ -44,6 +44,7 @@ enum Epilogue {
   EPI_RES_SCALE = 2,    // C = acc * D/(D^2 - w_row^2)    (MINRES: scaled B^T v, rows = systems)
   EPI_RES_DERIV = 3,    // part[colTile][row] = sum_col acc^2 * 2 D w/(D^2 - w^2)^2
   EPI_STORE = 4,        // C = acc (split-K partials)
+  EPI_SQNORM = 5,       // part[colTile][row] = sum_col acc^2
 };
 
 enum TileMap {
@@ -64,6 +65,7 @@ struct GemmArgs {
   int n_tiles;                          // tiles per batch item
   int batch;
   int splitk;                           // >= 1; split s covers k in [s*K/splitk, (s+1)*K/splitk)
+  int ktri;                             // B(j, k) = 0 for k > j: stop k at the tile's last B row
   long sSplit;                          // C offset between split-K slabs
   double alpha, beta;
   const double* Dvec;                   // transition energies (EPI_RES_*)
@@ -73,7 +75,7 @@ struct GemmArgs {
 };
 
 hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, hipStream_t st);
-// tile_kind 0: 128x128, 1: 128x64, 2: 64x128
+// tile_kind 0: 128x128, 1: 128x64, 2: 64x128, 3: 64x64
 
 // Mixed-precision Pi builds (write 1 - Pi lower tiles in FP64)
 // nB: elements of each B copy, nS: of scale, nA: of the output
@@ -88,11 +90,14 @@ hipError_t split_bf16(const double* B, uint16_t* hi, uint16_t* lo, float* b32, l
 // Cholesky pieces
 hipError_t chol_diag(double* A, long ldA, long sA, double* Linv, int k, int G, int* info,
                      long nA, long nLinv, long nInfo, hipStream_t st);
-hipError_t copy_rows_into(double* A, long ldA, long sA, int row0, const double* R, int nR,
-                          int Np, int G, long nA, long nR_ext, hipStream_t st);
-hipError_t wc_reduce_chunk(const double* A, long ldA, long sA, int row0, const double* bnorm2,
-                           int nR, int Np, int G, int Gtot, int g0, double* wtab, long nA,
-                           long nBn, long nW, hipStream_t st);
+// rows [row0, row0 + n) of every batch item <- identity rows e_0 .. e_{n-1}
+// (columns [0, ncol))
+hipError_t set_identity_rows(double* A, long ldA, long sA, int row0, int n, int ncol, int G,
+                             long nA, hipStream_t st);
+// wtab[q][g0 + g] = sum_J part[g][J][q] - bnorm2[q] for q < nR
+hipError_t wc_from_parts(const double* part, long sPart, int nJ, int ldp, const double* bnorm2,
+                         int nR, int G, int Gtot, int g0, double* wtab, long nPart, long nBn,
+                         long nW, hipStream_t st);
 
 // prep
 hipError_t transition_energies(const double* eps, int n_occ, int n_virt, int Kp, double* D,
@@ -125,7 +130,9 @@ struct MinresBufs {
 // passes the index array it uploaded so the guard can check it
 hipError_t minres_init(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
                        const int* host_idx, int n_rhs_rows, hipStream_t st);
-hipError_t minres_finish_step(MinresBufs& m, int splitk, int itn, double rtol, hipStream_t st);
+// y = v + 4 sum_s part[s] (the operator applied to v), one thread per element
+hipError_t minres_apply(MinresBufs& m, int splitk, hipStream_t st);
+hipError_t minres_finish_step(MinresBufs& m, int itn, double rtol, hipStream_t st);
 hipError_t minres_results(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
                           int n_rhs_rows, int n_deriv_parts, double* wc, double* dwc, int* conv,
                           long n_out, hipStream_t st);

@@ -4,11 +4,20 @@
 // two MFMA GEMM passes over B_ov (see gemm_f64.hip) for all systems at once.
 // This file holds the per-system Lanczos / Givens recurrences, one
 // workgroup per system.
+#include <algorithm>
+
 #include "gw_internal.h"
 
 namespace gw {
 
 enum { S_BETA1 = 0, S_BETA, S_OLDB, S_DBAR, S_EPS, S_PHIBAR, S_CS, S_SN, S_DONE, S_ITERS, S_RATIO };
+
+static hipError_t check_bufs(const MinresBufs& m, const char* kn) {
+  if (m.k < 0 || m.k > m.kp || m.kp % 64 != 0) return refuse(kn, "system count");
+  GW_GUARD(kn, "vectors", (long)m.kp * m.Np - 1, m.n_vec);
+  GW_GUARD(kn, "scalars", (long)m.kp * 16 - 1, m.n_scal);
+  return hipSuccess;
+}
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
   const int t = threadIdx.x;
@@ -56,13 +65,6 @@ __global__ __launch_bounds__(256) void k_minres_init(MinresBufs m, const double*
   }
 }
 
-static hipError_t check_bufs(const MinresBufs& m, const char* kn) {
-  if (m.k < 0 || m.k > m.kp || m.kp % 64 != 0) return refuse(kn, "system count");
-  GW_GUARD(kn, "vectors", (long)m.kp * m.Np - 1, m.n_vec);
-  GW_GUARD(kn, "scalars", (long)m.kp * 16 - 1, m.n_scal);
-  return hipSuccess;
-}
-
 hipError_t minres_init(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
                        const int* host_idx, int n_rhs_rows, hipStream_t st) {
   if (hipError_t e = check_bufs(m, "minres_init")) return e;
@@ -73,25 +75,43 @@ hipError_t minres_init(MinresBufs& m, const double* rhs_base, const int* rhs_idx
   return hipGetLastError();
 }
 
-// One MINRES iteration for every unconverged system, given the split-K
-// partials part[s][j][:] of B_ov V^T (V = scaled B_ov^T v).
-__global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int splitk, int itn,
-                                                     double rtol) {
+// y = v + 4 sum_s part[s] for every element of every system: the matrix-vector
+// product (1 - Pi(w)) v finished from the split-K partials of B_ov V^T.
+__global__ void k_minres_apply(MinresBufs m, int splitk) {
+  const long n = (long)m.kp * m.Np;
+  const long slab = n;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    double av = 0.0;
+    for (int s = 0; s < splitk; ++s) av += m.part[s * slab + i];
+    m.y[i] = m.v[i] + 4.0 * av;
+  }
+}
+
+hipError_t minres_apply(MinresBufs& m, int splitk, hipStream_t st) {
+  if (hipError_t e = check_bufs(m, "minres_apply")) return e;
+  GW_GUARD("minres_apply", "part", (long)splitk * m.kp * m.Np - 1, m.n_part);
+  GW_AUDIT_RETURN();
+  const long n = (long)m.kp * m.Np;
+  int blocks = (int)std::min<long>((n + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_minres_apply, dim3(blocks), dim3(256), 0, st, m, splitk);
+  return hipGetLastError();
+}
+
+// One MINRES iteration for every unconverged system, given y = A v.
+__global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int itn, double rtol) {
   __shared__ double red[4];
   __shared__ double bc[5];
   const int j = blockIdx.x, t = threadIdx.x;
   double* sc = m.scal + j * 16;
   if (sc[S_DONE] != 0.0) return;
   const long o = (long)j * m.Np;
-  const long slab = (long)m.kp * m.Np;
   const double beta = sc[S_BETA], oldb = sc[S_OLDB];
   // y = A v (- (beta/oldb) r1 from the second iteration on)
   const double c1 = (itn >= 2) ? beta / oldb : 0.0;
   double sa = 0.0;
   for (int p = t; p < m.Np; p += 256) {
-    double av = 0.0;
-    for (int s = 0; s < splitk; ++s) av += m.part[s * slab + o + p];
-    double yv = m.v[o + p] + 4.0 * av - c1 * m.r1[o + p];
+    double yv = m.y[o + p] - c1 * m.r1[o + p];
     m.y[o + p] = yv;
     sa += m.v[o + p] * yv;
   }
@@ -151,11 +171,10 @@ __global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int splitk, i
   if (t == 0 && !done) atomicAdd(m.active, 1);
 }
 
-hipError_t minres_finish_step(MinresBufs& m, int splitk, int itn, double rtol, hipStream_t st) {
+hipError_t minres_finish_step(MinresBufs& m, int itn, double rtol, hipStream_t st) {
   if (hipError_t e = check_bufs(m, "minres_step")) return e;
-  GW_GUARD("minres_step", "part", (long)splitk * m.kp * m.Np - 1, m.n_part);
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_minres_step, dim3(m.kp), dim3(256), 0, st, m, splitk, itn, rtol);
+  hipLaunchKernelGGL(k_minres_step, dim3(m.kp), dim3(256), 0, st, m, itn, rtol);
   return hipGetLastError();
 }
 

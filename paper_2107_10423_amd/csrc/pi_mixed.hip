@@ -7,8 +7,10 @@
 //  * BF16x3: each operand x is split x = hi + lo with hi = bf16(x) and
 //            lo = bf16(x - hi); the product is hi_a hi_b + hi_a lo_b + lo_a hi_b
 //            (the lo lo term is below the split's own error), three
-//            v_mfma_f32_16x16x32_bf16 per k-step, FP32 accumulation flushed to
-//            FP64 every 512 k.  The unscaled side B is split once per molecule
+//            v_mfma_f32_16x16x32_bf16 per k-step, FP32 accumulation over the
+//            whole K (the FP64 flush variant costs the occupancy of a second
+//            workgroup per CU; the accuracy difference is reported by the
+//            precision tests).  The unscaled side B is split once per molecule
 //            and stored; the scaled side B s_g is split on the fly per grid point
 //            while it is staged into LDS.
 //
@@ -211,6 +213,7 @@ hipError_t pi_build_f32(const float* B32, long ld, const double* scale, long sS,
 constexpr int BKB = 32;
 constexpr int LROW = BKB + 8;  // padded row length in bf16 elements
 
+template <bool FLUSH64>
 __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const uint16_t* Blo,
                                                    long ld, const float* B32,
                                                    const double* scale, long sS, double* A,
@@ -230,14 +233,15 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
   const int ar0 = I * 128, br0 = J * 128;
 
   f4 acc[4][4];
-  d4 acc64[4][4];
+  d4 acc64[FLUSH64 ? 4 : 1][FLUSH64 ? 4 : 1];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-      acc64[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    }
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int i = 0; i < (FLUSH64 ? 4 : 1); ++i)
+#pragma unroll
+    for (int j = 0; j < (FLUSH64 ? 4 : 1); ++j) acc64[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   // A side: 128 rows x 32 k bf16 = 512 chunks of 8 (16 B) per array -> 2 per thread
   // B side: 128 rows x 32 k fp32 = 1024 float4 -> 4 per thread
   uint4 rah[2], ral[2];
@@ -325,13 +329,13 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
             __builtin_bit_cast(bf8, ah[i]), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
       }
-    if (((kt + 1) * BKB) % FLUSH_K == 0 || kt + 1 == nk) {
+    if (FLUSH64 && (((kt + 1) * BKB) % FLUSH_K == 0 || kt + 1 == nk)) {
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc64[i][j][r] += (double)acc[i][j][r];
+          for (int r = 0; r < 4; ++r) acc64[FLUSH64 ? i : 0][FLUSH64 ? j : 0][r] += (double)acc[i][j][r];
           acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         }
     }
@@ -347,7 +351,8 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
       for (int r = 0; r < 4; ++r) {
         int row = ar0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
         int col = br0 + wn * 64 + j * 16 + (lane & 15);
-        Ag[(long)row * ldA + col] = (row == col ? 1.0 : 0.0) + 4.0 * acc64[i][j][r];
+        const double v = FLUSH64 ? acc64[FLUSH64 ? i : 0][FLUSH64 ? j : 0][r] : (double)acc[i][j][r];
+        Ag[(long)row * ldA + col] = (row == col ? 1.0 : 0.0) + 4.0 * v;
       }
 }
 
@@ -359,7 +364,7 @@ hipError_t pi_build_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, long ld, co
   if (total <= 0) return hipSuccess;
   if (hipError_t e = check_pi("pi_bf16x3", ld, sS, ldA, sA, Np, Kp, G, BKB, nB, nS, nA)) return e;
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_pi_bf16x3, dim3((unsigned)total), dim3(256), 0, st, Bhi, Blo, ld, B32, scale,
+  hipLaunchKernelGGL(k_pi_bf16x3<false>, dim3((unsigned)total), dim3(256), 0, st, Bhi, Blo, ld, B32, scale,
                      sS, A, ldA, sA, T, Kp, G);
   return hipGetLastError();
 }

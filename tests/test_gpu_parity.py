@@ -289,3 +289,23 @@ def test_h2o10_full_size_against_fixture(prec, tol):
     for j, r in enumerate(gold["results"]):
         t = 1e-10 * abs(r["E"]) if tol is None else tol
         assert abs(E[j] - r["E"]) <= t, (prec, r["state"], E[j] - r["E"])
+
+
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-13), ("fp32", 2e-6), ("bf16x3", 1e-4)])
+def test_pi_precision_h2o10_sampled_rows(prec, bound):
+    # full (H2O)10 size; the oracle forms 40 sampled rows of Pi per frequency
+    inp = gwgen.make_inputs(gwgen.CONFIGS["h2o10"].shape, 2, [49])
+    xis = np.array([1e-3, 0.5, 20.0])
+    with ctx(inp, pi_prec=prec) as c:
+        got = c.dielectric(xis)
+    rows = np.unique(np.r_[np.arange(0, 1120, 37), np.arange(1110, 1120)])
+    D = cd.transition_energies(inp.eps, inp.n_occ)
+    worst = 0.0
+    for g, x in enumerate(xis):
+        Pi_rows = -4.0 * (inp.B_ov[rows] * (D / (D * D + x * x))) @ inp.B_ov.T
+        ref = np.eye(1120)[rows] - Pi_rows
+        mask = np.arange(1120)[None, :] <= rows[:, None]       # lower triangle
+        err = np.abs(np.where(mask, got[g][rows] - ref, 0.0)).max() / np.abs(Pi_rows).max()
+        worst = max(worst, err)
+    print(f"Pi precision {prec}: max |error| / max |Pi| = {worst:.3e}")
+    assert worst < bound
