@@ -95,6 +95,110 @@ def cpu_baseline(inp, states, G, gold):
             "est_total_s": total}
 
 
+def serve_bench(args):
+    """Serving workload: water clusters of k ~ U{1..24} molecules (HOMO-2..LUMO+2,
+    64-point grid) through gw_server.  Phase 1: FP64, closed loop with 8
+    requests outstanding -> saturated throughput T.  Phase 2: Poisson
+    arrivals at rate 0.8 T, for the FP64 and the BF16x3 path -> throughput,
+    p50 / p99 latency (done - submit) and the per-request energy difference."""
+    import threading
+
+    import numpy as np
+    import gwgen
+    import paper_2107_10423_amd as gwl
+
+    stream = gwgen.serving_stream(n_requests=args.requests, k_max=args.kmax, seed=5000, rate=1.0)
+    cache = {}
+    log(f"serve: generating inputs for {len(set(r['k'] for r in stream))} cluster sizes")
+    for r in stream:
+        if r["k"] not in cache:
+            cache[r["k"]] = gwgen.serving_inputs(r["k"], 1000 + r["k"])
+    grid = gwl.Grid.gauss_legendre(64)
+
+    def run(prec, arrivals, window=None):
+        srv = gwl.Server(grid, pi_prec=prec, n_streams=args.streams)
+        tickets, E = {}, {}
+        lat, done_t, sub_t = [], [], []
+        lock = threading.Lock()
+        outstanding = threading.Semaphore(window) if window else None
+        t0 = time.perf_counter()
+
+        def producer():
+            for i, r in enumerate(stream):
+                if arrivals is not None:
+                    dt = arrivals[i] - (time.perf_counter() - t0)
+                    if dt > 0:
+                        time.sleep(dt)
+                if outstanding:
+                    outstanding.acquire()
+                inp = cache[r["k"]]
+                tk = srv.submit_inputs(inp, list(inp.row_ids))
+                with lock:
+                    tickets[tk] = i
+
+        th = threading.Thread(target=producer)
+        th.start()
+        n_done = 0
+        while n_done < len(stream):
+            with lock:
+                items = list(tickets.items())
+            progressed = False
+            for tk, i in items:
+                out = srv.poll(tk)
+                if out is None:
+                    continue
+                progressed = True
+                with lock:
+                    del tickets[tk]
+                if outstanding:
+                    outstanding.release()
+                info = out[4]
+                if info["rc"] != 0:
+                    raise RuntimeError(f"request {i} failed with {info['rc']}")
+                E[i] = out[0]
+                lat.append(info["t_done"] - info["t_submit"])
+                done_t.append(info["t_done"])
+                sub_t.append(info["t_submit"])
+                n_done += 1
+                if n_done % 16 == 0:
+                    log(f"serve: {prec}: {n_done}/{len(stream)} done")
+            if not progressed:
+                time.sleep(0.002)
+        th.join()
+        st = srv.stats()
+        srv.close()
+        span = max(done_t) - min(sub_t)
+        lat = np.array(lat)
+        return dict(E=E, span_s=span, req_per_s=len(stream) / span,
+                    qp_per_s=sum(len(cache[r["k"]].row_ids) for r in stream) / span,
+                    p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                    mean_s=float(lat.mean()), peak_active=st["peak_active"],
+                    peak_reserved_gb=st["peak_reserved_bytes"] / 2**30)
+
+    log("serve: phase 1, FP64 closed loop (8 outstanding)")
+    sat = run("fp64", None, window=8)
+    lam = 0.8 * sat["req_per_s"]
+    arr = np.array([r["arrival_s"] for r in stream]) / lam
+    res = {}
+    for prec in ("fp64", "bf16x3"):
+        log(f"serve: phase 2, {prec}, Poisson arrivals at {lam:.2f} req/s")
+        res[prec] = run(prec, arr)
+    dE = max(float(np.max(np.abs(res["bf16x3"]["E"][i] - res["fp64"]["E"][i])))
+             for i in range(len(stream)))
+    pick = lambda r: {k: (round(v, 4) if isinstance(v, float) else v)
+                      for k, v in r.items() if k != "E"}
+    out = {"metric": "serving: QP energies/s and p50/p99 latency, BF16x3 vs FP64 Pi",
+           "value": round(res["bf16x3"]["qp_per_s"], 3), "unit": "QP energies/s",
+           "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": f"{len(stream)} water clusters, k ~ U{{1..{args.kmax}}}, "
+                                  "HOMO-2..LUMO+2, 64-point grid, Poisson arrivals",
+                      "rate_req_per_s": round(lam, 4), "streams": args.streams},
+           "saturated_fp64": pick(sat), "fp64": pick(res["fp64"]), "bf16x3": pick(res["bf16x3"]),
+           "max_abs_dE_mixed_vs_fp64_mev": dE / MEV,
+           "mixed_over_fp64_qp_per_s": round(res["bf16x3"]["qp_per_s"] / res["fp64"]["qp_per_s"], 3)}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -102,6 +206,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default=None, help="time only this Pi precision (profiling)")
+    ap.add_argument("--serve", action="store_true", help="run the serving workload instead")
+    ap.add_argument("--requests", type=int, default=128)
+    ap.add_argument("--kmax", type=int, default=24)
+    ap.add_argument("--streams", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -113,6 +221,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.serve:
+        serve_bench(args)
+        return
     import gwgen
     import paper_2107_10423_amd as gwl
 

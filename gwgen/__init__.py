@@ -155,6 +155,36 @@ def make_inputs(shape: Shape, seed: int, row_ids: Sequence[int],
     return Inputs(shape=shape, seed=seed, eps=eps, B_ov=B_ov, row_ids=rows, B_rows=B_rows)
 
 
+def make_inputs_blocked(shape: Shape, seed: int, row_ids: Sequence[int]) -> Inputs:
+    """Same distribution as make_inputs (symmetric B, i.i.d. N(0, 0.25/(n_occ n_virt))
+    for p <= q), drawn block-wise so that large clusters are cheap: stream
+    (seed, 1) draws B_ov [N_aux][n_ov] in one go, and stream (seed, 2 + r)
+    draws, for requested row n = row_ids[r], the entries (n, m) that are not
+    occupied-virtual pairs and have m >= n or m not requested; the remaining
+    entries are copied from B_ov or from the mirror row, so B stays symmetric.
+    Used for the serving workload (values differ from make_inputs)."""
+    n_occ, n_virt, n_aux, n_mo = shape.n_occ, shape.n_virt, shape.n_aux, shape.n_mo
+    rows = np.asarray(list(row_ids), dtype=np.int32)
+    eps = make_eps(shape, seed)
+    std = np.sqrt(0.25 / (n_occ * n_virt))
+    B_ov = _rng(seed, 1).standard_normal((n_aux, n_occ * n_virt)) * std
+    Bv = B_ov.reshape(n_aux, n_occ, n_virt)
+    B_rows = np.empty((rows.size, n_mo, n_aux))
+    pos = {int(n): r for r, n in enumerate(rows)}
+    for r, n in enumerate(rows):
+        n = int(n)
+        own = _rng(seed, 2 + r).standard_normal((n_mo, n_aux)) * std
+        for m in range(n_mo):
+            if (n < n_occ) != (m < n_occ):           # occupied-virtual pair: from B_ov
+                i, a = (n, m - n_occ) if n < n_occ else (m, n - n_occ)
+                B_rows[r, m] = Bv[:, i, a]
+            elif m in pos and m < n:                  # mirror of an earlier requested row
+                B_rows[r, m] = B_rows[pos[m], n]
+            else:
+                B_rows[r, m] = own[m]
+    return Inputs(shape=shape, seed=seed, eps=eps, B_ov=B_ov, row_ids=rows, B_rows=B_rows)
+
+
 def full_B(inp_shape: Shape, seed: int, b_scale: float = 1.0) -> np.ndarray:
     """Full symmetric B [N_aux][n_mo][n_mo] (small shapes only)."""
     n_mo = inp_shape.n_mo
@@ -222,3 +252,9 @@ def serving_stream(n_requests: int = 512, k_max: int = 24, seed: int = 5000,
         out.append({"id": i, "k": int(ks[i]), "seed": 1000 + i, "arrival_s": float(t[i]),
                     "shape": shape, "states": _homo_lumo_window(shape, 2, 2)})
     return out
+
+
+def serving_inputs(k: int, seed: int) -> Inputs:
+    """Inputs of one serving request: a (H2O)_k cluster asking for HOMO-2..LUMO+2."""
+    shape = cluster_shape(k)
+    return make_inputs_blocked(shape, seed, _homo_lumo_window(shape, 2, 2))

@@ -71,6 +71,8 @@ typedef struct gw_opts {
   size_t mem_budget_bytes;  /* cap on device memory of this context (0: no cap) */
   size_t work_budget_bytes; /* cap on the stage-A workspace (0: 16 GiB); grid points
                                are factored in chunks that fit */
+  int minres_batch;         /* residue systems per MINRES batch, >= 64 (0: 256); bounds
+                               the MINRES workspace */
 } gw_opts;
 
 /* Imaginary-frequency quadrature: nodes xi[n] > 0 and d-xi weights w[n]
@@ -124,6 +126,14 @@ const char* gw_last_error(void);
  * cached W^c table.  GW_EINVAL for an unknown value. */
 int gw_set_pi_prec(gw_ctx* ctx, int pi_prec);
 
+/* Device memory (bytes requested from the allocator) that a context of
+ * these sizes uses over gw_setup plus gw_qp of up to n_states states on a
+ * grid of grid_n points with these options (NULL: defaults).  Setting
+ * opts->mem_budget_bytes to this value never makes such a context fail
+ * with GW_ENOMEM.  Returns 0 for invalid sizes. */
+size_t gw_footprint(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, int grid_n,
+                    const gw_opts* opts);
+
 /* Drop the cached W^c table: the next gw_qp / gw_sigma / gw_wtable call
  * rebuilds it (Pi build, Cholesky, reduction) from the resident inputs. */
 int gw_reset_cache(gw_ctx* ctx);
@@ -169,6 +179,73 @@ typedef struct gw_timing {
   int qp_rounds, minres_iters, minres_systems, fallback_systems, wtab_cached;
 } gw_timing;
 int gw_get_timing(gw_ctx* ctx, gw_timing* out);
+
+/* ---- serving ------------------------------------------------------------
+ * A request server for molecules of uneven size arriving over time (not in
+ * the paper, whose runs are one molecule per job).  gw_server_submit copies
+ * the request and returns at once.  Requests are admitted first come, first
+ * served when a pipeline slot is free and their device-memory footprint
+ * (gw_footprint) fits in the remaining budget; each admitted request keeps
+ * its inputs, W^c table and workspaces resident until it completes, and its
+ * context may not allocate past its reserved footprint.  Up to n_streams
+ * requests run at once, each on its own HIP stream, so the work of requests
+ * admitted while others are on the GPU overlaps with theirs.  Every request
+ * runs exactly the gw_qp path.  The server is internally synchronised. */
+typedef struct gw_server gw_server;
+
+typedef struct gw_server_opts {
+  int pi_prec, minres_max_iter, qp_max_iter;  /* as in gw_opts (0: defaults) */
+  double minres_rtol, qp_tol;                 /* as in gw_opts (0: defaults) */
+  int grid_n;                                 /* imaginary grid shared by all requests */
+  const double* grid_xi;                      /* [grid_n], copied */
+  const double* grid_w;                       /* [grid_n], copied */
+  size_t mem_budget_bytes;  /* admission budget; 0: 80% of free device memory */
+  int n_streams;            /* concurrent request pipelines, 1..4 (0: 2) */
+  size_t work_budget_bytes; /* stage-A workspace cap per request (0: 2 GiB) */
+} gw_server_opts;
+
+typedef struct gw_request {
+  int n_mo, n_occ, n_aux;
+  const double* eps;      /* [n_mo] */
+  const double* B_ov;     /* [n_aux][n_occ*n_virt] */
+  int n_rows;
+  const int* row_ids;     /* [n_rows] */
+  const double* B_rows;   /* [n_rows][n_mo][n_aux] */
+  int n_states;
+  const int* states;      /* [n_states], each among row_ids */
+  const double* dsig_x;   /* [n_mo] or NULL */
+} gw_request;
+
+typedef struct gw_request_info {
+  int rc;                 /* 0, or the GW_E* code the request failed with */
+  size_t footprint_bytes; /* reserved device memory while resident */
+  double t_submit, t_admit, t_done;  /* seconds on the server clock */
+  int slot;               /* pipeline (stream) that ran it */
+} gw_request_info;
+
+typedef struct gw_server_stats {
+  unsigned long long submitted, completed, failed;
+  size_t budget_bytes, reserved_bytes, peak_reserved_bytes;
+  int active, peak_active;
+} gw_server_stats;
+
+/* GW_EINVAL for bad options, GW_EDEVICE if no device or stream is usable. */
+int gw_server_create(gw_server** s, const gw_server_opts* opts);
+/* Copies the request; *ticket identifies it.  GW_EINVAL for a malformed
+ * request, GW_ENOMEM if its footprint exceeds the whole budget. */
+int gw_server_submit(gw_server* s, const gw_request* r, unsigned long long* ticket);
+/* 1 while pending or running; 0 when done: E_qp, sigma_c, Z, status
+ * ([n_states] each, each nullable) and info (nullable) are filled and the
+ * ticket is released.  A request that failed returns 0 with info->rc < 0. */
+int gw_server_poll(gw_server* s, unsigned long long ticket, double* E_qp, double* sigma_c,
+                   double* Z, int* status, gw_request_info* info);
+/* Blocks until every submitted request has finished. */
+int gw_server_drain(gw_server* s);
+int gw_server_get_stats(gw_server* s, gw_server_stats* out);
+/* Seconds since the server was created (the clock of gw_request_info). */
+double gw_server_clock(gw_server* s);
+/* Drains, stops the pipelines and frees everything. */
+void gw_server_destroy(gw_server* s);
 
 #ifdef __cplusplus
 }

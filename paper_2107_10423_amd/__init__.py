@@ -32,7 +32,8 @@ class _Opts(ctypes.Structure):
     _fields_ = [("pi_prec", ctypes.c_int), ("minres_max_iter", ctypes.c_int),
                 ("minres_rtol", ctypes.c_double), ("qp_tol", ctypes.c_double),
                 ("qp_max_iter", ctypes.c_int), ("dsig_x", _dp), ("stream", ctypes.c_void_p),
-                ("mem_budget_bytes", ctypes.c_size_t), ("work_budget_bytes", ctypes.c_size_t)]
+                ("mem_budget_bytes", ctypes.c_size_t), ("work_budget_bytes", ctypes.c_size_t),
+                ("minres_batch", ctypes.c_int)]
 
 
 class _Grid(ctypes.Structure):
@@ -46,6 +47,39 @@ class Timing(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("qp_rounds", ctypes.c_int),
                 ("minres_iters", ctypes.c_int), ("minres_systems", ctypes.c_int),
                 ("fallback_systems", ctypes.c_int), ("wtab_cached", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class _ServerOpts(ctypes.Structure):
+    _fields_ = [("pi_prec", ctypes.c_int), ("minres_max_iter", ctypes.c_int),
+                ("qp_max_iter", ctypes.c_int), ("minres_rtol", ctypes.c_double),
+                ("qp_tol", ctypes.c_double), ("grid_n", ctypes.c_int), ("grid_xi", _dp),
+                ("grid_w", _dp), ("mem_budget_bytes", ctypes.c_size_t),
+                ("n_streams", ctypes.c_int), ("work_budget_bytes", ctypes.c_size_t)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("n_mo", ctypes.c_int), ("n_occ", ctypes.c_int), ("n_aux", ctypes.c_int),
+                ("eps", _dp), ("B_ov", _dp), ("n_rows", ctypes.c_int), ("row_ids", _ip),
+                ("B_rows", _dp), ("n_states", ctypes.c_int), ("states", _ip), ("dsig_x", _dp)]
+
+
+class RequestInfo(ctypes.Structure):
+    _fields_ = [("rc", ctypes.c_int), ("footprint_bytes", ctypes.c_size_t),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("slot", ctypes.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_ulonglong), ("completed", ctypes.c_ulonglong),
+                ("failed", ctypes.c_ulonglong), ("budget_bytes", ctypes.c_size_t),
+                ("reserved_bytes", ctypes.c_size_t), ("peak_reserved_bytes", ctypes.c_size_t),
+                ("active", ctypes.c_int), ("peak_active", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -68,6 +102,16 @@ _sig = {
                                    _dp, _ip]),
     "gw_get_timing": (ctypes.c_int, [_ctxp, ctypes.POINTER(Timing)]),
     "gw_reset_cache": (ctypes.c_int, [_ctxp]),
+    "gw_footprint": (ctypes.c_size_t, [ctypes.c_int] * 6 + [ctypes.POINTER(_Opts)]),
+    "gw_server_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(_ServerOpts)]),
+    "gw_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(_Request),
+                                        ctypes.POINTER(ctypes.c_ulonglong)]),
+    "gw_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_ulonglong, _dp, _dp, _dp, _ip,
+                                      ctypes.POINTER(RequestInfo)]),
+    "gw_server_drain": (ctypes.c_int, [ctypes.c_void_p]),
+    "gw_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "gw_server_clock": (ctypes.c_double, [ctypes.c_void_p]),
+    "gw_server_destroy": (None, [ctypes.c_void_p]),
     "gw_audit_enable": (ctypes.c_int, []),
     "gw_audit_launch_count": (ctypes.c_long, []),
 }
@@ -133,7 +177,7 @@ class Context:
 
     def __init__(self, eps, n_occ, B_ov, row_ids, B_rows, pi_prec="fp64", minres_max_iter=0,
                  minres_rtol=0.0, qp_tol=0.0, qp_max_iter=0, dsig_x=None, stream=None,
-                 mem_budget_bytes=0, work_budget_bytes=0):
+                 mem_budget_bytes=0, work_budget_bytes=0, minres_batch=0):
         eps = _d(eps)
         B_ov = _d(B_ov)
         rows = _i(row_ids)
@@ -148,7 +192,7 @@ class Context:
         o = _Opts(PREC[pi_prec] if isinstance(pi_prec, str) else int(pi_prec),
                   int(minres_max_iter), float(minres_rtol), float(qp_tol), int(qp_max_iter),
                   _pd(self._dsx), ctypes.c_void_p(stream) if stream else None,
-                  int(mem_budget_bytes), int(work_budget_bytes))
+                  int(mem_budget_bytes), int(work_budget_bytes), int(minres_batch))
         h = _ctxp()
         _check(_lib.gw_setup(ctypes.byref(h), n_mo, int(n_occ), n_aux, _pd(eps), _pd(B_ov),
                              rows.size, _pi(rows), _pd(B_rows), ctypes.byref(o)))
@@ -232,6 +276,80 @@ class Context:
 
 
 GW_EAUDIT = -5
+
+
+def footprint(n_mo, n_occ, n_aux, n_rows, n_states, grid_n, pi_prec="fp64", work_budget_bytes=0,
+              minres_batch=0):
+    """gw_footprint: device bytes a context of these sizes uses."""
+    o = _Opts(PREC[pi_prec] if isinstance(pi_prec, str) else int(pi_prec), 0, 0.0, 0.0, 0, None,
+              None, 0, int(work_budget_bytes), int(minres_batch))
+    return int(_lib.gw_footprint(n_mo, n_occ, n_aux, n_rows, n_states, grid_n, ctypes.byref(o)))
+
+
+class Server:
+    """Request server (gw_server_*): submit molecules, poll results."""
+
+    def __init__(self, grid, pi_prec="fp64", mem_budget_bytes=0, n_streams=0,
+                 work_budget_bytes=0, qp_tol=0.0, minres_rtol=0.0):
+        self._grid = grid
+        o = _ServerOpts(PREC[pi_prec] if isinstance(pi_prec, str) else int(pi_prec), 0, 0,
+                        float(minres_rtol), float(qp_tol), grid.n, _pd(grid.xi), _pd(grid.w),
+                        int(mem_budget_bytes), int(n_streams), int(work_budget_bytes))
+        h = ctypes.c_void_p()
+        _check(_lib.gw_server_create(ctypes.byref(h), ctypes.byref(o)))
+        self._h = h
+        self._n = {}
+
+    def submit(self, eps, n_occ, B_ov, row_ids, B_rows, states, dsig_x=None):
+        eps, B_ov, rows, B_rows, st = _d(eps), _d(B_ov), _i(row_ids), _d(B_rows), _i(states)
+        dsx = _d(dsig_x) if dsig_x is not None else None
+        q = _Request(eps.size, int(n_occ), B_ov.shape[0], _pd(eps), _pd(B_ov), rows.size,
+                     _pi(rows), _pd(B_rows), st.size, _pi(st), _pd(dsx))
+        t = ctypes.c_ulonglong()
+        _check(_lib.gw_server_submit(self._h, ctypes.byref(q), ctypes.byref(t)))
+        self._n[t.value] = st.size
+        return t.value
+
+    def submit_inputs(self, inp, states):
+        return self.submit(inp.eps, inp.n_occ, inp.B_ov, inp.row_ids, inp.B_rows, states)
+
+    def poll(self, ticket):
+        """None while pending, else (E, sigma_c, Z, status, info dict)."""
+        n = self._n[ticket]
+        E, S, Z = np.empty(n), np.empty(n), np.empty(n)
+        st = np.empty(n, dtype=np.int32)
+        info = RequestInfo()
+        rc = _lib.gw_server_poll(self._h, ticket, _pd(E), _pd(S), _pd(Z), _pi(st),
+                                 ctypes.byref(info))
+        if rc == 1:
+            return None
+        _check(rc)
+        del self._n[ticket]
+        return E, S, Z, st, info.as_dict()
+
+    def drain(self):
+        _check(_lib.gw_server_drain(self._h))
+
+    def stats(self):
+        s = ServerStats()
+        _check(_lib.gw_server_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+    def clock(self):
+        return float(_lib.gw_server_clock(self._h))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.gw_server_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def audit_enable():

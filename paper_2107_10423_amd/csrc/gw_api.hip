@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -25,7 +26,7 @@ using namespace gw;
 namespace {
 
 thread_local std::string g_err;
-bool g_contexts_created = false;
+std::atomic<bool> g_contexts_created{false};
 
 // Host-side trace of every stage, to stderr, when GW_TRACE is set.
 bool trace_on() {
@@ -162,6 +163,7 @@ struct gw_ctx {
   double minres_rtol = 1e-12;
   double qp_tol = 1e-10;
   int qp_max_iter = 100;
+  int minres_batch = 256;     // systems per MINRES batch (bounds the workspace)
   size_t mem_budget = 0, work_budget = 16ull << 30;
   size_t mem_used = 0;
   // host copies
@@ -608,9 +610,39 @@ int backproject_pass(gw_ctx* c, int kp) {
 
 // Solve all systems; fills wc, dwc (host) and iteration counts (negative if
 // not converged by MINRES; fallback marks them solved when enabled).
+int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fallback,
+                         std::vector<double>& wc, std::vector<double>& dwc, std::vector<int>& iters,
+                         std::vector<double>* x_out);
+
+// Systems are solved in batches of at most minres_batch, which bounds the
+// MINRES workspace of a context.
 int solve_residues(gw_ctx* c, const std::vector<System>& sys, bool use_fallback,
                    std::vector<double>& wc, std::vector<double>& dwc, std::vector<int>& iters,
                    std::vector<double>* x_out = nullptr) {
+  const int k = (int)sys.size();
+  const int cap = c->minres_batch;
+  if (k <= cap) return solve_residues_batch(c, sys, use_fallback, wc, dwc, iters, x_out);
+  wc.assign(k, 0.0);
+  dwc.assign(k, 0.0);
+  iters.assign(k, 0);
+  if (x_out) x_out->assign((size_t)k * c->n_aux, 0.0);
+  for (int j0 = 0; j0 < k; j0 += cap) {
+    const int j1 = std::min(k, j0 + cap);
+    std::vector<System> part(sys.begin() + j0, sys.begin() + j1);
+    std::vector<double> a, b, xs;
+    std::vector<int> it;
+    RCHK(solve_residues_batch(c, part, use_fallback, a, b, it, x_out ? &xs : nullptr));
+    std::copy(a.begin(), a.end(), wc.begin() + j0);
+    std::copy(b.begin(), b.end(), dwc.begin() + j0);
+    std::copy(it.begin(), it.end(), iters.begin() + j0);
+    if (x_out) std::copy(xs.begin(), xs.end(), x_out->begin() + (size_t)j0 * c->n_aux);
+  }
+  return 0;
+}
+
+int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fallback,
+                         std::vector<double>& wc, std::vector<double>& dwc, std::vector<int>& iters,
+                         std::vector<double>* x_out) {
   const int k = (int)sys.size();
   wc.assign(k, 0.0);
   dwc.assign(k, 0.0);
@@ -923,6 +955,46 @@ int validate_states(gw_ctx* c, int n, const int* states) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Device-memory footprint of one context over gw_setup + gw_qp, mirroring
+// every allocation above (requested bytes).  n_states bounds the number of
+// residue systems per Sigma evaluation (n_states * n_mo, in batches of at
+// most minres_batch).
+size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, int G,
+                       int pi_prec, size_t work_budget, int minres_batch) {
+  const size_t d = sizeof(double);
+  const int Np = round_up(n_aux, 128);
+  const int Kov = n_occ * (n_mo - n_occ);
+  const int Kp = round_up(Kov, 128);
+  const int nR = n_rows * n_mo;
+  const int Rp = round_up(std::max(nR, 1), 128);
+  size_t b = 0;
+  b += (size_t)n_mo * d + (size_t)Kp * d + (size_t)Np * Kp * d + (size_t)Rp * Np * d +
+       (size_t)Rp * d;
+  if (pi_prec != GW_PI_FP64) b += (size_t)Np * Kp * (4 + 2 + 2);
+  // stage A
+  const size_t per_g = (size_t)(2L * Np + 128) * (Np + 128);
+  const size_t parts = (size_t)(Np / 128) * Rp;
+  const size_t per_bytes = per_g * d + (size_t)Kp * d + 64 * 64 * d + parts * d;
+  int chunk = (int)std::max<size_t>(1, work_budget / per_bytes);
+  if (chunk > G) chunk = G;
+  b += (size_t)chunk * (per_g * d + parts * d + 64 * 64 * d + sizeof(int) + (size_t)Kp * d);
+  b += 2 * (size_t)G * d + (size_t)std::max(nR, 1) * G * d;
+  // Sigma evaluation buffers
+  b += (size_t)n_states * (sizeof(int) + 3 * d);
+  // MINRES workspace for the largest batch
+  const int kmax = std::min(std::max(n_states, 1) * n_mo, minres_batch);
+  const int kp = round_up(kmax, 64);
+  const int tiles = (kp / 64) * (Np / 128);
+  const int splitk = std::max(1, std::min(1024 / std::max(tiles, 1), Kp / 256));
+  const size_t part = std::max((size_t)splitk * kp * Np, (size_t)(Kp / 64) * kp);
+  b += 7 * (size_t)kp * Np * d + (size_t)kp * 16 * d + (size_t)kp * Kp * d + part * d +
+       (size_t)kp * (d + sizeof(int) + 2 * d + sizeof(int)) + sizeof(int);
+  // dense fallback
+  b += (size_t)Np * Np * d + (size_t)Kp * d + (size_t)Np * d + sizeof(int);
+  return b;
+}
+
 // ===========================================================================
 // C-ABI
 
@@ -1016,6 +1088,7 @@ int gw_setup(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps, co
   if (o.qp_max_iter > 0) c->qp_max_iter = o.qp_max_iter;
   c->mem_budget = o.mem_budget_bytes;
   if (o.work_budget_bytes > 0) c->work_budget = o.work_budget_bytes;
+  if (o.minres_batch > 0) c->minres_batch = std::max(64, o.minres_batch);
   c->eps.assign(eps, eps + n_mo);
   c->dsig_x.assign(n_mo, 0.0);
   if (o.dsig_x) {
@@ -1094,6 +1167,16 @@ int gw_set_pi_prec(gw_ctx* c, int prec) {
   if (prec != c->pi_prec) c->wtab_valid = false;
   c->pi_prec = prec;
   return 0;
+}
+
+size_t gw_footprint(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, int grid_n,
+                    const gw_opts* opts) {
+  gw_opts o{};
+  if (opts) o = *opts;
+  const size_t wb = o.work_budget_bytes ? o.work_budget_bytes : (16ull << 30);
+  const int mb = o.minres_batch > 0 ? std::max(64, o.minres_batch) : 256;
+  if (n_mo < 2 || n_occ < 1 || n_occ >= n_mo || n_aux < 1 || n_rows < 0 || grid_n < 1) return 0;
+  return footprint_bytes(n_mo, n_occ, n_aux, n_rows, n_states, grid_n, o.pi_prec, wb, mb);
 }
 
 int gw_reset_cache(gw_ctx* c) {
