@@ -210,6 +210,8 @@ def main():
     ap.add_argument("--requests", type=int, default=128)
     ap.add_argument("--kmax", type=int, default=24)
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -223,6 +225,14 @@ def main():
         sys.exit(1)
     if args.serve:
         serve_bench(args)
+        return
+    if args.copy_calibration:
+        x = torch.ones(2**27, dtype=torch.float64, device="cuda")     # 1 GiB
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": x.numel() * 8}))
         return
     import gwgen
     import paper_2107_10423_amd as gwl

@@ -35,6 +35,11 @@ __device__ __forceinline__ void decode_tile(const GemmArgs& p, int tile, int& I,
     J = tile % p.tiles_n;
     return;
   }
+  if (p.map == MAP_FULL_J) {
+    I = tile % p.tiles_m;
+    J = tile / p.tiles_m;
+    return;
+  }
   // lower map: row tile I holds columns J <= ((I+1)*BM - 1) / BN
   int acc = 0;
   for (I = 0; I < p.tiles_m; ++I) {
@@ -85,7 +90,8 @@ struct Stager {
         Xs[k + 1][row] = v[u].y;
       } else {
         int k = q / (BR / 2), rp = (q % (BR / 2)) * 2;
-        *reinterpret_cast<double2*>(&Xs[k][rp]) = v[u];
+        Xs[k][rp] = v[u].x;
+        Xs[k][rp + 1] = v[u].y;
       }
     }
   }
@@ -265,7 +271,7 @@ static hipError_t check_gemm(const GemmArgs& a, int tile_kind, int la, int lb, i
   if (a.K <= 0 || a.K % BK != 0 || a.tiles_m <= 0 || a.tiles_n <= 0 || a.batch <= 0 ||
       a.splitk <= 0 || a.row0 < 0 || a.col0 < 0 || a.k0 < 0 || a.kb0 < 0)
     return refuse(kn, "shape");
-  long want = a.map == MAP_FULL ? (long)a.tiles_m * a.tiles_n : 0;
+  long want = (a.map == MAP_FULL || a.map == MAP_FULL_J) ? (long)a.tiles_m * a.tiles_n : 0;
   if (a.map == MAP_LOWER)
     for (int I = 0; I < a.tiles_m; ++I) {
       int c = ((I + 1) * BM - 1) / BN + 1;
@@ -324,9 +330,10 @@ hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, h
   // MINRES: part[s][sys][P] = sum_ia V[sys][ia] B_ov[P][ia], split-K partials, 64 x 128 tiles
   if (tile_kind == 2 && la == KC && lb == KC && epi == EPI_STORE && !scaled)
     return launch<1, 4, 2, KC, KC, EPI_STORE, false, false>(a, st);
-  // W^c reduction: |R^T Linv^T|^2 per row, Linv^T k-major, triangular k range
+  // W^c reduction: |R^T Linv^T|^2 per row, Linv^T k-major, triangular k range;
+  // grid point slowest so that the tiles reading one L^-T panel run together
   if (tile_kind == 0 && la == KC && lb == KM && epi == EPI_SQNORM && !scaled)
-    return launch<2, 4, 4, KC, KM, EPI_SQNORM, false, true>(a, st);
+    return launch<2, 4, 4, KC, KM, EPI_SQNORM, false, false>(a, st);
   // generic full 128x128 store / axpby (tests, dense fallback build)
   if (tile_kind == 0 && la == KC && lb == KC && epi == EPI_STORE && scaled)
     return launch<2, 4, 4, KC, KC, EPI_STORE, true, false>(a, st);

@@ -213,6 +213,9 @@ struct gw_ctx {
   int mr_splitk = 1;
   size_t part_cap = 0;  // doubles
   int* d_rhs_idx = nullptr;
+  int* d_warm = nullptr;       // [kp] 1 when the system starts from the cached solution
+  double* d_xcache = nullptr;  // [Rp][Np] last solution of each right-hand side row
+  std::vector<char> xvalid;    // host flags: d_xcache row holds a solution of this call
   double* d_wc = nullptr;
   double* d_dwc = nullptr;
   int* d_conv = nullptr;
@@ -527,7 +530,7 @@ int build_wtable(gw_ctx* c, const gw_grid* grid, int mode = 0, double* dbg_out =
       a.B = c->d_work + (long)c->Np * ldA; a.ldb = ldA; a.sB = per_g;
       a.C = c->d_parts; a.ldc = parts_ld(c); a.sC = parts_per_g(c);
       a.M = c->Rp; a.N = c->Np; a.K = c->Np;
-      a.map = MAP_FULL; a.tiles_m = c->Rp / 128; a.tiles_n = c->Np / 128;
+      a.map = MAP_FULL_J; a.tiles_m = c->Rp / 128; a.tiles_n = c->Np / 128;
       a.n_tiles = a.tiles_m * a.tiles_n; a.batch = Gc; a.splitk = 1; a.ktri = 1;
       RCHK(run_gemm(c, a, 0, KC, KM, EPI_SQNORM));
       HIPCHK(wc_from_parts(c->d_parts, parts_per_g(c), c->Np / 128, parts_ld(c), c->d_bn, c->nR,
@@ -555,11 +558,11 @@ int build_wtable(gw_ctx* c, const gw_grid* grid, int mode = 0, double* dbg_out =
 int ensure_minres(gw_ctx* c, int kp) {
   if (kp <= c->mr_cap) return 0;
   MinresBufs& m = c->mr;
-  void* olds[] = {m.x, m.w, m.w2, m.r1, m.r2, m.y, m.v, m.scal, m.V, m.part, m.omega, m.active,
-                  c->d_rhs_idx, c->d_wc, c->d_dwc, c->d_conv};
+  void* olds[] = {m.x, m.w, m.w2, m.r1, m.r2, m.y, m.v, m.x0, m.scal, m.V, m.part, m.omega,
+                  m.active, c->d_rhs_idx, c->d_warm, c->d_wc, c->d_dwc, c->d_conv};
   for (void* p : olds) c->release(p);
   const size_t vec = (size_t)kp * c->Np;
-  double** vecs[] = {&m.x, &m.w, &m.w2, &m.r1, &m.r2, &m.y, &m.v};
+  double** vecs[] = {&m.x, &m.w, &m.w2, &m.r1, &m.r2, &m.y, &m.v, &m.x0};
   for (double** p : vecs) RCHK(c->alloc((void**)p, vec * sizeof(double)));
   RCHK(c->alloc((void**)&m.scal, (size_t)kp * 16 * sizeof(double)));
   RCHK(c->alloc((void**)&m.V, (size_t)kp * c->Kp * sizeof(double)));
@@ -573,6 +576,7 @@ int ensure_minres(gw_ctx* c, int kp) {
   RCHK(c->alloc((void**)&m.omega, (size_t)kp * sizeof(double)));
   RCHK(c->alloc((void**)&m.active, sizeof(int)));
   RCHK(c->alloc((void**)&c->d_rhs_idx, (size_t)kp * sizeof(int)));
+  RCHK(c->alloc((void**)&c->d_warm, (size_t)kp * sizeof(int)));
   RCHK(c->alloc((void**)&c->d_wc, (size_t)kp * sizeof(double)));
   RCHK(c->alloc((void**)&c->d_dwc, (size_t)kp * sizeof(double)));
   RCHK(c->alloc((void**)&c->d_conv, (size_t)kp * sizeof(int)));
@@ -653,7 +657,7 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   MinresBufs& m = c->mr;
   m.k = k; m.kp = kp; m.Np = c->Np; m.Kp = c->Kp;
   m.n_vec = std::min({c->ext(m.x, 8), c->ext(m.w, 8), c->ext(m.w2, 8), c->ext(m.r1, 8),
-                      c->ext(m.r2, 8), c->ext(m.y, 8), c->ext(m.v, 8)});
+                      c->ext(m.r2, 8), c->ext(m.y, 8), c->ext(m.v, 8), c->ext(m.x0, 8)});
   m.n_scal = c->ext(m.scal, 8);
   m.n_part = c->ext(m.part, 8);
   m.n_V = c->ext(m.V, 8);
@@ -669,7 +673,29 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   HIPCHK(rt_memcpy(c->d_rhs_idx, idx.data(), kp * sizeof(int), hipMemcpyHostToDevice, c->st));
   HIPCHK(rt_memcpy(m.omega, om.data(), kp * sizeof(double), hipMemcpyHostToDevice, c->st));
   trace("minres k=%d kp=%d splitk=%d", k, kp, c->mr_splitk);
-  HIPCHK(minres_init(m, c->d_R, c->d_rhs_idx, idx.data(), c->Rp, c->st));
+  // warm start: a right-hand side solved earlier in this call starts from that
+  // solution; one operator pass gives A x0 for the start vector b - A x0
+  if (!c->d_xcache) {
+    RCHK(c->alloc((void**)&c->d_xcache, (size_t)c->Rp * c->Np * sizeof(double)));
+    c->xvalid.assign(c->Rp, 0);
+  }
+  std::vector<int> warm(kp, 0);
+  int n_warm = 0;
+  for (int j = 0; j < k; ++j)
+    if (c->xvalid[idx[j]]) {
+      warm[j] = 1;
+      n_warm++;
+    }
+  const long n_cache = c->ext(c->d_xcache, 8);
+  HIPCHK(rt_memcpy(c->d_warm, warm.data(), kp * sizeof(int), hipMemcpyHostToDevice, c->st));
+  HIPCHK(minres_gather(m, c->d_xcache, c->d_rhs_idx, idx.data(), c->Rp, c->d_warm, n_cache,
+                       c->st));
+  if (n_warm > 0) {
+    RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp));
+    RCHK(backproject_pass(c, kp));
+    HIPCHK(minres_apply(m, c->mr_splitk, c->st));
+  }
+  HIPCHK(minres_init(m, c->d_R, c->d_rhs_idx, idx.data(), c->Rp, n_warm > 0, c->st));
   int active = k;
   int itn = 0;
   // convergence is polled (one 4-byte copy and a stream sync) every `poll`
@@ -689,6 +715,9 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   }
   c->timing.minres_iters += std::min(itn, c->minres_max_iter);
   c->timing.minres_systems += k;
+  // x = x0 + correction; remember it for later solves of the same right-hand side
+  HIPCHK(minres_finalize(m, c->d_xcache, c->d_rhs_idx, idx.data(), c->Rp, n_cache, c->st));
+  for (int j = 0; j < k; ++j) c->xvalid[idx[j]] = 1;
   // derivative partials: sum over ia of (B^T x)^2 * 2 D w/(D^2 - w^2)^2
   const int nparts = c->Kp / 64;
   RCHK(matvec_pass(c, m.x, kp, EPI_RES_DERIV, m.part, kp));
@@ -733,6 +762,8 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
                          c->ext(c->d_db, 8), c->st));
       HIPCHK(copy_vec(c->d_db, m.x + (long)j * c->Np, c->Np, c->ext(c->d_db, 8),
                       c->ext(m.x + (long)j * c->Np, 8), c->st));
+      HIPCHK(copy_vec(c->d_db, c->d_xcache + (long)sys[j].q * c->Np, c->Np, c->ext(c->d_db, 8),
+                      c->ext(c->d_xcache + (long)sys[j].q * c->Np, 8), c->st));
       int dinfo = 0;
       HIPCHK(rt_memcpy(&dinfo, c->d_dinfo, sizeof(int), hipMemcpyDeviceToHost, c->st));
       HIPCHK(rt_sync(c->st));
@@ -940,6 +971,10 @@ void qp_step(gw_ctx* c, QPState& q, double sigma, double dsigma) {
 
 // Result-returning entry points end here: in launch-audit mode nothing was
 // computed, so they report GW_EAUDIT instead of success.
+// A public call starts without remembered residue solutions, so its results
+// do not depend on earlier calls.
+void forget_solutions(gw_ctx* c) { std::fill(c->xvalid.begin(), c->xvalid.end(), 0); }
+
 int finish() {
   if (audit_mode()) return fail(GW_EAUDIT, "launch audit: every launch was checked, none was run");
   return 0;
@@ -988,8 +1023,9 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   const int tiles = (kp / 64) * (Np / 128);
   const int splitk = std::max(1, std::min(1024 / std::max(tiles, 1), Kp / 256));
   const size_t part = std::max((size_t)splitk * kp * Np, (size_t)(Kp / 64) * kp);
-  b += 7 * (size_t)kp * Np * d + (size_t)kp * 16 * d + (size_t)kp * Kp * d + part * d +
-       (size_t)kp * (d + sizeof(int) + 2 * d + sizeof(int)) + sizeof(int);
+  b += 8 * (size_t)kp * Np * d + (size_t)kp * 16 * d + (size_t)kp * Kp * d + part * d +
+       (size_t)kp * (d + 2 * sizeof(int) + 2 * d + sizeof(int)) + sizeof(int);
+  b += (size_t)Rp * Np * d;  // remembered residue solutions
   // dense fallback
   b += (size_t)Np * Np * d + (size_t)Kp * d + (size_t)Np * d + sizeof(int);
   return b;
@@ -1226,6 +1262,7 @@ int gw_sigma(gw_ctx* c, int n, const int* states, const double* omega, const gw_
   RCHK(validate_states(c, n, states));
   for (int j = 0; j < n; ++j)
     if (!std::isfinite(omega[j])) return fail(GW_EINVAL, "omega[%d] is not finite", j);
+  forget_solutions(c);
   c->timing = gw_timing{};
   RCHK(build_wtable(c, grid, 0));
   std::vector<int> st(states, states + n), nres, flags;
@@ -1249,6 +1286,7 @@ int gw_residues(gw_ctx* c, int k, const int* states, const int* m, const double*
       return fail(GW_EINVAL, "bad system %d", j);
     sys[j] = System{c->row_of[states[j]] * c->n_mo + m[j], w[j]};
   }
+  forget_solutions(c);
   c->timing = gw_timing{};
   std::vector<double> a, b, xs;
   std::vector<int> it;
@@ -1267,6 +1305,7 @@ int gw_qp(gw_ctx* c, int n_states, const int* states, const gw_grid* grid, doubl
   if (!c || n_states < 0 || (n_states > 0 && (!E_qp || !sigma_c || !Z)))
     return fail(GW_EINVAL, "bad arguments");
   RCHK(validate_states(c, n_states, states));
+  forget_solutions(c);
   c->timing = gw_timing{};
   Timer total;
   total.a = c->ev0b;

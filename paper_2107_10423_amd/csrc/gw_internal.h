@@ -48,7 +48,8 @@ enum Epilogue {
 };
 
 enum TileMap {
-  MAP_FULL = 0,   // every (I, J) tile
+  MAP_FULL = 0,   // every (I, J) tile, row tiles outer
+  MAP_FULL_J = 2, // every (I, J) tile, column tiles outer (tiles sharing a B panel adjacent)
   MAP_LOWER = 1,  // tiles holding some element with row >= col (both offset by `diag_off`)
 };
 
@@ -122,14 +123,23 @@ struct MinresBufs {
   double *scal;            // [kp][16] per-system scalars
   double *V;               // [kp][Kp] scaled B^T v
   double *part;            // split-K partials [splitk][kp][Np] (reused for deriv partials)
+  double *x0;              // [kp][Np] starting guesses (0 for a cold start)
   double *omega;           // [kp] real frequencies
   int *active;             // [1] count of unconverged systems
   long n_vec, n_scal, n_part, n_V;   // extents in elements (per array)
 };
 // rhs_idx values must be < n_rhs_rows (rows of rhs_base, each Np long); the host
 // passes the index array it uploaded so the guard can check it
+// x0_j = v_j = warm_j ? xcache[rhs_idx_j] : 0 (then one operator pass gives y = A x0)
+hipError_t minres_gather(MinresBufs& m, const double* xcache, const int* rhs_idx,
+                         const int* host_idx, int n_rows, const int* warm, long n_cache,
+                         hipStream_t st);
+// start MINRES on b - A x0 (use_y: y holds A x0) with the stop test relative to |b|
 hipError_t minres_init(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
-                       const int* host_idx, int n_rhs_rows, hipStream_t st);
+                       const int* host_idx, int n_rhs_rows, int use_y, hipStream_t st);
+// x_j += x0_j, and xcache[rhs_idx_j] = x_j
+hipError_t minres_finalize(MinresBufs& m, double* xcache, const int* rhs_idx,
+                           const int* host_idx, int n_rows, long n_cache, hipStream_t st);
 // y = v + 4 sum_s part[s] (the operator applied to v), one thread per element
 hipError_t minres_apply(MinresBufs& m, int splitk, hipStream_t st);
 hipError_t minres_finish_step(MinresBufs& m, int itn, double rtol, hipStream_t st);

@@ -10,7 +10,10 @@
 
 namespace gw {
 
-enum { S_BETA1 = 0, S_BETA, S_OLDB, S_DBAR, S_EPS, S_PHIBAR, S_CS, S_SN, S_DONE, S_ITERS, S_RATIO };
+enum {
+  S_BETA1 = 0, S_BETA, S_OLDB, S_DBAR, S_EPS, S_PHIBAR, S_CS, S_SN, S_DONE, S_ITERS, S_RATIO,
+  S_BNORM
+};
 
 static hipError_t check_bufs(const MinresBufs& m, const char* kn) {
   if (m.k < 0 || m.k > m.kp || m.kp % 64 != 0) return refuse(kn, "system count");
@@ -29,24 +32,60 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return s;
 }
 
+__global__ void k_minres_gather(MinresBufs m, const double* xcache, const int* rhs_idx,
+                                const int* warm) {
+  const int j = blockIdx.y;
+  const long o = (long)j * m.Np;
+  const bool w = j < m.k && warm[j] != 0;
+  const double* src = w ? xcache + (long)rhs_idx[j] * m.Np : nullptr;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m.Np; p += gridDim.x * blockDim.x) {
+    const double v = w ? src[p] : 0.0;
+    m.x0[o + p] = v;
+    m.v[o + p] = v;
+  }
+}
+
+static hipError_t check_rows(const MinresBufs& m, const char* kn, const int* host_idx, int n_rows,
+                             long n_cache) {
+  for (int j = 0; j < m.k; ++j)
+    if (host_idx[j] < 0 || host_idx[j] >= n_rows) return refuse(kn, "rhs index");
+  GW_GUARD(kn, "xcache", (long)n_rows * m.Np - 1, n_cache);
+  return hipSuccess;
+}
+
+hipError_t minres_gather(MinresBufs& m, const double* xcache, const int* rhs_idx,
+                         const int* host_idx, int n_rows, const int* warm, long n_cache,
+                         hipStream_t st) {
+  if (hipError_t e = check_bufs(m, "minres_gather")) return e;
+  if (hipError_t e = check_rows(m, "minres_gather", host_idx, n_rows, n_cache)) return e;
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_minres_gather, dim3((m.Np + 255) / 256, m.kp), dim3(256), 0, st, m, xcache,
+                     rhs_idx, warm);
+  return hipGetLastError();
+}
+
+// Start vectors: r = b - A x0 when use_y (y = A x0), else r = b.
 __global__ __launch_bounds__(256) void k_minres_init(MinresBufs m, const double* rhs_base,
-                                                     const int* rhs_idx) {
+                                                     const int* rhs_idx, int use_y) {
   __shared__ double red[4];
   const int j = blockIdx.x, t = threadIdx.x;
   const long o = (long)j * m.Np;
   const double* b = (j < m.k) ? rhs_base + (long)rhs_idx[j] * m.Np : nullptr;
-  double s = 0.0;
+  double s = 0.0, sb = 0.0;
   for (int p = t; p < m.Np; p += 256) {
-    double bv = b ? b[p] : 0.0;
-    m.r1[o + p] = bv;
-    m.r2[o + p] = bv;
-    m.y[o + p] = bv;
+    const double bv = b ? b[p] : 0.0;
+    const double rv = use_y ? bv - m.y[o + p] : bv;
+    m.r1[o + p] = rv;
+    m.r2[o + p] = rv;
+    m.y[o + p] = rv;
     m.x[o + p] = 0.0;
     m.w[o + p] = 0.0;
     m.w2[o + p] = 0.0;
-    s += bv * bv;
+    s += rv * rv;
+    sb += bv * bv;
   }
   const double beta1 = sqrt(block_sum(s, red));
+  const double bnorm = sqrt(block_sum(sb, red));
   const double inv = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
   for (int p = t; p < m.Np; p += 256) m.v[o + p] = m.y[o + p] * inv;
   if (t == 0) {
@@ -62,16 +101,40 @@ __global__ __launch_bounds__(256) void k_minres_init(MinresBufs m, const double*
     sc[S_DONE] = (j < m.k && beta1 > 0.0) ? 0.0 : 1.0;
     sc[S_ITERS] = 0.0;
     sc[S_RATIO] = 0.0;
+    sc[S_BNORM] = bnorm;
   }
 }
 
 hipError_t minres_init(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
-                       const int* host_idx, int n_rhs_rows, hipStream_t st) {
+                       const int* host_idx, int n_rhs_rows, int use_y, hipStream_t st) {
   if (hipError_t e = check_bufs(m, "minres_init")) return e;
   for (int j = 0; j < m.k; ++j)
     if (host_idx[j] < 0 || host_idx[j] >= n_rhs_rows) return refuse("minres_init", "rhs index");
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_minres_init, dim3(m.kp), dim3(256), 0, st, m, rhs_base, rhs_idx);
+  hipLaunchKernelGGL(k_minres_init, dim3(m.kp), dim3(256), 0, st, m, rhs_base, rhs_idx, use_y);
+  return hipGetLastError();
+}
+
+__global__ void k_minres_finalize(MinresBufs m, double* xcache, const int* rhs_idx) {
+  const int j = blockIdx.y;
+  if (j >= m.k) return;
+  const long o = (long)j * m.Np;
+  double* dst = xcache + (long)rhs_idx[j] * m.Np;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m.Np; p += gridDim.x * blockDim.x) {
+    const double v = m.x[o + p] + m.x0[o + p];
+    m.x[o + p] = v;
+    dst[p] = v;
+  }
+}
+
+hipError_t minres_finalize(MinresBufs& m, double* xcache, const int* rhs_idx,
+                           const int* host_idx, int n_rows, long n_cache, hipStream_t st) {
+  if (m.k <= 0) return hipSuccess;
+  if (hipError_t e = check_bufs(m, "minres_finalize")) return e;
+  if (hipError_t e = check_rows(m, "minres_finalize", host_idx, n_rows, n_cache)) return e;
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_minres_finalize, dim3((m.Np + 255) / 256, m.k), dim3(256), 0, st, m, xcache,
+                     rhs_idx);
   return hipGetLastError();
 }
 
@@ -145,7 +208,8 @@ __global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int itn, doub
     sc[S_SN] = sn_n;
     sc[S_PHIBAR] = phibar;
     sc[S_ITERS] = (double)itn;
-    const double ratio = phibar / sc[S_BETA1];
+    // residual |b - A x| = phibar (the start vector is b - A x0); stop relative to |b|
+    const double ratio = phibar / sc[S_BNORM];
     sc[S_RATIO] = ratio;
     const bool done = (ratio <= rtol) || (beta_new <= 1e-300);
     if (done) sc[S_DONE] = 1.0;

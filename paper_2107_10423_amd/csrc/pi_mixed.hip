@@ -25,6 +25,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef short s8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int FLUSH_K = 512;
 
@@ -213,6 +216,65 @@ hipError_t pi_build_f32(const float* B32, long ld, const double* scale, long sS,
 constexpr int BKB = 32;
 constexpr int LROW = BKB + 8;  // padded row length in bf16 elements
 
+// Staging of one 32-wide K-step: the unscaled side is loaded pre-split
+// (bf16 hi and lo, 2 x 16 B per thread each); the scaled side is loaded as
+// FP32 (4 x 16 B per thread), multiplied by the grid point's scale and split
+// into hi/lo while it is written to LDS.
+__device__ __forceinline__ void bf_gload(const uint16_t* Bhi, const uint16_t* Blo,
+                                         const float* B32, const double* S, long ld, int ar0,
+                                         int br0, int k0, int t, u32x4 (&rah)[2],
+                                         u32x4 (&ral)[2], f32x4 (&rb)[4]) {
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    int q = t + 256 * u;
+    int row = q >> 2, kq = (q & 3) * 8;
+    rah[u] = *reinterpret_cast<const u32x4*>(Bhi + (long)(ar0 + row) * ld + k0 + kq);
+    ral[u] = *reinterpret_cast<const u32x4*>(Blo + (long)(ar0 + row) * ld + k0 + kq);
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int q = t + 256 * u;
+    int row = q >> 3, kq = (q & 7) * 4;
+    f32x4 v = *reinterpret_cast<const f32x4*>(B32 + (long)(br0 + row) * ld + k0 + kq);
+    double2 s01 = *reinterpret_cast<const double2*>(S + k0 + kq);
+    double2 s23 = *reinterpret_cast<const double2*>(S + k0 + kq + 2);
+    v.x *= (float)s01.x;
+    v.y *= (float)s01.y;
+    v.z *= (float)s23.x;
+    v.w *= (float)s23.y;
+    rb[u] = v;
+  }
+}
+
+__device__ __forceinline__ void bf_lstore(uint16_t* Ah, uint16_t* Al, uint16_t* Bh,
+                                          uint16_t* Bl, int t, const u32x4 (&rah)[2],
+                                          const u32x4 (&ral)[2], const f32x4 (&rb)[4]) {
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    int q = t + 256 * u;
+    int row = q >> 2, kq = (q & 3) * 8;
+    *reinterpret_cast<u32x4*>(&Ah[row * LROW + kq]) = rah[u];
+    *reinterpret_cast<u32x4*>(&Al[row * LROW + kq]) = ral[u];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    int q = t + 256 * u;
+    int row = q >> 3, kq = (q & 7) * 4;
+    const float x0 = rb[u].x, x1 = rb[u].y, x2 = rb[u].z, x3 = rb[u].w;
+    const unsigned short h0 = bf16_rne(x0), h1 = bf16_rne(x1), h2 = bf16_rne(x2),
+                         h3 = bf16_rne(x3);
+    const unsigned short l0 = bf16_rne(x0 - bf16_to_f(h0)), l1 = bf16_rne(x1 - bf16_to_f(h1)),
+                         l2 = bf16_rne(x2 - bf16_to_f(h2)), l3 = bf16_rne(x3 - bf16_to_f(h3));
+    u32x2 hv, lv;
+    hv.x = (unsigned)h0 | ((unsigned)h1 << 16);
+    hv.y = (unsigned)h2 | ((unsigned)h3 << 16);
+    lv.x = (unsigned)l0 | ((unsigned)l1 << 16);
+    lv.y = (unsigned)l2 | ((unsigned)l3 << 16);
+    *reinterpret_cast<u32x2*>(&Bh[row * LROW + kq]) = hv;
+    *reinterpret_cast<u32x2*>(&Bl[row * LROW + kq]) = lv;
+  }
+}
+
 template <bool FLUSH64>
 __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const uint16_t* Blo,
                                                    long ld, const float* B32,
@@ -244,65 +306,15 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
     for (int j = 0; j < (FLUSH64 ? 4 : 1); ++j) acc64[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   // A side: 128 rows x 32 k bf16 = 512 chunks of 8 (16 B) per array -> 2 per thread
   // B side: 128 rows x 32 k fp32 = 1024 float4 -> 4 per thread
-  uint4 rah[2], ral[2];
-  float4 rb[4];
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      int q = t + 256 * u;
-      int row = q >> 2, kq = (q & 3) * 8;
-      rah[u] = *reinterpret_cast<const uint4*>(Bhi + (long)(ar0 + row) * ld + k0 + kq);
-      ral[u] = *reinterpret_cast<const uint4*>(Blo + (long)(ar0 + row) * ld + k0 + kq);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int q = t + 256 * u;
-      int row = q >> 3, kq = (q & 7) * 4;
-      float4 v = *reinterpret_cast<const float4*>(B32 + (long)(br0 + row) * ld + k0 + kq);
-      double2 s01 = *reinterpret_cast<const double2*>(S + k0 + kq);
-      double2 s23 = *reinterpret_cast<const double2*>(S + k0 + kq + 2);
-      v.x *= (float)s01.x;
-      v.y *= (float)s01.y;
-      v.z *= (float)s23.x;
-      v.w *= (float)s23.y;
-      rb[u] = v;
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      int q = t + 256 * u;
-      int row = q >> 2, kq = (q & 3) * 8;
-      *reinterpret_cast<uint4*>(&Ah[buf][row * LROW + kq]) = rah[u];
-      *reinterpret_cast<uint4*>(&Al[buf][row * LROW + kq]) = ral[u];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      int q = t + 256 * u;
-      int row = q >> 3, kq = (q & 7) * 4;
-      float x[4] = {rb[u].x, rb[u].y, rb[u].z, rb[u].w};
-      unsigned short h[4], l[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        h[e] = bf16_rne(x[e]);
-        l[e] = bf16_rne(x[e] - bf16_to_f(h[e]));
-      }
-      uint2 hv, lv;
-      hv.x = (unsigned)h[0] | ((unsigned)h[1] << 16);
-      hv.y = (unsigned)h[2] | ((unsigned)h[3] << 16);
-      lv.x = (unsigned)l[0] | ((unsigned)l[1] << 16);
-      lv.y = (unsigned)l[2] | ((unsigned)l[3] << 16);
-      *reinterpret_cast<uint2*>(&Bh[buf][row * LROW + kq]) = hv;
-      *reinterpret_cast<uint2*>(&Bl[buf][row * LROW + kq]) = lv;
-    }
-  };
+  u32x4 rah[2], ral[2];
+  f32x4 rb[4];
   const int nk = Kp / BKB;
-  gload(0);
-  lstore(0);
+  bf_gload(Bhi, Blo, B32, S, ld, ar0, br0, 0, t, rah, ral, rb);
+  bf_lstore(Ah[0], Al[0], Bh[0], Bl[0], t, rah, ral, rb);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BKB);
+    if (kt + 1 < nk) bf_gload(Bhi, Blo, B32, S, ld, ar0, br0, (kt + 1) * BKB, t, rah, ral, rb);
     // operand fragments: lane l reads row l % 16, k = 8 (l / 16) .. +7
     const int ko = 8 * (lane >> 4);
     s8 ah[4], al[4], bh[4], bl[4];
@@ -339,7 +351,7 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
           acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
         }
     }
-    if (kt + 1 < nk) lstore(cur ^ 1);
+    if (kt + 1 < nk) bf_lstore(Ah[cur ^ 1], Al[cur ^ 1], Bh[cur ^ 1], Bl[cur ^ 1], t, rah, ral, rb);
     __syncthreads();
   }
   double* Ag = A + (long)g * sA;
