@@ -19,7 +19,7 @@ namespace gw {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BK = 16;
+constexpr int BK = 16;   // K-step of the default configurations
 
 __device__ __forceinline__ int xcd_swizzle(int wid, int total) {
   const int nx = 8;
@@ -51,10 +51,10 @@ __device__ __forceinline__ void decode_tile(const GemmArgs& p, int tile, int& I,
   I = p.tiles_m; J = 0;  // unreachable when n_tiles is consistent
 }
 
-template <int BR, int LAYOUT, bool SCALED>
+template <int BR, int LAYOUT, bool SCALED, int KS>
 struct Stager {
-  // number of double2 items per thread for a BR x 16 tile
-  static constexpr int NITEM = BR * BK / 2 / 256;
+  // number of double2 items per thread for a BR x KS tile
+  static constexpr int NITEM = BR * KS / 2 / 256;
   double2 v[NITEM];
   __device__ __forceinline__ void load(const double* X, long ld, int r0, int kk0,
                                        const double* s, int t) {
@@ -62,7 +62,7 @@ struct Stager {
     for (int u = 0; u < NITEM; ++u) {
       int q = t + 256 * u;
       if (LAYOUT == KC) {
-        int row = q / 8, k = (q % 8) * 2;
+        int row = q / (KS / 2), k = (q % (KS / 2)) * 2;
         v[u] = *reinterpret_cast<const double2*>(X + (long)(r0 + row) * ld + kk0 + k);
         if (SCALED) {
           double2 sv = *reinterpret_cast<const double2*>(s + kk0 + k);
@@ -85,7 +85,7 @@ struct Stager {
     for (int u = 0; u < NITEM; ++u) {
       int q = t + 256 * u;
       if (LAYOUT == KC) {
-        int row = q / 8, k = (q % 8) * 2;
+        int row = q / (KS / 2), k = (q % (KS / 2)) * 2;
         Xs[k][row] = v[u].x;
         Xs[k + 1][row] = v[u].y;
       } else {
@@ -97,13 +97,14 @@ struct Stager {
   }
 };
 
-template <int WAVES_M, int TM, int TN, int LA, int LB, int EPI, bool SCALED, bool BATCH_FAST>
+template <int WAVES_M, int TM, int TN, int LA, int LB, int EPI, bool SCALED, bool BATCH_FAST,
+          int KS = BK>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   constexpr int WAVES_N = 4 / WAVES_M;
   constexpr int BM = WAVES_M * TM * 16;
   constexpr int BN = WAVES_N * TN * 16;
-  __shared__ double As[2][BK][BM];
-  __shared__ double Bs[2][BK][BN];
+  __shared__ double As[2][KS][BM];
+  __shared__ double Bs[2][KS][BN];
   __shared__ double red[WAVES_N][BM];
 
   const int t = threadIdx.x;
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   const int arow0 = p.row0 + I * BM;
   const int brow0 = p.col0 + J * BN;
 
-  int kchunk = ((p.K / BK + p.splitk - 1) / p.splitk) * BK;
+  int kchunk = ((p.K / KS + p.splitk - 1) / p.splitk) * KS;
   int kbeg = split * kchunk;
   int kend = kbeg + kchunk;
   if (kend > p.K) kend = p.K;
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
     const int lim = p.col0 + (J + 1) * BN - p.kb0;
     if (kend > lim) kend = lim;
   }
-  const int nk = kend > kbeg ? (kend - kbeg) / BK : 0;
+  const int nk = kend > kbeg ? (kend - kbeg) / KS : 0;
 
   d4 acc[TM][TN];
 #pragma unroll
@@ -149,8 +150,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  Stager<BM, LA, false> sa;
-  Stager<BN, LB, SCALED> sb;
+  Stager<BM, LA, false, KS> sa;
+  Stager<BN, LB, SCALED, KS> sb;
   if (nk > 0) {
     sa.load(A, p.lda, arow0, p.k0 + kbeg, nullptr, t);
     sb.load(Bm, p.ldb, brow0, p.kb0 + kbeg, S, t);
@@ -161,12 +162,12 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      const int kstep = kbeg + (kt + 1) * BK;
+      const int kstep = kbeg + (kt + 1) * KS;
       sa.load(A, p.lda, arow0, p.k0 + kstep, nullptr, t);
       sb.load(Bm, p.ldb, brow0, p.kb0 + kstep, S, t);
     }
 #pragma unroll
-    for (int ks = 0; ks < BK / 4; ++ks) {
+    for (int ks = 0; ks < KS / 4; ++ks) {
       const int kr = ks * 4 + (lane >> 4);
       double av[TM], bv[TN];
 #pragma unroll
@@ -251,14 +252,14 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   }
 }
 
-template <int WAVES_M, int TM, int TN, int LA, int LB, int EPI, bool SCALED, bool BF>
+template <int WAVES_M, int TM, int TN, int LA, int LB, int EPI, bool SCALED, bool BF, int KS = BK>
 static hipError_t launch(const GemmArgs& a, hipStream_t st) {
   const long total = (long)a.n_tiles * a.batch * a.splitk;
   if (total <= 0) return hipSuccess;
   if (total > 0x7fffffffL) return hipErrorInvalidValue;
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL((k_gemm_f64<WAVES_M, TM, TN, LA, LB, EPI, SCALED, BF>), dim3((unsigned)total),
-                     dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_gemm_f64<WAVES_M, TM, TN, LA, LB, EPI, SCALED, BF, KS>),
+                     dim3((unsigned)total), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -267,8 +268,9 @@ static hipError_t launch(const GemmArgs& a, hipStream_t st) {
 static hipError_t check_gemm(const GemmArgs& a, int tile_kind, int la, int lb, int epi) {
   const int BM = (tile_kind == 2 || tile_kind == 3) ? 64 : 128;
   const int BN = (tile_kind == 1 || tile_kind == 3) ? 64 : 128;
+  const int KSTEP = BK;
   const char* kn = "gemm_f64";
-  if (a.K <= 0 || a.K % BK != 0 || a.tiles_m <= 0 || a.tiles_n <= 0 || a.batch <= 0 ||
+  if (a.K <= 0 || a.K % KSTEP != 0 || a.tiles_m <= 0 || a.tiles_n <= 0 || a.batch <= 0 ||
       a.splitk <= 0 || a.row0 < 0 || a.col0 < 0 || a.k0 < 0 || a.kb0 < 0)
     return refuse(kn, "shape");
   long want = (a.map == MAP_FULL || a.map == MAP_FULL_J) ? (long)a.tiles_m * a.tiles_n : 0;
@@ -322,6 +324,9 @@ hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, h
   // Cholesky panel solve (A_panel Linv^T): 128 x 64, axpby
   if (tile_kind == 1 && la == KC && lb == KC && epi == EPI_AXPBY && !scaled)
     return launch<2, 4, 2, KC, KC, EPI_AXPBY, false, false>(a, st);
+  // MINRES first pass split over N_aux: partial X B, 64 x 64 tiles
+  if (tile_kind == 3 && la == KC && lb == KM && epi == EPI_STORE && !scaled)
+    return launch<2, 2, 2, KC, KM, EPI_STORE, false, false>(a, st);
   // MINRES: V = scale(X B) with X [sys][P] (KC) and B_ov [P][ia] (KM): 64 x 64 tiles
   if (tile_kind == 3 && la == KC && lb == KM && epi == EPI_RES_SCALE && !scaled)
     return launch<2, 2, 2, KC, KM, EPI_RES_SCALE, false, false>(a, st);

@@ -115,6 +115,23 @@ inline long round_up_l(long x, long m) { return (x + m - 1) / m * m; }
 
 constexpr int PANEL = 64;  // Cholesky panel width (matches chol.hip)
 
+// Split counts of the two MINRES operator passes for kp systems: about 1024
+// workgroups each.  Pass 1 (64 x 64 tiles over n_ov, split over N_aux, at
+// least 4 K-steps per split); pass 2 (64 x 128 tiles over N_aux, split over
+// n_ov, at least 16 K-steps per split).
+void minres_splits(int kp, int Np, int Kp, int* splitk, int* splitk1) {
+  // K chunks of about `chunk2` (pass 2) and `chunk1` (pass 1) elements bound the
+  // latency chain of each workgroup; GW_TUNE_MINRES="chunk1,chunk2" overrides
+  int chunk1 = 288, chunk2 = 512;
+  if (const char* e = getenv("GW_TUNE_MINRES")) sscanf(e, "%d,%d", &chunk1, &chunk2);
+  chunk1 = std::max(64, chunk1);
+  chunk2 = std::max(64, chunk2);
+  const int t2 = (kp / 64) * (Np / 128);
+  *splitk = std::max(1, std::min(std::max(1024 / std::max(t2, 1), Kp / chunk2), Kp / 64));
+  *splitk1 = std::max(1, std::min(Np / chunk1, Np / 16));
+  (void)t2;
+}
+
 long lower_tile_count(int tiles_m, int tiles_n, int BM, int BN) {
   long n = 0;
   for (int I = 0; I < tiles_m; ++I) {
@@ -128,6 +145,7 @@ long lower_tile_count(int tiles_m, int tiles_n, int BM, int BN) {
 struct System {
   int q;        // row of the right-hand side in the padded R buffer (r * n_mo + m)
   double w;     // real frequency eps_m - omega
+  double tol;   // MINRES residual target relative to |b| (0: the context default)
 };
 
 struct Timer {
@@ -210,7 +228,8 @@ struct gw_ctx {
   // MINRES workspace
   MinresBufs mr{};
   int mr_cap = 0;       // kp capacity
-  int mr_splitk = 1;
+  int mr_splitk = 1;    // split-K of the B_ov V^T pass
+  int mr_splitk1 = 1;   // split over N_aux of the B_ov^T v pass
   size_t part_cap = 0;  // doubles
   int* d_rhs_idx = nullptr;
   int* d_warm = nullptr;       // [kp] 1 when the system starts from the cached solution
@@ -559,21 +578,24 @@ int ensure_minres(gw_ctx* c, int kp) {
   if (kp <= c->mr_cap) return 0;
   MinresBufs& m = c->mr;
   void* olds[] = {m.x, m.w, m.w2, m.r1, m.r2, m.y, m.v, m.x0, m.scal, m.V, m.part, m.omega,
-                  m.active, c->d_rhs_idx, c->d_warm, c->d_wc, c->d_dwc, c->d_conv};
+                  m.rtol, m.active, c->d_rhs_idx, c->d_warm, c->d_wc, c->d_dwc, c->d_conv};
   for (void* p : olds) c->release(p);
   const size_t vec = (size_t)kp * c->Np;
   double** vecs[] = {&m.x, &m.w, &m.w2, &m.r1, &m.r2, &m.y, &m.v, &m.x0};
   for (double** p : vecs) RCHK(c->alloc((void**)p, vec * sizeof(double)));
   RCHK(c->alloc((void**)&m.scal, (size_t)kp * 16 * sizeof(double)));
   RCHK(c->alloc((void**)&m.V, (size_t)kp * c->Kp * sizeof(double)));
-  // split-K partials for B_ov V^T: aim for about 1024 workgroups
-  const int tiles = (kp / 64) * (c->Np / 128);
-  int splitk = std::max(1, std::min(1024 / std::max(tiles, 1), c->Kp / 256));
+  // split-K partials: aim for about 1024 workgroups in both operator passes
+  int splitk = 1, splitk1 = 1;
+  minres_splits(kp, c->Np, c->Kp, &splitk, &splitk1);
   c->mr_splitk = splitk;
-  size_t part = std::max((size_t)splitk * kp * c->Np, (size_t)(c->Kp / 64) * kp);
+  c->mr_splitk1 = splitk1;
+  size_t part = std::max({(size_t)splitk * kp * c->Np, (size_t)(c->Kp / 64) * kp,
+                          (size_t)splitk1 * kp * c->Kp});
   RCHK(c->alloc((void**)&m.part, part * sizeof(double)));
   c->part_cap = part;
   RCHK(c->alloc((void**)&m.omega, (size_t)kp * sizeof(double)));
+  RCHK(c->alloc((void**)&m.rtol, (size_t)kp * sizeof(double)));
   RCHK(c->alloc((void**)&m.active, sizeof(int)));
   RCHK(c->alloc((void**)&c->d_rhs_idx, (size_t)kp * sizeof(int)));
   RCHK(c->alloc((void**)&c->d_warm, (size_t)kp * sizeof(int)));
@@ -594,6 +616,13 @@ int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long l
   a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Kp / 64;
   a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
   a.Dvec = c->d_D; a.wrow = c->mr.omega;
+  if (epi == EPI_RES_SCALE && c->mr_splitk1 > 1) {
+    // split over N_aux for parallelism: partials, then a deterministic sum + scale
+    a.C = c->mr.part; a.ldc = c->Kp; a.splitk = c->mr_splitk1; a.sSplit = (long)kp * c->Kp;
+    RCHK(run_gemm(c, a, 3, KC, KM, EPI_STORE));
+    HIPCHK(minres_scale_sum(c->mr, c->mr_splitk1, c->d_D, c->ext(c->d_D, 8), c->st));
+    return 0;
+  }
   RCHK(run_gemm(c, a, 3, KC, KM, epi));
   return 0;
 }
@@ -662,16 +691,18 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   m.n_part = c->ext(m.part, 8);
   m.n_V = c->ext(m.V, 8);
   std::vector<int> idx(kp, 0);
-  std::vector<double> om(kp, 0.0);
+  std::vector<double> om(kp, 0.0), tol(kp, c->minres_rtol);
   for (int j = 0; j < k; ++j) {
     idx[j] = sys[j].q;
     om[j] = sys[j].w;
+    if (sys[j].tol > 0) tol[j] = std::max(sys[j].tol, c->minres_rtol);
   }
   Timer tm;
   tm.a = c->ev0; tm.b = c->ev1;
   tm.start(c->st);
   HIPCHK(rt_memcpy(c->d_rhs_idx, idx.data(), kp * sizeof(int), hipMemcpyHostToDevice, c->st));
   HIPCHK(rt_memcpy(m.omega, om.data(), kp * sizeof(double), hipMemcpyHostToDevice, c->st));
+  HIPCHK(rt_memcpy(m.rtol, tol.data(), kp * sizeof(double), hipMemcpyHostToDevice, c->st));
   trace("minres k=%d kp=%d splitk=%d", k, kp, c->mr_splitk);
   // warm start: a right-hand side solved earlier in this call starts from that
   // solution; one operator pass gives A x0 for the start vector b - A x0
@@ -707,7 +738,7 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
     HIPCHK(minres_apply(m, c->mr_splitk, c->st));
     const bool check = (itn % poll == 0) || itn == c->minres_max_iter;
     if (check) HIPCHK(rt_memset(m.active, 0, sizeof(int), c->st));
-    HIPCHK(minres_finish_step(m, itn, c->minres_rtol, c->st));
+    HIPCHK(minres_finish_step(m, itn, c->st));
     if (!check) continue;
     HIPCHK(rt_memcpy(&active, m.active, sizeof(int), hipMemcpyDeviceToHost, c->st));
     HIPCHK(rt_sync(c->st));
@@ -822,7 +853,7 @@ int ensure_sig(gw_ctx* c, int n) {
 // Requires a valid W^c table for the grid in the context.
 int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<double>& omega,
                std::vector<double>& sig, std::vector<double>& dsig, std::vector<int>& nres,
-               std::vector<int>& flags) {
+               std::vector<int>& flags, const std::vector<double>* tols = nullptr) {
   const int n = (int)states.size();
   sig.assign(n, 0.0);
   dsig.assign(n, 0.0);
@@ -852,7 +883,8 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
     for (int m = 0; m < c->n_mo; ++m) {
       double f = residue_weight(c, m, omega[j]);
       if (f == 0.0) continue;
-      sys.push_back(System{rows[j] * c->n_mo + m, c->eps[m] - omega[j]});
+      sys.push_back(System{rows[j] * c->n_mo + m, c->eps[m] - omega[j],
+                           tols ? (*tols)[j] : 0.0});
       owner.push_back(j);
       weight.push_back(f);
       nres[j]++;
@@ -896,6 +928,7 @@ struct QPState {
   bool has_br = false;
   double s = 0, fs = 0, e = 0, fe = 0;
   double E = 0, sig = 0, Z = 0;
+  double last_f = -1;   // |f| at the previous evaluation (-1: none yet)
   int status = 0;
 };
 
@@ -942,6 +975,7 @@ double alpha_of(double f) { return f != 0.0 ? std::min(0.1, 0.1 / std::fabs(f)) 
 // One step-tree decision for a state that has just been evaluated.
 void qp_step(gw_ctx* c, QPState& q, double sigma, double dsigma) {
   const double f = c->eps[q.n] + c->dsig_x[q.n] + sigma - q.w;
+  q.last_f = std::fabs(f);
   const double fprime = dsigma - 1.0;
   const double Z = (fprime != 0.0) ? -1.0 / fprime : INFINITY;
   update_bracket(q, q.w, f);
@@ -1020,11 +1054,12 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   // MINRES workspace for the largest batch
   const int kmax = std::min(std::max(n_states, 1) * n_mo, minres_batch);
   const int kp = round_up(kmax, 64);
-  const int tiles = (kp / 64) * (Np / 128);
-  const int splitk = std::max(1, std::min(1024 / std::max(tiles, 1), Kp / 256));
-  const size_t part = std::max((size_t)splitk * kp * Np, (size_t)(Kp / 64) * kp);
+  int splitk = 1, splitk1 = 1;
+  minres_splits(kp, Np, Kp, &splitk, &splitk1);
+  const size_t part = std::max({(size_t)splitk * kp * Np, (size_t)(Kp / 64) * kp,
+                                (size_t)splitk1 * kp * Kp});
   b += 8 * (size_t)kp * Np * d + (size_t)kp * 16 * d + (size_t)kp * Kp * d + part * d +
-       (size_t)kp * (d + 2 * sizeof(int) + 2 * d + sizeof(int)) + sizeof(int);
+       (size_t)kp * (2 * d + 2 * sizeof(int) + 2 * d + sizeof(int)) + sizeof(int);
   b += (size_t)Rp * Np * d;  // remembered residue solutions
   // dense fallback
   b += (size_t)Np * Np * d + (size_t)Kp * d + (size_t)Np * d + sizeof(int);
@@ -1284,7 +1319,7 @@ int gw_residues(gw_ctx* c, int k, const int* states, const int* m, const double*
   for (int j = 0; j < k; ++j) {
     if (m[j] < 0 || m[j] >= c->n_mo || !std::isfinite(w[j]))
       return fail(GW_EINVAL, "bad system %d", j);
-    sys[j] = System{c->row_of[states[j]] * c->n_mo + m[j], w[j]};
+    sys[j] = System{c->row_of[states[j]] * c->n_mo + m[j], w[j], 0.0};
   }
   forget_solutions(c);
   c->timing = gw_timing{};
@@ -1321,17 +1356,21 @@ int gw_qp(gw_ctx* c, int n_states, const int* states, const gw_grid* grid, doubl
   int rounds = 0;
   while (true) {
     std::vector<int> act, st;
-    std::vector<double> om;
+    std::vector<double> om, tol;
     for (int j = 0; j < n_states; ++j)
       if (!qs[j].done) {
         act.push_back(j);
         st.push_back(qs[j].n);
         om.push_back(qs[j].w);
+        // inexact Newton: residue solves need an error well below the current
+        // |f| only; the last evaluations run at the full tolerance
+        const double lf = qs[j].last_f < 0 ? 1.0 : qs[j].last_f;
+        tol.push_back(std::min(1e-6, std::max(c->minres_rtol, 1e-4 * lf)));
       }
     if (act.empty()) break;
     std::vector<double> sg, dsg;
     std::vector<int> nres, flags;
-    rc = eval_sigma(c, st, om, sg, dsg, nres, flags);
+    rc = eval_sigma(c, st, om, sg, dsg, nres, flags, &tol);
     if (rc) break;
     rounds++;
     for (size_t a = 0; a < act.size(); ++a) {

@@ -125,6 +125,7 @@ struct MinresBufs {
   double *part;            // split-K partials [splitk][kp][Np] (reused for deriv partials)
   double *x0;              // [kp][Np] starting guesses (0 for a cold start)
   double *omega;           // [kp] real frequencies
+  double *rtol;            // [kp] per-system residual target relative to |b|
   int *active;             // [1] count of unconverged systems
   long n_vec, n_scal, n_part, n_V;   // extents in elements (per array)
 };
@@ -140,9 +141,11 @@ hipError_t minres_init(MinresBufs& m, const double* rhs_base, const int* rhs_idx
 // x_j += x0_j, and xcache[rhs_idx_j] = x_j
 hipError_t minres_finalize(MinresBufs& m, double* xcache, const int* rhs_idx,
                            const int* host_idx, int n_rows, long n_cache, hipStream_t st);
+// V[j][ia] = D/(D^2 - w_j^2) * sum_s part[s][j][ia] (split partials of B_ov^T v)
+hipError_t minres_scale_sum(MinresBufs& m, int splits, const double* D, long nD, hipStream_t st);
 // y = v + 4 sum_s part[s] (the operator applied to v), one thread per element
 hipError_t minres_apply(MinresBufs& m, int splitk, hipStream_t st);
-hipError_t minres_finish_step(MinresBufs& m, int itn, double rtol, hipStream_t st);
+hipError_t minres_finish_step(MinresBufs& m, int itn, hipStream_t st);
 hipError_t minres_results(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
                           int n_rhs_rows, int n_deriv_parts, double* wc, double* dwc, int* conv,
                           long n_out, hipStream_t st);

@@ -138,6 +138,32 @@ hipError_t minres_finalize(MinresBufs& m, double* xcache, const int* rhs_idx,
   return hipGetLastError();
 }
 
+// V[j][ia] = D_ia/(D_ia^2 - w_j^2) sum_s part[s][j][ia]: finishes the first
+// operator pass from its partials over N_aux, in a fixed order.
+__global__ void k_minres_scale_sum(MinresBufs m, int splits, const double* D) {
+  const long n = (long)m.kp * m.Kp;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int s = 0; s < splits; ++s) acc += m.part[s * n + i];
+    const int j = (int)(i / m.Kp), ia = (int)(i % m.Kp);
+    const double w = m.omega[j], d = D[ia];
+    m.V[i] = acc * (d / (d * d - w * w));
+  }
+}
+
+hipError_t minres_scale_sum(MinresBufs& m, int splits, const double* D, long nD, hipStream_t st) {
+  if (hipError_t e = check_bufs(m, "minres_scale_sum")) return e;
+  GW_GUARD("minres_scale_sum", "part", (long)splits * m.kp * m.Kp - 1, m.n_part);
+  GW_GUARD("minres_scale_sum", "V", (long)m.kp * m.Kp - 1, m.n_V);
+  GW_GUARD("minres_scale_sum", "D", m.Kp - 1, nD);
+  GW_AUDIT_RETURN();
+  const long n = (long)m.kp * m.Kp;
+  int blocks = (int)std::min<long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_minres_scale_sum, dim3(blocks), dim3(256), 0, st, m, splits, D);
+  return hipGetLastError();
+}
+
 // y = v + 4 sum_s part[s] for every element of every system: the matrix-vector
 // product (1 - Pi(w)) v finished from the split-K partials of B_ov V^T.
 __global__ void k_minres_apply(MinresBufs m, int splitk) {
@@ -162,7 +188,7 @@ hipError_t minres_apply(MinresBufs& m, int splitk, hipStream_t st) {
 }
 
 // One MINRES iteration for every unconverged system, given y = A v.
-__global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int itn, double rtol) {
+__global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int itn) {
   __shared__ double red[4];
   __shared__ double bc[5];
   const int j = blockIdx.x, t = threadIdx.x;
@@ -211,7 +237,7 @@ __global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int itn, doub
     // residual |b - A x| = phibar (the start vector is b - A x0); stop relative to |b|
     const double ratio = phibar / sc[S_BNORM];
     sc[S_RATIO] = ratio;
-    const bool done = (ratio <= rtol) || (beta_new <= 1e-300);
+    const bool done = (ratio <= m.rtol[j]) || (beta_new <= 1e-300);
     if (done) sc[S_DONE] = 1.0;
     bc[0] = oldeps;
     bc[1] = delta;
@@ -235,10 +261,10 @@ __global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int itn, doub
   if (t == 0 && !done) atomicAdd(m.active, 1);
 }
 
-hipError_t minres_finish_step(MinresBufs& m, int itn, double rtol, hipStream_t st) {
+hipError_t minres_finish_step(MinresBufs& m, int itn, hipStream_t st) {
   if (hipError_t e = check_bufs(m, "minres_step")) return e;
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_minres_step, dim3(m.kp), dim3(256), 0, st, m, itn, rtol);
+  hipLaunchKernelGGL(k_minres_step, dim3(m.kp), dim3(256), 0, st, m, itn);
   return hipGetLastError();
 }
 
