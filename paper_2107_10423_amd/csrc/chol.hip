@@ -17,61 +17,68 @@
 
 namespace gw {
 
-constexpr int NB = 64;
+constexpr int NB = 128;
 
-// Factor the 64x64 diagonal block at (k, k) of every batch item in LDS, write
-// L back (strict upper part zeroed) and L^-1 to Linv[g][64][64].
+// Factor the 128x128 diagonal block at (k, k) of every batch item in LDS,
+// write L back (strict upper part zeroed), invert L in place and write L^-1
+// to Linv[g][128][128].
 __global__ __launch_bounds__(256) void k_chol_diag(double* A, long ldA, long sA, double* Linv,
                                                    int k, int* info) {
   __shared__ double L[NB][NB + 1];
-  __shared__ double X[NB][NB + 1];
-  __shared__ double part[4][NB];
+  __shared__ double tcol[NB];
   const int g = blockIdx.x;
   const int t = threadIdx.x;
   double* Ag = A + (long)g * sA + (long)k * ldA + k;
   for (int idx = t; idx < NB * NB; idx += 256) {
-    int i = idx / NB, c = idx % NB;
+    const int i = idx / NB, c = idx % NB;
     L[i][c] = (c <= i) ? Ag[(long)i * ldA + c] : 0.0;
   }
   __syncthreads();
+  // right-looking unblocked Cholesky
   for (int j = 0; j < NB; ++j) {
     if (t == 0) {
       double d = L[j][j];
-      if (!(d > 0.0)) {  // not positive definite (or NaN): record, keep going with 1
+      if (!(d > 0.0)) {  // not positive definite (or NaN): record, continue with 1
         if (info[g] == 0) info[g] = k + j + 1;
         d = 1.0;
       }
       L[j][j] = sqrt(d);
     }
     __syncthreads();
-    for (int i = j + 1 + t; i < NB; i += 256) L[i][j] /= L[j][j];
+    const double piv = L[j][j];
+    for (int i = j + 1 + t; i < NB; i += 256) L[i][j] /= piv;
     __syncthreads();
-    for (int idx = t; idx < NB * NB; idx += 256) {
-      int i = idx / NB, c = idx % NB;
-      if (c > j && c <= i) L[i][c] -= L[i][j] * L[c][j];
+    // trailing update of the lower triangle, rows i > j and columns j < c <= i:
+    // thread pairs share a row, the two threads of a pair alternate columns
+    for (int i = j + 1 + (t >> 1); i < NB; i += 128) {
+      const double lij = L[i][j];
+      for (int c = j + 1 + (t & 1); c <= i; c += 2) L[i][c] -= lij * L[c][j];
     }
     __syncthreads();
   }
-  // X = L^-1 by forward substitution, row by row; 4 threads per column split
-  // the inner product.
-  const int col = t & 63, q = t >> 6;
-  for (int i = 0; i < NB; ++i) {
-    double s = 0.0;
-    for (int j = q; j < i; j += 4) s += L[i][j] * X[j][col];
-    part[q][col] = s;
-    __syncthreads();
-    if (q == 0) {
-      double tot = part[0][col] + part[1][col] + part[2][col] + part[3][col];
-      double rhs = (i == col) ? 1.0 : 0.0;
-      X[i][col] = (col <= i) ? (rhs - tot) / L[i][i] : 0.0;
+  for (int idx = t; idx < NB * NB; idx += 256) {
+    const int i = idx / NB, c = idx % NB;
+    Ag[(long)i * ldA + c] = (c <= i) ? L[i][c] : 0.0;
+  }
+  __syncthreads();
+  // in-place inverse, columns right to left: with X = L^-1 already in the
+  // lower-right block, X[i][j] = -(sum_{j<m<=i} X[i][m] L[m][j]) / L[j][j]
+  for (int j = NB - 1; j >= 0; --j) {
+    const double dinv = 1.0 / L[j][j];
+    if (t > j && t < NB) {
+      double s = 0.0;
+      for (int m = j + 1; m <= t; ++m) s += L[t][m] * L[m][j];
+      tcol[t] = -s * dinv;
     }
+    __syncthreads();
+    if (t > j && t < NB) L[t][j] = tcol[t];
+    if (t == 0) L[j][j] = dinv;
     __syncthreads();
   }
   double* Li = Linv + (long)g * NB * NB;
   for (int idx = t; idx < NB * NB; idx += 256) {
-    int i = idx / NB, c = idx % NB;
-    Ag[(long)i * ldA + c] = (c <= i) ? L[i][c] : 0.0;
-    Li[idx] = X[i][c];
+    const int i = idx / NB, c = idx % NB;
+    Li[idx] = (c <= i) ? L[i][c] : 0.0;
   }
 }
 

@@ -113,7 +113,7 @@ hipError_t rt_sync(hipStream_t st) { return audit_mode() ? hipSuccess : hipStrea
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
 inline long round_up_l(long x, long m) { return (x + m - 1) / m * m; }
 
-constexpr int PANEL = 64;  // Cholesky panel width (matches chol.hip)
+constexpr int PANEL = 128;  // Cholesky panel width (matches chol.hip)
 
 // Split counts of the two MINRES operator passes for kp systems: about 1024
 // workgroups each.  Pass 1 (64 x 64 tiles over n_ov, split over N_aux, at
@@ -425,7 +425,7 @@ int ensure_mixed_operands(gw_ctx* c) {
 
 // Blocked right-looking Cholesky of every item of the chunk over the rows
 // [0, Np) of 1 - Pi and the appended identity rows; panel k carries the
-// appended rows up to Np + k + 64 only (the later ones are still unit rows
+// appended rows up to Np + k + PANEL only (the later ones are still unit rows
 // that the panel does not touch).
 int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
   const int Np = c->Np;
@@ -435,7 +435,7 @@ int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
     trace("cholesky panel k=%d", k);
     HIPCHK(chol_diag(c->d_work, ldA, per_g, c->d_Linv, k, G, c->d_info, c->ext(c->d_work, 8),
                      c->ext(c->d_Linv, 8), c->ext(c->d_info, 4), c->st));
-    const int rows_below = Np + k + PANEL - (k + PANEL);  // rows [k + 64, Np + k + 64)
+    const int rows_below = Np;  // rows [k + PANEL, Np + k + PANEL)
     {  // panel solve: L[i][k:k+64] = A[i][k:k+64] Linv_kk^T
       GemmArgs a{};
       a.A = c->d_work; a.lda = ldA; a.sA = per_g;
@@ -447,7 +447,7 @@ int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
       a.M = a.tiles_m * 128; a.N = PANEL;
       a.n_tiles = a.tiles_m; a.batch = G; a.splitk = 1;
       a.alpha = 1.0; a.beta = 0.0;
-      RCHK(run_gemm(c, a, 1, KC, KC, EPI_AXPBY));
+      RCHK(run_gemm(c, a, 0, KC, KC, EPI_AXPBY));
     }
     const int cols_right = Np - (k + PANEL);
     if (cols_right <= 0) continue;
@@ -1044,10 +1044,10 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   // stage A
   const size_t per_g = (size_t)(2L * Np + 128) * (Np + 128);
   const size_t parts = (size_t)(Np / 128) * Rp;
-  const size_t per_bytes = per_g * d + (size_t)Kp * d + 64 * 64 * d + parts * d;
+  const size_t per_bytes = per_g * d + (size_t)Kp * d + PANEL * PANEL * d + parts * d;
   int chunk = (int)std::max<size_t>(1, work_budget / per_bytes);
   if (chunk > G) chunk = G;
-  b += (size_t)chunk * (per_g * d + parts * d + 64 * 64 * d + sizeof(int) + (size_t)Kp * d);
+  b += (size_t)chunk * (per_g * d + parts * d + PANEL * PANEL * d + sizeof(int) + (size_t)Kp * d);
   b += 2 * (size_t)G * d + (size_t)std::max(nR, 1) * G * d;
   // Sigma evaluation buffers
   b += (size_t)n_states * (sizeof(int) + 3 * d);
