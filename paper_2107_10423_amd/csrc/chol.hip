@@ -3,7 +3,7 @@
 //
 // The matrix of grid point g is stored augmented: rows [0, Np) hold 1 - Pi
 // (lower triangle), rows [Np, 2 Np) start as the identity.  A right-looking
-// blocked Cholesky (panel width 64) run over the rows factors 1 - Pi = L L^T
+// blocked Cholesky (panel width 128) run over the rows factors 1 - Pi = L L^T
 // and, because the appended rows are treated like rows below the diagonal,
 // leaves (L^-1 I)^T = L^-T in them (row Np + s holds column s of L^-1).
 // Identity row s is untouched until the panel that contains column s, so each
@@ -19,66 +19,114 @@ namespace gw {
 
 constexpr int NB = 128;
 
-// Factor the 128x128 diagonal block at (k, k) of every batch item in LDS,
-// write L back (strict upper part zeroed), invert L in place and write L^-1
-// to Linv[g][128][128].
-__global__ __launch_bounds__(256) void k_chol_diag(double* A, long ldA, long sA, double* Linv,
-                                                   int k, int* info) {
-  __shared__ double L[NB][NB + 1];
-  __shared__ double tcol[NB];
+// Factor the 128x128 diagonal block at (k, k) of every batch item, write L
+// back (strict upper part zeroed) and write L^-1 to Linv[g][128][128].
+//
+// One 1024-thread workgroup per batch item; the block lives in registers.
+// Thread (ti, tj) of a 32 x 32 grid holds L[ti + 32 a][tj + 32 b] and
+// Y[ti + 32 a][tj + 32 b] for a, b = 0..3, where Y starts as the identity and
+// is eliminated like rows appended below the block, so that it ends as L^-T
+// (column s of L^-1 in row s).  Column j is published through LDS by the
+// threads with tj = j mod 32 (double-buffered, one barrier per column); the
+// owner of the diagonal element adds 1 / sqrt(L[j][j]).  Register blocks that
+// cannot take part in column j (above or left of it, or upper-triangular) are
+// skipped at compile time, which leaves 1/4 of the dense update work.
+constexpr int CT = 32;       // thread grid edge
+constexpr int CR = NB / CT;  // register block edge (4)
+
+__global__ __launch_bounds__(1024) void k_chol_diag(double* A, long ldA, long sA, double* Linv,
+                                                    int k, int* info) {
+  __shared__ double colL[2][NB], colY[2][NB], rpiv[2];
+  __shared__ double stage[NB][NB + 1];
   const int g = blockIdx.x;
   const int t = threadIdx.x;
+  const int ti = t / CT, tj = t % CT;
   double* Ag = A + (long)g * sA + (long)k * ldA + k;
-  for (int idx = t; idx < NB * NB; idx += 256) {
-    const int i = idx / NB, c = idx % NB;
-    L[i][c] = (c <= i) ? Ag[(long)i * ldA + c] : 0.0;
-  }
-  __syncthreads();
-  // right-looking unblocked Cholesky
-  for (int j = 0; j < NB; ++j) {
-    if (t == 0) {
-      double d = L[j][j];
-      if (!(d > 0.0)) {  // not positive definite (or NaN): record, continue with 1
-        if (info[g] == 0) info[g] = k + j + 1;
-        d = 1.0;
+
+  double L[CR][CR], Y[CR][CR];
+#pragma unroll
+  for (int a = 0; a < CR; ++a)
+#pragma unroll
+    for (int b = 0; b < CR; ++b) {
+      const int i = ti + CT * a, c = tj + CT * b;
+      L[a][b] = (c <= i) ? Ag[(long)i * ldA + c] : 0.0;
+      Y[a][b] = (c == i) ? 1.0 : 0.0;
+    }
+
+#pragma unroll
+  for (int bj = 0; bj < CR; ++bj) {
+#pragma unroll 1
+    for (int jj = 0; jj < CT; ++jj) {
+      const int j = CT * bj + jj;
+      const int buf = jj & 1;
+      if (tj == jj) {
+#pragma unroll
+        for (int a = 0; a < CR; ++a) {
+          if (a >= bj) colL[buf][ti + CT * a] = L[a][bj];
+          if (a <= bj) colY[buf][ti + CT * a] = Y[a][bj];
+        }
+        if (ti == jj) {
+          double d = L[bj][bj];
+          if (!(d > 0.0)) {  // not positive definite (or NaN): record, continue with 1
+            if (info[g] == 0) info[g] = k + j + 1;
+            d = 1.0;
+          }
+          const double piv = sqrt(d);
+          rpiv[buf] = 1.0 / piv;
+          L[bj][bj] = piv;
+        }
       }
-      L[j][j] = sqrt(d);
+      __syncthreads();
+      const double rp = rpiv[buf];
+      double li[CR], lc[CR], ys[CR];
+#pragma unroll
+      for (int a = 0; a < CR; ++a) {
+        li[a] = (a >= bj) ? colL[buf][ti + CT * a] * rp : 0.0;
+        lc[a] = (a >= bj) ? colL[buf][tj + CT * a] * rp : 0.0;
+        ys[a] = (a <= bj) ? colY[buf][ti + CT * a] * rp : 0.0;
+      }
+      if (tj == jj) {
+#pragma unroll
+        for (int a = 0; a < CR; ++a) {
+          if (a >= bj && ti + CT * a > j) L[a][bj] = li[a];
+          if (a <= bj) Y[a][bj] = ys[a];
+        }
+      }
+      // trailing update of L: rows i > j, columns j < c <= i
+#pragma unroll
+      for (int a = bj; a < CR; ++a) {
+        const bool row_ok = (a > bj) || (ti > jj);
+#pragma unroll
+        for (int b = bj; b <= a; ++b) {
+          const bool col_ok = (b > bj) || (tj > jj);
+          if (row_ok && col_ok) L[a][b] -= li[a] * lc[b];
+        }
+      }
+      // appended rows: columns c > j of rows s <= j (rows s > j are still zero there)
+#pragma unroll
+      for (int a = 0; a <= bj; ++a)
+#pragma unroll
+        for (int b = bj; b < CR; ++b) {
+          const bool col_ok = (b > bj) || (tj > jj);
+          if (col_ok) Y[a][b] -= ys[a] * lc[b];
+        }
     }
-    __syncthreads();
-    const double piv = L[j][j];
-    for (int i = j + 1 + t; i < NB; i += 256) L[i][j] /= piv;
-    __syncthreads();
-    // trailing update of the lower triangle, rows i > j and columns j < c <= i:
-    // thread pairs share a row, the two threads of a pair alternate columns
-    for (int i = j + 1 + (t >> 1); i < NB; i += 128) {
-      const double lij = L[i][j];
-      for (int c = j + 1 + (t & 1); c <= i; c += 2) L[i][c] -= lij * L[c][j];
+  }
+
+#pragma unroll
+  for (int a = 0; a < CR; ++a)
+#pragma unroll
+    for (int b = 0; b < CR; ++b) {
+      const int i = ti + CT * a, c = tj + CT * b;
+      Ag[(long)i * ldA + c] = (c <= i) ? L[a][b] : 0.0;
+      stage[i][c] = Y[a][b];
     }
-    __syncthreads();
-  }
-  for (int idx = t; idx < NB * NB; idx += 256) {
-    const int i = idx / NB, c = idx % NB;
-    Ag[(long)i * ldA + c] = (c <= i) ? L[i][c] : 0.0;
-  }
   __syncthreads();
-  // in-place inverse, columns right to left: with X = L^-1 already in the
-  // lower-right block, X[i][j] = -(sum_{j<m<=i} X[i][m] L[m][j]) / L[j][j]
-  for (int j = NB - 1; j >= 0; --j) {
-    const double dinv = 1.0 / L[j][j];
-    if (t > j && t < NB) {
-      double s = 0.0;
-      for (int m = j + 1; m <= t; ++m) s += L[t][m] * L[m][j];
-      tcol[t] = -s * dinv;
-    }
-    __syncthreads();
-    if (t > j && t < NB) L[t][j] = tcol[t];
-    if (t == 0) L[j][j] = dinv;
-    __syncthreads();
-  }
+  // Linv[i][c] = (L^-1)[i][c] = Y[c][i]
   double* Li = Linv + (long)g * NB * NB;
-  for (int idx = t; idx < NB * NB; idx += 256) {
+  for (int idx = t; idx < NB * NB; idx += 1024) {
     const int i = idx / NB, c = idx % NB;
-    Li[idx] = (c <= i) ? L[i][c] : 0.0;
+    Li[idx] = (c <= i) ? stage[c][i] : 0.0;
   }
 }
 
@@ -89,7 +137,7 @@ hipError_t chol_diag(double* A, long ldA, long sA, double* Linv, int k, int G, i
   GW_GUARD("chol_diag", "Linv", (long)G * NB * NB - 1, nLinv);
   GW_GUARD("chol_diag", "info", G - 1, nInfo);
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_chol_diag, dim3(G), dim3(256), 0, st, A, ldA, sA, Linv, k, info);
+  hipLaunchKernelGGL(k_chol_diag, dim3(G), dim3(1024), 0, st, A, ldA, sA, Linv, k, info);
   return hipGetLastError();
 }
 

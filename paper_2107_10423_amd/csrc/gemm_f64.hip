@@ -4,10 +4,10 @@
 // Work tile: BM x BN outputs per 256-thread workgroup (4 wavefronts), staged
 // through LDS in K-steps of 16 with double buffering; each wavefront owns
 // TM x TN blocks of 16x16 and issues v_mfma_f64_16x16x4_f64.  Operands are
-// either k-contiguous ([row][k]) or k-major ([k][row]) in HBM; LDS always
-// holds [k][row] so that the 16 lanes of an MFMA row group read 16
-// consecutive doubles.  All extents handed to the kernel are padded to the
-// tile, so the inner loop carries no bounds checks.
+// either k-contiguous ([row][k]) or k-major ([k][row]) in HBM and keep that
+// orientation in LDS (layouts below, chosen to be free of bank conflicts on
+// the 64-bank LDS).  All extents handed to the kernel are padded to the tile,
+// so the inner loop carries no bounds checks.
 //
 // Workgroups are swizzled so that each XCD (workgroups are dealt round-robin
 // to the 8 XCDs) receives a contiguous range of the work list; with the batch
@@ -18,6 +18,7 @@
 namespace gw {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 
 constexpr int BK = 16;   // K-step of the default configurations
 
@@ -51,60 +52,82 @@ __device__ __forceinline__ void decode_tile(const GemmArgs& p, int tile, int& I,
   I = p.tiles_m; J = 0;  // unreachable when n_tiles is consistent
 }
 
-template <int BR, int LAYOUT, bool SCALED, int KS>
+// LDS tiles.  k-contiguous operands keep [row][k] (16 doubles, 128 bytes a
+// row) with the eight 16-byte chunks of a row XOR-permuted by the row pair, so
+// that both the staging stores (8 lanes per row) and the fragment reads (16
+// rows, one chunk each) spread over all 64 LDS banks.  k-major operands keep
+// [k][row] with the two 128-byte halves of each 32-double group swapped on
+// rows k with bit 2 set: the fragment reads of lane groups 4 rows apart then
+// land in opposite bank halves.
+template <int BR, int LAYOUT>
+struct LdsTile {
+  static_assert(BR % 32 == 0, "row tiles are multiples of 32");
+  static constexpr int ELEMS = BR * BK;
+};
+
+__device__ __forceinline__ int kc_chunk(int row, int c) { return c ^ ((row >> 1) & 7); }
+__device__ __forceinline__ int km_col(int k, int col) { return col ^ ((k & 4) << 2); }
+
+// Fragment of one 16-row block for two of the four MFMAs of a K-step (half h
+// = 0, 1).  The summation index inside a K-step is permuted identically for
+// both operands: MFMA ks, lane group g = lane / 16 contracts over k = 4 g + ks,
+// so a lane's values for ks = 2 h, 2 h + 1 form one 16-byte chunk of a
+// k-contiguous tile.
+template <int BR, int LAYOUT>
+__device__ __forceinline__ d2 load_frag(const double* Xs, int row, int g, int h) {
+  if (LAYOUT == KC) return *reinterpret_cast<const d2*>(Xs + row * BK + 2 * kc_chunk(row, 2 * g + h));
+  const int k = 4 * g + 2 * h;
+  d2 f;
+  f.x = Xs[k * BR + km_col(k, row)];
+  f.y = Xs[(k + 1) * BR + km_col(k + 1, row)];
+  return f;
+}
+
+template <int BR, int LAYOUT, bool SCALED>
 struct Stager {
-  // number of double2 items per thread for a BR x KS tile
-  static constexpr int NITEM = BR * KS / 2 / 256;
-  double2 v[NITEM];
+  // number of 16-byte items per thread for a BR x BK tile
+  static constexpr int NITEM = BR * BK / 2 / 256;
+  d2 v[NITEM];
   __device__ __forceinline__ void load(const double* X, long ld, int r0, int kk0,
                                        const double* s, int t) {
 #pragma unroll
     for (int u = 0; u < NITEM; ++u) {
       int q = t + 256 * u;
       if (LAYOUT == KC) {
-        int row = q / (KS / 2), k = (q % (KS / 2)) * 2;
-        v[u] = *reinterpret_cast<const double2*>(X + (long)(r0 + row) * ld + kk0 + k);
-        if (SCALED) {
-          double2 sv = *reinterpret_cast<const double2*>(s + kk0 + k);
-          v[u].x *= sv.x;
-          v[u].y *= sv.y;
-        }
+        int row = q / (BK / 2), k = (q % (BK / 2)) * 2;
+        v[u] = *reinterpret_cast<const d2*>(X + (long)(r0 + row) * ld + kk0 + k);
+        if (SCALED) v[u] *= *reinterpret_cast<const d2*>(s + kk0 + k);
       } else {
         int k = q / (BR / 2), rp = (q % (BR / 2)) * 2;
-        v[u] = *reinterpret_cast<const double2*>(X + (long)(kk0 + k) * ld + r0 + rp);
-        if (SCALED) {
-          double sk = s[kk0 + k];
-          v[u].x *= sk;
-          v[u].y *= sk;
-        }
+        v[u] = *reinterpret_cast<const d2*>(X + (long)(kk0 + k) * ld + r0 + rp);
+        if (SCALED) v[u] *= s[kk0 + k];
       }
     }
   }
-  __device__ __forceinline__ void store(double (*Xs)[BR], int t) {
+  __device__ __forceinline__ void store(double* Xs, int t) {
 #pragma unroll
     for (int u = 0; u < NITEM; ++u) {
       int q = t + 256 * u;
       if (LAYOUT == KC) {
-        int row = q / (KS / 2), k = (q % (KS / 2)) * 2;
-        Xs[k][row] = v[u].x;
-        Xs[k + 1][row] = v[u].y;
+        int row = q / (BK / 2), c = q % (BK / 2);
+        *reinterpret_cast<d2*>(Xs + row * BK + 2 * kc_chunk(row, c)) = v[u];
       } else {
         int k = q / (BR / 2), rp = (q % (BR / 2)) * 2;
-        Xs[k][rp] = v[u].x;
-        Xs[k][rp + 1] = v[u].y;
+        *reinterpret_cast<d2*>(Xs + k * BR + km_col(k, rp)) = v[u];
       }
     }
   }
 };
 
-template <int WAVES_M, int TM, int TN, int LA, int LB, int EPI, bool SCALED, bool BATCH_FAST,
-          int KS = BK>
+template <int WAVES_M, int TM, int TN, int LA, int LB, int EPI, bool SCALED, bool BATCH_FAST>
 __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   constexpr int WAVES_N = 4 / WAVES_M;
   constexpr int BM = WAVES_M * TM * 16;
   constexpr int BN = WAVES_N * TN * 16;
-  __shared__ double As[2][KS][BM];
-  __shared__ double Bs[2][KS][BN];
+  constexpr int LA_N = LdsTile<BM, LA>::ELEMS;
+  constexpr int LB_N = LdsTile<BN, LB>::ELEMS;
+  __shared__ __attribute__((aligned(16))) double As[2 * LA_N];
+  __shared__ __attribute__((aligned(16))) double Bs[2 * LB_N];
   __shared__ double red[WAVES_N][BM];
 
   const int t = threadIdx.x;
@@ -134,7 +157,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   const int arow0 = p.row0 + I * BM;
   const int brow0 = p.col0 + J * BN;
 
-  int kchunk = ((p.K / KS + p.splitk - 1) / p.splitk) * KS;
+  int kchunk = ((p.K / BK + p.splitk - 1) / p.splitk) * BK;
   int kbeg = split * kchunk;
   int kend = kbeg + kchunk;
   if (kend > p.K) kend = p.K;
@@ -142,7 +165,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
     const int lim = p.col0 + (J + 1) * BN - p.kb0;
     if (kend > lim) kend = lim;
   }
-  const int nk = kend > kbeg ? (kend - kbeg) / KS : 0;
+  const int nk = kend > kbeg ? (kend - kbeg) / BK : 0;
 
   d4 acc[TM][TN];
 #pragma unroll
@@ -150,39 +173,45 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  Stager<BM, LA, false, KS> sa;
-  Stager<BN, LB, SCALED, KS> sb;
+  Stager<BM, LA, false> sa;
+  Stager<BN, LB, SCALED> sb;
   if (nk > 0) {
     sa.load(A, p.lda, arow0, p.k0 + kbeg, nullptr, t);
     sb.load(Bm, p.ldb, brow0, p.kb0 + kbeg, S, t);
-    sa.store(As[0], t);
-    sb.store(Bs[0], t);
+    sa.store(As, t);
+    sb.store(Bs, t);
   }
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) {
-      const int kstep = kbeg + (kt + 1) * KS;
+      const int kstep = kbeg + (kt + 1) * BK;
       sa.load(A, p.lda, arow0, p.k0 + kstep, nullptr, t);
       sb.load(Bm, p.ldb, brow0, p.kb0 + kstep, S, t);
     }
+    {
+      const double* Ac = As + cur * LA_N;
+      const double* Bc = Bs + cur * LB_N;
+      const int g = lane >> 4;
 #pragma unroll
-    for (int ks = 0; ks < KS / 4; ++ks) {
-      const int kr = ks * 4 + (lane >> 4);
-      double av[TM], bv[TN];
+      for (int h = 0; h < 2; ++h) {
+        d2 av[TM], bv[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) av[i] = As[cur][kr][wm * TM * 16 + i * 16 + (lane & 15)];
+        for (int i = 0; i < TM; ++i) av[i] = load_frag<BM, LA>(Ac, wm * TM * 16 + i * 16 + (lane & 15), g, h);
 #pragma unroll
-      for (int j = 0; j < TN; ++j) bv[j] = Bs[cur][kr][wn * TN * 16 + j * 16 + (lane & 15)];
+        for (int j = 0; j < TN; ++j) bv[j] = load_frag<BN, LB>(Bc, wn * TN * 16 + j * 16 + (lane & 15), g, h);
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int e = 0; e < 2; ++e)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
+          for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][e], bv[j][e], acc[i][j], 0, 0, 0);
+      }
     }
     if (kt + 1 < nk) {
-      sa.store(As[cur ^ 1], t);
-      sb.store(Bs[cur ^ 1], t);
+      sa.store(As + (cur ^ 1) * LA_N, t);
+      sb.store(Bs + (cur ^ 1) * LB_N, t);
     }
     __syncthreads();
   }
@@ -252,13 +281,13 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   }
 }
 
-template <int WAVES_M, int TM, int TN, int LA, int LB, int EPI, bool SCALED, bool BF, int KS = BK>
+template <int WAVES_M, int TM, int TN, int LA, int LB, int EPI, bool SCALED, bool BF>
 static hipError_t launch(const GemmArgs& a, hipStream_t st) {
   const long total = (long)a.n_tiles * a.batch * a.splitk;
   if (total <= 0) return hipSuccess;
   if (total > 0x7fffffffL) return hipErrorInvalidValue;
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL((k_gemm_f64<WAVES_M, TM, TN, LA, LB, EPI, SCALED, BF, KS>),
+  hipLaunchKernelGGL((k_gemm_f64<WAVES_M, TM, TN, LA, LB, EPI, SCALED, BF>),
                      dim3((unsigned)total), dim3(256), 0, st, a);
   return hipGetLastError();
 }
