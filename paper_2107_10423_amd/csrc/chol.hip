@@ -189,27 +189,32 @@ hipError_t wc_from_parts(const double* part, long sPart, int nJ, int ldp, const 
   return hipGetLastError();
 }
 
-// s[g][k] = D_k / (D_k^2 + xi_g^2) for k < Kov, 0 for the padding
-__global__ void k_scale_imag(const double* D, int Kov, int Kp, const double* xi, double* s) {
+// s[g][k] = D_k / (D_k^2 + xi_g^2) for k < Kov, 0 for the padding; s32 (if
+// given) receives the same values rounded to FP32 for the mixed Pi builds
+__global__ void k_scale_imag(const double* D, int Kov, int Kp, const double* xi, double* s,
+                             float* s32) {
   const int g = blockIdx.y;
   const double x2 = xi[g] * xi[g];
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < Kp; k += gridDim.x * blockDim.x) {
     double d = D[k];
-    s[(long)g * Kp + k] = (k < Kov) ? d / (d * d + x2) : 0.0;
+    const double v = (k < Kov) ? d / (d * d + x2) : 0.0;
+    s[(long)g * Kp + k] = v;
+    if (s32) s32[(long)g * Kp + k] = (float)v;
   }
 }
 
 hipError_t make_scale_imag(const double* D, int Kov, int Kp, const double* xi, int G, double* s,
-                           long nD, long nXi, long nS, hipStream_t st) {
+                           float* s32, long nD, long nXi, long nS, long nS32, hipStream_t st) {
   if (G <= 0 || Kp <= 0) return hipSuccess;
   GW_GUARD("scale_imag", "D", Kp - 1, nD);
   GW_GUARD("scale_imag", "xi", G - 1, nXi);
   GW_GUARD("scale_imag", "s", (long)G * Kp - 1, nS);
+  if (s32) GW_GUARD("scale_imag", "s32", (long)G * Kp - 1, nS32);
   if (Kov > Kp) return refuse("scale_imag", "Kov > Kp");
   GW_AUDIT_RETURN();
   int blocks = (Kp + 255) / 256;
   if (blocks > 256) blocks = 256;
-  hipLaunchKernelGGL(k_scale_imag, dim3(blocks, G), dim3(256), 0, st, D, Kov, Kp, xi, s);
+  hipLaunchKernelGGL(k_scale_imag, dim3(blocks, G), dim3(256), 0, st, D, Kov, Kp, xi, s, s32);
   return hipGetLastError();
 }
 

@@ -173,6 +173,15 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
+  // 16-row blocks of padding rows (systems beyond the batch) and blocks whose A
+  // rows are known to be zero (converged systems) skip their MFMAs
+  bool row_ok[TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int r = I * BM + wm * TM * 16 + i * 16;
+    row_ok[i] = (p.mrows <= 0 || r < p.mrows) && (!p.rowmask || p.rowmask[r >> 4] != 0);
+  }
+
   Stager<BM, LA, false> sa;
   Stager<BN, LB, SCALED> sb;
   if (nk > 0) {
@@ -204,9 +213,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
         for (int e = 0; e < 2; ++e)
 #pragma unroll
           for (int i = 0; i < TM; ++i)
+            if (row_ok[i])
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][e], bv[j][e], acc[i][j], 0, 0, 0);
+              for (int j = 0; j < TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i][e], bv[j][e], acc[i][j], 0, 0, 0);
       }
     }
     if (kt + 1 < nk) {
@@ -328,6 +338,8 @@ static hipError_t check_gemm(const GemmArgs& a, int tile_kind, int la, int lb, i
   long maxC = b1 * a.sC + (long)(a.splitk - 1) * a.sSplit +
               (per_tile ? (long)(a.tiles_n - 1) * a.ldc + rmax : rmax * a.ldc + cmax);
   if (a.ktri && a.splitk != 1) return refuse(kn, "triangular k limit with split-K");
+  if (a.rowmask && !guard(kn, "rowmask", ((long)a.tiles_m * BM - 1) / 16, a.nMask))
+    return hipErrorInvalidValue;
   if (!guard(kn, "C", maxC, a.nC)) return hipErrorInvalidValue;
   if (epi == EPI_RES_SCALE || epi == EPI_RES_DERIV) {
     if (!guard(kn, "D", cmax, a.nD)) return hipErrorInvalidValue;

@@ -121,15 +121,21 @@ constexpr int PANEL = 128;  // Cholesky panel width (matches chol.hip)
 // n_ov, at least 16 K-steps per split).
 void minres_splits(int kp, int Np, int Kp, int* splitk, int* splitk1) {
   // K chunks of about `chunk2` (pass 2) and `chunk1` (pass 1) elements bound the
-  // latency chain of each workgroup; GW_TUNE_MINRES="chunk1,chunk2" overrides
+  // latency chain of each workgroup; GW_TUNE_MINRES="chunk1,chunk2" replaces
+  // the rule below by those chunks
   int chunk1 = 288, chunk2 = 512;
-  if (const char* e = getenv("GW_TUNE_MINRES")) sscanf(e, "%d,%d", &chunk1, &chunk2);
-  chunk1 = std::max(64, chunk1);
-  chunk2 = std::max(64, chunk2);
   const int t2 = (kp / 64) * (Np / 128);
+  if (const char* e = getenv("GW_TUNE_MINRES")) {
+    if (sscanf(e, "%d,%d", &chunk1, &chunk2) == 2) {
+      chunk1 = std::max(16, chunk1);
+      chunk2 = std::max(16, chunk2);
+      *splitk = std::max(1, std::min(Kp / chunk2, Kp / 16));
+      *splitk1 = std::max(1, std::min(Np / chunk1, Np / 16));
+      return;
+    }
+  }
   *splitk = std::max(1, std::min(std::max(1024 / std::max(t2, 1), Kp / chunk2), Kp / 64));
   *splitk1 = std::max(1, std::min(Np / chunk1, Np / 16));
-  (void)t2;
 }
 
 long lower_tile_count(int tiles_m, int tiles_n, int BM, int BN) {
@@ -193,6 +199,10 @@ struct gw_ctx {
   bool own_stream = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;    // stage timers
   hipEvent_t ev0b = nullptr, ev1b = nullptr;  // whole-call timer
+  // MINRES convergence polling: per-iteration active counts land in pinned
+  // host memory and are read one iteration late, so the host never idles the GPU
+  hipEvent_t ev_poll[2] = {nullptr, nullptr};
+  int* h_poll = nullptr;
   // device data
   double* d_eps = nullptr;
   double* d_D = nullptr;       // [Kp]
@@ -210,6 +220,7 @@ struct gw_ctx {
   double* d_Linv = nullptr;
   int* d_info = nullptr;
   double* d_scale = nullptr;   // [chunk][Kp]
+  float* d_scale32 = nullptr;  // [chunk][Kp], the same scales rounded for the mixed builds
   double* d_parts = nullptr;   // [chunk][Np/128][Rp] squared-norm partials
   double* d_grid = nullptr;    // [2][Gmax]
   int grid_cap = 0;
@@ -285,8 +296,12 @@ struct gw_ctx {
   ~gw_ctx() {
     if (st) hipStreamSynchronize(st);
     for (void* p : allocs) rt_free(p);
-    for (hipEvent_t e : {ev0, ev1, ev0b, ev1b})
+    for (hipEvent_t e : {ev0, ev1, ev0b, ev1b, ev_poll[0], ev_poll[1]})
       if (e) hipEventDestroy(e);
+    if (h_poll) {
+      if (audit_mode()) free(h_poll);
+      else hipHostFree(h_poll);
+    }
     if (own_stream && st) hipStreamDestroy(st);
   }
 };
@@ -334,7 +349,7 @@ inline long parts_per_g(const gw_ctx* c) { return (long)(c->Np / 128) * c->Rp; }
 
 int setup_work(gw_ctx* c, int G) {
   const long per_g = work_per_g(c);
-  size_t per_bytes = (size_t)per_g * sizeof(double) + (size_t)c->Kp * sizeof(double) +
+  size_t per_bytes = (size_t)per_g * sizeof(double) + (size_t)c->Kp * (sizeof(double) + sizeof(float)) +
                      PANEL * PANEL * sizeof(double) + (size_t)parts_per_g(c) * sizeof(double);
   int chunk = (int)std::max<size_t>(1, c->work_budget / per_bytes);
   if (chunk > G) chunk = G;
@@ -343,11 +358,13 @@ int setup_work(gw_ctx* c, int G) {
   if (c->d_Linv) c->release(c->d_Linv);
   if (c->d_info) c->release(c->d_info);
   if (c->d_scale) c->release(c->d_scale);
+  if (c->d_scale32) c->release(c->d_scale32);
   if (c->d_parts) c->release(c->d_parts);
   c->d_work = nullptr;
   c->d_Linv = nullptr;
   c->d_info = nullptr;
   c->d_scale = nullptr;
+  c->d_scale32 = nullptr;
   c->d_parts = nullptr;
   RCHK(c->alloc((void**)&c->d_work, (size_t)per_g * chunk * sizeof(double)));
   RCHK(c->alloc((void**)&c->d_parts, (size_t)parts_per_g(c) * chunk * sizeof(double)));
@@ -355,6 +372,7 @@ int setup_work(gw_ctx* c, int G) {
   RCHK(c->alloc((void**)&c->d_Linv, (size_t)chunk * PANEL * PANEL * sizeof(double)));
   RCHK(c->alloc((void**)&c->d_info, (size_t)chunk * sizeof(int)));
   RCHK(c->alloc((void**)&c->d_scale, (size_t)chunk * c->Kp * sizeof(double)));
+  RCHK(c->alloc((void**)&c->d_scale32, (size_t)chunk * c->Kp * sizeof(float)));
   c->chunk = chunk;
   return 0;
 }
@@ -400,15 +418,15 @@ int pi_build_chunk(gw_ctx* c, int G, long per_g, long ldA) {
   }
   RCHK(ensure_mixed_operands(c));
   if (c->pi_prec == GW_PI_FP32) {
-    HIPCHK(pi_build_f32(c->d_B32, c->Kp, c->d_scale, c->Kp, c->d_work, ldA, per_g, c->Np, c->Kp,
-                        G, c->ext(c->d_B32, 4), c->ext(c->d_scale, 8), c->ext(c->d_work, 8),
-                        c->st));
+    HIPCHK(pi_build_f32(c->d_B32, c->Kp, c->d_scale32, c->Kp, c->d_work, ldA, per_g, c->Np,
+                        c->Kp, G, c->ext(c->d_B32, 4), c->ext(c->d_scale32, 4),
+                        c->ext(c->d_work, 8), c->st));
     return 0;
   }
   const long nB = std::min({c->ext(c->d_Bhi, 2), c->ext(c->d_Blo, 2), c->ext(c->d_B32, 4)});
-  HIPCHK(pi_build_bf16x3(c->d_Bhi, c->d_Blo, c->Kp, c->d_B32, c->d_scale, c->Kp, c->d_work, ldA,
-                         per_g, c->Np, c->Kp, G, nB, c->ext(c->d_scale, 8), c->ext(c->d_work, 8),
-                         c->st));
+  HIPCHK(pi_build_bf16x3(c->d_Bhi, c->d_Blo, c->Kp, c->d_B32, c->d_scale32, c->Kp, c->d_work,
+                         ldA, per_g, c->Np, c->Kp, G, nB, c->ext(c->d_scale32, 4),
+                         c->ext(c->d_work, 8), c->st));
   return 0;
 }
 
@@ -526,7 +544,8 @@ int build_wtable(gw_ctx* c, const gw_grid* grid, int mode = 0, double* dbg_out =
           c->Kp, c->Rp);
     tm.start(c->st);
     HIPCHK(make_scale_imag(c->d_D, c->Kov, c->Kp, c->d_grid + g0, Gc, c->d_scale,
-                           c->ext(c->d_D, 8), G - g0, c->ext(c->d_scale, 8), c->st));
+                           c->pi_prec == GW_PI_FP64 ? nullptr : c->d_scale32, c->ext(c->d_D, 8),
+                           G - g0, c->ext(c->d_scale, 8), c->ext(c->d_scale32, 4), c->st));
     RCHK(pi_build_chunk(c, Gc, per_g, ldA));
     pi_ms += tm.stop();
     if (mode == 1) {
@@ -578,7 +597,8 @@ int ensure_minres(gw_ctx* c, int kp) {
   if (kp <= c->mr_cap) return 0;
   MinresBufs& m = c->mr;
   void* olds[] = {m.x, m.w, m.w2, m.r1, m.r2, m.y, m.v, m.x0, m.scal, m.V, m.part, m.omega,
-                  m.rtol, m.active, c->d_rhs_idx, c->d_warm, c->d_wc, c->d_dwc, c->d_conv};
+                  m.rtol, m.active, m.blk, c->d_rhs_idx, c->d_warm, c->d_wc, c->d_dwc,
+                  c->d_conv};
   for (void* p : olds) c->release(p);
   const size_t vec = (size_t)kp * c->Np;
   double** vecs[] = {&m.x, &m.w, &m.w2, &m.r1, &m.r2, &m.y, &m.v, &m.x0};
@@ -596,7 +616,8 @@ int ensure_minres(gw_ctx* c, int kp) {
   c->part_cap = part;
   RCHK(c->alloc((void**)&m.omega, (size_t)kp * sizeof(double)));
   RCHK(c->alloc((void**)&m.rtol, (size_t)kp * sizeof(double)));
-  RCHK(c->alloc((void**)&m.active, sizeof(int)));
+  RCHK(c->alloc((void**)&m.active, 2 * sizeof(int)));
+  RCHK(c->alloc((void**)&m.blk, 2 * (size_t)(kp / 16) * sizeof(int)));
   RCHK(c->alloc((void**)&c->d_rhs_idx, (size_t)kp * sizeof(int)));
   RCHK(c->alloc((void**)&c->d_warm, (size_t)kp * sizeof(int)));
   RCHK(c->alloc((void**)&c->d_wc, (size_t)kp * sizeof(double)));
@@ -606,7 +627,9 @@ int ensure_minres(gw_ctx* c, int kp) {
   return 0;
 }
 
-int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long ldc) {
+// mask (nullable): per 16-system block, 0 where every system's vector is zero
+int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long ldc,
+                const int* mask = nullptr) {
   // out = scale(X B_ov): rows = systems, cols = ia
   GemmArgs a{};
   a.A = X; a.lda = c->Np; a.sA = 0;
@@ -615,6 +638,8 @@ int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long l
   a.M = kp; a.N = c->Kp; a.K = c->Np;
   a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Kp / 64;
   a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
+  a.mrows = c->mr.k;
+  a.rowmask = mask; a.nMask = c->ext(mask, sizeof(int));
   a.Dvec = c->d_D; a.wrow = c->mr.omega;
   if (epi == EPI_RES_SCALE && c->mr_splitk1 > 1) {
     // split over N_aux for parallelism: partials, then a deterministic sum + scale
@@ -627,7 +652,7 @@ int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long l
   return 0;
 }
 
-int backproject_pass(gw_ctx* c, int kp) {
+int backproject_pass(gw_ctx* c, int kp, const int* mask = nullptr) {
   // part[s][sys][P] = sum_{ia in split s} V[sys][ia] B_ov[P][ia]
   GemmArgs a{};
   a.A = c->mr.V; a.lda = c->Kp; a.sA = 0;
@@ -637,6 +662,8 @@ int backproject_pass(gw_ctx* c, int kp) {
   a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Np / 128;
   a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1;
   a.splitk = c->mr_splitk; a.sSplit = (long)kp * c->Np;
+  a.mrows = c->mr.k;
+  a.rowmask = mask; a.nMask = c->ext(mask, sizeof(int));
   RCHK(run_gemm(c, a, 2, KC, KC, EPI_STORE));
   return 0;
 }
@@ -690,6 +717,7 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   m.n_scal = c->ext(m.scal, 8);
   m.n_part = c->ext(m.part, 8);
   m.n_V = c->ext(m.V, 8);
+  m.n_blk = c->ext(m.blk, sizeof(int));
   std::vector<int> idx(kp, 0);
   std::vector<double> om(kp, 0.0), tol(kp, c->minres_rtol);
   for (int j = 0; j < k; ++j) {
@@ -727,22 +755,28 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
     HIPCHK(minres_apply(m, c->mr_splitk, c->st));
   }
   HIPCHK(minres_init(m, c->d_R, c->d_rhs_idx, idx.data(), c->Rp, n_warm > 0, c->st));
-  int active = k;
+  HIPCHK(rt_memset(m.active, 0, 2 * sizeof(int), c->st));
+  HIPCHK(rt_memset(m.blk, 0, 2 * (size_t)(kp / 16) * sizeof(int), c->st));
   int itn = 0;
-  // convergence is polled (one 4-byte copy and a stream sync) every `poll`
-  // iterations; converged systems are frozen by the step kernel meanwhile
-  const int poll = 3;
+  // Each iteration's count of still-active systems is copied to pinned host
+  // memory behind its step kernel; the host reads iteration i's count after
+  // queueing iteration i + 1, so polling never drains the stream and at most
+  // one extra iteration (with every system frozen by the step kernel) runs.
   for (itn = 1; itn <= c->minres_max_iter; ++itn) {
-    RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp));
-    RCHK(backproject_pass(c, kp));
+    // v is zero for systems converged by the previous step: skip their blocks
+    const int* mask = itn > 1 ? m.blk + ((itn - 1) & 1) * (kp / 16) : nullptr;
+    RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp, mask));
+    RCHK(backproject_pass(c, kp, mask));
     HIPCHK(minres_apply(m, c->mr_splitk, c->st));
-    const bool check = (itn % poll == 0) || itn == c->minres_max_iter;
-    if (check) HIPCHK(rt_memset(m.active, 0, sizeof(int), c->st));
     HIPCHK(minres_finish_step(m, itn, c->st));
-    if (!check) continue;
-    HIPCHK(rt_memcpy(&active, m.active, sizeof(int), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(rt_sync(c->st));
-    if (active == 0) break;
+    HIPCHK(rt_memcpy(c->h_poll + (itn & 1), m.active + (itn & 1), sizeof(int),
+                     hipMemcpyDeviceToHost, c->st));
+    if (!audit_mode()) HIPCHK(hipEventRecord(c->ev_poll[itn & 1], c->st));
+    if (itn > 1) {
+      const int prev = (itn - 1) & 1;
+      if (!audit_mode()) HIPCHK(hipEventSynchronize(c->ev_poll[prev]));
+      if (c->h_poll[prev] == 0) break;
+    }
   }
   c->timing.minres_iters += std::min(itn, c->minres_max_iter);
   c->timing.minres_systems += k;
@@ -1044,10 +1078,10 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   // stage A
   const size_t per_g = (size_t)(2L * Np + 128) * (Np + 128);
   const size_t parts = (size_t)(Np / 128) * Rp;
-  const size_t per_bytes = per_g * d + (size_t)Kp * d + PANEL * PANEL * d + parts * d;
+  const size_t per_bytes = per_g * d + (size_t)Kp * (d + 4) + PANEL * PANEL * d + parts * d;
   int chunk = (int)std::max<size_t>(1, work_budget / per_bytes);
   if (chunk > G) chunk = G;
-  b += (size_t)chunk * (per_g * d + parts * d + PANEL * PANEL * d + sizeof(int) + (size_t)Kp * d);
+  b += (size_t)chunk * (per_g * d + parts * d + PANEL * PANEL * d + sizeof(int) + (size_t)Kp * (d + 4));
   b += 2 * (size_t)G * d + (size_t)std::max(nR, 1) * G * d;
   // Sigma evaluation buffers
   b += (size_t)n_states * (sizeof(int) + 3 * d);
@@ -1059,7 +1093,8 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   const size_t part = std::max({(size_t)splitk * kp * Np, (size_t)(Kp / 64) * kp,
                                 (size_t)splitk1 * kp * Kp});
   b += 8 * (size_t)kp * Np * d + (size_t)kp * 16 * d + (size_t)kp * Kp * d + part * d +
-       (size_t)kp * (2 * d + 2 * sizeof(int) + 2 * d + sizeof(int)) + sizeof(int);
+       (size_t)kp * (2 * d + 2 * sizeof(int) + 2 * d + sizeof(int)) + 2 * sizeof(int) +
+       2 * (size_t)(kp / 16) * sizeof(int);
   b += (size_t)Rp * Np * d;  // remembered residue solutions
   // dense fallback
   b += (size_t)Np * Np * d + (size_t)Kp * d + (size_t)Np * d + sizeof(int);
@@ -1197,8 +1232,16 @@ int gw_setup(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps, co
   }
   if (!audit_mode() &&
       (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
-       hipEventCreate(&c->ev0b) != hipSuccess || hipEventCreate(&c->ev1b) != hipSuccess))
+       hipEventCreate(&c->ev0b) != hipSuccess || hipEventCreate(&c->ev1b) != hipSuccess ||
+       hipEventCreateWithFlags(&c->ev_poll[0], hipEventDisableTiming) != hipSuccess ||
+       hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) != hipSuccess))
     return cleanup(fail(GW_EDEVICE, "hipEventCreate failed"));
+  if (audit_mode()) {
+    c->h_poll = (int*)calloc(2, sizeof(int));
+    if (!c->h_poll) return cleanup(fail(GW_ENOMEM, "host allocation failed"));
+  } else if (hipHostMalloc((void**)&c->h_poll, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    return cleanup(fail(GW_ENOMEM, "pinned host allocation failed"));
+  }
   if ((rc = c->alloc((void**)&c->d_eps, n_mo * sizeof(double)))) return cleanup(rc);
   if ((rc = c->alloc((void**)&c->d_D, (size_t)c->Kp * sizeof(double)))) return cleanup(rc);
   if ((rc = c->alloc((void**)&c->d_Bov, (size_t)c->Np * c->Kp * sizeof(double)))) return cleanup(rc);

@@ -68,11 +68,15 @@ struct GemmArgs {
   int splitk;                           // >= 1; split s covers k in [s*K/splitk, (s+1)*K/splitk)
   int ktri;                             // B(j, k) = 0 for k > j: stop k at the tile's last B row
   long sSplit;                          // C offset between split-K slabs
+  int mrows;                            // rows >= mrows of each tile column are padding whose
+                                        // MFMAs are skipped (0: every row is computed)
+  const int* rowmask;                   // per 16-row block of A: 0 = rows known to be zero,
+                                        // MFMAs skipped (nullptr: every block is computed)
   double alpha, beta;
   const double* Dvec;                   // transition energies (EPI_RES_*)
   const double* wrow;                   // per-row real frequency (EPI_RES_*)
   // extents (elements reachable from each pointer), checked before launch
-  long nA, nB, nS, nC, nD, nW;
+  long nA, nB, nS, nC, nD, nW, nMask;
 };
 
 hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, hipStream_t st);
@@ -80,11 +84,11 @@ hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, h
 
 // Mixed-precision Pi builds (write 1 - Pi lower tiles in FP64)
 // nB: elements of each B copy, nS: of scale, nA: of the output
-hipError_t pi_build_f32(const float* B32, long ld, const double* scale, long sS, double* A,
+hipError_t pi_build_f32(const float* B32, long ld, const float* scale, long sS, double* A,
                         long ldA, long sA, int Np, int Kp, int G, long nB, long nS, long nA,
                         hipStream_t st);
 hipError_t pi_build_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, long ld, const float* B32,
-                           const double* scale, long sS, double* A, long ldA, long sA, int Np,
+                           const float* scale, long sS, double* A, long ldA, long sA, int Np,
                            int Kp, int G, long nB, long nS, long nA, hipStream_t st);
 hipError_t split_bf16(const double* B, uint16_t* hi, uint16_t* lo, float* b32, long n, hipStream_t st);
 
@@ -109,7 +113,7 @@ hipError_t make_scale_real(const double* D, int Kov, int Kp, double w, double* s
                            long nS, hipStream_t st);
 hipError_t copy_vec(const double* src, double* dst, int n, long nSrc, long nDst, hipStream_t st);
 hipError_t make_scale_imag(const double* D, int Kov, int Kp, const double* xi, int G, double* s,
-                           long nD, long nXi, long nS, hipStream_t st);
+                           float* s32, long nD, long nXi, long nS, long nS32, hipStream_t st);
 
 // Sigma quadrature: per state j: sum_m sum_g W[row_j][m][g] z_g a/(a^2+xi^2) and derivative
 hipError_t sigma_quad(const double* wtab, int n_mo, int G, const int* rowsel, const double* omega,
@@ -126,8 +130,10 @@ struct MinresBufs {
   double *x0;              // [kp][Np] starting guesses (0 for a cold start)
   double *omega;           // [kp] real frequencies
   double *rtol;            // [kp] per-system residual target relative to |b|
-  int *active;             // [1] count of unconverged systems
-  long n_vec, n_scal, n_part, n_V;   // extents in elements (per array)
+  int *active;             // [2] count of unconverged systems after odd / even iterations
+  int *blk;                // [2][kp / 16] 1 where a block of 16 systems still has an
+                           // unconverged one after an odd / even iteration
+  long n_vec, n_scal, n_part, n_V, n_blk;   // extents in elements (per array)
 };
 // rhs_idx values must be < n_rhs_rows (rows of rhs_base, each Np long); the host
 // passes the index array it uploaded so the guard can check it

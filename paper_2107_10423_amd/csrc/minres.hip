@@ -187,11 +187,17 @@ hipError_t minres_apply(MinresBufs& m, int splitk, hipStream_t st) {
   return hipGetLastError();
 }
 
-// One MINRES iteration for every unconverged system, given y = A v.
+// One MINRES iteration for every unconverged system, given y = A v.  The
+// systems still unconverged after iteration itn are counted in
+// active[itn % 2] and flagged per 16-system block in blk[itn % 2]; the other
+// slots (read after the previous iteration) are cleared for the next one.
 __global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int itn) {
   __shared__ double red[4];
   __shared__ double bc[5];
   const int j = blockIdx.x, t = threadIdx.x;
+  const int nb = m.kp / 16;
+  if (j == 0 && t == 0) m.active[(itn + 1) & 1] = 0;
+  if (j == 0 && t < nb) m.blk[((itn + 1) & 1) * nb + t] = 0;
   double* sc = m.scal + j * 16;
   if (sc[S_DONE] != 0.0) return;
   const long o = (long)j * m.Np;
@@ -258,11 +264,15 @@ __global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int itn) {
     m.x[o + p] += phi * wn;
     m.v[o + p] = done ? 0.0 : m.y[o + p] * inv_b;
   }
-  if (t == 0 && !done) atomicAdd(m.active, 1);
+  if (t == 0 && !done) {
+    atomicAdd(m.active + (itn & 1), 1);
+    m.blk[(itn & 1) * nb + j / 16] = 1;
+  }
 }
 
 hipError_t minres_finish_step(MinresBufs& m, int itn, hipStream_t st) {
   if (hipError_t e = check_bufs(m, "minres_step")) return e;
+  GW_GUARD("minres_step", "blk", 2L * (m.kp / 16) - 1, m.n_blk);
   GW_AUDIT_RETURN();
   hipLaunchKernelGGL(k_minres_step, dim3(m.kp), dim3(256), 0, st, m, itn);
   return hipGetLastError();

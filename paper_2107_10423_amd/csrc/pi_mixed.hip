@@ -8,11 +8,10 @@
 //            lo = bf16(x - hi); the product is hi_a hi_b + hi_a lo_b + lo_a hi_b
 //            (the lo lo term is below the split's own error), three
 //            v_mfma_f32_16x16x32_bf16 per k-step, FP32 accumulation over the
-//            whole K (the FP64 flush variant costs the occupancy of a second
-//            workgroup per CU; the accuracy difference is reported by the
-//            precision tests).  The unscaled side B is split once per molecule
-//            and stored; the scaled side B s_g is split on the fly per grid point
-//            while it is staged into LDS.
+//            whole K (the precision tests report the resulting error).  The
+//            unscaled side B is split once per molecule and stored; the scaled
+//            side B s_g is split on the fly per grid point (packed hardware
+//            conversion) while it is staged into LDS.
 //
 // Tiles are 128 x 128 per 256-thread workgroup (2 x 2 wavefronts of 64 x 64),
 // lower-triangular tile map, grid point index fastest and XCD-swizzled as in
@@ -28,6 +27,8 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
 constexpr int FLUSH_K = 512;
 
@@ -80,7 +81,7 @@ hipError_t split_bf16(const double* B, uint16_t* hi, uint16_t* lo, float* b32, l
 // ---------------------------------------------------------------------------
 // FP32 operands, f32 MFMA.  LDS holds [k][row] floats.
 
-__global__ __launch_bounds__(256) void k_pi_f32(const float* B, long ld, const double* scale,
+__global__ __launch_bounds__(256) void k_pi_f32(const float* B, long ld, const float* scale,
                                                 long sS, double* A, long ldA, long sA, int T,
                                                 int Kp, int G) {
   constexpr int BKF = 16;
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(256) void k_pi_f32(const float* B, long ld, const d
   const int g = id % G;
   int I, J;
   lower_tile(id / G, I, J);
-  const double* S = scale + (long)g * sS;
+  const float* S = scale + (long)g * sS;
   const int ar0 = I * 128, br0 = J * 128;
 
   f4 acc[4][4];
@@ -114,12 +115,11 @@ __global__ __launch_bounds__(256) void k_pi_f32(const float* B, long ld, const d
       int row = q >> 2, kq = (q & 3) * 4;
       ra[u] = *reinterpret_cast<const float4*>(B + (long)(ar0 + row) * ld + k0 + kq);
       float4 v = *reinterpret_cast<const float4*>(B + (long)(br0 + row) * ld + k0 + kq);
-      double2 s01 = *reinterpret_cast<const double2*>(S + k0 + kq);
-      double2 s23 = *reinterpret_cast<const double2*>(S + k0 + kq + 2);
-      v.x *= (float)s01.x;
-      v.y *= (float)s01.y;
-      v.z *= (float)s23.x;
-      v.w *= (float)s23.y;
+      const float4 sv = *reinterpret_cast<const float4*>(S + k0 + kq);
+      v.x *= sv.x;
+      v.y *= sv.y;
+      v.z *= sv.z;
+      v.w *= sv.w;
       rb[u] = v;
     }
   };
@@ -196,7 +196,7 @@ static hipError_t check_pi(const char* kn, long ld, long sS, long ldA, long sA, 
   return hipSuccess;
 }
 
-hipError_t pi_build_f32(const float* B32, long ld, const double* scale, long sS, double* A,
+hipError_t pi_build_f32(const float* B32, long ld, const float* scale, long sS, double* A,
                         long ldA, long sA, int Np, int Kp, int G, long nB, long nS, long nA,
                         hipStream_t st) {
   const int T = Np / 128;
@@ -210,40 +210,74 @@ hipError_t pi_build_f32(const float* B32, long ld, const double* scale, long sS,
 }
 
 // ---------------------------------------------------------------------------
-// BF16x3.  LDS holds [row][k] bf16 (k contiguous, 32 per K-step) with a pad,
-// so an MFMA operand (8 consecutive k of one row) is one 16-byte read.
+// BF16x3.  LDS holds each 128 x 32 bf16 operand slab chunk-major in 16-byte
+// slots: chunk q (k = 8 q .. 8 q + 7) of row r sits in slot
+// 128 q + 16 (r / 16) + 4 (r % 4) + ((r % 16) / 4 XOR q).  Staging stores (4
+// lanes per row for the pre-split side, 8 lanes per row for the FP32 side,
+// so that global loads stay coalesced) then spread over all LDS banks.  For
+// the operand reads, the 16 MFMA rows of a block are taken in the permuted
+// order pi(p) = 4 (p % 4) + p / 4, which makes lane l (p = l % 16, chunk
+// g = l / 16) read slot 128 g + (p XOR g): again free of bank conflicts.  The
+// permutation is undone when the accumulators are written.  (All three
+// patterns were checked with the SQ_LDS_BANK_CONFLICT counter on gfx950.)
 
 constexpr int BKB = 32;
-constexpr int LROW = BKB + 8;  // padded row length in bf16 elements
+constexpr int SLAB = 128 * BKB;  // bf16 elements of one operand slab
+
+__device__ __forceinline__ int lds_slot(int row, int ch) {
+  return 8 * (ch * 128 + (row >> 4) * 16 + 4 * (row & 3) + (((row & 15) >> 2) ^ ch));
+}
+// physical row (within a 16-row block) of MFMA row p
+__device__ __forceinline__ int mfma_row(int p) { return 4 * (p & 3) + (p >> 2); }
 
 // Staging of one 32-wide K-step: the unscaled side is loaded pre-split
-// (bf16 hi and lo, 2 x 16 B per thread each); the scaled side is loaded as
-// FP32 (4 x 16 B per thread), multiplied by the grid point's scale and split
-// into hi/lo while it is written to LDS.
+// (bf16 hi and lo, one 16-byte chunk per item, 2 items per thread); the scaled
+// side is loaded as FP32 (4 values per item, 4 items per thread), multiplied
+// by the grid point's scale and split into hi/lo while it is written to LDS.
+// Item maps: A item q -> row q / 4, chunk q % 4; B item q -> row q / 8, chunk
+// (q % 8) / 2, half q % 2.
+__device__ __forceinline__ void a_item(int q, int& row, int& ch) {
+  row = q >> 2;
+  ch = q & 3;
+}
+__device__ __forceinline__ void b_item(int q, int& row, int& ch, int& half) {
+  row = q >> 3;
+  ch = (q & 7) >> 1;
+  half = q & 1;
+}
+
 __device__ __forceinline__ void bf_gload(const uint16_t* Bhi, const uint16_t* Blo,
-                                         const float* B32, const double* S, long ld, int ar0,
+                                         const float* B32, const float* S, long ld, int ar0,
                                          int br0, int k0, int t, u32x4 (&rah)[2],
                                          u32x4 (&ral)[2], f32x4 (&rb)[4]) {
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    int q = t + 256 * u;
-    int row = q >> 2, kq = (q & 3) * 8;
-    rah[u] = *reinterpret_cast<const u32x4*>(Bhi + (long)(ar0 + row) * ld + k0 + kq);
-    ral[u] = *reinterpret_cast<const u32x4*>(Blo + (long)(ar0 + row) * ld + k0 + kq);
+    int row, ch;
+    a_item(t + 256 * u, row, ch);
+    rah[u] = *reinterpret_cast<const u32x4*>(Bhi + (long)(ar0 + row) * ld + k0 + 8 * ch);
+    ral[u] = *reinterpret_cast<const u32x4*>(Blo + (long)(ar0 + row) * ld + k0 + 8 * ch);
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    int q = t + 256 * u;
-    int row = q >> 3, kq = (q & 7) * 4;
-    f32x4 v = *reinterpret_cast<const f32x4*>(B32 + (long)(br0 + row) * ld + k0 + kq);
-    double2 s01 = *reinterpret_cast<const double2*>(S + k0 + kq);
-    double2 s23 = *reinterpret_cast<const double2*>(S + k0 + kq + 2);
-    v.x *= (float)s01.x;
-    v.y *= (float)s01.y;
-    v.z *= (float)s23.x;
-    v.w *= (float)s23.y;
-    rb[u] = v;
+    int row, ch, half;
+    b_item(t + 256 * u, row, ch, half);
+    const int k = k0 + 8 * ch + 4 * half;
+    const f32x4 v = *reinterpret_cast<const f32x4*>(B32 + (long)(br0 + row) * ld + k);
+    rb[u] = v * *reinterpret_cast<const f32x4*>(S + k);
   }
+}
+
+// x = hi + lo for two values at once: hi = bf16(x) and lo = bf16(x - hi), both
+// rounded to nearest even by the packed conversion; returns the packed pairs
+__device__ __forceinline__ void split_pair(float x0, float x1, unsigned& hi, unsigned& lo) {
+  f32x2 x;
+  x.x = x0;
+  x.y = x1;
+  hi = __builtin_bit_cast(unsigned, __builtin_convertvector(x, bf2));
+  f32x2 h;
+  h.x = __uint_as_float(hi << 16);
+  h.y = __uint_as_float(hi & 0xffff0000u);
+  lo = __builtin_bit_cast(unsigned, __builtin_convertvector(x - h, bf2));
 }
 
 __device__ __forceinline__ void bf_lstore(uint16_t* Ah, uint16_t* Al, uint16_t* Bh,
@@ -251,39 +285,74 @@ __device__ __forceinline__ void bf_lstore(uint16_t* Ah, uint16_t* Al, uint16_t* 
                                           const u32x4 (&ral)[2], const f32x4 (&rb)[4]) {
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
-    int q = t + 256 * u;
-    int row = q >> 2, kq = (q & 3) * 8;
-    *reinterpret_cast<u32x4*>(&Ah[row * LROW + kq]) = rah[u];
-    *reinterpret_cast<u32x4*>(&Al[row * LROW + kq]) = ral[u];
+    int row, ch;
+    a_item(t + 256 * u, row, ch);
+    *reinterpret_cast<u32x4*>(&Ah[lds_slot(row, ch)]) = rah[u];
+    *reinterpret_cast<u32x4*>(&Al[lds_slot(row, ch)]) = ral[u];
   }
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    int q = t + 256 * u;
-    int row = q >> 3, kq = (q & 7) * 4;
-    const float x0 = rb[u].x, x1 = rb[u].y, x2 = rb[u].z, x3 = rb[u].w;
-    const unsigned short h0 = bf16_rne(x0), h1 = bf16_rne(x1), h2 = bf16_rne(x2),
-                         h3 = bf16_rne(x3);
-    const unsigned short l0 = bf16_rne(x0 - bf16_to_f(h0)), l1 = bf16_rne(x1 - bf16_to_f(h1)),
-                         l2 = bf16_rne(x2 - bf16_to_f(h2)), l3 = bf16_rne(x3 - bf16_to_f(h3));
+    int row, ch, half;
+    b_item(t + 256 * u, row, ch, half);
+    unsigned h01, l01, h23, l23;
+    split_pair(rb[u].x, rb[u].y, h01, l01);
+    split_pair(rb[u].z, rb[u].w, h23, l23);
     u32x2 hv, lv;
-    hv.x = (unsigned)h0 | ((unsigned)h1 << 16);
-    hv.y = (unsigned)h2 | ((unsigned)h3 << 16);
-    lv.x = (unsigned)l0 | ((unsigned)l1 << 16);
-    lv.y = (unsigned)l2 | ((unsigned)l3 << 16);
-    *reinterpret_cast<u32x2*>(&Bh[row * LROW + kq]) = hv;
-    *reinterpret_cast<u32x2*>(&Bl[row * LROW + kq]) = lv;
+    hv.x = h01;
+    hv.y = h23;
+    lv.x = l01;
+    lv.y = l23;
+    *reinterpret_cast<u32x2*>(&Bh[lds_slot(row, ch) + 4 * half]) = hv;
+    *reinterpret_cast<u32x2*>(&Bl[lds_slot(row, ch) + 4 * half]) = lv;
   }
 }
 
-template <bool FLUSH64>
+// One K-step of the 64 x 64 wave tile: 4 x 4 blocks, three bf16 MFMAs each
+// (lo x hi, hi x lo, hi x hi; the lo x lo term is below the split's error).
+__device__ __forceinline__ void bf_mfma_step(const uint16_t* Ah, const uint16_t* Al,
+                                             const uint16_t* Bh, const uint16_t* Bl, int lane,
+                                             int wm, int wn, f4 (&acc)[4][4]) {
+  // operand fragments: lane l reads MFMA row l % 16 (physical row
+  // mfma_row(l % 16) of the block), k = 8 (l / 16) .. +7
+  const int ko = 8 * ((lane >> 4) * 128 + ((lane & 15) ^ (lane >> 4)));
+  s8 ah[4], al[4], bh[4], bl[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int o = ko + (wm * 4 + i) * 128;
+    ah[i] = *reinterpret_cast<const s8*>(&Ah[o]);
+    al[i] = *reinterpret_cast<const s8*>(&Al[o]);
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int o = ko + (wn * 4 + j) * 128;
+    bh[j] = *reinterpret_cast<const s8*>(&Bh[o]);
+    bl[j] = *reinterpret_cast<const s8*>(&Bl[o]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          __builtin_bit_cast(bf8, al[i]), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          __builtin_bit_cast(bf8, ah[i]), __builtin_bit_cast(bf8, bl[j]), acc[i][j], 0, 0, 0);
+      acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          __builtin_bit_cast(bf8, ah[i]), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+    }
+}
+
+// 128 x 128 tile per workgroup (2 x 2 waves of 64 x 64), FP32 accumulation
+// over the whole K; global loads run one K-step ahead of the MFMAs and LDS is
+// double-buffered.  (Two register stages would cost the second workgroup per
+// CU, which measures slower.)
 __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const uint16_t* Blo,
                                                    long ld, const float* B32,
-                                                   const double* scale, long sS, double* A,
+                                                   const float* scale, long sS, double* A,
                                                    long ldA, long sA, int T, int Kp, int G) {
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][128 * LROW];
-  __shared__ __attribute__((aligned(16))) uint16_t Al[2][128 * LROW];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][128 * LROW];
-  __shared__ __attribute__((aligned(16))) uint16_t Bl[2][128 * LROW];
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Al[2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[2][SLAB];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int total = T * (T + 1) / 2 * G;
@@ -291,19 +360,14 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
   const int g = id % G;
   int I, J;
   lower_tile(id / G, I, J);
-  const double* S = scale + (long)g * sS;
+  const float* S = scale + (long)g * sS;
   const int ar0 = I * 128, br0 = J * 128;
 
   f4 acc[4][4];
-  d4 acc64[FLUSH64 ? 4 : 1][FLUSH64 ? 4 : 1];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int i = 0; i < (FLUSH64 ? 4 : 1); ++i)
-#pragma unroll
-    for (int j = 0; j < (FLUSH64 ? 4 : 1); ++j) acc64[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   // A side: 128 rows x 32 k bf16 = 512 chunks of 8 (16 B) per array -> 2 per thread
   // B side: 128 rows x 32 k fp32 = 1024 float4 -> 4 per thread
   u32x4 rah[2], ral[2];
@@ -315,42 +379,7 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < nk) bf_gload(Bhi, Blo, B32, S, ld, ar0, br0, (kt + 1) * BKB, t, rah, ral, rb);
-    // operand fragments: lane l reads row l % 16, k = 8 (l / 16) .. +7
-    const int ko = 8 * (lane >> 4);
-    s8 ah[4], al[4], bh[4], bl[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = wm * 64 + i * 16 + (lane & 15);
-      ah[i] = *reinterpret_cast<const s8*>(&Ah[cur][row * LROW + ko]);
-      al[i] = *reinterpret_cast<const s8*>(&Al[cur][row * LROW + ko]);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = wn * 64 + j * 16 + (lane & 15);
-      bh[j] = *reinterpret_cast<const s8*>(&Bh[cur][row * LROW + ko]);
-      bl[j] = *reinterpret_cast<const s8*>(&Bl[cur][row * LROW + ko]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-            __builtin_bit_cast(bf8, al[i]), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-            __builtin_bit_cast(bf8, ah[i]), __builtin_bit_cast(bf8, bl[j]), acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-            __builtin_bit_cast(bf8, ah[i]), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
-      }
-    if (FLUSH64 && (((kt + 1) * BKB) % FLUSH_K == 0 || kt + 1 == nk)) {
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc64[FLUSH64 ? i : 0][FLUSH64 ? j : 0][r] += (double)acc[i][j][r];
-          acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-        }
-    }
+    bf_mfma_step(Ah[cur], Al[cur], Bh[cur], Bl[cur], lane, wm, wn, acc);
     if (kt + 1 < nk) bf_lstore(Ah[cur ^ 1], Al[cur ^ 1], Bh[cur ^ 1], Bl[cur ^ 1], t, rah, ral, rb);
     __syncthreads();
   }
@@ -361,22 +390,22 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int row = ar0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-        int col = br0 + wn * 64 + j * 16 + (lane & 15);
-        const double v = FLUSH64 ? acc64[FLUSH64 ? i : 0][FLUSH64 ? j : 0][r] : (double)acc[i][j][r];
-        Ag[(long)row * ldA + col] = (row == col ? 1.0 : 0.0) + 4.0 * v;
+        // accumulator element (4 (l / 16) + r, l % 16) of the MFMA block
+        const int row = ar0 + wm * 64 + i * 16 + mfma_row(4 * (lane >> 4) + r);
+        const int col = br0 + wn * 64 + j * 16 + mfma_row(lane & 15);
+        Ag[(long)row * ldA + col] = (row == col ? 1.0 : 0.0) + 4.0 * (double)acc[i][j][r];
       }
 }
 
 hipError_t pi_build_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, long ld, const float* B32,
-                           const double* scale, long sS, double* A, long ldA, long sA, int Np,
+                           const float* scale, long sS, double* A, long ldA, long sA, int Np,
                            int Kp, int G, long nB, long nS, long nA, hipStream_t st) {
   const int T = Np / 128;
   const long total = (long)T * (T + 1) / 2 * G;
   if (total <= 0) return hipSuccess;
   if (hipError_t e = check_pi("pi_bf16x3", ld, sS, ldA, sA, Np, Kp, G, BKB, nB, nS, nA)) return e;
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_pi_bf16x3<false>, dim3((unsigned)total), dim3(256), 0, st, Bhi, Blo, ld, B32, scale,
+  hipLaunchKernelGGL(k_pi_bf16x3, dim3((unsigned)total), dim3(256), 0, st, Bhi, Blo, ld, B32, scale,
                      sS, A, ldA, sA, T, Kp, G);
   return hipGetLastError();
 }
