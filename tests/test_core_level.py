@@ -1,0 +1,43 @@
+"""(H2O)20-shaped core level: the deepest core state, whose residue term runs
+over every state between its QP energy and the Fermi level (about 100
+right-hand sides per QP step), against the oracle fixture
+tests/golden/h2o20_core.json (written by tests/golden/make_golden.py from
+oracle/ only).  FP64 must match to 1e-10 relative; the mixed-precision Pi
+builds within 1 meV."""
+import json
+import os
+
+import pytest
+
+import gwgen
+
+pytestmark = pytest.mark.gpu
+
+MEV = 1e-3 / 27.211386245988   # 1 meV in Hartree
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def core():
+    with open(os.path.join(HERE, "golden", "h2o20_core.json")) as f:
+        gold = json.load(f)
+    return gold, gwgen.make_config("h2o20_core")
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", None), ("fp32", MEV), ("bf16x3", MEV)])
+def test_deepest_core_level(core, prec, tol):
+    import paper_2107_10423_amd as gwl
+    gold, inp = core
+    r = gold["results"][0]
+    grid = gwl.Grid.gauss_legendre(gold["grid_points"])
+    with gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=gold["qp_tol"]) as c:
+        E, S, Z, st = c.qp(gold["states"], grid)
+        t = c.timing()
+    print(f"{prec}: E = {E[0]:.12f} (oracle {r['E']:.12f}), Z = {Z[0]:.6f}, "
+          f"residue systems {t['minres_systems']}, MINRES iterations {t['minres_iters']}",
+          flush=True)
+    bound = 1e-10 * abs(r["E"]) if tol is None else tol
+    assert abs(E[0] - r["E"]) <= bound, (prec, E[0] - r["E"])
+    assert st[0] & 1 == 0                       # the step tree converged
+    assert abs(Z[0] - r["Z"]) <= (1e-8 if tol is None else 1e-3)
+    assert t["minres_systems"] >= 80            # the residue set spans the valence band
