@@ -73,6 +73,9 @@ typedef struct gw_opts {
                                are factored in chunks that fit */
   int minres_batch;         /* residue systems per MINRES batch, >= 64 (0: 256); bounds
                                the MINRES workspace */
+  int no_graphs;            /* nonzero: launch every MINRES iteration eagerly instead of
+                               replaying it from a captured HIP graph (0: graphs; they
+                               are also skipped on a stream that cannot be captured) */
 } gw_opts;
 
 /* Imaginary-frequency quadrature: nodes xi[n] > 0 and d-xi weights w[n]

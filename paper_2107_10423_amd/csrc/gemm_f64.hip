@@ -53,12 +53,13 @@ __device__ __forceinline__ void decode_tile(const GemmArgs& p, int tile, int& I,
 }
 
 // LDS tiles.  k-contiguous operands keep [row][k] (16 doubles, 128 bytes a
-// row) with the eight 16-byte chunks of a row XOR-permuted by the row pair, so
-// that both the staging stores (8 lanes per row) and the fragment reads (16
-// rows, one chunk each) spread over all 64 LDS banks.  k-major operands keep
-// [k][row] with the two 128-byte halves of each 32-double group swapped on
-// rows k with bit 2 set: the fragment reads of lane groups 4 rows apart then
-// land in opposite bank halves.
+// row) with the eight 16-byte chunks of a row XOR-permuted by the row pair;
+// k-major operands keep [k][row] with the two 128-byte halves of each
+// 32-double group swapped on rows k with bit 1 set.  Together with the
+// K-step permutation below this keeps the staging stores and the fragment
+// reads free of LDS bank conflicts (checked with SQ_LDS_BANK_CONFLICT on
+// gfx950, whose 16-byte reads serve the four 16-lane groups of a wave
+// together: their slot patterns may differ only in the low two slot bits).
 template <int BR, int LAYOUT>
 struct LdsTile {
   static_assert(BR % 32 == 0, "row tiles are multiples of 32");
@@ -66,17 +67,18 @@ struct LdsTile {
 };
 
 __device__ __forceinline__ int kc_chunk(int row, int c) { return c ^ ((row >> 1) & 7); }
-__device__ __forceinline__ int km_col(int k, int col) { return col ^ ((k & 4) << 2); }
+__device__ __forceinline__ int km_col(int k, int col) { return col ^ ((k & 2) << 3); }
 
 // Fragment of one 16-row block for two of the four MFMAs of a K-step (half h
 // = 0, 1).  The summation index inside a K-step is permuted identically for
-// both operands: MFMA ks, lane group g = lane / 16 contracts over k = 4 g + ks,
-// so a lane's values for ks = 2 h, 2 h + 1 form one 16-byte chunk of a
-// k-contiguous tile.
+// both operands: MFMA (h, e), lane group g = lane / 16 contracts over
+// k = 2 g + 8 h + e, so a lane's two values form chunk g + 4 h of a
+// k-contiguous row, and the four lane groups read chunks differing only in
+// their low two bits.
 template <int BR, int LAYOUT>
 __device__ __forceinline__ d2 load_frag(const double* Xs, int row, int g, int h) {
-  if (LAYOUT == KC) return *reinterpret_cast<const d2*>(Xs + row * BK + 2 * kc_chunk(row, 2 * g + h));
-  const int k = 4 * g + 2 * h;
+  if (LAYOUT == KC) return *reinterpret_cast<const d2*>(Xs + row * BK + 2 * kc_chunk(row, g + 4 * h));
+  const int k = 2 * g + 8 * h;
   d2 f;
   f.x = Xs[k * BR + km_col(k, row)];
   f.y = Xs[(k + 1) * BR + km_col(k + 1, row)];

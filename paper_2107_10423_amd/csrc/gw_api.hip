@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -203,6 +204,16 @@ struct gw_ctx {
   // host memory and are read one iteration late, so the host never idles the GPU
   hipEvent_t ev_poll[2] = {nullptr, nullptr};
   int* h_poll = nullptr;
+  // MINRES iterations 2, 3, ... replay a captured graph per (padded batch,
+  // iteration parity); valid while the MINRES workspace is not reallocated
+  std::map<int, std::array<hipGraphExec_t, 2>> mr_graphs;
+  bool graphs_off = false;     // opts.no_graphs, or the stream cannot be captured
+  void drop_graphs() {
+    for (auto& kv : mr_graphs)
+      for (hipGraphExec_t g : kv.second)
+        if (g) hipGraphExecDestroy(g);
+    mr_graphs.clear();
+  }
   // device data
   double* d_eps = nullptr;
   double* d_D = nullptr;       // [Kp]
@@ -295,6 +306,7 @@ struct gw_ctx {
 
   ~gw_ctx() {
     if (st) hipStreamSynchronize(st);
+    drop_graphs();
     for (void* p : allocs) rt_free(p);
     for (hipEvent_t e : {ev0, ev1, ev0b, ev1b, ev_poll[0], ev_poll[1]})
       if (e) hipEventDestroy(e);
@@ -595,6 +607,7 @@ int build_wtable(gw_ctx* c, const gw_grid* grid, int mode = 0, double* dbg_out =
 
 int ensure_minres(gw_ctx* c, int kp) {
   if (kp <= c->mr_cap) return 0;
+  c->drop_graphs();
   MinresBufs& m = c->mr;
   void* olds[] = {m.x, m.w, m.w2, m.r1, m.r2, m.y, m.v, m.x0, m.scal, m.V, m.part, m.omega,
                   m.rtol, m.active, m.blk, c->d_rhs_idx, c->d_warm, c->d_wc, c->d_dwc,
@@ -638,7 +651,7 @@ int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long l
   a.M = kp; a.N = c->Kp; a.K = c->Np;
   a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Kp / 64;
   a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
-  a.mrows = c->mr.k;
+  a.mrows = mask ? 0 : c->mr.k;   // a mask also marks the padding systems
   a.rowmask = mask; a.nMask = c->ext(mask, sizeof(int));
   a.Dvec = c->d_D; a.wrow = c->mr.omega;
   if (epi == EPI_RES_SCALE && c->mr_splitk1 > 1) {
@@ -662,9 +675,54 @@ int backproject_pass(gw_ctx* c, int kp, const int* mask = nullptr) {
   a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Np / 128;
   a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1;
   a.splitk = c->mr_splitk; a.sSplit = (long)kp * c->Np;
-  a.mrows = c->mr.k;
+  a.mrows = mask ? 0 : c->mr.k;
   a.rowmask = mask; a.nMask = c->ext(mask, sizeof(int));
   RCHK(run_gemm(c, a, 2, KC, KC, EPI_STORE));
+  return 0;
+}
+
+// One MINRES iteration: both operator passes (from the second iteration on
+// skipping the 16-system blocks the previous step found converged), the
+// apply and step kernels, and the copy of this iteration's count of active
+// systems to pinned host memory.  Its launches depend on the iteration only
+// through its parity.
+int minres_iteration(gw_ctx* c, int kp, int itn) {
+  MinresBufs& m = c->mr;
+  const int par = itn & 1;
+  const int* mask = itn > 1 ? m.blk + (par ^ 1) * (kp / 16) : nullptr;
+  RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp, mask));
+  RCHK(backproject_pass(c, kp, mask));
+  HIPCHK(minres_apply(m, c->mr_splitk, c->st));
+  HIPCHK(minres_finish_step(m, par, c->st));
+  HIPCHK(rt_memcpy(c->h_poll + par, m.active + par, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  return 0;
+}
+
+// The same iteration (itn >= 2) replayed from a graph captured on first use.
+// A stream that refuses capture switches the context to eager launches.
+int minres_iteration_graph(gw_ctx* c, int kp, int itn) {
+  const int par = itn & 1;
+  auto& slot = c->mr_graphs[kp];   // value-initialised: no graphs yet
+  if (!slot[par]) {
+    if (hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      c->graphs_off = true;
+      return minres_iteration(c, kp, itn);
+    }
+    const int rc = minres_iteration(c, kp, itn);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(c->st, &g);
+    if (rc != 0 || e != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      if (rc != 0) return rc;
+      HIPCHK(e);
+    }
+    const hipError_t ei = hipGraphInstantiate(&slot[par], g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    HIPCHK(ei);
+    trace("minres graph captured kp=%d parity=%d", kp, par);
+  }
+  HIPCHK(hipGraphLaunch(slot[par], c->st));
   return 0;
 }
 
@@ -763,14 +821,10 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   // queueing iteration i + 1, so polling never drains the stream and at most
   // one extra iteration (with every system frozen by the step kernel) runs.
   for (itn = 1; itn <= c->minres_max_iter; ++itn) {
-    // v is zero for systems converged by the previous step: skip their blocks
-    const int* mask = itn > 1 ? m.blk + ((itn - 1) & 1) * (kp / 16) : nullptr;
-    RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp, mask));
-    RCHK(backproject_pass(c, kp, mask));
-    HIPCHK(minres_apply(m, c->mr_splitk, c->st));
-    HIPCHK(minres_finish_step(m, itn, c->st));
-    HIPCHK(rt_memcpy(c->h_poll + (itn & 1), m.active + (itn & 1), sizeof(int),
-                     hipMemcpyDeviceToHost, c->st));
+    if (itn >= 2 && !c->graphs_off && !audit_mode())
+      RCHK(minres_iteration_graph(c, kp, itn));
+    else
+      RCHK(minres_iteration(c, kp, itn));
     if (!audit_mode()) HIPCHK(hipEventRecord(c->ev_poll[itn & 1], c->st));
     if (itn > 1) {
       const int prev = (itn - 1) & 1;
@@ -1195,6 +1249,7 @@ int gw_setup(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps, co
   c->mem_budget = o.mem_budget_bytes;
   if (o.work_budget_bytes > 0) c->work_budget = o.work_budget_bytes;
   if (o.minres_batch > 0) c->minres_batch = std::max(64, o.minres_batch);
+  c->graphs_off = o.no_graphs != 0;
   c->eps.assign(eps, eps + n_mo);
   c->dsig_x.assign(n_mo, 0.0);
   if (o.dsig_x) {

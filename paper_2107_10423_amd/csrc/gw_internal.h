@@ -151,7 +151,8 @@ hipError_t minres_finalize(MinresBufs& m, double* xcache, const int* rhs_idx,
 hipError_t minres_scale_sum(MinresBufs& m, int splits, const double* D, long nD, hipStream_t st);
 // y = v + 4 sum_s part[s] (the operator applied to v), one thread per element
 hipError_t minres_apply(MinresBufs& m, int splitk, hipStream_t st);
-hipError_t minres_finish_step(MinresBufs& m, int itn, hipStream_t st);
+// one MINRES step per unconverged system; par = global iteration parity
+hipError_t minres_finish_step(MinresBufs& m, int par, hipStream_t st);
 hipError_t minres_results(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
                           int n_rhs_rows, int n_deriv_parts, double* wc, double* dwc, int* conv,
                           long n_out, hipStream_t st);

@@ -187,23 +187,26 @@ hipError_t minres_apply(MinresBufs& m, int splitk, hipStream_t st) {
   return hipGetLastError();
 }
 
-// One MINRES iteration for every unconverged system, given y = A v.  The
-// systems still unconverged after iteration itn are counted in
-// active[itn % 2] and flagged per 16-system block in blk[itn % 2]; the other
-// slots (read after the previous iteration) are cleared for the next one.
-__global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int itn) {
+// One MINRES iteration for every unconverged system, given y = A v.  Each
+// system counts its own iterations (S_ITERS), so the kernel depends on the
+// global iteration only through its parity `par`: the systems still
+// unconverged afterwards are counted in active[par] and flagged per 16-system
+// block in blk[par]; the other slots (read after the previous iteration) are
+// cleared for the next one.  This keeps the launch replayable from a graph.
+__global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int par) {
   __shared__ double red[4];
   __shared__ double bc[5];
   const int j = blockIdx.x, t = threadIdx.x;
   const int nb = m.kp / 16;
-  if (j == 0 && t == 0) m.active[(itn + 1) & 1] = 0;
-  if (j == 0 && t < nb) m.blk[((itn + 1) & 1) * nb + t] = 0;
+  if (j == 0 && t == 0) m.active[par ^ 1] = 0;
+  if (j == 0 && t < nb) m.blk[(par ^ 1) * nb + t] = 0;
   double* sc = m.scal + j * 16;
   if (sc[S_DONE] != 0.0) return;
   const long o = (long)j * m.Np;
   const double beta = sc[S_BETA], oldb = sc[S_OLDB];
+  const double itn = sc[S_ITERS] + 1.0;   // this system's iteration number
   // y = A v (- (beta/oldb) r1 from the second iteration on)
-  const double c1 = (itn >= 2) ? beta / oldb : 0.0;
+  const double c1 = (itn >= 2.0) ? beta / oldb : 0.0;
   double sa = 0.0;
   for (int p = t; p < m.Np; p += 256) {
     double yv = m.y[o + p] - c1 * m.r1[o + p];
@@ -239,7 +242,7 @@ __global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int itn) {
     sc[S_CS] = cs_n;
     sc[S_SN] = sn_n;
     sc[S_PHIBAR] = phibar;
-    sc[S_ITERS] = (double)itn;
+    sc[S_ITERS] = itn;
     // residual |b - A x| = phibar (the start vector is b - A x0); stop relative to |b|
     const double ratio = phibar / sc[S_BNORM];
     sc[S_RATIO] = ratio;
@@ -265,16 +268,17 @@ __global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int itn) {
     m.v[o + p] = done ? 0.0 : m.y[o + p] * inv_b;
   }
   if (t == 0 && !done) {
-    atomicAdd(m.active + (itn & 1), 1);
-    m.blk[(itn & 1) * nb + j / 16] = 1;
+    atomicAdd(m.active + par, 1);
+    m.blk[par * nb + j / 16] = 1;
   }
 }
 
-hipError_t minres_finish_step(MinresBufs& m, int itn, hipStream_t st) {
+hipError_t minres_finish_step(MinresBufs& m, int par, hipStream_t st) {
   if (hipError_t e = check_bufs(m, "minres_step")) return e;
   GW_GUARD("minres_step", "blk", 2L * (m.kp / 16) - 1, m.n_blk);
+  if (par != 0 && par != 1) return refuse("minres_step", "parity");
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_minres_step, dim3(m.kp), dim3(256), 0, st, m, itn);
+  hipLaunchKernelGGL(k_minres_step, dim3(m.kp), dim3(256), 0, st, m, par);
   return hipGetLastError();
 }
 

@@ -271,6 +271,30 @@ def test_core_level_residues_many_systems():
     assert t["minres_systems"] >= 11
 
 
+def test_minres_graph_replay_matches_eager():
+    # MINRES iterations 2.. replay captured graphs (two parities, several padded
+    # batch sizes across QP rounds, host work and synchronisation between the
+    # replays); results must equal the eagerly launched ones bit for bit, on
+    # the first call and on a second call that reuses the captured graphs
+    shape = gwgen.custom_shape(12, 70, 220, n_core=3)
+    inp = gwgen.make_inputs(shape, 44, [0, 5, 11, 12])
+    g = gwl().Grid.gauss_legendre(32)
+    states = [0, 5, 11, 12]
+    with ctx(inp, qp_tol=1e-12, graphs=False) as c:
+        ref = c.qp(states, g)
+        t_ref = c.timing()
+    with ctx(inp, qp_tol=1e-12) as c:
+        first = c.qp(states, g)
+        t_first = c.timing()
+        c.reset_cache()
+        second = c.qp(states, g)
+    assert t_ref["minres_iters"] > 2 * t_ref["qp_rounds"]   # graphs were replayed
+    assert t_first["minres_iters"] == t_ref["minres_iters"]
+    for out in (first, second):
+        for a, b in zip(out, ref):
+            assert np.array_equal(a, b)
+
+
 # ---------------------------------------------------------------- full size
 
 @pytest.mark.parametrize("prec,tol", [("fp64", None), ("bf16x3", MEV), ("fp32", MEV)])
