@@ -234,8 +234,11 @@ typedef struct gw_server_stats {
 
 /* GW_EINVAL for bad options, GW_EDEVICE if no device or stream is usable. */
 int gw_server_create(gw_server** s, const gw_server_opts* opts);
-/* Copies the request; *ticket identifies it.  GW_EINVAL for a malformed
- * request, GW_ENOMEM if its footprint exceeds the whole budget. */
+/* Checks the request's inputs as gw_setup does, then copies them (into
+ * pinned host memory from a pool the server reuses, while it stays within
+ * 64 GiB; pageable memory beyond) on the calling thread; *ticket identifies
+ * the request.  GW_EINVAL for a malformed request, GW_ENOMEM if its footprint
+ * exceeds the whole budget. */
 int gw_server_submit(gw_server* s, const gw_request* r, unsigned long long* ticket);
 /* 1 while pending or running; 0 when done: E_qp, sigma_c, Z, status
  * ([n_states] each, each nullable) and info (nullable) are filled and the

@@ -16,6 +16,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/gw.h"
@@ -1155,6 +1156,74 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   return b;
 }
 
+// First flat index of a non-finite value in src[0, n), or -1; with dst, src is
+// also copied to dst chunk by chunk (the check then reads the copy while it is
+// still in cache).  Exponent-bit test over chunks (vectorisable); arrays above
+// 4 Mi values are split over up to 8 host threads.
+long copy_check_finite(double* dst, const double* src, long n) {
+  auto scan = [dst, src](long lo, long hi) -> long {
+    const long CH = 4096;
+    for (long c = lo; c < hi; c += CH) {
+      const long e = std::min(hi, c + CH);
+      const double* x = src + c;
+      if (dst) {
+        memcpy(dst + c, src + c, (size_t)(e - c) * sizeof(double));
+        x = dst + c;
+      }
+      unsigned long long bad = 0;
+      for (long i = 0; i < e - c; ++i) {
+        unsigned long long b;
+        memcpy(&b, x + i, sizeof b);
+        bad |= ((b >> 52) & 0x7ffULL) == 0x7ffULL;
+      }
+      if (bad)
+        for (long i = c; i < e; ++i)
+          if (!std::isfinite(src[i])) return i;
+    }
+    return -1;
+  };
+  const long big = 1L << 22;
+  if (n < big) return scan(0, n);
+  const int nt = 8;
+  std::vector<long> found(nt, -1);
+  std::vector<std::thread> th;
+  const long per = (n + nt - 1) / nt;
+  for (int t = 0; t < nt; ++t)
+    th.emplace_back([&, t] { found[t] = scan(std::min(n, t * per), std::min(n, (t + 1) * per)); });
+  for (auto& t : th) t.join();
+  for (long f : found)
+    if (f >= 0) return f;
+  return -1;
+}
+
+// Host-side checks of gw_setup's inputs (sizes, ordering, finiteness; the
+// finiteness of B_ov and B_rows only when check_arrays).
+int validate_inputs(int n_mo, int n_occ, int n_aux, const double* eps, const double* B_ov,
+                    int n_rows, const int* row_ids, const double* B_rows, bool check_arrays) {
+  if (n_mo < 2 || n_occ < 1 || n_occ >= n_mo || n_aux < 1 || n_rows < 0)
+    return fail(GW_EINVAL, "bad sizes: n_mo=%d n_occ=%d n_aux=%d n_rows=%d", n_mo, n_occ, n_aux,
+                n_rows);
+  if (!eps || !B_ov || (n_rows > 0 && (!row_ids || !B_rows)))
+    return fail(GW_EINVAL, "NULL input array");
+  for (int i = 0; i < n_mo; ++i) {
+    if (!std::isfinite(eps[i])) return fail(GW_EINVAL, "eps[%d] is not finite", i);
+    if (i > 0 && !(eps[i] > eps[i - 1])) return fail(GW_EINVAL, "eps is not strictly ascending at %d", i);
+  }
+  const long Kov = (long)n_occ * (n_mo - n_occ);
+  if (Kov > 0x3fffffffL || (long)n_aux * n_mo > 0x3fffffffL)
+    return fail(GW_EINVAL, "sizes too large");
+  if (!check_arrays) return 0;
+  long f = copy_check_finite(nullptr, B_ov, (long)n_aux * Kov);
+  if (f >= 0) return fail(GW_EINVAL, "B_ov has a non-finite entry at %ld", f);
+  f = copy_check_finite(nullptr, B_rows, (long)n_rows * n_mo * n_aux);
+  if (f >= 0) return fail(GW_EINVAL, "B_rows has a non-finite entry at %ld", f);
+  return 0;
+}
+
+int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps,
+                    const double* B_ov, int n_rows, const int* row_ids, const double* B_rows,
+                    const gw_opts* opts);
+
 // ===========================================================================
 // C-ABI
 
@@ -1210,22 +1279,18 @@ int gw_setup(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps, co
              int n_rows, const int* row_ids, const double* B_rows, const gw_opts* opts) {
   if (!out) return fail(GW_EINVAL, "ctx pointer is NULL");
   *out = nullptr;
-  if (n_mo < 2 || n_occ < 1 || n_occ >= n_mo || n_aux < 1 || n_rows < 0)
-    return fail(GW_EINVAL, "bad sizes: n_mo=%d n_occ=%d n_aux=%d n_rows=%d", n_mo, n_occ, n_aux,
-                n_rows);
-  if (!eps || !B_ov || (n_rows > 0 && (!row_ids || !B_rows)))
-    return fail(GW_EINVAL, "NULL input array");
-  for (int i = 0; i < n_mo; ++i) {
-    if (!std::isfinite(eps[i])) return fail(GW_EINVAL, "eps[%d] is not finite", i);
-    if (i > 0 && !(eps[i] > eps[i - 1])) return fail(GW_EINVAL, "eps is not strictly ascending at %d", i);
-  }
+  if (int rc = validate_inputs(n_mo, n_occ, n_aux, eps, B_ov, n_rows, row_ids, B_rows, true))
+    return rc;
+  return setup_validated(out, n_mo, n_occ, n_aux, eps, B_ov, n_rows, row_ids, B_rows, opts);
+}
+
+}  // extern "C"
+
+int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps,
+                    const double* B_ov, int n_rows, const int* row_ids, const double* B_rows,
+                    const gw_opts* opts) {
+  *out = nullptr;
   const long Kov = (long)n_occ * (n_mo - n_occ);
-  if (Kov > 0x3fffffffL || (long)n_aux * n_mo > 0x3fffffffL)
-    return fail(GW_EINVAL, "sizes too large");
-  for (long i = 0; i < (long)n_aux * Kov; ++i)
-    if (!std::isfinite(B_ov[i])) return fail(GW_EINVAL, "B_ov has a non-finite entry at %ld", i);
-  for (long i = 0; i < (long)n_rows * n_mo * n_aux; ++i)
-    if (!std::isfinite(B_rows[i])) return fail(GW_EINVAL, "B_rows has a non-finite entry at %ld", i);
   gw_opts o{};
   if (opts) o = *opts;
   if (o.pi_prec < 0 || o.pi_prec > 2) return fail(GW_EINVAL, "unknown pi_prec %d", o.pi_prec);
@@ -1327,6 +1392,8 @@ int gw_setup(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps, co
   *out = c;
   return 0;
 }
+
+extern "C" {
 
 void gw_free(gw_ctx* ctx) { delete ctx; }
 

@@ -1,7 +1,9 @@
 // Request server (include/gw.h, "serving"): first-come-first-served
 // admission by device-memory footprint, one HIP stream per pipeline slot,
 // each admitted request run through exactly the gw_setup / gw_qp path with
-// its context capped at its reserved footprint.
+// its context capped at its reserved footprint.  Inputs are validated and
+// copied into pinned host memory (a reused pool) on the submitting thread, so
+// a slot's upload is one DMA that overlaps the other slots' kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -18,15 +20,70 @@
 
 size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, int G,
                        int pi_prec, size_t work_budget, int minres_batch);
+int validate_inputs(int n_mo, int n_occ, int n_aux, const double* eps, const double* B_ov,
+                    int n_rows, const int* row_ids, const double* B_rows, bool check_arrays);
+long copy_check_finite(double* dst, const double* src, long n);
+int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps,
+                    const double* B_ov, int n_rows, const int* row_ids, const double* B_rows,
+                    const gw_opts* opts);
 
 namespace {
 
 using clk = std::chrono::steady_clock;
 
+// Pinned host buffers, kept for reuse in power-of-two size classes (from 64
+// MiB) up to a total cap; a request that finds no pinned buffer within the cap
+// keeps pageable memory.
+struct PinnedPool {
+  std::mutex mu;
+  std::multimap<size_t, void*> free_bufs;
+  size_t total = 0, cap = 0;
+  static size_t size_class(size_t b) {
+    size_t s = 64ull << 20;
+    while (s < b) s <<= 1;
+    return s;
+  }
+  void* acquire(size_t bytes, size_t* got) {
+    const size_t want = size_class(bytes);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = free_bufs.lower_bound(want);
+    if (it != free_bufs.end() && it->first <= 2 * want) {
+      void* p = it->second;
+      *got = it->first;
+      free_bufs.erase(it);
+      return p;
+    }
+    while (total + want > cap && !free_bufs.empty()) {  // make room: drop the largest free buffer
+      auto last = std::prev(free_bufs.end());
+      hipHostFree(last->second);
+      total -= last->first;
+      free_bufs.erase(last);
+    }
+    if (total + want > cap) return nullptr;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) return nullptr;
+    total += want;
+    *got = want;
+    return p;
+  }
+  void release(void* p, size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu);
+    free_bufs.emplace(bytes, p);
+  }
+  ~PinnedPool() {
+    for (auto& kv : free_bufs) hipHostFree(kv.second);
+  }
+};
+
 struct Req {
   unsigned long long ticket = 0;
   int n_mo = 0, n_occ = 0, n_aux = 0, n_rows = 0;
-  std::vector<double> eps, B_ov, B_rows, dsig_x;
+  std::vector<double> eps, dsig_x;
+  // B_ov [n_aux][n_occ n_virt] then B_rows [n_rows][n_mo][n_aux]: pinned pool
+  // memory (pinned_bytes > 0) or the pageable fallback
+  double* B = nullptr;
+  size_t pinned_bytes = 0;
+  std::vector<double> B_pageable;
   std::vector<int> row_ids, states;
   size_t footprint = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
@@ -41,6 +98,7 @@ struct Req {
 
 struct gw_server {
   gw_server_opts opts{};
+  PinnedPool pinned;
   std::vector<double> xi, w;
   size_t budget = 0, reserved = 0, peak_reserved = 0;
   int active = 0, peak_active = 0;
@@ -104,8 +162,14 @@ struct gw_server {
     o.mem_budget_bytes = r->footprint;
     o.work_budget_bytes = opts.work_budget_bytes;
     gw_ctx* c = nullptr;
-    int rc = gw_setup(&c, r->n_mo, r->n_occ, r->n_aux, r->eps.data(), r->B_ov.data(), r->n_rows,
-                      r->row_ids.data(), r->B_rows.data(), &o);
+    const size_t nov = (size_t)r->n_occ * (r->n_mo - r->n_occ);
+    int rc = setup_validated(&c, r->n_mo, r->n_occ, r->n_aux, r->eps.data(), r->B, r->n_rows,
+                             r->row_ids.data(), r->B + nov * r->n_aux, &o);
+    // the device holds its copies now (setup synchronises its stream)
+    if (r->pinned_bytes) pinned.release(r->B, r->pinned_bytes);
+    r->B = nullptr;
+    r->pinned_bytes = 0;
+    std::vector<double>().swap(r->B_pageable);
     const int n = (int)r->states.size();
     r->E.assign(n, 0.0);
     r->S.assign(n, 0.0);
@@ -117,9 +181,6 @@ struct gw_server {
                  r->status.data());
     }
     gw_free(c);
-    // the input copies are no longer needed
-    std::vector<double>().swap(r->B_ov);
-    std::vector<double>().swap(r->B_rows);
     r->rc = rc;
   }
 };
@@ -152,6 +213,7 @@ int gw_server_create(gw_server** out, const gw_server_opts* opts) {
     }
     s->budget = free_b / 10 * 8;
   }
+  s->pinned.cap = 64ull << 30;
   for (int i = 0; i < ns; ++i) {
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
@@ -171,15 +233,31 @@ int gw_server_submit(gw_server* s, const gw_request* q, unsigned long long* tick
   if (q->n_mo < 2 || q->n_occ < 1 || q->n_occ >= q->n_mo || q->n_aux < 1 || q->n_rows < 1 ||
       q->n_states < 1 || !q->eps || !q->B_ov || !q->row_ids || !q->B_rows || !q->states)
     return GW_EINVAL;
+  if (int rc = validate_inputs(q->n_mo, q->n_occ, q->n_aux, q->eps, q->B_ov, q->n_rows,
+                               q->row_ids, q->B_rows, false))
+    return rc;
   Req* r = new Req();
   r->n_mo = q->n_mo;
   r->n_occ = q->n_occ;
   r->n_aux = q->n_aux;
   r->n_rows = q->n_rows;
   const size_t nov = (size_t)q->n_occ * (q->n_mo - q->n_occ);
+  const size_t n_bov = nov * q->n_aux, n_brows = (size_t)q->n_rows * q->n_mo * q->n_aux;
   r->eps.assign(q->eps, q->eps + q->n_mo);
-  r->B_ov.assign(q->B_ov, q->B_ov + nov * q->n_aux);
-  r->B_rows.assign(q->B_rows, q->B_rows + (size_t)q->n_rows * q->n_mo * q->n_aux);
+  r->B = (double*)s->pinned.acquire((n_bov + n_brows) * sizeof(double), &r->pinned_bytes);
+  if (!r->B) {
+    r->pinned_bytes = 0;
+    r->B_pageable.resize(n_bov + n_brows);
+    r->B = r->B_pageable.data();
+  }
+  // copy and check finiteness in one pass
+  const long bad_ov = copy_check_finite(r->B, q->B_ov, (long)n_bov);
+  const long bad_rows = bad_ov >= 0 ? -1 : copy_check_finite(r->B + n_bov, q->B_rows, (long)n_brows);
+  if (bad_ov >= 0 || bad_rows >= 0) {
+    if (r->pinned_bytes) s->pinned.release(r->B, r->pinned_bytes);
+    delete r;
+    return GW_EINVAL;
+  }
   r->row_ids.assign(q->row_ids, q->row_ids + q->n_rows);
   r->states.assign(q->states, q->states + q->n_states);
   if (q->dsig_x) r->dsig_x.assign(q->dsig_x, q->dsig_x + q->n_mo);
@@ -189,6 +267,7 @@ int gw_server_submit(gw_server* s, const gw_request* q, unsigned long long* tick
   r->footprint = footprint_bytes(q->n_mo, q->n_occ, q->n_aux, q->n_rows, q->n_states,
                                  (int)s->xi.size(), s->opts.pi_prec, s->opts.work_budget_bytes, 256);
   if (r->footprint > s->budget) {
+    if (r->pinned_bytes) s->pinned.release(r->B, r->pinned_bytes);
     delete r;
     return GW_ENOMEM;
   }
