@@ -56,24 +56,40 @@ def recorded_traffic(kernel):
 def time_path(gwl, inp, states, grid, prec, steps, warmup):
     import numpy as np
     import torch
-    with gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=1e-10) as c:
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter()
+    c = gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=1e-10)
+    torch.cuda.synchronize()
+    setup_ms = 1e3 * (time.perf_counter() - t_setup)   # host -> HBM upload and setup
+    with c:
         for _ in range(warmup):
             c.reset_cache()
             out = c.qp(states, grid)
         torch.cuda.synchronize()
-        pi_ms, tot_ms, stages = [], [], []
+        pi_ms, tot_ms, stages, each = [], [], [], []
         t0 = time.perf_counter()
         for _ in range(steps):
+            t1 = time.perf_counter()
             c.reset_cache()
             out = c.qp(states, grid)
+            each.append(1e3 * (time.perf_counter() - t1))
             t = c.timing()
             pi_ms.append(t["pi_ms"])
             tot_ms.append(t["total_ms"])
             stages.append(t)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        # the same call with the W^c table kept (a second molecule-independent
+        # number: QP energies only, stage A cached)
+        cached = []
+        for _ in range(max(3, steps // 2)):
+            t1 = time.perf_counter()
+            c.qp(states, grid)
+            cached.append(1e3 * (time.perf_counter() - t1))
     E = out[0]
     return dict(E=E, Z=out[2], status=out[3], wall_s=wall, ms_per_step=1e3 * wall / steps,
+                median_ms=float(np.median(each)), setup_ms=setup_ms,
+                cached_ms=float(np.median(cached)),
                 pi_ms=float(np.mean(pi_ms)), total_ms=float(np.mean(tot_ms)),
                 stages={k: float(np.mean([s[k] for s in stages])) for k in stages[0]})
 
@@ -291,6 +307,8 @@ def main():
             "frac": round(h["pi_tflops"] / PEAK_TFLOPS[head], 4),
             "traffic": recorded_traffic(kname),
             "flops_per_launch": flops, "launch_ms": round(h["pi_ms"], 4),
+            "traffic_gb_per_s": (round(recorded_traffic(kname) / (h["pi_ms"] / 1e3) / 1e9, 1)
+                                 if recorded_traffic(kname) else None),
             "note": "achieved = algorithmic flops N_aux(N_aux+1)N_ov per grid point x 64 grid "
                     "points / launch time (HIP events on the context stream); BF16x3 issues 3 "
                     "bf16 MFMA products per algorithmic product, so its issued rate is 3x"}
@@ -307,6 +325,9 @@ def main():
                    "n_occ": 50, "n_virt": 380, "n_aux": 1120, "grid_points": 64, "states": 10},
         "roofline": roof,
         "paths": {p: {"qp_per_s": round(r["qp_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
+                      "median_ms_per_step": round(r["median_ms"], 3),
+                      "setup_ms": round(r["setup_ms"], 1),
+                      "cached_wtable_qp_per_s": round(len(states) / (r["cached_ms"] / 1e3), 3),
                       "pi_ms": round(r["pi_ms"], 3), "pi_tflops": round(r["pi_tflops"], 2),
                       "pi_frac_of_peak": round(r["pi_tflops"] / PEAK_TFLOPS[p], 4),
                       "max_err_mev_vs_oracle": r["err_mev"],

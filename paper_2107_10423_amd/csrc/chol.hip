@@ -2,7 +2,7 @@
 // screened-interaction reduction.
 //
 // The matrix of grid point g is stored augmented: rows [0, Np) hold 1 - Pi
-// (lower triangle), rows [Np, 2 Np) start as the identity.  A right-looking
+// (lower triangle), rows [Np, 2 Np) start as the identity.  A left-looking
 // blocked Cholesky (panel width 128) run over the rows factors 1 - Pi = L L^T
 // and, because the appended rows are treated like rows below the diagonal,
 // leaves (L^-1 I)^T = L^-T in them (row Np + s holds column s of L^-1).
@@ -220,19 +220,24 @@ hipError_t make_scale_imag(const double* D, int Kov, int Kp, const double* xi, i
 
 // Imaginary-axis part of Re Sigma^c and its omega-derivative for n states.
 // sig_j = -(1/pi) sum_m sum_g W[r_j][m][g] z_g a/(a^2 + xi_g^2), a = omega_j - eps_m.
-__global__ __launch_bounds__(256) void k_sigma_quad(const double* wtab, int n_mo, int G,
-                                                    const int* rowsel, const double* omega,
-                                                    const double* eps, const double* xi,
-                                                    const double* z, double* sig,
-                                                    double* dsig) {
+// The n_mo G terms of a state are split over QUAD_SLICES workgroups whose
+// partial sums are added in a fixed order by a second small kernel.
+constexpr int QUAD_SLICES = 16;
+
+__global__ __launch_bounds__(256) void k_sigma_quad_part(const double* wtab, int n_mo, int G,
+                                                         const int* rowsel, const double* omega,
+                                                         const double* eps, const double* xi,
+                                                         const double* z, double* part) {
   __shared__ double rs[256], rd[256];
-  const int j = blockIdx.x, t = threadIdx.x;
+  const int j = blockIdx.x, sl = blockIdx.y, t = threadIdx.x;
   const int r = rowsel[j];
   const double w = omega[j];
   const double* W = wtab + (long)r * n_mo * G;
-  double s = 0.0, d = 0.0;
   const long n = (long)n_mo * G;
-  for (long idx = t; idx < n; idx += 256) {
+  const long chunk = (n + QUAD_SLICES - 1) / QUAD_SLICES;
+  const long lo = sl * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  double s = 0.0, d = 0.0;
+  for (long idx = lo + t; idx < hi; idx += 256) {
     int m = (int)(idx / G), g = (int)(idx % G);
     double a = w - eps[m];
     double x2 = xi[g] * xi[g];
@@ -252,21 +257,36 @@ __global__ __launch_bounds__(256) void k_sigma_quad(const double* wtab, int n_mo
     __syncthreads();
   }
   if (t == 0) {
-    const double inv_pi = 0.31830988618379067154;
-    sig[j] = -inv_pi * rs[0];
-    dsig[j] = -inv_pi * rd[0];
+    part[(long)(j * QUAD_SLICES + sl) * 2] = rs[0];
+    part[(long)(j * QUAD_SLICES + sl) * 2 + 1] = rd[0];
   }
+}
+
+__global__ void k_sigma_quad_sum(const double* part, int n, double* sig, double* dsig) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0, d = 0.0;
+  for (int sl = 0; sl < QUAD_SLICES; ++sl) {
+    s += part[(long)(j * QUAD_SLICES + sl) * 2];
+    d += part[(long)(j * QUAD_SLICES + sl) * 2 + 1];
+  }
+  const double inv_pi = 0.31830988618379067154;
+  sig[j] = -inv_pi * s;
+  dsig[j] = -inv_pi * d;
 }
 
 hipError_t sigma_quad(const double* wtab, int n_mo, int G, const int* rowsel, const double* omega,
                       const double* eps, const double* xi, const double* z, int n, double* sig,
-                      double* dsig, int n_rows, long nW, hipStream_t st) {
+                      double* dsig, double* part, int n_rows, long nW, long nPart,
+                      hipStream_t st) {
   if (n <= 0) return hipSuccess;
   // row indices come from the context's validated state -> row map (< n_rows)
   GW_GUARD("sigma_quad", "wtab", (long)n_rows * n_mo * G - 1, nW);
+  GW_GUARD("sigma_quad", "partials", (long)n * QUAD_SLICES * 2 - 1, nPart);
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_sigma_quad, dim3(n), dim3(256), 0, st, wtab, n_mo, G, rowsel, omega, eps,
-                     xi, z, sig, dsig);
+  hipLaunchKernelGGL(k_sigma_quad_part, dim3(n, QUAD_SLICES), dim3(256), 0, st, wtab, n_mo, G,
+                     rowsel, omega, eps, xi, z, part);
+  hipLaunchKernelGGL(k_sigma_quad_sum, dim3((n + 63) / 64), dim3(64), 0, st, part, n, sig, dsig);
   return hipGetLastError();
 }
 

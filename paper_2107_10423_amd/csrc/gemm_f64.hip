@@ -167,6 +167,10 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
     const int lim = p.col0 + (J + 1) * BN - p.kb0;
     if (kend > lim) kend = lim;
   }
+  if (p.klo_from > 0) {
+    const int r0 = p.row0 + I * BM - p.klo_from;
+    if (r0 > kbeg) kbeg = (r0 / BK) * BK;
+  }
   const int nk = kend > kbeg ? (kend - kbeg) / BK : 0;
 
   d4 acc[TM][TN];
@@ -339,7 +343,7 @@ static hipError_t check_gemm(const GemmArgs& a, int tile_kind, int la, int lb, i
   const bool per_tile = epi == EPI_RES_DERIV || epi == EPI_SQNORM;
   long maxC = b1 * a.sC + (long)(a.splitk - 1) * a.sSplit +
               (per_tile ? (long)(a.tiles_n - 1) * a.ldc + rmax : rmax * a.ldc + cmax);
-  if (a.ktri && a.splitk != 1) return refuse(kn, "triangular k limit with split-K");
+  if ((a.ktri || a.klo_from > 0) && a.splitk != 1) return refuse(kn, "triangular k limit with split-K");
   if (a.rowmask && !guard(kn, "rowmask", ((long)a.tiles_m * BM - 1) / 16, a.nMask))
     return hipErrorInvalidValue;
   if (!guard(kn, "C", maxC, a.nC)) return hipErrorInvalidValue;
@@ -361,12 +365,9 @@ hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, h
   // Pi build: KC x KC, scaled, 1 + 4 acc, batch-fastest
   if (tile_kind == 0 && la == KC && lb == KC && epi == EPI_ONE_PLUS_4 && scaled)
     return launch<2, 4, 4, KC, KC, EPI_ONE_PLUS_4, true, true>(a, st);
-  // Cholesky trailing update: KC x KC, axpby
+  // Cholesky panel update (C -= L_left L_panel^T) and panel solve: KC x KC, axpby
   if (tile_kind == 0 && la == KC && lb == KC && epi == EPI_AXPBY && !scaled)
     return launch<2, 4, 4, KC, KC, EPI_AXPBY, false, false>(a, st);
-  // Cholesky panel solve (A_panel Linv^T): 128 x 64, axpby
-  if (tile_kind == 1 && la == KC && lb == KC && epi == EPI_AXPBY && !scaled)
-    return launch<2, 4, 2, KC, KC, EPI_AXPBY, false, false>(a, st);
   // MINRES first pass split over N_aux: partial X B, 64 x 64 tiles
   if (tile_kind == 3 && la == KC && lb == KM && epi == EPI_STORE && !scaled)
     return launch<2, 2, 2, KC, KM, EPI_STORE, false, false>(a, st);

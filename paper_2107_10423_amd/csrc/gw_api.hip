@@ -205,6 +205,13 @@ struct gw_ctx {
   // host memory and are read one iteration late, so the host never idles the GPU
   hipEvent_t ev_poll[2] = {nullptr, nullptr};
   int* h_poll = nullptr;
+  hipEvent_t ev_quad[2] = {nullptr, nullptr};   // brackets the imaginary-axis quadrature
+  // pinned host staging for the small per-round transfers (QP frequencies in,
+  // Sigma parts out; MINRES parameters in, results out), so that they are
+  // plain DMA commands on the stream and a QP round synchronises once;
+  // stage_off is where the MINRES region starts (after the Sigma region)
+  char* h_stage = nullptr;
+  size_t h_stage_cap = 0, stage_off = 0;
   // MINRES iterations 2, 3, ... replay a captured graph per (padded batch,
   // iteration parity); valid while the MINRES workspace is not reallocated
   std::map<int, std::array<hipGraphExec_t, 2>> mr_graphs;
@@ -247,6 +254,7 @@ struct gw_ctx {
   double* d_omega = nullptr;
   double* d_sig = nullptr;
   double* d_dsig = nullptr;
+  double* d_sigpart = nullptr;   // [n][16][2] quadrature partial sums
   int sig_cap = 0;
   // MINRES workspace
   MinresBufs mr{};
@@ -309,8 +317,12 @@ struct gw_ctx {
     if (st) hipStreamSynchronize(st);
     drop_graphs();
     for (void* p : allocs) rt_free(p);
-    for (hipEvent_t e : {ev0, ev1, ev0b, ev1b, ev_poll[0], ev_poll[1]})
+    for (hipEvent_t e : {ev0, ev1, ev0b, ev1b, ev_poll[0], ev_poll[1], ev_quad[0], ev_quad[1]})
       if (e) hipEventDestroy(e);
+    if (h_stage) {
+      if (audit_mode()) free(h_stage);
+      else hipHostFree(h_stage);
+    }
     if (h_poll) {
       if (audit_mode()) free(h_poll);
       else hipHostFree(h_poll);
@@ -454,7 +466,7 @@ int ensure_mixed_operands(gw_ctx* c) {
   return 0;
 }
 
-// Blocked right-looking Cholesky of every item of the chunk over the rows
+// Blocked left-looking Cholesky of every item of the chunk over the rows
 // [0, Np) of 1 - Pi and the appended identity rows; panel k carries the
 // appended rows up to Np + k + PANEL only (the later ones are still unit rows
 // that the panel does not touch).
@@ -462,12 +474,32 @@ int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
   const int Np = c->Np;
   HIPCHK(rt_memset(c->d_info, 0, G * sizeof(int), c->st));
   HIPCHK(set_identity_rows(c->d_work, ldA, per_g, Np, Np, Np, G, c->ext(c->d_work, 8), c->st));
+  // Left-looking (Crout) panels over the augmented rows: panel k is first
+  // brought up to date with every factored column to its left (one GEMM with
+  // K = k over rows [k, Np + k); identity row Np + s is zero left of column s,
+  // so its tile starts its k loop at s), then its diagonal block is factored
+  // and inverted, then the rows below are solved against that block.  Only
+  // the panel is read-modified-written per step, never the trailing matrix.
   for (int k = 0; k < Np; k += PANEL) {
     trace("cholesky panel k=%d", k);
+    if (k > 0) {  // P[r][k:k+128] -= L[r][0:k] L[k:k+128][0:k]^T, r in [k, Np + k)
+      GemmArgs a{};
+      a.A = c->d_work; a.lda = ldA; a.sA = per_g;
+      a.B = c->d_work; a.ldb = ldA; a.sB = per_g;
+      a.C = c->d_work; a.ldc = ldA; a.sC = per_g;
+      a.K = k; a.row0 = k; a.col0 = k; a.k0 = 0; a.kb0 = 0;
+      a.klo_from = Np;
+      a.map = MAP_FULL;
+      a.tiles_m = Np / 128; a.tiles_n = 1;
+      a.M = Np; a.N = PANEL;
+      a.n_tiles = a.tiles_m; a.batch = G; a.splitk = 1;
+      a.alpha = -1.0; a.beta = 1.0;
+      RCHK(run_gemm(c, a, 0, KC, KC, EPI_AXPBY));
+    }
     HIPCHK(chol_diag(c->d_work, ldA, per_g, c->d_Linv, k, G, c->d_info, c->ext(c->d_work, 8),
                      c->ext(c->d_Linv, 8), c->ext(c->d_info, 4), c->st));
     const int rows_below = Np;  // rows [k + PANEL, Np + k + PANEL)
-    {  // panel solve: L[i][k:k+64] = A[i][k:k+64] Linv_kk^T
+    {  // panel solve: L[i][k:k+128] = P[i][k:k+128] Linv_kk^T
       GemmArgs a{};
       a.A = c->d_work; a.lda = ldA; a.sA = per_g;
       a.B = c->d_Linv; a.ldb = PANEL; a.sB = PANEL * PANEL;
@@ -478,22 +510,6 @@ int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
       a.M = a.tiles_m * 128; a.N = PANEL;
       a.n_tiles = a.tiles_m; a.batch = G; a.splitk = 1;
       a.alpha = 1.0; a.beta = 0.0;
-      RCHK(run_gemm(c, a, 0, KC, KC, EPI_AXPBY));
-    }
-    const int cols_right = Np - (k + PANEL);
-    if (cols_right <= 0) continue;
-    {  // trailing update of the lower trapezoid: A -= L_panel L_panel^T
-      GemmArgs a{};
-      a.A = c->d_work; a.lda = ldA; a.sA = per_g;
-      a.B = c->d_work; a.ldb = ldA; a.sB = per_g;
-      a.C = c->d_work; a.ldc = ldA; a.sC = per_g;
-      a.K = PANEL; a.row0 = k + PANEL; a.col0 = k + PANEL; a.k0 = k; a.kb0 = k;
-      a.map = MAP_LOWER;
-      a.tiles_m = (rows_below + 127) / 128; a.tiles_n = (cols_right + 127) / 128;
-      a.M = a.tiles_m * 128; a.N = a.tiles_n * 128;
-      a.n_tiles = (int)lower_tile_count(a.tiles_m, a.tiles_n, 128, 128);
-      a.batch = G; a.splitk = 1;
-      a.alpha = -1.0; a.beta = 1.0;
       RCHK(run_gemm(c, a, 0, KC, KC, EPI_AXPBY));
     }
   }
@@ -605,6 +621,34 @@ int build_wtable(gw_ctx* c, const gw_grid* grid, int mode = 0, double* dbg_out =
 
 // ---------------------------------------------------------------------------
 // Residues: batched MINRES with dense fallback
+
+// Pinned staging of at least `bytes`.  Growing it first drains the stream
+// (copies into the old buffer complete) and carries the old contents over, so
+// callers re-derive their pointers from h_stage after this call.
+int ensure_stage(gw_ctx* c, size_t bytes) {
+  if (bytes <= c->h_stage_cap) return 0;
+  HIPCHK(rt_sync(c->st));
+  const size_t cap = std::max<size_t>(64 << 10, 2 * bytes);
+  char* p = nullptr;
+  if (audit_mode()) {
+    p = (char*)calloc(cap, 1);
+    if (!p) return fail(GW_ENOMEM, "host allocation failed");
+  } else if (hipHostMalloc((void**)&p, cap, hipHostMallocDefault) != hipSuccess) {
+    return fail(GW_ENOMEM, "pinned host allocation of %zu bytes failed", cap);
+  }
+  if (c->h_stage) {
+    memcpy(p, c->h_stage, c->h_stage_cap);
+    if (audit_mode()) free(c->h_stage);
+    else hipHostFree(c->h_stage);
+  }
+  c->h_stage = p;
+  c->h_stage_cap = cap;
+  return 0;
+}
+
+// Staging bytes of one MINRES batch of kp systems: rhs index, warm flag,
+// frequency, tolerance in; W^c, dW^c, convergence out.
+inline size_t mr_stage_bytes(int kp) { return (size_t)kp * (4 + 4 + 8 + 8 + 8 + 8 + 4); }
 
 int ensure_minres(gw_ctx* c, int kp) {
   if (kp <= c->mr_cap) return 0;
@@ -777,19 +821,25 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   m.n_part = c->ext(m.part, 8);
   m.n_V = c->ext(m.V, 8);
   m.n_blk = c->ext(m.blk, sizeof(int));
-  std::vector<int> idx(kp, 0);
-  std::vector<double> om(kp, 0.0), tol(kp, c->minres_rtol);
-  for (int j = 0; j < k; ++j) {
-    idx[j] = sys[j].q;
-    om[j] = sys[j].w;
-    if (sys[j].tol > 0) tol[j] = std::max(sys[j].tol, c->minres_rtol);
+  RCHK(ensure_stage(c, c->stage_off + mr_stage_bytes(kp)));
+  int* idx = (int*)(c->h_stage + c->stage_off);
+  int* warm = idx + kp;
+  double* om = (double*)(warm + kp);
+  double* tol = om + kp;
+  double* h_wc = tol + kp;
+  double* h_dwc = h_wc + kp;
+  int* h_conv = (int*)(h_dwc + kp);
+  for (int j = 0; j < kp; ++j) {
+    idx[j] = j < k ? sys[j].q : 0;
+    om[j] = j < k ? sys[j].w : 0.0;
+    tol[j] = (j < k && sys[j].tol > 0) ? std::max(sys[j].tol, c->minres_rtol) : c->minres_rtol;
   }
   Timer tm;
   tm.a = c->ev0; tm.b = c->ev1;
   tm.start(c->st);
-  HIPCHK(rt_memcpy(c->d_rhs_idx, idx.data(), kp * sizeof(int), hipMemcpyHostToDevice, c->st));
-  HIPCHK(rt_memcpy(m.omega, om.data(), kp * sizeof(double), hipMemcpyHostToDevice, c->st));
-  HIPCHK(rt_memcpy(m.rtol, tol.data(), kp * sizeof(double), hipMemcpyHostToDevice, c->st));
+  HIPCHK(rt_memcpy(c->d_rhs_idx, idx, kp * sizeof(int), hipMemcpyHostToDevice, c->st));
+  HIPCHK(rt_memcpy(m.omega, om, kp * sizeof(double), hipMemcpyHostToDevice, c->st));
+  HIPCHK(rt_memcpy(m.rtol, tol, kp * sizeof(double), hipMemcpyHostToDevice, c->st));
   trace("minres k=%d kp=%d splitk=%d", k, kp, c->mr_splitk);
   // warm start: a right-hand side solved earlier in this call starts from that
   // solution; one operator pass gives A x0 for the start vector b - A x0
@@ -797,23 +847,20 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
     RCHK(c->alloc((void**)&c->d_xcache, (size_t)c->Rp * c->Np * sizeof(double)));
     c->xvalid.assign(c->Rp, 0);
   }
-  std::vector<int> warm(kp, 0);
   int n_warm = 0;
-  for (int j = 0; j < k; ++j)
-    if (c->xvalid[idx[j]]) {
-      warm[j] = 1;
-      n_warm++;
-    }
+  for (int j = 0; j < kp; ++j) {
+    warm[j] = (j < k && c->xvalid[idx[j]]) ? 1 : 0;
+    n_warm += warm[j];
+  }
   const long n_cache = c->ext(c->d_xcache, 8);
-  HIPCHK(rt_memcpy(c->d_warm, warm.data(), kp * sizeof(int), hipMemcpyHostToDevice, c->st));
-  HIPCHK(minres_gather(m, c->d_xcache, c->d_rhs_idx, idx.data(), c->Rp, c->d_warm, n_cache,
-                       c->st));
+  HIPCHK(rt_memcpy(c->d_warm, warm, kp * sizeof(int), hipMemcpyHostToDevice, c->st));
+  HIPCHK(minres_gather(m, c->d_xcache, c->d_rhs_idx, idx, c->Rp, c->d_warm, n_cache, c->st));
   if (n_warm > 0) {
     RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp));
     RCHK(backproject_pass(c, kp));
     HIPCHK(minres_apply(m, c->mr_splitk, c->st));
   }
-  HIPCHK(minres_init(m, c->d_R, c->d_rhs_idx, idx.data(), c->Rp, n_warm > 0, c->st));
+  HIPCHK(minres_init(m, c->d_R, c->d_rhs_idx, idx, c->Rp, n_warm > 0, c->st));
   HIPCHK(rt_memset(m.active, 0, 2 * sizeof(int), c->st));
   HIPCHK(rt_memset(m.blk, 0, 2 * (size_t)(kp / 16) * sizeof(int), c->st));
   int itn = 0;
@@ -836,18 +883,21 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   c->timing.minres_iters += std::min(itn, c->minres_max_iter);
   c->timing.minres_systems += k;
   // x = x0 + correction; remember it for later solves of the same right-hand side
-  HIPCHK(minres_finalize(m, c->d_xcache, c->d_rhs_idx, idx.data(), c->Rp, n_cache, c->st));
+  HIPCHK(minres_finalize(m, c->d_xcache, c->d_rhs_idx, idx, c->Rp, n_cache, c->st));
   for (int j = 0; j < k; ++j) c->xvalid[idx[j]] = 1;
   // derivative partials: sum over ia of (B^T x)^2 * 2 D w/(D^2 - w^2)^2
   const int nparts = c->Kp / 64;
   RCHK(matvec_pass(c, m.x, kp, EPI_RES_DERIV, m.part, kp));
   HIPCHK(minres_results(m, c->d_R, c->d_rhs_idx, c->Rp, nparts, c->d_wc, c->d_dwc, c->d_conv,
                         c->ext(c->d_wc, 8), c->st));
-  HIPCHK(rt_memcpy(wc.data(), c->d_wc, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(rt_memcpy(dwc.data(), c->d_dwc, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(rt_memcpy(iters.data(), c->d_conv, k * sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(rt_memcpy(h_wc, c->d_wc, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(rt_memcpy(h_dwc, c->d_dwc, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(rt_memcpy(h_conv, c->d_conv, k * sizeof(int), hipMemcpyDeviceToHost, c->st));
   HIPCHK(rt_sync(c->st));
   c->timing.minres_ms += tm.stop();
+  std::copy(h_wc, h_wc + k, wc.begin());
+  std::copy(h_dwc, h_dwc + k, dwc.begin());
+  std::copy(h_conv, h_conv + k, iters.begin());
 
   if (audit_mode())  // no results exist; walk the fallback launches for every system
     for (int j = 0; j < k; ++j) iters[j] = -1;
@@ -931,10 +981,12 @@ int ensure_sig(gw_ctx* c, int n) {
   c->release(c->d_omega);
   c->release(c->d_sig);
   c->release(c->d_dsig);
+  c->release(c->d_sigpart);
   RCHK(c->alloc((void**)&c->d_rowsel, n * sizeof(int)));
   RCHK(c->alloc((void**)&c->d_omega, n * sizeof(double)));
   RCHK(c->alloc((void**)&c->d_sig, n * sizeof(double)));
   RCHK(c->alloc((void**)&c->d_dsig, n * sizeof(double)));
+  RCHK(c->alloc((void**)&c->d_sigpart, (size_t)n * 32 * sizeof(double)));
   c->sig_cap = n;
   return 0;
 }
@@ -952,19 +1004,7 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
   RCHK(ensure_sig(c, n));
   std::vector<int> rows(n);
   for (int j = 0; j < n; ++j) rows[j] = c->row_of[states[j]];
-  Timer tm;
-  tm.a = c->ev0; tm.b = c->ev1;
-  tm.start(c->st);
-  HIPCHK(rt_memcpy(c->d_rowsel, rows.data(), n * sizeof(int), hipMemcpyHostToDevice, c->st));
-  HIPCHK(rt_memcpy(c->d_omega, omega.data(), n * sizeof(double), hipMemcpyHostToDevice, c->st));
-  HIPCHK(sigma_quad(c->d_wtab, c->n_mo, c->wtab_G, c->d_rowsel, c->d_omega, c->d_eps, c->d_grid,
-                    c->d_grid + c->grid_cap, n, c->d_sig, c->d_dsig, c->n_rows,
-                    c->ext(c->d_wtab, 8), c->st));
-  HIPCHK(rt_memcpy(sig.data(), c->d_sig, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(rt_memcpy(dsig.data(), c->d_dsig, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(rt_sync(c->st));
-  c->timing.quad_ms += tm.stop();
-  // residue systems of every entry
+  // residue systems of every entry (host only)
   std::vector<System> sys;
   std::vector<int> owner;
   std::vector<double> weight;
@@ -979,9 +1019,45 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
       nres[j]++;
     }
   }
+  // pinned staging: [omega n][sig n][dsig n][row n], then the MINRES region;
+  // the quadrature's results are read after the round's single synchronisation
+  const size_t sig_bytes = ((size_t)n * (3 * sizeof(double) + sizeof(int)) + 63) / 64 * 64;
+  const int kmax = std::min((int)sys.size(), c->minres_batch);
+  RCHK(ensure_stage(c, sig_bytes + mr_stage_bytes(round_up(std::max(kmax, 1), 64))));
+  {
+    double* h_om = (double*)c->h_stage;
+    int* h_row = (int*)(h_om + 3 * n);
+    std::copy(omega.begin(), omega.end(), h_om);
+    std::copy(rows.begin(), rows.end(), h_row);
+    if (!audit_mode()) HIPCHK(hipEventRecord(c->ev_quad[0], c->st));
+    HIPCHK(rt_memcpy(c->d_rowsel, h_row, n * sizeof(int), hipMemcpyHostToDevice, c->st));
+    HIPCHK(rt_memcpy(c->d_omega, h_om, n * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(sigma_quad(c->d_wtab, c->n_mo, c->wtab_G, c->d_rowsel, c->d_omega, c->d_eps, c->d_grid,
+                      c->d_grid + c->grid_cap, n, c->d_sig, c->d_dsig, c->d_sigpart,
+                      c->n_rows, c->ext(c->d_wtab, 8), c->ext(c->d_sigpart, 8), c->st));
+    HIPCHK(rt_memcpy(h_om + n, c->d_sig, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(rt_memcpy(h_om + 2 * n, c->d_dsig, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    if (!audit_mode()) HIPCHK(hipEventRecord(c->ev_quad[1], c->st));
+  }
   std::vector<double> wc, dwc;
   std::vector<int> it;
-  RCHK(solve_residues(c, sys, true, wc, dwc, it));
+  c->stage_off = sig_bytes;
+  const int rc = solve_residues(c, sys, true, wc, dwc, it);
+  c->stage_off = 0;
+  RCHK(rc);
+  HIPCHK(rt_sync(c->st));   // (already drained when there were residue systems)
+  if (!audit_mode()) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev_quad[0], c->ev_quad[1]));
+    c->timing.quad_ms += ms;
+  }
+  {
+    const double* h_sig = (const double*)c->h_stage + n;   // h_stage may have moved
+    for (int j = 0; j < n; ++j) {
+      sig[j] = h_sig[j];
+      dsig[j] = h_sig[n + j];
+    }
+  }
   for (size_t s = 0; s < sys.size(); ++s) {
     const int j = owner[s];
     sig[j] += weight[s] * wc[s];
@@ -1139,7 +1215,7 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   b += (size_t)chunk * (per_g * d + parts * d + PANEL * PANEL * d + sizeof(int) + (size_t)Kp * (d + 4));
   b += 2 * (size_t)G * d + (size_t)std::max(nR, 1) * G * d;
   // Sigma evaluation buffers
-  b += (size_t)n_states * (sizeof(int) + 3 * d);
+  b += (size_t)n_states * (sizeof(int) + 3 * d + 32 * d);
   // MINRES workspace for the largest batch
   const int kmax = std::min(std::max(n_states, 1) * n_mo, minres_batch);
   const int kp = round_up(kmax, 64);
@@ -1354,7 +1430,8 @@ int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* 
       (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
        hipEventCreate(&c->ev0b) != hipSuccess || hipEventCreate(&c->ev1b) != hipSuccess ||
        hipEventCreateWithFlags(&c->ev_poll[0], hipEventDisableTiming) != hipSuccess ||
-       hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) != hipSuccess))
+       hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) != hipSuccess ||
+       hipEventCreate(&c->ev_quad[0]) != hipSuccess || hipEventCreate(&c->ev_quad[1]) != hipSuccess))
     return cleanup(fail(GW_EDEVICE, "hipEventCreate failed"));
   if (audit_mode()) {
     c->h_poll = (int*)calloc(2, sizeof(int));

@@ -67,6 +67,9 @@ struct GemmArgs {
   int batch;
   int splitk;                           // >= 1; split s covers k in [s*K/splitk, (s+1)*K/splitk)
   int ktri;                             // B(j, k) = 0 for k > j: stop k at the tile's last B row
+  int klo_from;                         // > 0: A rows r >= klo_from are zero for
+                                        // k < r - klo_from; a row tile starting at r0
+                                        // begins its k loop there (splitk 1 only)
   long sSplit;                          // C offset between split-K slabs
   int mrows;                            // rows >= mrows of each tile column are padding whose
                                         // MFMAs are skipped (0: every row is computed)
@@ -116,9 +119,11 @@ hipError_t make_scale_imag(const double* D, int Kov, int Kp, const double* xi, i
                            float* s32, long nD, long nXi, long nS, long nS32, hipStream_t st);
 
 // Sigma quadrature: per state j: sum_m sum_g W[row_j][m][g] z_g a/(a^2+xi^2) and derivative
+// Sigma quadrature of n states; part: scratch of n * 32 doubles (16 slices, 2 sums)
 hipError_t sigma_quad(const double* wtab, int n_mo, int G, const int* rowsel, const double* omega,
-                      const double* eps, const double* xi, const double* z, int n,
-                      double* sig, double* dsig, int n_rows, long nW, hipStream_t st);
+                      const double* eps, const double* xi, const double* z, int n, double* sig,
+                      double* dsig, double* part, int n_rows, long nW, long nPart,
+                      hipStream_t st);
 
 // MINRES
 struct MinresBufs {
