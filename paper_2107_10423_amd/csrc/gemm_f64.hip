@@ -180,12 +180,20 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
     for (int j = 0; j < TN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   // 16-row blocks of padding rows (systems beyond the batch) and blocks whose A
-  // rows are known to be zero (converged systems) skip their MFMAs
+  // rows are known to be zero (converged systems) skip their MFMAs; a tile
+  // with no live block at all returns before loading anything (its output
+  // rows belong to systems that no longer read them)
   bool row_ok[TM];
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int r = I * BM + wm * TM * 16 + i * 16;
     row_ok[i] = (p.mrows <= 0 || r < p.mrows) && (!p.rowmask || p.rowmask[r >> 4] != 0);
+  }
+  if (p.rowmask) {
+    bool live = false;
+    for (int r = I * BM; r < I * BM + BM; r += 16)
+      live |= (p.mrows <= 0 || r < p.mrows) && p.rowmask[r >> 4] != 0;
+    if (!live) return;
   }
 
   Stager<BM, LA, false> sa;

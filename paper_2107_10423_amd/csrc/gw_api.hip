@@ -882,6 +882,7 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   }
   c->timing.minres_iters += std::min(itn, c->minres_max_iter);
   c->timing.minres_systems += k;
+  trace("minres done k=%d iterations=%d warm=%d", k, std::min(itn, c->minres_max_iter), n_warm);
   // x = x0 + correction; remember it for later solves of the same right-hand side
   HIPCHK(minres_finalize(m, c->d_xcache, c->d_rhs_idx, idx, c->Rp, n_cache, c->st));
   for (int j = 0; j < k; ++j) c->xvalid[idx[j]] = 1;

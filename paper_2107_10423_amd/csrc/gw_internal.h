@@ -73,8 +73,10 @@ struct GemmArgs {
   long sSplit;                          // C offset between split-K slabs
   int mrows;                            // rows >= mrows of each tile column are padding whose
                                         // MFMAs are skipped (0: every row is computed)
-  const int* rowmask;                   // per 16-row block of A: 0 = rows known to be zero,
-                                        // MFMAs skipped (nullptr: every block is computed)
+  const int* rowmask;                   // per 16-row block of A: 0 = rows known to be zero
+                                        // whose outputs nobody reads: MFMAs skipped, and a
+                                        // tile without a live block writes nothing
+                                        // (nullptr: every block is computed)
   double alpha, beta;
   const double* Dvec;                   // transition energies (EPI_RES_*)
   const double* wrow;                   // per-row real frequency (EPI_RES_*)
