@@ -255,6 +255,8 @@ struct gw_ctx {
   double* d_sig = nullptr;
   double* d_dsig = nullptr;
   double* d_sigpart = nullptr;   // [n][16][2] quadrature partial sums
+  char* d_mrin = nullptr;        // MINRES parameters [omega | rtol | rhs index | warm], cap each
+  char* d_mrout = nullptr;       // MINRES results [W^c | dW^c | convergence], cap each
   int sig_cap = 0;
   // MINRES workspace
   MinresBufs mr{};
@@ -648,15 +650,14 @@ int ensure_stage(gw_ctx* c, size_t bytes) {
 
 // Staging bytes of one MINRES batch of kp systems: rhs index, warm flag,
 // frequency, tolerance in; W^c, dW^c, convergence out.
-inline size_t mr_stage_bytes(int kp) { return (size_t)kp * (4 + 4 + 8 + 8 + 8 + 8 + 4); }
+inline size_t mr_stage_bytes(int cap) { return (size_t)cap * (4 + 4 + 8 + 8 + 8 + 8 + 4); }
 
 int ensure_minres(gw_ctx* c, int kp) {
   if (kp <= c->mr_cap) return 0;
   c->drop_graphs();
   MinresBufs& m = c->mr;
-  void* olds[] = {m.x, m.w, m.w2, m.r1, m.r2, m.y, m.v, m.x0, m.scal, m.V, m.part, m.omega,
-                  m.rtol, m.active, m.blk, c->d_rhs_idx, c->d_warm, c->d_wc, c->d_dwc,
-                  c->d_conv};
+  void* olds[] = {m.x, m.w, m.w2, m.r1, m.r2, m.y, m.v, m.x0, m.scal, m.V, m.part, m.active,
+                  m.blk, c->d_mrin, c->d_mrout};
   for (void* p : olds) c->release(p);
   const size_t vec = (size_t)kp * c->Np;
   double** vecs[] = {&m.x, &m.w, &m.w2, &m.r1, &m.r2, &m.y, &m.v, &m.x0};
@@ -672,15 +673,18 @@ int ensure_minres(gw_ctx* c, int kp) {
                           (size_t)splitk1 * kp * c->Kp});
   RCHK(c->alloc((void**)&m.part, part * sizeof(double)));
   c->part_cap = part;
-  RCHK(c->alloc((void**)&m.omega, (size_t)kp * sizeof(double)));
-  RCHK(c->alloc((void**)&m.rtol, (size_t)kp * sizeof(double)));
   RCHK(c->alloc((void**)&m.active, 2 * sizeof(int)));
   RCHK(c->alloc((void**)&m.blk, 2 * (size_t)(kp / 16) * sizeof(int)));
-  RCHK(c->alloc((void**)&c->d_rhs_idx, (size_t)kp * sizeof(int)));
-  RCHK(c->alloc((void**)&c->d_warm, (size_t)kp * sizeof(int)));
-  RCHK(c->alloc((void**)&c->d_wc, (size_t)kp * sizeof(double)));
-  RCHK(c->alloc((void**)&c->d_dwc, (size_t)kp * sizeof(double)));
-  RCHK(c->alloc((void**)&c->d_conv, (size_t)kp * sizeof(int)));
+  // parameters and results each in one block, moved by one copy per batch
+  RCHK(c->alloc((void**)&c->d_mrin, (size_t)kp * (2 * sizeof(double) + 2 * sizeof(int))));
+  m.omega = (double*)c->d_mrin;
+  m.rtol = m.omega + kp;
+  c->d_rhs_idx = (int*)(m.rtol + kp);
+  c->d_warm = c->d_rhs_idx + kp;
+  RCHK(c->alloc((void**)&c->d_mrout, (size_t)kp * (2 * sizeof(double) + sizeof(int))));
+  c->d_wc = (double*)c->d_mrout;
+  c->d_dwc = c->d_wc + kp;
+  c->d_conv = (int*)(c->d_dwc + kp);
   c->mr_cap = kp;
   return 0;
 }
@@ -821,14 +825,20 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   m.n_part = c->ext(m.part, 8);
   m.n_V = c->ext(m.V, 8);
   m.n_blk = c->ext(m.blk, sizeof(int));
-  RCHK(ensure_stage(c, c->stage_off + mr_stage_bytes(kp)));
-  int* idx = (int*)(c->h_stage + c->stage_off);
-  int* warm = idx + kp;
-  double* om = (double*)(warm + kp);
-  double* tol = om + kp;
-  double* h_wc = tol + kp;
-  double* h_dwc = h_wc + kp;
-  int* h_conv = (int*)(h_dwc + kp);
+  // host mirror of the device parameter and result blocks (same layout)
+  const int cap = c->mr_cap;
+  RCHK(ensure_stage(c, c->stage_off + mr_stage_bytes(cap)));
+  char* h_in = c->h_stage + c->stage_off;
+  double* om = (double*)h_in;
+  double* tol = om + cap;
+  int* idx = (int*)(tol + cap);
+  int* warm = idx + cap;
+  char* h_out = (char*)(warm + cap);
+  double* h_wc = (double*)h_out;
+  double* h_dwc = h_wc + cap;
+  int* h_conv = (int*)(h_dwc + cap);
+  const size_t in_bytes = (size_t)cap * (2 * sizeof(double) + 2 * sizeof(int));
+  const size_t out_bytes = (size_t)cap * (2 * sizeof(double) + sizeof(int));
   for (int j = 0; j < kp; ++j) {
     idx[j] = j < k ? sys[j].q : 0;
     om[j] = j < k ? sys[j].w : 0.0;
@@ -837,9 +847,7 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   Timer tm;
   tm.a = c->ev0; tm.b = c->ev1;
   tm.start(c->st);
-  HIPCHK(rt_memcpy(c->d_rhs_idx, idx, kp * sizeof(int), hipMemcpyHostToDevice, c->st));
-  HIPCHK(rt_memcpy(m.omega, om, kp * sizeof(double), hipMemcpyHostToDevice, c->st));
-  HIPCHK(rt_memcpy(m.rtol, tol, kp * sizeof(double), hipMemcpyHostToDevice, c->st));
+
   trace("minres k=%d kp=%d splitk=%d", k, kp, c->mr_splitk);
   // warm start: a right-hand side solved earlier in this call starts from that
   // solution; one operator pass gives A x0 for the start vector b - A x0
@@ -853,7 +861,7 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
     n_warm += warm[j];
   }
   const long n_cache = c->ext(c->d_xcache, 8);
-  HIPCHK(rt_memcpy(c->d_warm, warm, kp * sizeof(int), hipMemcpyHostToDevice, c->st));
+  HIPCHK(rt_memcpy(c->d_mrin, h_in, in_bytes, hipMemcpyHostToDevice, c->st));
   HIPCHK(minres_gather(m, c->d_xcache, c->d_rhs_idx, idx, c->Rp, c->d_warm, n_cache, c->st));
   if (n_warm > 0) {
     RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp));
@@ -861,8 +869,6 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
     HIPCHK(minres_apply(m, c->mr_splitk, c->st));
   }
   HIPCHK(minres_init(m, c->d_R, c->d_rhs_idx, idx, c->Rp, n_warm > 0, c->st));
-  HIPCHK(rt_memset(m.active, 0, 2 * sizeof(int), c->st));
-  HIPCHK(rt_memset(m.blk, 0, 2 * (size_t)(kp / 16) * sizeof(int), c->st));
   int itn = 0;
   // Each iteration's count of still-active systems is copied to pinned host
   // memory behind its step kernel; the host reads iteration i's count after
@@ -891,9 +897,7 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   RCHK(matvec_pass(c, m.x, kp, EPI_RES_DERIV, m.part, kp));
   HIPCHK(minres_results(m, c->d_R, c->d_rhs_idx, c->Rp, nparts, c->d_wc, c->d_dwc, c->d_conv,
                         c->ext(c->d_wc, 8), c->st));
-  HIPCHK(rt_memcpy(h_wc, c->d_wc, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(rt_memcpy(h_dwc, c->d_dwc, k * sizeof(double), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(rt_memcpy(h_conv, c->d_conv, k * sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(rt_memcpy(h_out, c->d_mrout, out_bytes, hipMemcpyDeviceToHost, c->st));
   HIPCHK(rt_sync(c->st));
   c->timing.minres_ms += tm.stop();
   std::copy(h_wc, h_wc + k, wc.begin());
@@ -978,15 +982,14 @@ double residue_weight(const gw_ctx* c, int m, double w) {
 
 int ensure_sig(gw_ctx* c, int n) {
   if (n <= c->sig_cap) return 0;
-  c->release(c->d_rowsel);
   c->release(c->d_omega);
   c->release(c->d_sig);
-  c->release(c->d_dsig);
   c->release(c->d_sigpart);
-  RCHK(c->alloc((void**)&c->d_rowsel, n * sizeof(int)));
-  RCHK(c->alloc((void**)&c->d_omega, n * sizeof(double)));
-  RCHK(c->alloc((void**)&c->d_sig, n * sizeof(double)));
-  RCHK(c->alloc((void**)&c->d_dsig, n * sizeof(double)));
+  // inputs [omega | rows] and outputs [sig | dsig] each in one block
+  RCHK(c->alloc((void**)&c->d_omega, (size_t)n * (sizeof(double) + sizeof(int))));
+  c->d_rowsel = (int*)(c->d_omega + n);
+  RCHK(c->alloc((void**)&c->d_sig, 2 * (size_t)n * sizeof(double)));
+  c->d_dsig = c->d_sig + n;
   RCHK(c->alloc((void**)&c->d_sigpart, (size_t)n * 32 * sizeof(double)));
   c->sig_cap = n;
   return 0;
@@ -1020,24 +1023,27 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
       nres[j]++;
     }
   }
-  // pinned staging: [omega n][sig n][dsig n][row n], then the MINRES region;
-  // the quadrature's results are read after the round's single synchronisation
-  const size_t sig_bytes = ((size_t)n * (3 * sizeof(double) + sizeof(int)) + 63) / 64 * 64;
+  // pinned staging mirrors the device blocks: [omega cap | rows cap] in,
+  // [sig cap | dsig cap] out, then the MINRES region; the quadrature's results
+  // are read after the round's single synchronisation
+  const int sc = c->sig_cap;
+  const size_t sig_bytes = ((size_t)sc * (3 * sizeof(double) + sizeof(int)) + 63) / 64 * 64;
   const int kmax = std::min((int)sys.size(), c->minres_batch);
-  RCHK(ensure_stage(c, sig_bytes + mr_stage_bytes(round_up(std::max(kmax, 1), 64))));
+  RCHK(ensure_stage(c, sig_bytes + mr_stage_bytes(std::max(c->mr_cap, round_up(std::max(kmax, 1), 64)))));
   {
     double* h_om = (double*)c->h_stage;
-    int* h_row = (int*)(h_om + 3 * n);
+    int* h_row = (int*)(h_om + sc);
+    double* h_sig = (double*)(h_row + sc);
     std::copy(omega.begin(), omega.end(), h_om);
     std::copy(rows.begin(), rows.end(), h_row);
     if (!audit_mode()) HIPCHK(hipEventRecord(c->ev_quad[0], c->st));
-    HIPCHK(rt_memcpy(c->d_rowsel, h_row, n * sizeof(int), hipMemcpyHostToDevice, c->st));
-    HIPCHK(rt_memcpy(c->d_omega, h_om, n * sizeof(double), hipMemcpyHostToDevice, c->st));
+    HIPCHK(rt_memcpy(c->d_omega, h_om, (size_t)sc * (sizeof(double) + sizeof(int)),
+                     hipMemcpyHostToDevice, c->st));
     HIPCHK(sigma_quad(c->d_wtab, c->n_mo, c->wtab_G, c->d_rowsel, c->d_omega, c->d_eps, c->d_grid,
                       c->d_grid + c->grid_cap, n, c->d_sig, c->d_dsig, c->d_sigpart,
                       c->n_rows, c->ext(c->d_wtab, 8), c->ext(c->d_sigpart, 8), c->st));
-    HIPCHK(rt_memcpy(h_om + n, c->d_sig, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
-    HIPCHK(rt_memcpy(h_om + 2 * n, c->d_dsig, n * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(rt_memcpy(h_sig, c->d_sig, 2 * (size_t)sc * sizeof(double), hipMemcpyDeviceToHost,
+                     c->st));
     if (!audit_mode()) HIPCHK(hipEventRecord(c->ev_quad[1], c->st));
   }
   std::vector<double> wc, dwc;
@@ -1053,10 +1059,11 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
     c->timing.quad_ms += ms;
   }
   {
-    const double* h_sig = (const double*)c->h_stage + n;   // h_stage may have moved
+    // (h_stage may have moved; the layout is unchanged)
+    const double* h_sig = (const double*)((const int*)((const double*)c->h_stage + sc) + sc);
     for (int j = 0; j < n; ++j) {
       sig[j] = h_sig[j];
-      dsig[j] = h_sig[n + j];
+      dsig[j] = h_sig[sc + j];
     }
   }
   for (size_t s = 0; s < sys.size(); ++s) {

@@ -64,11 +64,16 @@ hipError_t minres_gather(MinresBufs& m, const double* xcache, const int* rhs_idx
   return hipGetLastError();
 }
 
-// Start vectors: r = b - A x0 when use_y (y = A x0), else r = b.
+// Start vectors: r = b - A x0 when use_y (y = A x0), else r = b.  Block 0
+// also clears the convergence counters and block flags of both parities.
 __global__ __launch_bounds__(256) void k_minres_init(MinresBufs m, const double* rhs_base,
                                                      const int* rhs_idx, int use_y) {
   __shared__ double red[4];
   const int j = blockIdx.x, t = threadIdx.x;
+  if (j == 0) {
+    if (t < 2) m.active[t] = 0;
+    for (int i = t; i < 2 * (m.kp / 16); i += 256) m.blk[i] = 0;
+  }
   const long o = (long)j * m.Np;
   const double* b = (j < m.k) ? rhs_base + (long)rhs_idx[j] * m.Np : nullptr;
   double s = 0.0, sb = 0.0;
@@ -108,6 +113,7 @@ __global__ __launch_bounds__(256) void k_minres_init(MinresBufs m, const double*
 hipError_t minres_init(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
                        const int* host_idx, int n_rhs_rows, int use_y, hipStream_t st) {
   if (hipError_t e = check_bufs(m, "minres_init")) return e;
+  GW_GUARD("minres_init", "blk", 2L * (m.kp / 16) - 1, m.n_blk);
   for (int j = 0; j < m.k; ++j)
     if (host_idx[j] < 0 || host_idx[j] >= n_rhs_rows) return refuse("minres_init", "rhs index");
   GW_AUDIT_RETURN();
