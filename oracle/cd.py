@@ -92,7 +92,7 @@ def residue_weights(eps, n_occ, omega):
 def residue_value(eps, n_occ, B_ov, b, w):
     """W^c(w) = b^T[(1 - Pi(w))^-1 - 1] b and dW^c/dw at a real frequency w,
     by building 1 - Pi(w) and inverting it (what the paper's iterative solver
-    avoids; here it is the definition)."""
+    avoids; here it is the definition).  eps: the eigenvalues in Pi."""
     n = B_ov.shape[0]
     Pi = pi_real(eps, n_occ, B_ov, w)
     Ainv = np.linalg.inv(np.eye(n) - Pi)
@@ -103,28 +103,41 @@ def residue_value(eps, n_occ, B_ov, b, w):
     return wc, dwc
 
 
-def sigma_c(eps, n_occ, B_ov, b_row, wtab_row, xi, z, omega, derivative=True):
+def sigma_c(eps, n_occ, B_ov, b_row, wtab_row, xi, z, omega, derivative=True, eps_w=None,
+            w0_row=None):
     """Re Sigma^c_nn(omega) and d/d omega of it for one state.
 
+    eps:      the energies in G (poles eps_m: the quadrature's a = omega - eps_m,
+              the residue set and the residue frequencies eps_m - omega)
+    eps_w:    the energies in W (transition energies of Pi); None: eps
     b_row:    [n_mo, N_aux]  (P|nm) for every m
-    wtab_row: [n_mo, G]      W^c_nm(i xi_g)
+    wtab_row: [n_mo, G]      W^c_nm(i xi_g), built from eps_w
+    w0_row:   [n_mo] W^c_nm(0), or None.  When given, the static part of each
+              I integrand is integrated exactly, int_0^inf a/(a^2 + xi^2) d xi
+              = (pi/2) sgn(a), and only W^c(i xi) - W^c(0) goes through the
+              quadrature, which stays accurate as omega approaches a pole eps_m
     Returns (sigma, dsigma, n_residues).
     """
+    if eps_w is None:
+        eps_w = eps
     eps = np.asarray(eps, dtype=np.float64)
     a = omega - eps                                   # [n_mo]
     den = a[:, None] ** 2 + xi[None, :] ** 2          # [n_mo, G]
-    sig = -(1.0 / np.pi) * float(np.sum(z[None, :] * wtab_row * a[:, None] / den))
+    wq = wtab_row if w0_row is None else wtab_row - np.asarray(w0_row)[:, None]
+    sig = -(1.0 / np.pi) * float(np.sum(z[None, :] * wq * a[:, None] / den))
+    if w0_row is not None:
+        sig += -0.5 * float(np.sum(np.sign(a) * np.asarray(w0_row)))
     dsig = 0.0
     if derivative:
         dsig = -(1.0 / np.pi) * float(
-            np.sum(z[None, :] * wtab_row * (xi[None, :] ** 2 - a[:, None] ** 2) / den ** 2))
+            np.sum(z[None, :] * wq * (xi[None, :] ** 2 - a[:, None] ** 2) / den ** 2))
     f = residue_weights(eps, n_occ, omega)
     nres = 0
     for m in range(eps.size):
         if f[m] == 0.0:
             continue
         nres += 1
-        wc, dwc = residue_value(eps, n_occ, B_ov, b_row[m], eps[m] - omega)
+        wc, dwc = residue_value(eps_w, n_occ, B_ov, b_row[m], eps[m] - omega)
         sig += f[m] * wc
         # the residue frequency eps_m - omega moves opposite to omega
         dsig += -f[m] * dwc

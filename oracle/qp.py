@@ -137,12 +137,18 @@ def step_tree(feval, w0, tol=1e-10, max_iter=100):
     return dict(E=w, f=f, dfdw=fp, Z=Z, status=st, iters=max_iter, trace=trace)
 
 
-def make_feval(eps, n_occ, B_ov, b_row, wtab_row, xi, z, n, dsig_x_n=0.0, counter=None):
-    """f(w) and df/dw for state n from the contour-deformation Sigma^c."""
-    eps_n = float(eps[n])
+def make_feval(eps, n_occ, B_ov, b_row, wtab_row, xi, z, n, dsig_x_n=0.0, counter=None,
+               eps_ref_n=None, eps_w=None, w0_row=None):
+    """f(w) and df/dw for state n from the contour-deformation Sigma^c.
+
+    eps are the energies in G; eps_w those in W (None: eps); eps_ref_n the
+    constant term of the QP equation (None: eps[n]); w0_row the static
+    W^c_nm(0) for the split quadrature of cd.sigma_c (None: plain quadrature)."""
+    eps_n = float(eps[n] if eps_ref_n is None else eps_ref_n)
 
     def feval(w):
-        s, ds, nres = cd.sigma_c(eps, n_occ, B_ov, b_row, wtab_row, xi, z, w)
+        s, ds, nres = cd.sigma_c(eps, n_occ, B_ov, b_row, wtab_row, xi, z, w, eps_w=eps_w,
+                                 w0_row=w0_row)
         if counter is not None:
             counter.append((w, s, ds, nres))
         return float(eps_n + dsig_x_n + s - w), float(ds - 1.0)
