@@ -119,6 +119,37 @@ int gw_setup(gw_ctx** ctx, int n_mo, int n_occ, int n_aux, const double* eps,
 int gw_qp(gw_ctx* ctx, int n_states, const int* states, const gw_grid* grid, double* E_qp,
           double* sigma_c, double* Z, int* status);
 
+/* Eigenvalue self-consistent GW [Alg1] (its outer loop over maxeviter) in
+ * the two flavours the Introduction names: evGW0 updates the energies in G
+ * only, evGW in G and W.
+ *   mode: GW_EVGW0 or GW_EVGW.  Cycle 1 solves the QP equations of `states`
+ *   as gw_qp does; after every cycle the states' QP energies replace their
+ *   eigenvalues in G (the residue set, the residue frequencies and the
+ *   imaginary-axis term) and, for GW_EVGW, in the transition energies of Pi,
+ *   so that the next cycle rebuilds W^c; the next cycle then solves again,
+ *   starting from those energies.  The QP equation keeps gw_setup's eps_n as
+ *   its constant term; states not requested keep their eigenvalues.
+ *   The imaginary-axis term integrates the static part exactly: W^c is also
+ *   built at xi = 0 (one more grid point), the quadrature takes
+ *   W^c(i xi) - W^c(0) only and -(1/2) sum_m sgn(omega - eps_m) W^c_nm(0) is
+ *   added, which stays accurate when omega sits next to a state's own moved
+ *   pole (plain quadrature cannot resolve a/(a^2 + xi^2) there).  Cycle 1
+ *   therefore differs from gw_qp by the quadrature error of the static part.
+ *   Cycles stop after n_cycles (>= 1), or earlier once the largest change of
+ *   a QP energy from the previous cycle is below ev_tol (>= 0; 0: never).
+ *   Outputs (caller arrays of length n_states) as gw_qp's, from the last
+ *   cycle; E_cycles (nullable) [n_cycles][n_states]: the QP energies of each
+ *   cycle run (later rows untouched); cycles_done (nullable): cycles run.
+ * On return, also on error, the context holds gw_setup's energies again; a
+ * W^c table built from moved energies is dropped from its cache.
+ * Errors: as gw_qp; GW_ENOTSPD also when GW_EVGW's updated energies put an
+ * occupied level at or above a virtual one. */
+#define GW_EVGW0 0
+#define GW_EVGW 1
+int gw_evgw(gw_ctx* ctx, int mode, int n_cycles, double ev_tol, int n_states, const int* states,
+            const gw_grid* grid, double* E_qp, double* sigma_c, double* Z, int* status,
+            double* E_cycles, int* cycles_done);
+
 /* Release the context and all of its device memory.  NULL is ignored. */
 void gw_free(gw_ctx* ctx);
 
@@ -175,8 +206,9 @@ int gw_sigma(gw_ctx* ctx, int n, const int* states, const double* omega, const g
 int gw_residues(gw_ctx* ctx, int k, const int* states, const int* m, const double* w,
                 int use_fallback, double* x, double* wc, double* dwc, int* iters);
 
-/* Per-context timing of the last gw_qp / gw_wtable call, milliseconds,
- * measured with HIP events on the context stream. */
+/* Per-context timing of the last gw_qp / gw_evgw / gw_wtable call,
+ * milliseconds, measured with HIP events on the context stream (stage times
+ * summed over the W^c builds of the call). */
 typedef struct gw_timing {
   double pi_ms, chol_ms, wtab_ms, quad_ms, minres_ms, fallback_ms, total_ms;
   int qp_rounds, minres_iters, minres_systems, fallback_systems, wtab_cached;

@@ -92,6 +92,8 @@ _sig = {
     "gw_setup": (ctypes.c_int, [ctypes.POINTER(_ctxp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 _dp, _dp, ctypes.c_int, _ip, _dp, ctypes.POINTER(_Opts)]),
     "gw_qp": (ctypes.c_int, [_ctxp, ctypes.c_int, _ip, ctypes.POINTER(_Grid), _dp, _dp, _dp, _ip]),
+    "gw_evgw": (ctypes.c_int, [_ctxp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                               _ip, ctypes.POINTER(_Grid), _dp, _dp, _dp, _ip, _dp, _ip]),
     "gw_free": (None, [_ctxp]),
     "gw_set_pi_prec": (ctypes.c_int, [_ctxp, ctypes.c_int]),
     "gw_dielectric": (ctypes.c_int, [_ctxp, ctypes.c_int, _dp, _dp]),
@@ -229,6 +231,21 @@ class Context:
         _check(_lib.gw_qp(self._h, n, _pi(st), ctypes.byref(grid._g), _pd(E), _pd(S), _pd(Z),
                           _pi(status)))
         return E, S, Z, status
+
+    def evgw(self, states: Sequence[int], grid: Grid, mode="evgw0", n_cycles=3, ev_tol=0.0):
+        """Eigenvalue self-consistent GW (gw_evgw).  Returns (E, sigma_c, Z, status)
+        of the last cycle and the QP energies of every cycle, [cycles][n_states]."""
+        st = _i(states)
+        n = st.size
+        m = {"evgw0": 0, "evgw": 1}[mode] if isinstance(mode, str) else int(mode)
+        E, S, Z = np.empty(n), np.empty(n), np.empty(n)
+        status = np.empty(n, dtype=np.int32)
+        hist = np.zeros((max(int(n_cycles), 1), n))
+        done = ctypes.c_int(0)
+        _check(_lib.gw_evgw(self._h, m, int(n_cycles), float(ev_tol), n, _pi(st),
+                            ctypes.byref(grid._g), _pd(E), _pd(S), _pd(Z), _pi(status), _pd(hist),
+                            ctypes.byref(done)))
+        return E, S, Z, status, hist[:done.value].copy()
 
     def wtable(self, grid: Grid):
         out = np.empty((self.row_ids.size, self.n_mo, grid.n))

@@ -224,25 +224,37 @@ hipError_t make_scale_imag(const double* D, int Kov, int Kp, const double* xi, i
 // partial sums are added in a fixed order by a second small kernel.
 constexpr int QUAD_SLICES = 16;
 
+// Table rows hold ld >= G columns per m; with w0 the column G holds the static
+// W^c_nm(0): the quadrature then takes W^c(i xi) - W^c(0) only, and the static
+// part's integral int_0^inf a/(a^2 + xi^2) d xi = (pi/2) sgn(a) is added
+// exactly (once per m, by the thread that visits g = 0).
 __global__ __launch_bounds__(256) void k_sigma_quad_part(const double* wtab, int n_mo, int G,
-                                                         const int* rowsel, const double* omega,
+                                                         int ld, int w0, const int* rowsel,
+                                                         const double* omega,
                                                          const double* eps, const double* xi,
                                                          const double* z, double* part) {
   __shared__ double rs[256], rd[256];
   const int j = blockIdx.x, sl = blockIdx.y, t = threadIdx.x;
   const int r = rowsel[j];
   const double w = omega[j];
-  const double* W = wtab + (long)r * n_mo * G;
+  const double* W = wtab + (long)r * n_mo * ld;
   const long n = (long)n_mo * G;
   const long chunk = (n + QUAD_SLICES - 1) / QUAD_SLICES;
   const long lo = sl * chunk, hi = lo + chunk < n ? lo + chunk : n;
+  const double half_pi = 1.57079632679489661923;
   double s = 0.0, d = 0.0;
   for (long idx = lo + t; idx < hi; idx += 256) {
     int m = (int)(idx / G), g = (int)(idx % G);
     double a = w - eps[m];
     double x2 = xi[g] * xi[g];
     double den = a * a + x2;
-    double wz = W[idx] * z[g];
+    double wv = W[(long)m * ld + g];
+    if (w0) {
+      const double ws = W[(long)m * ld + G];
+      wv -= ws;
+      if (g == 0) s += half_pi * (double)((a > 0.0) - (a < 0.0)) * ws;
+    }
+    double wz = wv * z[g];
     s += wz * a / den;
     d += wz * (x2 - a * a) / (den * den);
   }
@@ -275,17 +287,18 @@ __global__ void k_sigma_quad_sum(const double* part, int n, double* sig, double*
   dsig[j] = -inv_pi * d;
 }
 
-hipError_t sigma_quad(const double* wtab, int n_mo, int G, const int* rowsel, const double* omega,
-                      const double* eps, const double* xi, const double* z, int n, double* sig,
-                      double* dsig, double* part, int n_rows, long nW, long nPart,
-                      hipStream_t st) {
+hipError_t sigma_quad(const double* wtab, int n_mo, int G, int ld, int w0, const int* rowsel,
+                      const double* omega, const double* eps, const double* xi, const double* z,
+                      int n, double* sig, double* dsig, double* part, int n_rows, long nW,
+                      long nPart, hipStream_t st) {
   if (n <= 0) return hipSuccess;
+  if (G < 1 || ld < G + (w0 ? 1 : 0)) return hipErrorInvalidValue;
   // row indices come from the context's validated state -> row map (< n_rows)
-  GW_GUARD("sigma_quad", "wtab", (long)n_rows * n_mo * G - 1, nW);
+  GW_GUARD("sigma_quad", "wtab", (long)n_rows * n_mo * ld - 1, nW);
   GW_GUARD("sigma_quad", "partials", (long)n * QUAD_SLICES * 2 - 1, nPart);
   GW_AUDIT_RETURN();
   hipLaunchKernelGGL(k_sigma_quad_part, dim3(n, QUAD_SLICES), dim3(256), 0, st, wtab, n_mo, G,
-                     rowsel, omega, eps, xi, z, part);
+                     ld, w0, rowsel, omega, eps, xi, z, part);
   hipLaunchKernelGGL(k_sigma_quad_sum, dim3((n + 63) / 64), dim3(64), 0, st, part, n, sig, dsig);
   return hipGetLastError();
 }

@@ -192,8 +192,11 @@ struct gw_ctx {
   int minres_batch = 256;     // systems per MINRES batch (bounds the workspace)
   size_t mem_budget = 0, work_budget = 16ull << 30;
   size_t mem_used = 0;
-  // host copies
-  std::vector<double> eps, dsig_x;
+  // host copies: eps_ks are the mean-field eigenvalues (the QP equation's
+  // constant term); eps the energies in G (the poles of G in the residue set,
+  // the residue frequencies and the quadrature), equal to eps_ks except while
+  // gw_evgw runs; d_eps mirrors eps, d_D holds the transition energies of W
+  std::vector<double> eps_ks, eps, dsig_x;
   std::vector<int> row_ids;
   std::map<int, int> row_of;
   // stream
@@ -244,8 +247,10 @@ struct gw_ctx {
   double* d_grid = nullptr;    // [2][Gmax]
   int grid_cap = 0;
   // W^c table cache
-  double* d_wtab = nullptr;    // [nR][G]
-  int wtab_G = 0;
+  double* d_wtab = nullptr;    // [nR][wtab_G]
+  int wtab_G = 0;              // table columns
+  int quad_G = 0;              // quadrature points (wtab_G, or wtab_G - 1 with wtab_w0)
+  int wtab_w0 = 0;             // last column is W^c(0) for the split quadrature
   bool wtab_valid = false;
   std::vector<double> wtab_xi, wtab_w;
   int wtab_prec = -1;
@@ -542,11 +547,25 @@ int copy_out_blocks(gw_ctx* c, double* dst, int Gc, long per_g, long ldA) {
 
 // Build the W^c table for `grid` unless cached.  mode: 0 normal; 1/2 write
 // the dielectric matrix / Cholesky factor of each point to `dbg_out`.
-int build_wtable(gw_ctx* c, const gw_grid* grid, int mode = 0, double* dbg_out = nullptr) {
-  RCHK(check_grid(grid));
+// with_w0 (mode 0): one more column, W^c at xi = 0, for the split quadrature.
+int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_out = nullptr,
+                 bool with_w0 = false) {
+  RCHK(check_grid(grid_in));
+  std::vector<double> ext_xi, ext_w;
+  gw_grid ext = *grid_in;
+  if (with_w0) {
+    ext_xi.assign(grid_in->xi, grid_in->xi + grid_in->n);
+    ext_w.assign(grid_in->w, grid_in->w + grid_in->n);
+    ext_xi.push_back(0.0);
+    ext_w.push_back(0.0);
+    ext.n = grid_in->n + 1;
+    ext.xi = ext_xi.data();
+    ext.w = ext_w.data();
+  }
+  const gw_grid* grid = &ext;
   const int G = grid->n;
-  if (mode == 0 && c->wtab_valid && c->wtab_G == G && c->wtab_prec == c->pi_prec &&
-      std::equal(grid->xi, grid->xi + G, c->wtab_xi.begin()) &&
+  if (mode == 0 && c->wtab_valid && c->wtab_G == G && c->wtab_w0 == (int)with_w0 &&
+      c->wtab_prec == c->pi_prec && std::equal(grid->xi, grid->xi + G, c->wtab_xi.begin()) &&
       std::equal(grid->w, grid->w + G, c->wtab_w.begin())) {
     c->timing.wtab_cached = 1;
     return 0;
@@ -608,12 +627,14 @@ int build_wtable(gw_ctx* c, const gw_grid* grid, int mode = 0, double* dbg_out =
     }
     wt_ms += tm.stop();
   }
-  c->timing.pi_ms = pi_ms;
-  c->timing.chol_ms = chol_ms;
-  c->timing.wtab_ms = wt_ms;
+  c->timing.pi_ms += pi_ms;
+  c->timing.chol_ms += chol_ms;
+  c->timing.wtab_ms += wt_ms;
   if (mode == 0) {
     c->wtab_valid = true;
     c->wtab_G = G;
+    c->wtab_w0 = with_w0 ? 1 : 0;
+    c->quad_G = with_w0 ? G - 1 : G;
     c->wtab_prec = c->pi_prec;
     c->wtab_xi.assign(grid->xi, grid->xi + G);
     c->wtab_w.assign(grid->w, grid->w + G);
@@ -1039,9 +1060,10 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
     if (!audit_mode()) HIPCHK(hipEventRecord(c->ev_quad[0], c->st));
     HIPCHK(rt_memcpy(c->d_omega, h_om, (size_t)sc * (sizeof(double) + sizeof(int)),
                      hipMemcpyHostToDevice, c->st));
-    HIPCHK(sigma_quad(c->d_wtab, c->n_mo, c->wtab_G, c->d_rowsel, c->d_omega, c->d_eps, c->d_grid,
-                      c->d_grid + c->grid_cap, n, c->d_sig, c->d_dsig, c->d_sigpart,
-                      c->n_rows, c->ext(c->d_wtab, 8), c->ext(c->d_sigpart, 8), c->st));
+    HIPCHK(sigma_quad(c->d_wtab, c->n_mo, c->quad_G, c->wtab_G, c->wtab_w0, c->d_rowsel,
+                      c->d_omega, c->d_eps, c->d_grid, c->d_grid + c->grid_cap, n, c->d_sig,
+                      c->d_dsig, c->d_sigpart, c->n_rows, c->ext(c->d_wtab, 8),
+                      c->ext(c->d_sigpart, 8), c->st));
     HIPCHK(rt_memcpy(h_sig, c->d_sig, 2 * (size_t)sc * sizeof(double), hipMemcpyDeviceToHost,
                      c->st));
     if (!audit_mode()) HIPCHK(hipEventRecord(c->ev_quad[1], c->st));
@@ -1147,7 +1169,7 @@ double alpha_of(double f) { return f != 0.0 ? std::min(0.1, 0.1 / std::fabs(f)) 
 
 // One step-tree decision for a state that has just been evaluated.
 void qp_step(gw_ctx* c, QPState& q, double sigma, double dsigma) {
-  const double f = c->eps[q.n] + c->dsig_x[q.n] + sigma - q.w;
+  const double f = c->eps_ks[q.n] + c->dsig_x[q.n] + sigma - q.w;
   q.last_f = std::fabs(f);
   const double fprime = dsigma - 1.0;
   const double Z = (fprime != 0.0) ? -1.0 / fprime : INFINITY;
@@ -1192,6 +1214,53 @@ int validate_states(gw_ctx* c, int n, const int* states) {
   for (int j = 0; j < n; ++j)
     if (!c->row_of.count(states[j]))
       return fail(GW_EINVAL, "state %d was not among the rows given to gw_setup", states[j]);
+  return 0;
+}
+
+// The QP equations of `states` on the context's current W^c table, all states
+// advancing together one step-tree decision per round (one batched Sigma
+// evaluation per round); start: first frequency per state (NULL: the energy
+// of the state in G).
+int solve_qp(gw_ctx* c, int n_states, const int* states, std::vector<QPState>& qs, int* rounds,
+             const double* start = nullptr) {
+  qs.assign(n_states, QPState{});
+  for (int j = 0; j < n_states; ++j) {
+    qs[j].n = states[j];
+    qs[j].w = start ? start[j] : c->eps[states[j]];
+  }
+  *rounds = 0;
+  while (true) {
+    std::vector<int> act, st;
+    std::vector<double> om, tol;
+    for (int j = 0; j < n_states; ++j)
+      if (!qs[j].done) {
+        act.push_back(j);
+        st.push_back(qs[j].n);
+        om.push_back(qs[j].w);
+        // inexact Newton: residue solves need an error well below the current
+        // |f| only; the last evaluations run at the full tolerance
+        const double lf = qs[j].last_f < 0 ? 1.0 : qs[j].last_f;
+        tol.push_back(std::min(1e-6, std::max(c->minres_rtol, 1e-4 * lf)));
+      }
+    if (act.empty()) break;
+    std::vector<double> sg, dsg;
+    std::vector<int> nres, flags;
+    RCHK(eval_sigma(c, st, om, sg, dsg, nres, flags, &tol));
+    (*rounds)++;
+    for (size_t a = 0; a < act.size(); ++a) {
+      QPState& q = qs[act[a]];
+      q.status |= flags[a];
+      qp_step(c, q, sg[a], dsg[a]);
+      if (!q.done && q.iter >= c->qp_max_iter) {
+        // report the last evaluated point
+        q.done = true;
+        q.E = q.wp;
+        q.sig = sg[a];
+        const double fprime = dsg[a] - 1.0;
+        q.Z = fprime != 0.0 ? -1.0 / fprime : INFINITY;
+      }
+    }
+  }
   return 0;
 }
 
@@ -1400,6 +1469,7 @@ int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* 
   if (o.minres_batch > 0) c->minres_batch = std::max(64, o.minres_batch);
   c->graphs_off = o.no_graphs != 0;
   c->eps.assign(eps, eps + n_mo);
+  c->eps_ks = c->eps;
   c->dsig_x.assign(n_mo, 0.0);
   if (o.dsig_x) {
     for (int i = 0; i < n_mo; ++i) {
@@ -1516,6 +1586,7 @@ int gw_dielectric(gw_ctx* c, int n_xi, const double* xi, double* out) {
   if (!c || n_xi < 1 || !xi || !out) return fail(GW_EINVAL, "bad arguments");
   std::vector<double> w(n_xi, 1.0);
   gw_grid g{n_xi, xi, w.data()};
+  c->timing = gw_timing{};
   RCHK(build_wtable(c, &g, 1, out));
   return finish();
 }
@@ -1524,6 +1595,7 @@ int gw_cholesky(gw_ctx* c, int n_xi, const double* xi, double* out) {
   if (!c || n_xi < 1 || !xi || !out) return fail(GW_EINVAL, "bad arguments");
   std::vector<double> w(n_xi, 1.0);
   gw_grid g{n_xi, xi, w.data()};
+  c->timing = gw_timing{};
   RCHK(build_wtable(c, &g, 2, out));
   return finish();
 }
@@ -1598,45 +1670,9 @@ int gw_qp(gw_ctx* c, int n_states, const int* states, const gw_grid* grid, doubl
   total.start(c->st);
   int rc = build_wtable(c, grid, 0);
   if (rc) return rc;
-  std::vector<QPState> qs(n_states);
-  for (int j = 0; j < n_states; ++j) {
-    qs[j].n = states[j];
-    qs[j].w = c->eps[states[j]];
-  }
+  std::vector<QPState> qs;
   int rounds = 0;
-  while (true) {
-    std::vector<int> act, st;
-    std::vector<double> om, tol;
-    for (int j = 0; j < n_states; ++j)
-      if (!qs[j].done) {
-        act.push_back(j);
-        st.push_back(qs[j].n);
-        om.push_back(qs[j].w);
-        // inexact Newton: residue solves need an error well below the current
-        // |f| only; the last evaluations run at the full tolerance
-        const double lf = qs[j].last_f < 0 ? 1.0 : qs[j].last_f;
-        tol.push_back(std::min(1e-6, std::max(c->minres_rtol, 1e-4 * lf)));
-      }
-    if (act.empty()) break;
-    std::vector<double> sg, dsg;
-    std::vector<int> nres, flags;
-    rc = eval_sigma(c, st, om, sg, dsg, nres, flags, &tol);
-    if (rc) break;
-    rounds++;
-    for (size_t a = 0; a < act.size(); ++a) {
-      QPState& q = qs[act[a]];
-      q.status |= flags[a];
-      qp_step(c, q, sg[a], dsg[a]);
-      if (!q.done && q.iter >= c->qp_max_iter) {
-        // report the last evaluated point
-        q.done = true;
-        q.E = q.wp;
-        q.sig = sg[a];
-        const double fprime = dsg[a] - 1.0;
-        q.Z = fprime != 0.0 ? -1.0 / fprime : INFINITY;
-      }
-    }
-  }
+  rc = solve_qp(c, n_states, states, qs, &rounds);
   const double ms = total.stop();
   if (rc) return rc;
   c->timing.total_ms = ms;
@@ -1647,6 +1683,101 @@ int gw_qp(gw_ctx* c, int n_states, const int* states, const gw_grid* grid, doubl
     Z[j] = qs[j].Z;
     if (status) status[j] = qs[j].status;
   }
+  return finish();
+}
+
+int gw_evgw(gw_ctx* c, int mode, int n_cycles, double ev_tol, int n_states, const int* states,
+            const gw_grid* grid, double* E_qp, double* sigma_c, double* Z, int* status,
+            double* E_cycles, int* cycles_done) {
+  if (!c || n_states < 0 || (n_states > 0 && (!E_qp || !sigma_c || !Z)))
+    return fail(GW_EINVAL, "bad arguments");
+  if (mode != GW_EVGW0 && mode != GW_EVGW) return fail(GW_EINVAL, "unknown mode %d", mode);
+  if (n_cycles < 1 || !(ev_tol >= 0.0) || !std::isfinite(ev_tol))
+    return fail(GW_EINVAL, "need n_cycles >= 1 and a finite ev_tol >= 0");
+  RCHK(validate_states(c, n_states, states));
+  forget_solutions(c);
+  c->timing = gw_timing{};
+  Timer total;
+  total.a = c->ev0b;
+  total.b = c->ev1b;
+  total.start(c->st);
+  // Whatever happens below, the context leaves with its mean-field energies in
+  // G and W again; a W^c table built from moved energies is dropped.
+  bool w_moved = false;
+  auto restore = [&]() -> int {
+    c->eps = c->eps_ks;
+    HIPCHK(rt_memcpy(c->d_eps, c->eps.data(), c->n_mo * sizeof(double), hipMemcpyHostToDevice,
+                     c->st));
+    if (w_moved) {
+      c->wtab_valid = false;
+      HIPCHK(transition_energies(c->d_eps, c->n_occ, c->n_virt, c->Kp, c->d_D,
+                                 c->ext(c->d_eps, 8), c->ext(c->d_D, 8), c->st));
+    }
+    HIPCHK(rt_sync(c->st));
+    return 0;
+  };
+  std::vector<double> prev(n_states, 0.0), cur(n_states, 0.0);
+  std::vector<QPState> qs;
+  int rc = 0, rounds = 0, cycles = 0;
+  for (int cyc = 0; cyc < n_cycles; ++cyc) {
+    if (mode == GW_EVGW && cyc > 0) {
+      // W from the current energies: transition energies, then a fresh table
+      const double homo = *std::max_element(c->eps.begin(), c->eps.begin() + c->n_occ);
+      const double lumo = *std::min_element(c->eps.begin() + c->n_occ, c->eps.end());
+      if (!(lumo > homo)) {
+        rc = fail(GW_ENOTSPD, "evGW: the updated energies close the gap (%.17g >= %.17g)",
+                  homo, lumo);
+        break;
+      }
+      w_moved = true;
+      c->wtab_valid = false;
+      if (transition_energies(c->d_eps, c->n_occ, c->n_virt, c->Kp, c->d_D, c->ext(c->d_eps, 8),
+                              c->ext(c->d_D, 8), c->st) != hipSuccess) {
+        rc = fail(GW_EDEVICE, "transition energies failed");
+        break;
+      }
+    }
+    if ((rc = build_wtable(c, grid, 0, nullptr, true))) break;
+    // each cycle starts its solves from the current energies in G
+    std::vector<double> start(n_states);
+    for (int j = 0; j < n_states; ++j) start[j] = c->eps[states[j]];
+    int r = 0;
+    if ((rc = solve_qp(c, n_states, states, qs, &r, start.data()))) break;
+    rounds += r;
+    for (int j = 0; j < n_states; ++j) cur[j] = qs[j].E;
+    if (E_cycles) std::copy(cur.begin(), cur.end(), E_cycles + (size_t)cyc * n_states);
+    cycles = cyc + 1;
+    double change = 0.0;
+    for (int j = 0; j < n_states; ++j) change = std::max(change, std::fabs(cur[j] - prev[j]));
+    const bool converged = cyc > 0 && change < ev_tol;
+    trace("evgw mode=%d cycle=%d max change=%.3e", mode, cyc, cyc > 0 ? change : 0.0);
+    prev = cur;
+    // the requested states' QP energies become their energies in G (and W)
+    for (int j = 0; j < n_states; ++j) c->eps[states[j]] = cur[j];
+    if (rt_memcpy(c->d_eps, c->eps.data(), c->n_mo * sizeof(double), hipMemcpyHostToDevice,
+                  c->st) != hipSuccess) {
+      rc = fail(GW_EDEVICE, "energy upload failed");
+      break;
+    }
+    if (converged) break;
+  }
+  const std::string err = g_err;
+  const int rrc = restore();
+  const double ms = total.stop();
+  if (rc) {
+    g_err = err;
+    return rc;
+  }
+  if (rrc) return rrc;
+  c->timing.total_ms = ms;
+  c->timing.qp_rounds = rounds;
+  for (int j = 0; j < n_states; ++j) {
+    E_qp[j] = qs[j].E;
+    sigma_c[j] = qs[j].sig;
+    Z[j] = qs[j].Z;
+    if (status) status[j] = qs[j].status;
+  }
+  if (cycles_done) *cycles_done = cycles;
   return finish();
 }
 

@@ -120,12 +120,14 @@ hipError_t copy_vec(const double* src, double* dst, int n, long nSrc, long nDst,
 hipError_t make_scale_imag(const double* D, int Kov, int Kp, const double* xi, int G, double* s,
                            float* s32, long nD, long nXi, long nS, long nS32, hipStream_t st);
 
-// Sigma quadrature: per state j: sum_m sum_g W[row_j][m][g] z_g a/(a^2+xi^2) and derivative
-// Sigma quadrature of n states; part: scratch of n * 32 doubles (16 slices, 2 sums)
-hipError_t sigma_quad(const double* wtab, int n_mo, int G, const int* rowsel, const double* omega,
-                      const double* eps, const double* xi, const double* z, int n, double* sig,
-                      double* dsig, double* part, int n_rows, long nW, long nPart,
-                      hipStream_t st);
+// Sigma quadrature of n states: per state j, -(1/pi) sum_m sum_{g<G} W[row_j][m][g] z_g
+// a/(a^2+xi^2) and its derivative, the table holding ld columns per m; w0 != 0: column G
+// is W^c(0), whose part is integrated exactly.  part: scratch of n * 32 doubles (16
+// slices, 2 sums)
+hipError_t sigma_quad(const double* wtab, int n_mo, int G, int ld, int w0, const int* rowsel,
+                      const double* omega, const double* eps, const double* xi, const double* z,
+                      int n, double* sig, double* dsig, double* part, int n_rows, long nW,
+                      long nPart, hipStream_t st);
 
 // MINRES
 struct MinresBufs {

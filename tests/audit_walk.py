@@ -44,7 +44,9 @@ def run_case(n_occ, n_virt, n_aux, rows, G, wb, cap):
                          lambda: c.residues([rows[0]] * 70, list(range(70 % (n_occ + n_virt))) *
                                             0 + [m % (n_occ + n_virt) for m in range(70)],
                                             np.linspace(-1, 22, 70)),
-                         lambda: c.qp(list(rows), g)):
+                         lambda: c.qp(list(rows), g),
+                         lambda: c.evgw(list(rows), g, mode="evgw0", n_cycles=2),
+                         lambda: c.evgw(list(rows), g, mode="evgw", n_cycles=2)):
                 try:
                     call()
                 except gwl.GWError as e:
