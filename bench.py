@@ -94,6 +94,31 @@ def time_path(gwl, inp, states, grid, prec, steps, warmup):
                 stages={k: float(np.mean([s[k] for s in stages])) for k in stages[0]})
 
 
+def time_evgw(gwl, inp, states, grid, prec, reps=2, n_cycles=3):
+    """evGW0 and evGW, n_cycles cycles each, on the same workload: wall time
+    per call (W^c built inside the call), QP rounds, and the last cycle's
+    energies."""
+    import numpy as np
+    import torch
+    out = {}
+    with gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=1e-10) as c:
+        for mode in ("evgw0", "evgw"):
+            each, rounds = [], []
+            for _ in range(reps + 1):        # the first call warms up
+                c.reset_cache()
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                E, S, Z, st, hist = c.evgw(states, grid, mode=mode, n_cycles=n_cycles)
+                torch.cuda.synchronize()
+                each.append(1e3 * (time.perf_counter() - t1))
+                t = c.timing()
+                rounds.append(t["qp_rounds"])
+            out[mode] = dict(ms_per_call=float(np.median(each[1:])), cycles=int(hist.shape[0]),
+                             qp_rounds=int(rounds[-1]), hist=hist, status=st,
+                             stages={k: round(float(v), 3) for k, v in t.items()})
+    return out
+
+
 def cpu_baseline(inp, states, G, gold):
     """Oracle timed on a bounded sample of the same workload: the W^c table on
     one grid point and one Sigma^c evaluation (with its residues) of the HOMO,
@@ -242,6 +267,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-evgw", action="store_true", help="skip the evGW0 / evGW timing")
     ap.add_argument("--only", default=None, help="time only this Pi precision (profiling)")
     ap.add_argument("--serve", action="store_true", help="run the serving workload instead")
     ap.add_argument("--requests", type=int, default=128)
@@ -337,6 +363,23 @@ def main():
     if "fp64" in res and head != "fp64":
         out["mixed_over_fp64"] = {"qp_per_s": round(h["qp_per_s"] / res["fp64"]["qp_per_s"], 3),
                                   "pi_tflops": round(h["pi_tflops"] / res["fp64"]["pi_tflops"], 3)}
+    if not args.no_evgw:
+        log(f"bench: timing evGW0 / evGW (3 cycles) on the {head} path")
+        evr = time_evgw(gwl, inp, states, grid, head)
+        out["evgw"] = {}
+        for mode, r in evr.items():
+            d = {"ms_per_call": round(r["ms_per_call"], 3), "cycles": r["cycles"],
+                 "qp_rounds": r["qp_rounds"],
+                 "qp_per_s": round(len(states) / (r["ms_per_call"] / 1e3), 3),
+                 "status_nonzero": int(np.count_nonzero(r["status"])),
+                 "stages_ms": r["stages"]}
+            p = os.path.join(ROOT, "tests", "golden", f"{name}_{mode}.json")
+            if os.path.exists(p):
+                ref = np.array(json.load(open(p))["cycles"])
+                if ref.shape == r["hist"].shape:
+                    d["max_err_mev_vs_oracle"] = float(np.max(np.abs(r["hist"] - ref)) / MEV)
+            out["evgw"][mode] = d
+            log(f"bench: {mode}: {json.dumps(d)}")
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(inp, states, cfg.grid_points, gold)

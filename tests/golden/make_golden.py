@@ -1,6 +1,7 @@
 """Write oracle fixtures for the named workloads (calls only oracle/ and gwgen).
 
     python tests/golden/make_golden.py monomer h2o10
+    python tests/golden/make_golden.py h2o10:evgw0 h2o10:evgw     (3 cycles each)
 
 Each fixture is a JSON file tests/golden/<name>.json with the inputs' recipe
 (seed, sizes, grid), the oracle's QP energies, Re Sigma^c at the root, Z,
@@ -18,7 +19,7 @@ sys.path.insert(0, ROOT)
 import numpy as np  # noqa: E402
 
 import gwgen  # noqa: E402
-from oracle import cd, grid, qp  # noqa: E402
+from oracle import cd, ev, grid, qp  # noqa: E402
 
 
 def _threads():
@@ -65,6 +66,34 @@ def make(name, qp_tol=1e-12):
     print(f"{name}: {t_all:.1f} s -> {path}")
 
 
+def make_ev(name, mode, n_cycles=3, qp_tol=1e-12):
+    """Fixture <name>_<mode>.json: the QP energies of every evGW0 / evGW cycle."""
+    cfg = gwgen.CONFIGS[name]
+    inp = gwgen.make_config(name)
+    xi, z = grid.gauss_legendre(cfg.grid_points)
+    t0 = time.time()
+    res, cycles, hist = ev.evgw(inp.eps, inp.n_occ, inp.B_ov, inp.row_ids, inp.B_rows,
+                                list(cfg.states), xi, z, mode=mode, n_cycles=n_cycles,
+                                tol=qp_tol)
+    t_all = time.time() - t0
+    out = dict(name=name, mode=mode, n_cycles=n_cycles, seed=cfg.seed, n_occ=cfg.shape.n_occ,
+               n_virt=cfg.shape.n_virt, n_aux=cfg.shape.n_aux, grid_points=cfg.grid_points,
+               x0=0.5, qp_tol=qp_tol, states=list(cfg.states),
+               cycles=[[float(e) for e in E] for E in hist],
+               results=[dict(state=int(r["state"]), E=r["E"], sigma_c=r["sigma_c"], Z=r["Z"],
+                             status=r["status"]) for r in res],
+               oracle_seconds=t_all, threads=_threads(),
+               note="written by tests/golden/make_golden.py from oracle/ only")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"{name}_{mode}.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(f"{name} {mode}: {t_all:.1f} s -> {path}")
+
+
 if __name__ == "__main__":
     for nm in sys.argv[1:] or ["monomer"]:
-        make(nm)
+        if ":" in nm:
+            base, mode = nm.split(":")
+            make_ev(base, mode)
+        else:
+            make(nm)
