@@ -26,15 +26,18 @@ Readings (listed in DESIGN.md):
 """
 import numpy as np
 
-from . import cd, qp
+from . import cd, cluster, qp
 
 
 def evgw(eps, n_occ, B_ov, row_ids, B_rows, states, xi, z, mode="evgw0", n_cycles=3,
-         ev_tol=0.0, dsig_x=None, tol=1e-10, max_iter=100):
+         ev_tol=0.0, dsig_x=None, tol=1e-10, max_iter=100, cluster_width=0.0):
     """QP energies of `states` after eigenvalue self-consistency.
 
-    mode: "evgw0" (G only) or "evgw" (G and W).  Returns (results of the last
-    cycle as qp.solve returns them, number of cycles run, energies per cycle)."""
+    mode: "evgw0" (G only) or "evgw" (G and W).  cluster_width > 0 applies the
+    cluster initial-guess layer (oracle/cluster.py) in every cycle, with the
+    clusters formed from the current energies in G.  Returns (results of the
+    last cycle as qp.solve returns them, number of cycles run, energies per
+    cycle)."""
     if mode not in ("evgw0", "evgw"):
         raise ValueError(mode)
     eps_ref = np.array(eps, dtype=np.float64)
@@ -50,15 +53,19 @@ def evgw(eps, n_occ, B_ov, row_ids, B_rows, states, xi, z, mode="evgw0", n_cycle
         if mode == "evgw" and cyc > 0:
             wtab = cd.w_table(eps_w, n_occ, B_ov, B_rows, xi)
             w0 = cd.w_table(eps_w, n_occ, B_ov, B_rows, np.zeros(1))[:, :, 0]
-        res = []
+        fevals, dxs = [], []
         for n in states:
             r = row_ids.index(int(n))
             dx = 0.0 if dsig_x is None else float(dsig_x[n])
-            fe = qp.make_feval(eps_g, n_occ, B_ov, B_rows[r], wtab[r], xi, z, int(n), dx,
-                               eps_ref_n=eps_ref[n], eps_w=eps_w, w0_row=w0[r])
-            out = qp.step_tree(fe, eps_g[n], tol=tol, max_iter=max_iter)
-            out.update(state=int(n), sigma_c=out["f"] - (eps_ref[n] + dx - out["E"]))
-            res.append(out)
+            fevals.append(qp.make_feval(eps_g, n_occ, B_ov, B_rows[r], wtab[r], xi, z, int(n),
+                                        dx, eps_ref_n=eps_ref[n], eps_w=eps_w, w0_row=w0[r]))
+            dxs.append(dx)
+        # width 0: every state is its own cluster and starts at its energy in G
+        res = cluster.solve_states(fevals, [float(eps_g[int(n)]) for n in states],
+                                   cluster_width, tol=tol, max_iter=max_iter)
+        for k, n in enumerate(states):
+            res[k].update(state=int(n),
+                          sigma_c=res[k]["f"] - (eps_ref[n] + dxs[k] - res[k]["E"]))
         E = np.array([o["E"] for o in res])
         cycles = cyc + 1
         converged = bool(history) and float(np.max(np.abs(E - history[-1]))) < ev_tol
