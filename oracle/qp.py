@@ -27,7 +27,8 @@ Readings (listed in DESIGN.md):
   * "golden section" on a bracket: with s the end of smaller |f| and e the
     other, the next point is s + 0.381966 (e - s);
   * convergence: |f| < qp_tol.  Between poles df/dw <= -1, so the root is
-    then within qp_tol of w.
+    then within qp_tol of w;
+  * at the iteration cap the last evaluated point is returned, flagged.
 
 Parity unpinned: when the scan finds several roots in the window (core levels
 near a dense pole band), which one the step tree returns is fixed only by
@@ -98,6 +99,8 @@ def step_tree(feval, w0, tol=1e-10, max_iter=100):
 
     feval(w) -> (f, dfdw).  Returns dict(E, f, dfdw, Z, status, iters, trace).
     """
+    if max_iter < 1:
+        raise ValueError("max_iter must be >= 1")
     w = float(w0)
     prev = None
     br = None
@@ -131,10 +134,10 @@ def step_tree(feval, w0, tol=1e-10, max_iter=100):
         trace.append((w, f, kind))
         prev = (w, f)
         w = wn
-    f, fp = feval(w)
-    Z = -1.0 / fp if fp != 0.0 else math.inf
+    # iteration cap: the last evaluated point is the answer (f, Z as evaluated
+    # there); the step computed after it is not taken
     st = STATUS_MAXITER | (STATUS_SMALL_Z if Z < 0.1 else 0)
-    return dict(E=w, f=f, dfdw=fp, Z=Z, status=st, iters=max_iter, trace=trace)
+    return dict(E=prev[0], f=f, dfdw=fp, Z=Z, status=st, iters=max_iter, trace=trace)
 
 
 def make_feval(eps, n_occ, B_ov, b_row, wtab_row, xi, z, n, dsig_x_n=0.0, counter=None,
