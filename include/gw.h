@@ -76,6 +76,15 @@ typedef struct gw_opts {
   int no_graphs;            /* nonzero: launch every MINRES iteration eagerly instead of
                                replaying it from a captured HIP graph (0: graphs; they
                                are also skipped on a stream that cannot be captured) */
+  double cluster_width;     /* > 0: the cluster initial-guess layer of [QP] in gw_qp and
+                               every gw_evgw cycle (0: off).  The requested states,
+                               sorted by their energy in G, form clusters wherever
+                               neighbours lie within cluster_width Ha; each cluster's
+                               median member is solved first, the others start the step
+                               tree at eps_n plus its QP shift (at eps_n if it hit the
+                               iteration cap).  States of different clusters advance
+                               together; a member joins the batched rounds once its
+                               representative is done. */
 } gw_opts;
 
 /* Imaginary-frequency quadrature: nodes xi[n] > 0 and d-xi weights w[n]

@@ -33,7 +33,8 @@ class _Opts(ctypes.Structure):
                 ("minres_rtol", ctypes.c_double), ("qp_tol", ctypes.c_double),
                 ("qp_max_iter", ctypes.c_int), ("dsig_x", _dp), ("stream", ctypes.c_void_p),
                 ("mem_budget_bytes", ctypes.c_size_t), ("work_budget_bytes", ctypes.c_size_t),
-                ("minres_batch", ctypes.c_int), ("no_graphs", ctypes.c_int)]
+                ("minres_batch", ctypes.c_int), ("no_graphs", ctypes.c_int),
+                ("cluster_width", ctypes.c_double)]
 
 
 class _Grid(ctypes.Structure):
@@ -179,7 +180,8 @@ class Context:
 
     def __init__(self, eps, n_occ, B_ov, row_ids, B_rows, pi_prec="fp64", minres_max_iter=0,
                  minres_rtol=0.0, qp_tol=0.0, qp_max_iter=0, dsig_x=None, stream=None,
-                 mem_budget_bytes=0, work_budget_bytes=0, minres_batch=0, graphs=True):
+                 mem_budget_bytes=0, work_budget_bytes=0, minres_batch=0, graphs=True,
+                 cluster_width=0.0):
         eps = _d(eps)
         B_ov = _d(B_ov)
         rows = _i(row_ids)
@@ -195,7 +197,7 @@ class Context:
                   int(minres_max_iter), float(minres_rtol), float(qp_tol), int(qp_max_iter),
                   _pd(self._dsx), ctypes.c_void_p(stream) if stream else None,
                   int(mem_budget_bytes), int(work_budget_bytes), int(minres_batch),
-                  0 if graphs else 1)
+                  0 if graphs else 1, float(cluster_width))
         h = _ctxp()
         _check(_lib.gw_setup(ctypes.byref(h), n_mo, int(n_occ), n_aux, _pd(eps), _pd(B_ov),
                              rows.size, _pi(rows), _pd(B_rows), ctypes.byref(o)))

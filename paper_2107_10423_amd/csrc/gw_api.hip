@@ -189,6 +189,7 @@ struct gw_ctx {
   double minres_rtol = 1e-12;
   double qp_tol = 1e-10;
   int qp_max_iter = 100;
+  double cluster_width = 0.0;  // > 0: cluster initial-guess layer
   int minres_batch = 256;     // systems per MINRES batch (bounds the workspace)
   size_t mem_budget = 0, work_budget = 16ull << 30;
   size_t mem_used = 0;
@@ -1217,23 +1218,48 @@ int validate_states(gw_ctx* c, int n, const int* states) {
   return 0;
 }
 
-// The QP equations of `states` on the context's current W^c table, all states
-// advancing together one step-tree decision per round (one batched Sigma
-// evaluation per round); start: first frequency per state (NULL: the energy
-// of the state in G).
+// The QP equations of `states` on the context's current W^c table, the
+// states advancing together one step-tree decision per round (one batched
+// Sigma evaluation per round); start: first frequency per state (NULL: the
+// energy of the state in G).
+//
+// Cluster initial-guess layer ([QP], the layer after the step tree): with
+// cluster_width > 0 the states, sorted by start energy (ties in request
+// order), split into clusters wherever neighbours are more than the width
+// apart.  A cluster's median member (the lower one for an even count) starts
+// at once; the other members wait, and join the rounds after it is done,
+// starting at their own energy plus its QP shift (their own energy if it hit
+// the iteration cap).  A state's trajectory depends only on its start, so the
+// schedule does not change results.
 int solve_qp(gw_ctx* c, int n_states, const int* states, std::vector<QPState>& qs, int* rounds,
              const double* start = nullptr) {
   qs.assign(n_states, QPState{});
+  std::vector<double> e0(n_states);
   for (int j = 0; j < n_states; ++j) {
     qs[j].n = states[j];
-    qs[j].w = start ? start[j] : c->eps[states[j]];
+    e0[j] = start ? start[j] : c->eps[states[j]];
+    qs[j].w = e0[j];
+  }
+  std::vector<int> waits_for(n_states, -1);   // representative a member waits for
+  if (c->cluster_width > 0.0 && n_states > 1) {
+    std::vector<int> order(n_states);
+    for (int j = 0; j < n_states; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return e0[a] < e0[b]; });
+    for (int i = 0; i < n_states;) {
+      int j = i + 1;
+      while (j < n_states && e0[order[j]] - e0[order[j - 1]] <= c->cluster_width) ++j;
+      const int rep = order[i + (j - i - 1) / 2];
+      for (int k = i; k < j; ++k)
+        if (order[k] != rep) waits_for[order[k]] = rep;
+      i = j;
+    }
   }
   *rounds = 0;
   while (true) {
     std::vector<int> act, st;
     std::vector<double> om, tol;
     for (int j = 0; j < n_states; ++j)
-      if (!qs[j].done) {
+      if (!qs[j].done && waits_for[j] < 0) {
         act.push_back(j);
         st.push_back(qs[j].n);
         om.push_back(qs[j].w);
@@ -1242,7 +1268,7 @@ int solve_qp(gw_ctx* c, int n_states, const int* states, std::vector<QPState>& q
         const double lf = qs[j].last_f < 0 ? 1.0 : qs[j].last_f;
         tol.push_back(std::min(1e-6, std::max(c->minres_rtol, 1e-4 * lf)));
       }
-    if (act.empty()) break;
+    if (act.empty()) break;   // (members are released as soon as their representative is done)
     std::vector<double> sg, dsg;
     std::vector<int> nres, flags;
     RCHK(eval_sigma(c, st, om, sg, dsg, nres, flags, &tol));
@@ -1258,7 +1284,17 @@ int solve_qp(gw_ctx* c, int n_states, const int* states, std::vector<QPState>& q
         q.sig = sg[a];
         const double fprime = dsg[a] - 1.0;
         q.Z = fprime != 0.0 ? -1.0 / fprime : INFINITY;
+        if (q.Z < 0.1) q.status |= GW_ST_SMALL_Z;
       }
+    }
+    for (int r : act) {
+      if (!qs[r].done) continue;
+      const bool guess = !(qs[r].status & GW_ST_MAXITER);
+      for (int j = 0; j < n_states; ++j)
+        if (waits_for[j] == r) {
+          waits_for[j] = -1;
+          if (guess) qs[j].w = e0[j] + (qs[r].E - e0[r]);
+        }
     }
   }
   return 0;
@@ -1447,8 +1483,9 @@ int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* 
   gw_opts o{};
   if (opts) o = *opts;
   if (o.pi_prec < 0 || o.pi_prec > 2) return fail(GW_EINVAL, "unknown pi_prec %d", o.pi_prec);
-  if (o.minres_max_iter < 0 || o.qp_max_iter < 0 || o.minres_rtol < 0 || o.qp_tol < 0)
-    return fail(GW_EINVAL, "negative option");
+  if (o.minres_max_iter < 0 || o.qp_max_iter < 0 || o.minres_rtol < 0 || o.qp_tol < 0 ||
+      !(o.cluster_width >= 0.0) || !std::isfinite(o.cluster_width))
+    return fail(GW_EINVAL, "negative or non-finite option");
 
   gw_ctx* c = new gw_ctx();
   g_contexts_created = true;
@@ -1468,6 +1505,7 @@ int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* 
   if (o.work_budget_bytes > 0) c->work_budget = o.work_budget_bytes;
   if (o.minres_batch > 0) c->minres_batch = std::max(64, o.minres_batch);
   c->graphs_off = o.no_graphs != 0;
+  c->cluster_width = o.cluster_width;
   c->eps.assign(eps, eps + n_mo);
   c->eps_ks = c->eps;
   c->dsig_x.assign(n_mo, 0.0);
