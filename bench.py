@@ -119,6 +119,49 @@ def time_evgw(gwl, inp, states, grid, prec, reps=2, n_cycles=3):
     return out
 
 
+def time_core_spectrum(gwl, prec, reps=2):
+    """Every core level of the (H2O)20-shaped input (20 states, ~100 residue
+    systems each per QP round), plain and with the cluster initial-guess
+    layer; W^c table cached after the first call, so the calls time the QP
+    stage (batched FP64 MINRES).  State 0 is checked against its oracle
+    fixture."""
+    import numpy as np
+    import torch
+    import gwgen
+    cfg = gwgen.CONFIGS["h2o20_core"]
+    n_core = 20
+    inp = gwgen.make_inputs(cfg.shape, cfg.seed, list(range(n_core)))
+    grid = gwl.Grid.gauss_legendre(cfg.grid_points)
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "h2o20_core.json")))
+    out = {"workload": f"(H2O)20-shaped, all {n_core} core levels: n_occ={cfg.shape.n_occ}, "
+                       f"n_virt={cfg.shape.n_virt}, N_aux={cfg.shape.n_aux}, "
+                       f"{cfg.grid_points}-point grid, seed {cfg.seed}", "pi_prec": prec}
+    for width in (0.0, 0.5):
+        with gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=1e-10, cluster_width=width) as c:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            E, S, Z, st = c.qp(list(range(n_core)), grid)
+            torch.cuda.synchronize()
+            first = 1e3 * (time.perf_counter() - t1)
+            each = []
+            for _ in range(reps):
+                t1 = time.perf_counter()
+                E, S, Z, st = c.qp(list(range(n_core)), grid)
+                torch.cuda.synchronize()
+                each.append(1e3 * (time.perf_counter() - t1))
+            t = c.timing()
+        key = "clusters" if width > 0 else "plain"
+        out[key] = {"cluster_width": width, "ms_first_call": round(first, 1),
+                    "ms_cached_wtable": round(float(np.median(each)), 1),
+                    "qp_per_s_cached_wtable": round(n_core / (np.median(each) / 1e3), 2),
+                    "qp_rounds": t["qp_rounds"], "minres_systems": t["minres_systems"],
+                    "minres_iters": t["minres_iters"], "minres_ms": round(t["minres_ms"], 1),
+                    "status_nonzero": int(np.count_nonzero(st)),
+                    "state0_err_mev_vs_oracle": float(abs(E[0] - gold["results"][0]["E"]) / MEV)}
+        log(f"bench: core spectrum {key}: {json.dumps(out[key])}")
+    return out
+
+
 def cpu_baseline(inp, states, G, gold):
     """Oracle timed on a bounded sample of the same workload: the W^c table on
     one grid point and one Sigma^c evaluation (with its residues) of the HOMO,
@@ -268,6 +311,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-evgw", action="store_true", help="skip the evGW0 / evGW timing")
+    ap.add_argument("--no-core", action="store_true", help="skip the full core spectrum timing")
     ap.add_argument("--only", default=None, help="time only this Pi precision (profiling)")
     ap.add_argument("--serve", action="store_true", help="run the serving workload instead")
     ap.add_argument("--requests", type=int, default=128)
@@ -380,6 +424,9 @@ def main():
                     d["max_err_mev_vs_oracle"] = float(np.max(np.abs(r["hist"] - ref)) / MEV)
             out["evgw"][mode] = d
             log(f"bench: {mode}: {json.dumps(d)}")
+    if not args.no_core:
+        log(f"bench: timing the full core spectrum on the {head} path")
+        out["core_spectrum"] = time_core_spectrum(gwl, head)
     if not args.no_cpu_baseline:
         log("bench: timing the oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(inp, states, cfg.grid_points, gold)

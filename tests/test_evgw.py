@@ -124,3 +124,25 @@ def test_bad_arguments():
                 c.evgw([5], g, **args)
         with pytest.raises(gwl().GWError):
             c.evgw([3], g)   # not among the supplied rows
+
+
+@pytest.mark.parametrize("mode", ["evgw0", "evgw"])
+@pytest.mark.parametrize("prec,tol", [("fp64", None), ("bf16x3", MEV)])
+def test_h2o10_full_size_against_fixture(mode, prec, tol):
+    """The (H2O)10 workload, three cycles, against the oracle's cycles stored
+    by tests/golden/make_golden.py."""
+    import json
+    import os
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"h2o10_{mode}.json")
+    if not os.path.exists(p):
+        pytest.skip(f"fixture {p} not written")
+    gold = json.load(open(p))
+    inp = gwgen.make_config("h2o10")
+    with gwl().Context.from_inputs(inp, pi_prec=prec, qp_tol=gold["qp_tol"]) as c:
+        E, S, Z, st, h = c.evgw(gold["states"], gwl().Grid.gauss_legendre(gold["grid_points"]),
+                                mode=mode, n_cycles=gold["n_cycles"])
+    ref = np.array(gold["cycles"])
+    assert h.shape == ref.shape
+    bound = 1e-10 * np.abs(ref) if tol is None else tol
+    assert np.all(np.abs(h - ref) <= bound), np.abs(h - ref).max()
+    assert np.all(st == [r["status"] for r in gold["results"]])
