@@ -38,7 +38,8 @@ import numpy as np
 
 __all__ = [
     "Shape", "Inputs", "CONFIGS", "cluster_shape", "monomer_shape",
-    "make_eps", "make_inputs", "make_config", "serving_stream",
+    "make_eps", "make_inputs", "make_config", "serving_stream", "InputsUHF",
+    "make_inputs_uhf",
 ]
 
 # Sizes per water molecule (n_occ, n_virt, N_aux)
@@ -199,6 +200,54 @@ def full_B(inp_shape: Shape, seed: int, b_scale: float = 1.0) -> np.ndarray:
         B[P][iu] = tri
         B[P] = B[P] + np.triu(B[P], 1).T
     return B
+
+
+@dataclasses.dataclass
+class InputsUHF:
+    """Open-shell inputs: one set of levels and integrals per spin (0 = up,
+    1 = down) over a shared auxiliary basis.  States are named by their
+    spin-orbital index sigma * n_mo + n."""
+    n_mo: int
+    n_occ: tuple            # (n_occ_up, n_occ_down)
+    n_aux: int
+    seed: int
+    eps: np.ndarray         # [2][n_mo], each row ascending
+    B_ov: tuple             # per spin [N_aux][n_occ_s * (n_mo - n_occ_s)]
+    row_ids: np.ndarray     # [n_rows] int32 spin-orbital indices
+    B_rows: np.ndarray      # [n_rows][n_mo][N_aux]: (P|n m) within the row's spin
+
+
+def make_inputs_uhf(shape: Shape, seed: int, row_ids: Sequence[int], n_unpaired: int = 1,
+                    same_spins: bool = False) -> InputsUHF:
+    """Open-shell stand-in built from a closed-shell recipe: spin down has
+    shape.n_occ occupied levels, spin up n_unpaired more (and as many fewer
+    virtual).  Each spin draws its levels and its symmetric B from the recipe
+    with its own key: spin up uses `seed`, spin down `seed + 2**32`.  With
+    same_spins both spins take spin up's draws and n_unpaired must be 0 (the
+    closed-shell inputs of make_inputs, twice)."""
+    if same_spins and n_unpaired != 0:
+        raise ValueError("same_spins needs n_unpaired = 0")
+    n_mo = shape.n_mo
+    occ = (shape.n_occ + n_unpaired, shape.n_occ)
+    if not (1 <= occ[1] and occ[0] < n_mo):
+        raise ValueError("bad open-shell occupation")
+    rows = np.asarray(list(row_ids), dtype=np.int32)
+    if rows.size and (rows.min() < 0 or rows.max() >= 2 * n_mo):
+        raise ValueError("row id out of range")
+    eps = np.empty((2, n_mo))
+    B_ov = [None, None]
+    B_rows = np.empty((rows.size, n_mo, shape.n_aux))
+    for s in (0, 1):
+        sh = dataclasses.replace(shape, n_occ=occ[s], n_virt=n_mo - occ[s])
+        mine = [k for k, r in enumerate(rows) if r // n_mo == s]
+        sub = make_inputs(sh, seed if (s == 0 or same_spins) else seed + (1 << 32),
+                          [int(rows[k]) % n_mo for k in mine])
+        eps[s] = sub.eps
+        B_ov[s] = sub.B_ov
+        for j, k in enumerate(mine):
+            B_rows[k] = sub.B_rows[j]
+    return InputsUHF(n_mo=n_mo, n_occ=occ, n_aux=shape.n_aux, seed=seed, eps=eps,
+                     B_ov=tuple(B_ov), row_ids=rows, B_rows=B_rows)
 
 
 # ---------------------------------------------------------------------------

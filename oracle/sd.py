@@ -60,6 +60,35 @@ def sigma_c(eps, n_occ, rho_row, Omega, omega):
     return sig, dsig
 
 
+def casida_uhf(eps, n_occ, B_ov):
+    """Open-shell excitations from the spin-block Casida equations ("Theory -
+    Spectral Decomposition"): with K_{ia s1, jb s2} = (ia s1|jb s2) =
+    sum_P B^P_{ia s1} B^P_{jb s2} over both spins, A = D + K and B = K, so
+    A - B = D and A + B = D + 2 K in the stacked (up, down) transition space.
+    Returns Omega, orthonormal T, the stacked D and the stacked B_ov
+    [N_aux, N_ov_up + N_ov_down]."""
+    Ds, Bs = [], []
+    for s in (0, 1):
+        e = np.asarray(eps[s], dtype=np.float64)
+        Ds.append((e[None, n_occ[s]:] - e[:n_occ[s], None]).reshape(-1))
+        Bs.append(np.asarray(B_ov[s], dtype=np.float64))
+    D = np.concatenate(Ds)
+    Bc = np.concatenate(Bs, axis=1)
+    sD = np.sqrt(D)
+    M = np.diag(D * D) + 2.0 * sD[:, None] * (Bc.T @ Bc) * sD[None, :]
+    om2, T = np.linalg.eigh(M)
+    if om2.min() <= 0:
+        raise ValueError("RPA instability: non-positive Omega^2")
+    return np.sqrt(om2), T, D, Bc
+
+
+def pole_strengths_uhf(Bc, D, T, b):
+    """rho[..., s] with rho_s^2 / (2 Omega_s) = (w^s)^2, the paper's open-shell
+    pole weight w^s = sum (mn|ia s')(X + Y)^s_{ia s'}, (X + Y) = D^1/2 T
+    Omega^-1/2: rho_s = sqrt(2) b^T B D^1/2 T_s."""
+    return np.sqrt(2.0) * ((b @ Bc) * np.sqrt(D)) @ T
+
+
 def poles(eps, n_occ, Omega):
     """All pole positions of Sigma^c: eps_i - Omega_s and eps_a + Omega_s."""
     eps = np.asarray(eps, dtype=np.float64)
