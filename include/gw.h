@@ -115,6 +115,26 @@ int gw_setup(gw_ctx** ctx, int n_mo, int n_occ, int n_aux, const double* eps,
              const double* B_ov, int n_rows, const int* row_ids, const double* B_rows,
              const gw_opts* opts);
 
+/* Open-shell context [CD-impl] (Pi_PQ(omega) with its explicit sum over the
+ * spin sigma; W_{mn sigma, mn sigma} and I_{nn sigma} per spin):
+ * Pi(i xi) = -2 sum_s (P|ia s) D_s/(D_s^2 + xi^2) (ia s|Q), and a state of
+ * spin s sees only the levels and occupation of spin s in its residue set,
+ * residue frequencies and quadrature.
+ *   n_occ [2]                  occupied levels of spin up, spin down
+ *   eps   [2][n_mo]            levels of each spin, each row strictly ascending
+ *   B_ov_up   [n_aux][n_occ[0]*(n_mo-n_occ[0])]   (P|ia up), column i*n_virt + a
+ *   B_ov_down [n_aux][n_occ[1]*(n_mo-n_occ[1])]   (P|ia down)
+ *   row_ids[n_rows]            spin-orbitals sigma*n_mo + n whose rows are supplied
+ *   B_rows [n_rows][n_mo][n_aux]  (P|nm sigma) over the orbitals m of the row's spin
+ *   opts   as for gw_setup; opts->dsig_x, if given, has 2*n_mo entries
+ * Every other entry point then names states by spin-orbital index.  Both
+ * spins' transitions share one Pi build, Cholesky, W^c table and MINRES
+ * operator.  gw_footprint and the server cover closed-shell contexts only.
+ * Errors: as gw_setup. */
+int gw_setup_uhf(gw_ctx** ctx, int n_mo, const int* n_occ, int n_aux, const double* eps,
+                 const double* B_ov_up, const double* B_ov_down, int n_rows, const int* row_ids,
+                 const double* B_rows, const gw_opts* opts);
+
 /* G0W0 quasiparticle energies [QP], [Alg1] with maxeviter = 0:
  * for each state n solves eps_QP = eps_n + dsig_x_n + Re Sigma^c_nn(eps_QP)
  * with Sigma^c = R - I [CD-theory]: the imaginary-axis term from the W^c
@@ -151,6 +171,7 @@ int gw_qp(gw_ctx* ctx, int n_states, const int* states, const gw_grid* grid, dou
  *   cycle run (later rows untouched); cycles_done (nullable): cycles run.
  * On return, also on error, the context holds gw_setup's energies again; a
  * W^c table built from moved energies is dropped from its cache.
+ * Closed-shell contexts only (GW_EINVAL for a gw_setup_uhf context).
  * Errors: as gw_qp; GW_ENOTSPD also when GW_EVGW's updated energies put an
  * occupied level at or above a virtual one. */
 #define GW_EVGW0 0

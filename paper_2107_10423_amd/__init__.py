@@ -92,6 +92,8 @@ _sig = {
     "gw_grid_gauss_legendre": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _dp, _dp]),
     "gw_setup": (ctypes.c_int, [ctypes.POINTER(_ctxp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 _dp, _dp, ctypes.c_int, _ip, _dp, ctypes.POINTER(_Opts)]),
+    "gw_setup_uhf": (ctypes.c_int, [ctypes.POINTER(_ctxp), ctypes.c_int, _ip, ctypes.c_int, _dp,
+                                    _dp, _dp, ctypes.c_int, _ip, _dp, ctypes.POINTER(_Opts)]),
     "gw_qp": (ctypes.c_int, [_ctxp, ctypes.c_int, _ip, ctypes.POINTER(_Grid), _dp, _dp, _dp, _ip]),
     "gw_evgw": (ctypes.c_int, [_ctxp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                _ip, ctypes.POINTER(_Grid), _dp, _dp, _dp, _ip, _dp, _ip]),
@@ -192,12 +194,9 @@ class Context:
             raise ValueError("B_ov must be [n_aux][n_occ*n_virt]")
         if B_rows.shape != (rows.size, n_mo, n_aux):
             raise ValueError("B_rows must be [n_rows][n_mo][n_aux]")
-        self._dsx = _d(dsig_x) if dsig_x is not None else None
-        o = _Opts(PREC[pi_prec] if isinstance(pi_prec, str) else int(pi_prec),
-                  int(minres_max_iter), float(minres_rtol), float(qp_tol), int(qp_max_iter),
-                  _pd(self._dsx), ctypes.c_void_p(stream) if stream else None,
-                  int(mem_budget_bytes), int(work_budget_bytes), int(minres_batch),
-                  0 if graphs else 1, float(cluster_width))
+        o = self._make_opts(pi_prec, minres_max_iter, minres_rtol, qp_tol, qp_max_iter,
+                            dsig_x, stream, mem_budget_bytes, work_budget_bytes, minres_batch,
+                            graphs, cluster_width)
         h = _ctxp()
         _check(_lib.gw_setup(ctypes.byref(h), n_mo, int(n_occ), n_aux, _pd(eps), _pd(B_ov),
                              rows.size, _pi(rows), _pd(B_rows), ctypes.byref(o)))
@@ -205,9 +204,54 @@ class Context:
         self.n_mo, self.n_occ, self.n_aux = n_mo, int(n_occ), n_aux
         self.row_ids = rows.copy()
 
+    def _make_opts(self, pi_prec="fp64", minres_max_iter=0, minres_rtol=0.0, qp_tol=0.0,
+                   qp_max_iter=0, dsig_x=None, stream=None, mem_budget_bytes=0,
+                   work_budget_bytes=0, minres_batch=0, graphs=True, cluster_width=0.0):
+        self._dsx = _d(dsig_x) if dsig_x is not None else None
+        return _Opts(PREC[pi_prec] if isinstance(pi_prec, str) else int(pi_prec),
+                     int(minres_max_iter), float(minres_rtol), float(qp_tol), int(qp_max_iter),
+                     _pd(self._dsx), ctypes.c_void_p(stream) if stream else None,
+                     int(mem_budget_bytes), int(work_budget_bytes), int(minres_batch),
+                     0 if graphs else 1, float(cluster_width))
+
     @classmethod
     def from_inputs(cls, inp, **kw):
         return cls(inp.eps, inp.n_occ, inp.B_ov, inp.row_ids, inp.B_rows, **kw)
+
+    @classmethod
+    def uhf(cls, eps, n_occ, B_ov_up, B_ov_down, row_ids, B_rows, **kw):
+        """Open-shell context (gw_setup_uhf): eps [2][n_mo], n_occ (up, down),
+        row ids and states as spin-orbital indices sigma * n_mo + n."""
+        self = cls.__new__(cls)
+        self._h = None
+        eps = _d(eps)
+        if eps.ndim != 2 or eps.shape[0] != 2:
+            raise ValueError("eps must be [2][n_mo]")
+        n_mo = eps.shape[1]
+        occ = _i(list(n_occ))
+        Bs = [_d(B_ov_up), _d(B_ov_down)]
+        n_aux = Bs[0].shape[0]
+        for sp in (0, 1):
+            if Bs[sp].shape != (n_aux, int(occ[sp]) * (n_mo - int(occ[sp]))):
+                raise ValueError(f"B_ov of spin {sp} must be [n_aux][n_occ*n_virt]")
+        rows = _i(row_ids)
+        B_rows = _d(B_rows)
+        if B_rows.shape != (rows.size, n_mo, n_aux):
+            raise ValueError("B_rows must be [n_rows][n_mo][n_aux]")
+        o = self._make_opts(**kw)
+        h = _ctxp()
+        _check(_lib.gw_setup_uhf(ctypes.byref(h), n_mo, _pi(occ), n_aux, _pd(eps), _pd(Bs[0]),
+                                 _pd(Bs[1]), rows.size, _pi(rows), _pd(B_rows),
+                                 ctypes.byref(o)))
+        self._h = h
+        self.n_mo, self.n_occ, self.n_aux = n_mo, (int(occ[0]), int(occ[1])), n_aux
+        self.row_ids = rows.copy()
+        return self
+
+    @classmethod
+    def from_inputs_uhf(cls, inp, **kw):
+        return cls.uhf(inp.eps, inp.n_occ, inp.B_ov[0], inp.B_ov[1], inp.row_ids, inp.B_rows,
+                       **kw)
 
     def close(self):
         if getattr(self, "_h", None):

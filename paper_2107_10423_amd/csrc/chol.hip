@@ -230,12 +230,14 @@ constexpr int QUAD_SLICES = 16;
 // exactly (once per m, by the thread that visits g = 0).
 __global__ __launch_bounds__(256) void k_sigma_quad_part(const double* wtab, int n_mo, int G,
                                                          int ld, int w0, const int* rowsel,
+                                                         const int* rowspin,
                                                          const double* omega,
                                                          const double* eps, const double* xi,
                                                          const double* z, double* part) {
   __shared__ double rs[256], rd[256];
   const int j = blockIdx.x, sl = blockIdx.y, t = threadIdx.x;
   const int r = rowsel[j];
+  if (rowspin) eps += (long)rowspin[r] * n_mo;
   const double w = omega[j];
   const double* W = wtab + (long)r * n_mo * ld;
   const long n = (long)n_mo * G;
@@ -288,17 +290,20 @@ __global__ void k_sigma_quad_sum(const double* part, int n, double* sig, double*
 }
 
 hipError_t sigma_quad(const double* wtab, int n_mo, int G, int ld, int w0, const int* rowsel,
-                      const double* omega, const double* eps, const double* xi, const double* z,
-                      int n, double* sig, double* dsig, double* part, int n_rows, long nW,
-                      long nPart, hipStream_t st) {
+                      const int* rowspin, const double* omega, const double* eps,
+                      const double* xi, const double* z, int n, double* sig, double* dsig,
+                      double* part, int n_rows, long nW, long nPart, long nEps,
+                      hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (G < 1 || ld < G + (w0 ? 1 : 0)) return hipErrorInvalidValue;
+  // (row spins are 0 or 1, set by the context from validated row ids)
+  GW_GUARD("sigma_quad", "eps", (rowspin ? 2L : 1L) * n_mo - 1, nEps);
   // row indices come from the context's validated state -> row map (< n_rows)
   GW_GUARD("sigma_quad", "wtab", (long)n_rows * n_mo * ld - 1, nW);
   GW_GUARD("sigma_quad", "partials", (long)n * QUAD_SLICES * 2 - 1, nPart);
   GW_AUDIT_RETURN();
   hipLaunchKernelGGL(k_sigma_quad_part, dim3(n, QUAD_SLICES), dim3(256), 0, st, wtab, n_mo, G,
-                     ld, w0, rowsel, omega, eps, xi, z, part);
+                     ld, w0, rowsel, rowspin, omega, eps, xi, z, part);
   hipLaunchKernelGGL(k_sigma_quad_sum, dim3((n + 63) / 64), dim3(64), 0, st, part, n, sig, dsig);
   return hipGetLastError();
 }

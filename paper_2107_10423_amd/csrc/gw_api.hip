@@ -178,6 +178,11 @@ struct Timer {
 struct gw_ctx {
   // sizes
   int n_mo = 0, n_occ = 0, n_virt = 0, n_aux = 0, n_rows = 0;
+  // spins: 1 (closed shell) or 2 (open shell, up then down); per-spin
+  // occupations; levels, dsig_x and state names run over n_spin * n_mo
+  // spin-orbitals (sigma * n_mo + n)
+  int n_spin = 1;
+  int n_occ_s[2] = {0, 0};
   int Np = 0;      // n_aux padded to 128
   int Kov = 0;     // n_occ * n_virt
   int Kp = 0;      // Kov padded to 128
@@ -199,6 +204,7 @@ struct gw_ctx {
   // gw_evgw runs; d_eps mirrors eps, d_D holds the transition energies of W
   std::vector<double> eps_ks, eps, dsig_x;
   std::vector<int> row_ids;
+  std::vector<int> row_spin;   // spin of each row
   std::map<int, int> row_of;
   // stream
   hipStream_t st = nullptr;
@@ -257,6 +263,7 @@ struct gw_ctx {
   int wtab_prec = -1;
   // Sigma quadrature buffers
   int* d_rowsel = nullptr;
+  int* d_rowspin = nullptr;      // [n_rows] (open shell only)
   double* d_omega = nullptr;
   double* d_sig = nullptr;
   double* d_dsig = nullptr;
@@ -992,9 +999,9 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
 
 // Residue weight of the residue term R_nn: occupied m carry -theta(eps_m - w),
 // virtual m carry +theta(w - eps_m), with theta(0) = 1/2.
-double residue_weight(const gw_ctx* c, int m, double w) {
-  const double e = c->eps[m];
-  if (m < c->n_occ) {
+double residue_weight(const gw_ctx* c, int spin, int m, double w) {
+  const double e = c->eps[(size_t)spin * c->n_mo + m];
+  if (m < c->n_occ_s[spin]) {
     double x = e - w;
     return x > 0 ? -1.0 : (x == 0 ? -0.5 : 0.0);
   }
@@ -1035,10 +1042,12 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
   std::vector<int> owner;
   std::vector<double> weight;
   for (int j = 0; j < n; ++j) {
+    const int sp = c->row_spin[rows[j]];
+    const double* e = c->eps.data() + (size_t)sp * c->n_mo;
     for (int m = 0; m < c->n_mo; ++m) {
-      double f = residue_weight(c, m, omega[j]);
+      double f = residue_weight(c, sp, m, omega[j]);
       if (f == 0.0) continue;
-      sys.push_back(System{rows[j] * c->n_mo + m, c->eps[m] - omega[j],
+      sys.push_back(System{rows[j] * c->n_mo + m, e[m] - omega[j],
                            tols ? (*tols)[j] : 0.0});
       owner.push_back(j);
       weight.push_back(f);
@@ -1062,9 +1071,10 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
     HIPCHK(rt_memcpy(c->d_omega, h_om, (size_t)sc * (sizeof(double) + sizeof(int)),
                      hipMemcpyHostToDevice, c->st));
     HIPCHK(sigma_quad(c->d_wtab, c->n_mo, c->quad_G, c->wtab_G, c->wtab_w0, c->d_rowsel,
-                      c->d_omega, c->d_eps, c->d_grid, c->d_grid + c->grid_cap, n, c->d_sig,
-                      c->d_dsig, c->d_sigpart, c->n_rows, c->ext(c->d_wtab, 8),
-                      c->ext(c->d_sigpart, 8), c->st));
+                      c->n_spin > 1 ? c->d_rowspin : nullptr, c->d_omega, c->d_eps, c->d_grid,
+                      c->d_grid + c->grid_cap, n, c->d_sig, c->d_dsig, c->d_sigpart, c->n_rows,
+                      c->ext(c->d_wtab, 8), c->ext(c->d_sigpart, 8), c->ext(c->d_eps, 8),
+                      c->st));
     HIPCHK(rt_memcpy(h_sig, c->d_sig, 2 * (size_t)sc * sizeof(double), hipMemcpyDeviceToHost,
                      c->st));
     if (!audit_mode()) HIPCHK(hipEventRecord(c->ev_quad[1], c->st));
@@ -1413,6 +1423,20 @@ int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* 
                     const double* B_ov, int n_rows, const int* row_ids, const double* B_rows,
                     const gw_opts* opts);
 
+// Validated inputs of one context: n_spin = 1 (closed shell) or 2 (open
+// shell); eps [n_spin][n_mo]; B_ov[s] [n_aux][n_occ[s] * (n_mo - n_occ[s])];
+// row ids name spin-orbitals s * n_mo + n.
+struct SetupIn {
+  int n_spin, n_mo, n_occ[2], n_aux;
+  const double* eps;
+  const double* B_ov[2];
+  int n_rows;
+  const int* row_ids;
+  const double* B_rows;
+};
+
+int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts);
+
 // ===========================================================================
 // C-ABI
 
@@ -1473,13 +1497,34 @@ int gw_setup(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps, co
   return setup_validated(out, n_mo, n_occ, n_aux, eps, B_ov, n_rows, row_ids, B_rows, opts);
 }
 
+int gw_setup_uhf(gw_ctx** out, int n_mo, const int* n_occ, int n_aux, const double* eps,
+                 const double* B_ov_up, const double* B_ov_down, int n_rows, const int* row_ids,
+                 const double* B_rows, const gw_opts* opts) {
+  if (!out) return fail(GW_EINVAL, "ctx pointer is NULL");
+  *out = nullptr;
+  if (!n_occ) return fail(GW_EINVAL, "n_occ is NULL");
+  const double* Bs[2] = {B_ov_up, B_ov_down};
+  for (int sp = 0; sp < 2; ++sp) {
+    // each spin's levels and integrals pass the closed-shell checks (the rows
+    // are checked once, with spin up)
+    if (int rc = validate_inputs(n_mo, n_occ[sp], n_aux, eps ? eps + (size_t)sp * n_mo : nullptr,
+                                 Bs[sp], sp == 0 ? n_rows : 0, row_ids, B_rows, true))
+      return fail(rc, "spin %d: %s", sp, gw_last_error());
+  }
+  SetupIn in{2, n_mo, {n_occ[0], n_occ[1]}, n_aux, eps, {B_ov_up, B_ov_down}, n_rows, row_ids,
+             B_rows};
+  return setup_core(out, in, opts);
+}
+
 }  // extern "C"
 
-int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps,
-                    const double* B_ov, int n_rows, const int* row_ids, const double* B_rows,
-                    const gw_opts* opts) {
+int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts) {
   *out = nullptr;
-  const long Kov = (long)n_occ * (n_mo - n_occ);
+  const int n_mo = in.n_mo, n_aux = in.n_aux, n_rows = in.n_rows, n_spin = in.n_spin;
+  long Ks[2] = {0, 0};
+  for (int sp = 0; sp < n_spin; ++sp) Ks[sp] = (long)in.n_occ[sp] * (n_mo - in.n_occ[sp]);
+  const long Kov = Ks[0] + Ks[1];
+  if (Kov > 0x3fffffffL) return fail(GW_EINVAL, "sizes too large");
   gw_opts o{};
   if (opts) o = *opts;
   if (o.pi_prec < 0 || o.pi_prec > 2) return fail(GW_EINVAL, "unknown pi_prec %d", o.pi_prec);
@@ -1489,7 +1534,10 @@ int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* 
 
   gw_ctx* c = new gw_ctx();
   g_contexts_created = true;
-  c->n_mo = n_mo; c->n_occ = n_occ; c->n_virt = n_mo - n_occ; c->n_aux = n_aux;
+  c->n_spin = n_spin;
+  c->n_occ_s[0] = in.n_occ[0];
+  c->n_occ_s[1] = n_spin > 1 ? in.n_occ[1] : in.n_occ[0];
+  c->n_mo = n_mo; c->n_occ = in.n_occ[0]; c->n_virt = n_mo - in.n_occ[0]; c->n_aux = n_aux;
   c->n_rows = n_rows;
   c->Np = round_up(n_aux, 128);
   c->Kov = (int)Kov;
@@ -1506,11 +1554,12 @@ int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* 
   if (o.minres_batch > 0) c->minres_batch = std::max(64, o.minres_batch);
   c->graphs_off = o.no_graphs != 0;
   c->cluster_width = o.cluster_width;
-  c->eps.assign(eps, eps + n_mo);
+  const int n_so = n_spin * n_mo;   // spin-orbitals
+  c->eps.assign(in.eps, in.eps + n_so);
   c->eps_ks = c->eps;
-  c->dsig_x.assign(n_mo, 0.0);
+  c->dsig_x.assign(n_so, 0.0);
   if (o.dsig_x) {
-    for (int i = 0; i < n_mo; ++i) {
+    for (int i = 0; i < n_so; ++i) {
       if (!std::isfinite(o.dsig_x[i])) {
         delete c;
         return fail(GW_EINVAL, "dsig_x[%d] is not finite", i);
@@ -1519,12 +1568,14 @@ int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* 
     }
   }
   for (int r = 0; r < n_rows; ++r) {
-    if (row_ids[r] < 0 || row_ids[r] >= n_mo || c->row_of.count(row_ids[r])) {
+    const int id = in.row_ids[r];
+    if (id < 0 || id >= n_so || c->row_of.count(id)) {
       delete c;
-      return fail(GW_EINVAL, "row_ids[%d] = %d is out of range or repeated", r, row_ids[r]);
+      return fail(GW_EINVAL, "row_ids[%d] = %d is out of range or repeated", r, id);
     }
-    c->row_of[row_ids[r]] = r;
-    c->row_ids.push_back(row_ids[r]);
+    c->row_of[id] = r;
+    c->row_ids.push_back(id);
+    c->row_spin.push_back(id / n_mo);
   }
   int rc = 0;
   auto cleanup = [&](int code) {
@@ -1555,11 +1606,14 @@ int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* 
   } else if (hipHostMalloc((void**)&c->h_poll, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     return cleanup(fail(GW_ENOMEM, "pinned host allocation failed"));
   }
-  if ((rc = c->alloc((void**)&c->d_eps, n_mo * sizeof(double)))) return cleanup(rc);
+  if ((rc = c->alloc((void**)&c->d_eps, (size_t)n_so * sizeof(double)))) return cleanup(rc);
   if ((rc = c->alloc((void**)&c->d_D, (size_t)c->Kp * sizeof(double)))) return cleanup(rc);
   if ((rc = c->alloc((void**)&c->d_Bov, (size_t)c->Np * c->Kp * sizeof(double)))) return cleanup(rc);
   if ((rc = c->alloc((void**)&c->d_R, (size_t)c->Rp * c->Np * sizeof(double)))) return cleanup(rc);
   if ((rc = c->alloc((void**)&c->d_bn, (size_t)c->Rp * sizeof(double)))) return cleanup(rc);
+  if (n_spin > 1 &&
+      (rc = c->alloc((void**)&c->d_rowspin, (size_t)std::max(n_rows, 1) * sizeof(int))))
+    return cleanup(rc);
   hipStream_t st = c->st;
 #define SETUP_CHK(expr)                                                                     \
   do {                                                                                      \
@@ -1567,23 +1621,41 @@ int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* 
     if (e_ != hipSuccess)                                                                   \
       return cleanup(fail(GW_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)));      \
   } while (0)
-  SETUP_CHK(rt_memcpy(c->d_eps, eps, n_mo * sizeof(double), hipMemcpyHostToDevice, st));
-  SETUP_CHK(transition_energies(c->d_eps, n_occ, c->n_virt, c->Kp, c->d_D, c->ext(c->d_eps, 8),
-                                c->ext(c->d_D, 8), st));
+  SETUP_CHK(rt_memcpy(c->d_eps, in.eps, (size_t)n_so * sizeof(double), hipMemcpyHostToDevice, st));
+  SETUP_CHK(transition_energies(c->d_eps, n_spin, n_mo, c->n_occ_s, c->Kp, c->d_D,
+                                c->ext(c->d_eps, 8), c->ext(c->d_D, 8), st));
   SETUP_CHK(rt_memset(c->d_Bov, 0, (size_t)c->Np * c->Kp * sizeof(double), st));
-  SETUP_CHK(rt_memcpy2d(c->d_Bov, (size_t)c->Kp * sizeof(double), B_ov, (size_t)Kov * sizeof(double),
-                             (size_t)Kov * sizeof(double), n_aux, hipMemcpyHostToDevice, st));
+  // the spins' transitions side by side: columns [0, K_up) then [K_up, K_up + K_down)
+  for (int sp = 0; sp < n_spin; ++sp)
+    SETUP_CHK(rt_memcpy2d(c->d_Bov + (sp ? Ks[0] : 0), (size_t)c->Kp * sizeof(double),
+                          in.B_ov[sp], (size_t)Ks[sp] * sizeof(double),
+                          (size_t)Ks[sp] * sizeof(double), n_aux, hipMemcpyHostToDevice, st));
+  // Pi = -2 sum_s B_s diag(.) B_s^T for two spins is the closed-shell form
+  // -4 B diag(.) B^T of the stacked B / sqrt(2): every kernel keeps its factor 4
+  if (n_spin > 1)
+    SETUP_CHK(scale_inplace(c->d_Bov, (long)c->Np * c->Kp, std::sqrt(0.5), c->ext(c->d_Bov, 8),
+                            st));
   SETUP_CHK(rt_memset(c->d_R, 0, (size_t)c->Rp * c->Np * sizeof(double), st));
   if (c->nR > 0) {
-    SETUP_CHK(rt_memcpy2d(c->d_R, (size_t)c->Np * sizeof(double), B_rows,
+    SETUP_CHK(rt_memcpy2d(c->d_R, (size_t)c->Np * sizeof(double), in.B_rows,
                                (size_t)n_aux * sizeof(double), (size_t)n_aux * sizeof(double),
                                c->nR, hipMemcpyHostToDevice, st));
   }
+  if (n_spin > 1 && n_rows > 0)
+    SETUP_CHK(rt_memcpy(c->d_rowspin, c->row_spin.data(), (size_t)n_rows * sizeof(int),
+                        hipMemcpyHostToDevice, st));
   SETUP_CHK(row_norm2(c->d_R, c->Rp, c->Np, c->d_bn, c->ext(c->d_R, 8), c->ext(c->d_bn, 8), st));
   SETUP_CHK(rt_sync(st));
 #undef SETUP_CHK
   *out = c;
   return 0;
+}
+
+int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps,
+                    const double* B_ov, int n_rows, const int* row_ids, const double* B_rows,
+                    const gw_opts* opts) {
+  SetupIn in{1, n_mo, {n_occ, n_occ}, n_aux, eps, {B_ov, nullptr}, n_rows, row_ids, B_rows};
+  return setup_core(out, in, opts);
 }
 
 extern "C" {
@@ -1732,6 +1804,7 @@ int gw_evgw(gw_ctx* c, int mode, int n_cycles, double ev_tol, int n_states, cons
   if (mode != GW_EVGW0 && mode != GW_EVGW) return fail(GW_EINVAL, "unknown mode %d", mode);
   if (n_cycles < 1 || !(ev_tol >= 0.0) || !std::isfinite(ev_tol))
     return fail(GW_EINVAL, "need n_cycles >= 1 and a finite ev_tol >= 0");
+  if (c->n_spin != 1) return fail(GW_EINVAL, "gw_evgw needs a closed-shell context");
   RCHK(validate_states(c, n_states, states));
   forget_solutions(c);
   c->timing = gw_timing{};
@@ -1744,11 +1817,11 @@ int gw_evgw(gw_ctx* c, int mode, int n_cycles, double ev_tol, int n_states, cons
   bool w_moved = false;
   auto restore = [&]() -> int {
     c->eps = c->eps_ks;
-    HIPCHK(rt_memcpy(c->d_eps, c->eps.data(), c->n_mo * sizeof(double), hipMemcpyHostToDevice,
-                     c->st));
+    HIPCHK(rt_memcpy(c->d_eps, c->eps.data(), c->eps.size() * sizeof(double),
+                     hipMemcpyHostToDevice, c->st));
     if (w_moved) {
       c->wtab_valid = false;
-      HIPCHK(transition_energies(c->d_eps, c->n_occ, c->n_virt, c->Kp, c->d_D,
+      HIPCHK(transition_energies(c->d_eps, c->n_spin, c->n_mo, c->n_occ_s, c->Kp, c->d_D,
                                  c->ext(c->d_eps, 8), c->ext(c->d_D, 8), c->st));
     }
     HIPCHK(rt_sync(c->st));
@@ -1760,17 +1833,19 @@ int gw_evgw(gw_ctx* c, int mode, int n_cycles, double ev_tol, int n_states, cons
   for (int cyc = 0; cyc < n_cycles; ++cyc) {
     if (mode == GW_EVGW && cyc > 0) {
       // W from the current energies: transition energies, then a fresh table
-      const double homo = *std::max_element(c->eps.begin(), c->eps.begin() + c->n_occ);
-      const double lumo = *std::min_element(c->eps.begin() + c->n_occ, c->eps.end());
-      if (!(lumo > homo)) {
-        rc = fail(GW_ENOTSPD, "evGW: the updated energies close the gap (%.17g >= %.17g)",
-                  homo, lumo);
-        break;
+      for (int sp = 0; sp < c->n_spin && rc == 0; ++sp) {
+        const auto e = c->eps.begin() + (size_t)sp * c->n_mo;
+        const double homo = *std::max_element(e, e + c->n_occ_s[sp]);
+        const double lumo = *std::min_element(e + c->n_occ_s[sp], e + c->n_mo);
+        if (!(lumo > homo))
+          rc = fail(GW_ENOTSPD, "evGW: the updated energies close the gap of spin %d "
+                    "(%.17g >= %.17g)", sp, homo, lumo);
       }
+      if (rc) break;
       w_moved = true;
       c->wtab_valid = false;
-      if (transition_energies(c->d_eps, c->n_occ, c->n_virt, c->Kp, c->d_D, c->ext(c->d_eps, 8),
-                              c->ext(c->d_D, 8), c->st) != hipSuccess) {
+      if (transition_energies(c->d_eps, c->n_spin, c->n_mo, c->n_occ_s, c->Kp, c->d_D,
+                              c->ext(c->d_eps, 8), c->ext(c->d_D, 8), c->st) != hipSuccess) {
         rc = fail(GW_EDEVICE, "transition energies failed");
         break;
       }
@@ -1792,8 +1867,8 @@ int gw_evgw(gw_ctx* c, int mode, int n_cycles, double ev_tol, int n_states, cons
     prev = cur;
     // the requested states' QP energies become their energies in G (and W)
     for (int j = 0; j < n_states; ++j) c->eps[states[j]] = cur[j];
-    if (rt_memcpy(c->d_eps, c->eps.data(), c->n_mo * sizeof(double), hipMemcpyHostToDevice,
-                  c->st) != hipSuccess) {
+    if (rt_memcpy(c->d_eps, c->eps.data(), c->eps.size() * sizeof(double),
+                  hipMemcpyHostToDevice, c->st) != hipSuccess) {
       rc = fail(GW_EDEVICE, "energy upload failed");
       break;
     }

@@ -110,8 +110,10 @@ hipError_t wc_from_parts(const double* part, long sPart, int nJ, int ldp, const 
                          long nW, hipStream_t st);
 
 // prep
-hipError_t transition_energies(const double* eps, int n_occ, int n_virt, int Kp, double* D,
-                               long nEps, long nD, hipStream_t st);
+// stacked transition energies of n_spin (1 or 2) spins, eps [n_spin][n_mo]
+hipError_t transition_energies(const double* eps, int n_spin, int n_mo, const int* n_occ, int Kp,
+                               double* D, long nEps, long nD, hipStream_t st);
+hipError_t scale_inplace(double* x, long n, double f, long nX, hipStream_t st);
 hipError_t row_norm2(const double* R, int nR, int Np, double* bn, long nRext, long nBn,
                      hipStream_t st);
 hipError_t make_scale_real(const double* D, int Kov, int Kp, double w, double* s, long nD,
@@ -124,10 +126,12 @@ hipError_t make_scale_imag(const double* D, int Kov, int Kp, const double* xi, i
 // a/(a^2+xi^2) and its derivative, the table holding ld columns per m; w0 != 0: column G
 // is W^c(0), whose part is integrated exactly.  part: scratch of n * 32 doubles (16
 // slices, 2 sums)
+// rowspin (nullable): spin of each table row; its levels are eps + rowspin[r] * n_mo
 hipError_t sigma_quad(const double* wtab, int n_mo, int G, int ld, int w0, const int* rowsel,
-                      const double* omega, const double* eps, const double* xi, const double* z,
-                      int n, double* sig, double* dsig, double* part, int n_rows, long nW,
-                      long nPart, hipStream_t st);
+                      const int* rowspin, const double* omega, const double* eps,
+                      const double* xi, const double* z, int n, double* sig, double* dsig,
+                      double* part, int n_rows, long nW, long nPart, long nEps,
+                      hipStream_t st);
 
 // MINRES
 struct MinresBufs {

@@ -4,28 +4,60 @@
 
 namespace gw {
 
-// D[i*n_virt + a] = eps[n_occ + a] - eps[i]; padding entries get a large
-// value so that D/(D^2 - w^2) stays finite there (their B columns are 0).
-__global__ void k_transition(const double* eps, int n_occ, int n_virt, int Kp, double* D) {
-  const int Kov = n_occ * n_virt;
+// Transition energies of every spin, stacked: spin s contributes
+// D[k_s + i*n_virt_s + a] = eps_s[n_occ_s + a] - eps_s[i] with k_0 = 0 and
+// k_1 = n_occ_0 * n_virt_0, eps_s = eps + s * n_mo.  Padding entries get a
+// large value so that D/(D^2 - w^2) stays finite there (their B columns are 0).
+__global__ void k_transition(const double* eps, int n_spin, int n_mo, int n_occ0, int n_occ1,
+                             int Kp, double* D) {
+  const int K0 = n_occ0 * (n_mo - n_occ0);
+  const int K1 = n_spin > 1 ? n_occ1 * (n_mo - n_occ1) : 0;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < Kp; k += gridDim.x * blockDim.x) {
-    if (k < Kov) {
-      int i = k / n_virt, a = k % n_virt;
-      D[k] = eps[n_occ + a] - eps[i];
+    if (k < K0) {
+      const int nv = n_mo - n_occ0, i = k / nv, a = k % nv;
+      D[k] = eps[n_occ0 + a] - eps[i];
+    } else if (k < K0 + K1) {
+      const int nv = n_mo - n_occ1, i = (k - K0) / nv, a = (k - K0) % nv;
+      D[k] = eps[n_mo + n_occ1 + a] - eps[n_mo + i];
     } else {
       D[k] = 1.0e6;
     }
   }
 }
 
-hipError_t transition_energies(const double* eps, int n_occ, int n_virt, int Kp, double* D,
-                               long nEps, long nD, hipStream_t st) {
-  GW_GUARD("transition", "eps", n_occ + n_virt - 1, nEps);
+hipError_t transition_energies(const double* eps, int n_spin, int n_mo, const int* n_occ, int Kp,
+                               double* D, long nEps, long nD, hipStream_t st) {
+  if (n_spin < 1 || n_spin > 2) return refuse("transition", "n_spin");
+  long K = 0;
+  for (int s = 0; s < n_spin; ++s) {
+    if (n_occ[s] < 1 || n_occ[s] >= n_mo) return refuse("transition", "n_occ");
+    K += (long)n_occ[s] * (n_mo - n_occ[s]);
+  }
+  if (K > Kp) return refuse("transition", "K > Kp");
+  GW_GUARD("transition", "eps", (long)n_spin * n_mo - 1, nEps);
   GW_GUARD("transition", "D", Kp - 1, nD);
   GW_AUDIT_RETURN();
   int blocks = (Kp + 255) / 256;
   if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(k_transition, dim3(blocks), dim3(256), 0, st, eps, n_occ, n_virt, Kp, D);
+  hipLaunchKernelGGL(k_transition, dim3(blocks), dim3(256), 0, st, eps, n_spin, n_mo, n_occ[0],
+                     n_spin > 1 ? n_occ[1] : 0, Kp, D);
+  return hipGetLastError();
+}
+
+// x[k] *= f for k < n
+__global__ void k_scale_inplace(double* x, long n, double f) {
+  for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n;
+       k += (long)gridDim.x * blockDim.x)
+    x[k] *= f;
+}
+
+hipError_t scale_inplace(double* x, long n, double f, long nX, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  GW_GUARD("scale_inplace", "x", n - 1, nX);
+  GW_AUDIT_RETURN();
+  long blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_scale_inplace, dim3((unsigned)blocks), dim3(256), 0, st, x, n, f);
   return hipGetLastError();
 }
 

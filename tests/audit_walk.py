@@ -59,10 +59,40 @@ def run_case(n_occ, n_virt, n_aux, rows, G, wb, cap):
               flush=True)
 
 
+def run_uhf_case(n_occ, n_virt, n_aux, rows, G):
+    """Open-shell context: both spins' transitions stacked in one operator."""
+    shape = gwgen.custom_shape(n_occ, n_virt, n_aux, n_core=1)
+    inp = gwgen.make_inputs_uhf(shape, 2, rows)
+    g = gwl.Grid.gauss_legendre(G)
+    n_mo = inp.n_mo
+    for prec in ("fp64", "bf16x3"):
+        c = gwl.Context.from_inputs_uhf(inp, pi_prec=prec)
+        before = gwl.audit_launch_count()
+        for call in (lambda: c.dielectric([0.1]), lambda: c.cholesky([0.3]),
+                     lambda: c.wtable(g),
+                     lambda: c.sigma([rows[0], rows[-1]], [inp.eps[0][1], -0.3], g),
+                     lambda: c.residues([rows[-1]] * 5, [0, 1, 2, 3, n_mo - 1],
+                                        np.linspace(-1, 2, 5)),
+                     lambda: c.qp(list(rows), g)):
+            try:
+                call()
+            except gwl.GWError as e:
+                if e.code != gwl.GW_EAUDIT:
+                    raise
+            else:
+                raise AssertionError("audit mode returned results")
+        n = gwl.audit_launch_count() - before
+        c.close()
+        print(f"uhf case {n_occ}/{n_virt}/{n_aux} rows={len(rows)} G={G} {prec}: {n} launches "
+              f"checked", flush=True)
+
+
 def main():
     gwl.audit_enable()
     for case in CASES:
         run_case(*case)
+    run_uhf_case(6, 40, 150, (3, 6, 46 + 4, 46 + 5), 6)
+    run_uhf_case(1, 3, 20, (0, 4, 5), 3)
     print("audit ok")
 
 

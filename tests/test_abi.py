@@ -76,6 +76,28 @@ def test_setup_rejects_bad_input_before_device_work(mutate, frag):
         assert e.value.code == -1 and frag in str(e.value)
 
 
+@pytest.mark.parametrize("mutate,frag", [
+    (lambda d: d["eps"].__setitem__((1, slice(None)), d["eps"][1][::-1].copy()), "ascending"),
+    (lambda d: d["eps"].__setitem__((1, 2), np.nan), "finite"),
+    (lambda d: d.update(row_ids=np.array([2, 2])), "repeated"),
+    (lambda d: d.update(row_ids=np.array([2, 16])), "range"),
+    (lambda d: d["B_dn"].__setitem__((0, 0), np.inf), "non-finite"),
+])
+def test_open_shell_setup_rejects_bad_input_before_device_work(mutate, frag):
+    import gwgen
+    import paper_2107_10423_amd as gwl
+    u = gwgen.make_inputs_uhf(gwgen.custom_shape(3, 5, 9), 3, [2, 8 + 3])
+    d = dict(eps=u.eps.copy(), B_up=u.B_ov[0].copy(), B_dn=u.B_ov[1].copy(),
+             row_ids=u.row_ids.copy(), B_rows=u.B_rows.copy())
+    mutate(d)
+    if d["B_rows"].shape[0] != d["row_ids"].size:
+        d["B_rows"] = np.zeros((d["row_ids"].size,) + d["B_rows"].shape[1:])
+    with pytest.raises((gwl.GWError, ValueError)) as e:
+        gwl.Context.uhf(d["eps"], u.n_occ, d["B_up"], d["B_dn"], d["row_ids"], d["B_rows"])
+    if isinstance(e.value, gwl.GWError):
+        assert e.value.code == -1 and frag in str(e.value), str(e.value)
+
+
 def test_generator_is_reproducible_and_shaped():
     import gwgen
     a = gwgen.make_config("monomer")
