@@ -115,6 +115,17 @@ int gw_setup(gw_ctx** ctx, int n_mo, int n_occ, int n_aux, const double* eps,
              const double* B_ov, int n_rows, const int* row_ids, const double* B_rows,
              const gw_opts* opts);
 
+/* Setup from the full symmetric tensor B [n_aux][n_mo][n_mo], B[P][p][q] =
+ * (P|pq) [RVF] (the orthonormalised three-index integrals that [Alg1]'s
+ * initialisation produces).  The same as gw_setup with
+ * B_ov[P][i*n_virt + a] = B[P][i][n_occ + a], row_ids = 0..n_mo-1 and
+ * B_rows[n][m][P] = B[P][n][m], so that every state may be requested; the
+ * rows of all states stay resident (n_mo * n_mo * n_aux doubles of device
+ * memory).  B is read as given (rows from B[P][n][m]); it must be symmetric
+ * in p, q.  Errors: as gw_setup. */
+int gw_setup_full(gw_ctx** ctx, int n_mo, int n_occ, int n_aux, const double* eps,
+                  const double* B, const gw_opts* opts);
+
 /* Open-shell context [CD-impl] (Pi_PQ(omega) with its explicit sum over the
  * spin sigma; W_{mn sigma, mn sigma} and I_{nn sigma} per spin):
  * Pi(i xi) = -2 sum_s (P|ia s) D_s/(D_s^2 + xi^2) (ia s|Q), and a state of

@@ -92,6 +92,8 @@ _sig = {
     "gw_grid_gauss_legendre": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, _dp, _dp]),
     "gw_setup": (ctypes.c_int, [ctypes.POINTER(_ctxp), ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 _dp, _dp, ctypes.c_int, _ip, _dp, ctypes.POINTER(_Opts)]),
+    "gw_setup_full": (ctypes.c_int, [ctypes.POINTER(_ctxp), ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, _dp, _dp, ctypes.POINTER(_Opts)]),
     "gw_setup_uhf": (ctypes.c_int, [ctypes.POINTER(_ctxp), ctypes.c_int, _ip, ctypes.c_int, _dp,
                                     _dp, _dp, ctypes.c_int, _ip, _dp, ctypes.POINTER(_Opts)]),
     "gw_qp": (ctypes.c_int, [_ctxp, ctypes.c_int, _ip, ctypes.POINTER(_Grid), _dp, _dp, _dp, _ip]),
@@ -217,6 +219,26 @@ class Context:
     @classmethod
     def from_inputs(cls, inp, **kw):
         return cls(inp.eps, inp.n_occ, inp.B_ov, inp.row_ids, inp.B_rows, **kw)
+
+    @classmethod
+    def full(cls, eps, n_occ, B, **kw):
+        """Context from the full symmetric B [n_aux][n_mo][n_mo] (gw_setup_full):
+        every state may be requested."""
+        self = cls.__new__(cls)
+        self._h = None
+        eps = _d(eps)
+        B = _d(B)
+        n_mo = eps.size
+        if B.ndim != 3 or B.shape[1:] != (n_mo, n_mo):
+            raise ValueError("B must be [n_aux][n_mo][n_mo]")
+        o = self._make_opts(**kw)
+        h = _ctxp()
+        _check(_lib.gw_setup_full(ctypes.byref(h), n_mo, int(n_occ), B.shape[0], _pd(eps),
+                                  _pd(B), ctypes.byref(o)))
+        self._h = h
+        self.n_mo, self.n_occ, self.n_aux = n_mo, int(n_occ), B.shape[0]
+        self.row_ids = np.arange(n_mo, dtype=np.int32)
+        return self
 
     @classmethod
     def uhf(cls, eps, n_occ, B_ov_up, B_ov_down, row_ids, B_rows, **kw):

@@ -1497,6 +1497,36 @@ int gw_setup(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps, co
   return setup_validated(out, n_mo, n_occ, n_aux, eps, B_ov, n_rows, row_ids, B_rows, opts);
 }
 
+int gw_setup_full(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps,
+                  const double* B, const gw_opts* opts) {
+  if (!out) return fail(GW_EINVAL, "ctx pointer is NULL");
+  *out = nullptr;
+  if (!B) return fail(GW_EINVAL, "NULL input array");
+  if (n_mo < 2 || n_occ < 1 || n_occ >= n_mo || n_aux < 1 ||
+      (double)n_aux * n_mo * n_mo > 4.0e9)
+    return fail(GW_EINVAL, "bad sizes: n_mo=%d n_occ=%d n_aux=%d", n_mo, n_occ, n_aux);
+  // B_ov[P][i*n_virt + a] = B[P][i][n_occ + a]; rows of every state,
+  // B_rows[n][m][P] = B[P][n][m]
+  const int n_virt = n_mo - n_occ;
+  std::vector<double> B_ov((size_t)n_aux * n_occ * n_virt);
+  std::vector<double> rows((size_t)n_mo * n_mo * n_aux);
+  std::vector<int> ids(n_mo);
+  for (int n = 0; n < n_mo; ++n) ids[n] = n;
+  for (int P = 0; P < n_aux; ++P) {
+    const double* BP = B + (size_t)P * n_mo * n_mo;
+    for (int i = 0; i < n_occ; ++i)
+      memcpy(&B_ov[((size_t)P * n_occ + i) * n_virt], BP + (size_t)i * n_mo + n_occ,
+             (size_t)n_virt * sizeof(double));
+    for (int n = 0; n < n_mo; ++n)
+      for (int m = 0; m < n_mo; ++m) rows[((size_t)n * n_mo + m) * n_aux + P] = BP[(size_t)n * n_mo + m];
+  }
+  if (int rc = validate_inputs(n_mo, n_occ, n_aux, eps, B_ov.data(), n_mo, ids.data(),
+                               rows.data(), true))
+    return rc;
+  return setup_validated(out, n_mo, n_occ, n_aux, eps, B_ov.data(), n_mo, ids.data(),
+                         rows.data(), opts);
+}
+
 int gw_setup_uhf(gw_ctx** out, int n_mo, const int* n_occ, int n_aux, const double* eps,
                  const double* B_ov_up, const double* B_ov_down, int n_rows, const int* row_ids,
                  const double* B_rows, const gw_opts* opts) {

@@ -113,3 +113,18 @@ def test_generator_is_reproducible_and_shaped():
     c = gwgen.make_config("h2o10", states=[49])
     assert abs(c.B_ov.std() / np.sqrt(0.25 / (50 * 380)) - 1) < 0.01
     assert np.sum(c.eps < -10) == 10 and np.sum(c.eps > 0) == 380
+
+
+def test_full_setup_rejects_bad_input_before_device_work():
+    import gwgen
+    import paper_2107_10423_amd as gwl
+    a = gwgen.make_inputs(gwgen.custom_shape(3, 5, 9), 3, [2])
+    B = gwgen.full_B(a.shape, 3)
+    bad = B.copy()
+    bad[2, 1, 6] = np.nan
+    with pytest.raises(gwl.GWError) as e:
+        gwl.Context.full(a.eps, 3, bad)
+    assert e.value.code == -1 and "non-finite" in str(e.value)
+    with pytest.raises(gwl.GWError) as e:
+        gwl.Context.full(a.eps, 8, B)
+    assert e.value.code == -1 and "sizes" in str(e.value)

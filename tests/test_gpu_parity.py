@@ -333,3 +333,20 @@ def test_pi_precision_h2o10_sampled_rows(prec, bound):
         worst = max(worst, err)
     print(f"Pi precision {prec}: max |error| / max |Pi| = {worst:.3e}")
     assert worst < bound
+
+
+def test_setup_from_the_full_tensor():
+    """gw_setup_full takes B [n_aux][n_mo][n_mo] and serves every state: the
+    same energies as the row-supplied context, and states outside it."""
+    inp = gwgen.make_config("monomer")
+    B = gwgen.full_B(inp.shape, inp.seed)
+    g = gwl().Grid.gauss_legendre(64)
+    with ctx(inp, qp_tol=1e-12) as c:
+        E0, S0, Z0, _ = c.qp([4, 5], g)
+    with gwl().Context.full(inp.eps, inp.n_occ, B, qp_tol=1e-12) as c:
+        E1, S1, Z1, _ = c.qp([4, 5], g)
+        E2, _, _, st2 = c.qp([3, 6], g)
+    assert np.all(np.abs(E1 - E0) <= 1e-12 * np.abs(E0))
+    ref = _oracle_qp(gwgen.make_config("monomer", states=[3, 6]), [3, 6], 64)
+    for j, r in enumerate(ref):
+        assert abs(E2[j] - r["E"]) <= 1e-10 * abs(r["E"])
