@@ -162,6 +162,53 @@ def time_core_spectrum(gwl, prec, reps=2):
     return out
 
 
+def crossover(gwl, ks, reps=3):
+    """Spectral-decomposition route against contour deformation on the GPU
+    for (H2O)_k-shaped inputs (HOMO and LUMO, 64-point grid for CD): wall
+    time of a first call (decomposition or W^c table built inside) and of a
+    cached call, per route."""
+    import numpy as np
+    import torch
+    import gwgen
+    rows = []
+    for k in ks:
+        shape = gwgen.cluster_shape(k)
+        states = [shape.n_occ - 1, shape.n_occ]
+        inp = gwgen.make_inputs(shape, 100 + k, states)
+        grid = gwl.Grid.gauss_legendre(64)
+        row = {"k": k, "n_ov": shape.n_ov, "n_aux": shape.n_aux}
+        E = {}
+        for route in ("sd", "cd_fp64", "cd_bf16x3"):
+            prec = "bf16x3" if route == "cd_bf16x3" else "fp64"
+            with gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=1e-10) as c:
+                call = (lambda: c.qp_sd(states)) if route == "sd" else (lambda: c.qp(states, grid))
+                times = []
+                for rep in range(reps + 1):
+                    if rep > 0:
+                        c.reset_cache()
+                    torch.cuda.synchronize()
+                    t1 = time.perf_counter()
+                    out = call()
+                    torch.cuda.synchronize()
+                    times.append(1e3 * (time.perf_counter() - t1))
+                t0 = time.perf_counter()
+                call()
+                torch.cuda.synchronize()
+                cached = 1e3 * (time.perf_counter() - t0)
+                tm = c.timing()
+            E[route] = out[0]
+            row[route] = {"ms": round(float(np.median(times[1:])), 3), "ms_cached": round(cached, 3)}
+            if route == "sd":
+                c2 = gwl.Context.from_inputs(inp)
+                c2.qp_sd(states)
+                row[route]["jacobi_sweeps"] = c2.timing()["sd_sweeps"]
+                c2.close()
+        row["max_abs_diff_sd_cd_fp64"] = float(np.max(np.abs(E["sd"] - E["cd_fp64"])))
+        rows.append(row)
+        log(f"bench: crossover k={k}: {json.dumps(row)}")
+    return rows
+
+
 def cpu_baseline(inp, states, G, gold):
     """Oracle timed on a bounded sample of the same workload: the W^c table on
     one grid point and one Sigma^c evaluation (with its residues) of the HOMO,
@@ -312,6 +359,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-evgw", action="store_true", help="skip the evGW0 / evGW timing")
     ap.add_argument("--no-core", action="store_true", help="skip the full core spectrum timing")
+    ap.add_argument("--crossover", default=None,
+                    help="comma-separated cluster sizes k: time the SD and CD routes instead")
     ap.add_argument("--only", default=None, help="time only this Pi precision (profiling)")
     ap.add_argument("--serve", action="store_true", help="run the serving workload instead")
     ap.add_argument("--requests", type=int, default=128)
@@ -332,6 +381,13 @@ def main():
         sys.exit(1)
     if args.serve:
         serve_bench(args)
+        return
+    if args.crossover:
+        import paper_2107_10423_amd as gwl
+        ks = [int(k) for k in args.crossover.split(",")]
+        print(json.dumps({"metric": "G0W0 wall time per call, spectral decomposition vs "
+                                    "contour deformation (HOMO, LUMO)", "unit": "ms",
+                          "n_gpus": 1, "data": "synthetic", "rows": crossover(gwl, ks)}))
         return
     if args.copy_calibration:
         x = torch.ones(2**27, dtype=torch.float64, device="cuda")     # 1 GiB

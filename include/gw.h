@@ -13,6 +13,10 @@
  *   [Alg1]       Algorithm 1 (CD-GW)
  *   [QP]         Implementation - Solution of the Quasiparticle Equations
  *                (QP equation, Z, the step-selection tree figure)
+ *   [SD-theory]  Theory - Spectral Decomposition (Casida equations, W and
+ *                Sigma_nn as sums over the excitations Omega_s)
+ *   [SD-impl]    Implementation - Spectral Decomposition (the Hermitian form
+ *                of the Casida problem, A + B in the fitted basis, w^s_mn)
  *   [RVF]        Implementation - Variational Fitting Approximation (the
  *                orthonormalised three-index integrals (P|pq))
  *
@@ -191,6 +195,27 @@ int gw_evgw(gw_ctx* ctx, int mode, int n_cycles, double ev_tol, int n_states, co
             const gw_grid* grid, double* E_qp, double* sigma_c, double* Z, int* status,
             double* E_cycles, int* cycles_done);
 
+/* G0W0 by the spectral-decomposition route [SD-impl], [SD-theory]: the
+ * Hermitian Casida problem (A-B)^1/2 (A+B) (A-B)^1/2 T = Omega^2 T with
+ * A - B = diag(D) and A + B = diag(D) + 4 B_ov^T B_ov (closed shell; an
+ * open-shell context uses its spin-block form) is built and diagonalised on
+ * the GPU (two-sided block Jacobi), the pole strengths w^s_nm of every
+ * supplied row are formed, and the QP equations of `states` are solved with
+ * the step tree of [QP] on the pole form
+ *   Re Sigma^c_nn(omega) = sum_{i,s} (w^s_in)^2/(omega - eps_i + Omega_s)
+ *                        + sum_{a,s} (w^s_an)^2/(omega - eps_a - Omega_s).
+ * No frequency grid and no residue solves are involved.  The decomposition
+ * is kept in the context until gw_reset_cache; it needs two N_ov x N_ov
+ * FP64 matrices, and N_ov above 16384 is refused (GW_EINVAL): the route is
+ * meant for small systems.  Outputs as gw_qp's.
+ * Errors: GW_EINVAL, GW_ENOMEM, GW_EDEVICE (no Jacobi convergence). */
+int gw_qp_sd(gw_ctx* ctx, int n_states, const int* states, double* E_qp, double* sigma_c,
+             double* Z, int* status);
+
+/* The RPA excitation energies Omega_s [SD-impl] of the context, ascending:
+ * Omega [N_ov], N_ov = n_occ * n_virt (open shell: the sum over spins). */
+int gw_rpa_excitations(gw_ctx* ctx, double* Omega);
+
 /* Release the context and all of its device memory.  NULL is ignored. */
 void gw_free(gw_ctx* ctx);
 
@@ -253,6 +278,8 @@ int gw_residues(gw_ctx* ctx, int k, const int* states, const int* m, const doubl
 typedef struct gw_timing {
   double pi_ms, chol_ms, wtab_ms, quad_ms, minres_ms, fallback_ms, total_ms;
   int qp_rounds, minres_iters, minres_systems, fallback_systems, wtab_cached;
+  double sd_ms;     /* spectral-decomposition build (Casida matrix, Jacobi, pole strengths) */
+  int sd_sweeps;    /* block-Jacobi sweeps of that build */
 } gw_timing;
 int gw_get_timing(gw_ctx* ctx, gw_timing* out);
 

@@ -47,7 +47,8 @@ class Timing(ctypes.Structure):
                 ("minres_ms", ctypes.c_double), ("fallback_ms", ctypes.c_double),
                 ("total_ms", ctypes.c_double), ("qp_rounds", ctypes.c_int),
                 ("minres_iters", ctypes.c_int), ("minres_systems", ctypes.c_int),
-                ("fallback_systems", ctypes.c_int), ("wtab_cached", ctypes.c_int)]
+                ("fallback_systems", ctypes.c_int), ("wtab_cached", ctypes.c_int),
+                ("sd_ms", ctypes.c_double), ("sd_sweeps", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -99,6 +100,8 @@ _sig = {
     "gw_qp": (ctypes.c_int, [_ctxp, ctypes.c_int, _ip, ctypes.POINTER(_Grid), _dp, _dp, _dp, _ip]),
     "gw_evgw": (ctypes.c_int, [_ctxp, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                _ip, ctypes.POINTER(_Grid), _dp, _dp, _dp, _ip, _dp, _ip]),
+    "gw_qp_sd": (ctypes.c_int, [_ctxp, ctypes.c_int, _ip, _dp, _dp, _dp, _ip]),
+    "gw_rpa_excitations": (ctypes.c_int, [_ctxp, _dp]),
     "gw_free": (None, [_ctxp]),
     "gw_set_pi_prec": (ctypes.c_int, [_ctxp, ctypes.c_int]),
     "gw_dielectric": (ctypes.c_int, [_ctxp, ctypes.c_int, _dp, _dp]),
@@ -314,6 +317,23 @@ class Context:
                             ctypes.byref(grid._g), _pd(E), _pd(S), _pd(Z), _pi(status), _pd(hist),
                             ctypes.byref(done)))
         return E, S, Z, status, hist[:done.value].copy()
+
+    def qp_sd(self, states: Sequence[int]):
+        """G0W0 by the spectral-decomposition route (gw_qp_sd)."""
+        st = _i(states)
+        n = st.size
+        E, S, Z = np.empty(n), np.empty(n), np.empty(n)
+        status = np.empty(n, dtype=np.int32)
+        _check(_lib.gw_qp_sd(self._h, n, _pi(st), _pd(E), _pd(S), _pd(Z), _pi(status)))
+        return E, S, Z, status
+
+    def rpa_excitations(self):
+        """Casida excitation energies Omega_s, ascending (gw_rpa_excitations)."""
+        occ = self.n_occ if isinstance(self.n_occ, tuple) else (self.n_occ,)
+        n_ov = sum(o * (self.n_mo - o) for o in occ)
+        out = np.empty(n_ov)
+        _check(_lib.gw_rpa_excitations(self._h, _pd(out)))
+        return out
 
     def wtable(self, grid: Grid):
         out = np.empty((self.row_ids.size, self.n_mo, grid.n))

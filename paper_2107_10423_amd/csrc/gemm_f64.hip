@@ -391,6 +391,9 @@ hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, h
   // grid point slowest so that the tiles reading one L^-T panel run together
   if (tile_kind == 0 && la == KC && lb == KM && epi == EPI_SQNORM && !scaled)
     return launch<2, 4, 4, KC, KM, EPI_SQNORM, false, false>(a, st);
+  // Casida matrix: B_ov^T B_ov with both operands k-major (B_ov [P][ia])
+  if (tile_kind == 0 && la == KM && lb == KM && epi == EPI_STORE && !scaled)
+    return launch<2, 4, 4, KM, KM, EPI_STORE, false, false>(a, st);
   // generic full 128x128 store / axpby (tests, dense fallback build)
   if (tile_kind == 0 && la == KC && lb == KC && epi == EPI_STORE && scaled)
     return launch<2, 4, 4, KC, KC, EPI_STORE, true, false>(a, st);

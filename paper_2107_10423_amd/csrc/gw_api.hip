@@ -284,6 +284,17 @@ struct gw_ctx {
   double* d_wc = nullptr;
   double* d_dwc = nullptr;
   int* d_conv = nullptr;
+  // spectral-decomposition route (built on first use; dropped when the
+  // transition energies change)
+  bool sd_valid = false;
+  double* d_sdM = nullptr;     // [Kp][Kp] Casida matrix, diagonalised in place
+  double* d_sdT = nullptr;     // [Kp][Kp] its eigenvectors (columns)
+  double* d_sdV = nullptr;     // [Kp/64][64][64] rotations of one Jacobi round
+  double* d_sdY = nullptr;     // [Rp][Kp] R B_ov, then the pole strengths rho
+  double* d_sdRho = nullptr;   // [Rp][Kp]
+  double* d_sdO = nullptr;     // [Kp] Omega
+  double* d_sdPart = nullptr;  // [2][SD_NORM_BLOCKS]
+  int sd_sweeps = 0;
   // dense fallback workspace
   double* d_dense = nullptr;
   double* d_dscale = nullptr;
@@ -1110,6 +1121,138 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
 }
 
 // ---------------------------------------------------------------------------
+// Spectral-decomposition route (Implementation - Spectral Decomposition)
+
+constexpr int SD_NORM_BLOCKS = 256;
+constexpr int SD_MAX_KP = 16384;    // the dense Kp x Kp eigenproblem is for small systems
+
+// Casida matrix M = D^2 + 4 D^1/2 B_ov^T B_ov D^1/2, its eigendecomposition
+// M = T Omega^2 T^T by block Jacobi, and the pole strengths
+// rho = 2 (R B_ov) D^1/2 T of every supplied row.
+int build_sd(gw_ctx* c) {
+  if (c->sd_valid) return 0;
+  const int Kp = c->Kp;
+  if (Kp > SD_MAX_KP)
+    return fail(GW_EINVAL, "the spectral-decomposition route holds N_ov x N_ov matrices; "
+                "N_ov = %d exceeds its limit %d", c->Kov, SD_MAX_KP);
+  Timer tm;
+  tm.a = c->ev0; tm.b = c->ev1;
+  tm.start(c->st);
+  if (!c->d_sdM) {
+    RCHK(c->alloc((void**)&c->d_sdM, (size_t)Kp * Kp * sizeof(double)));
+    RCHK(c->alloc((void**)&c->d_sdT, (size_t)Kp * Kp * sizeof(double)));
+    RCHK(c->alloc((void**)&c->d_sdV, (size_t)(Kp / 64) * 64 * 64 * sizeof(double)));
+    RCHK(c->alloc((void**)&c->d_sdY, (size_t)c->Rp * Kp * sizeof(double)));
+    RCHK(c->alloc((void**)&c->d_sdRho, (size_t)c->Rp * Kp * sizeof(double)));
+    RCHK(c->alloc((void**)&c->d_sdO, (size_t)Kp * sizeof(double)));
+    RCHK(c->alloc((void**)&c->d_sdPart, 2 * (size_t)SD_NORM_BLOCKS * sizeof(double)));
+  }
+  {  // B_ov^T B_ov (both operands k-major), then the Casida scaling
+    GemmArgs a{};
+    a.A = c->d_Bov; a.lda = Kp;
+    a.B = c->d_Bov; a.ldb = Kp;
+    a.C = c->d_sdM; a.ldc = Kp;
+    a.M = Kp; a.N = Kp; a.K = c->Np;
+    a.map = MAP_FULL; a.tiles_m = Kp / 128; a.tiles_n = Kp / 128;
+    a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
+    RCHK(run_gemm(c, a, 0, KM, KM, EPI_STORE));
+  }
+  HIPCHK(casida_matrix(c->d_sdM, Kp, c->d_D, c->Kov, Kp, c->ext(c->d_sdM, 8), c->ext(c->d_D, 8),
+                       c->st));
+  HIPCHK(set_identity(c->d_sdT, Kp, Kp, c->ext(c->d_sdT, 8), c->st));
+  const int nb = Kp / 32;
+  // inner Jacobi sweeps per 64 x 64 subproblem (GW_TUNE_SD="sweeps" replaces the default)
+  int inner = 1;
+  if (const char* e = getenv("GW_TUNE_SD")) inner = std::max(1, std::min(16, atoi(e)));
+  std::vector<double> part(2 * SD_NORM_BLOCKS);
+  int sweeps = 0;
+  double off_prev = -1.0;
+  for (; sweeps < 40; ++sweeps) {
+    HIPCHK(offnorm(c->d_sdM, Kp, c->Kov, c->d_sdPart, SD_NORM_BLOCKS, c->ext(c->d_sdM, 8),
+                   c->ext(c->d_sdPart, 8), c->st));
+    HIPCHK(rt_memcpy(part.data(), c->d_sdPart, part.size() * sizeof(double),
+                     hipMemcpyDeviceToHost, c->st));
+    HIPCHK(rt_sync(c->st));
+    double off = 0.0, dia = 0.0;
+    for (int b = 0; b < SD_NORM_BLOCKS; ++b) {
+      off += part[2 * b];
+      dia += part[2 * b + 1];
+    }
+    trace("sd sweep %d: off/diag = %.3e", sweeps, dia > 0 ? std::sqrt(off / dia) : 0.0);
+    // converged: off-diagonal norm below 1e-15 of the diagonal's, or stalled
+    // at the rounding floor once below 1e-10 of it
+    const bool stalled = off_prev >= 0.0 && off < 1e-20 * dia && off > 0.25 * off_prev;
+    if (audit_mode() ? sweeps >= 1 : (!(off > 1e-30 * dia) || stalled)) break;
+    off_prev = off;
+    for (int r = 0; r < nb - 1; ++r)
+      HIPCHK(jacobi_round(c->d_sdM, c->d_sdT, Kp, Kp, r, c->d_sdV, inner, c->ext(c->d_sdM, 8),
+                          c->ext(c->d_sdT, 8), c->ext(c->d_sdV, 8), c->st));
+  }
+  if (sweeps >= 40) return fail(GW_EDEVICE, "block Jacobi did not converge in 40 sweeps");
+  c->sd_sweeps = sweeps;
+  HIPCHK(diag_sqrt(c->d_sdM, Kp, c->Kov, c->d_sdO, c->ext(c->d_sdM, 8), c->ext(c->d_sdO, 8),
+                   c->st));
+  if (c->nR > 0) {
+    GemmArgs a{};  // Y = R B_ov: rows of (P|nm) times B_ov [P][ia] (k-major)
+    a.A = c->d_R; a.lda = c->Np;
+    a.B = c->d_Bov; a.ldb = Kp;
+    a.C = c->d_sdY; a.ldc = Kp;
+    a.M = c->Rp; a.N = Kp; a.K = c->Np;
+    a.map = MAP_FULL; a.tiles_m = c->Rp / 64; a.tiles_n = Kp / 64;
+    a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
+    RCHK(run_gemm(c, a, 3, KC, KM, EPI_STORE));
+    HIPCHK(pole_scale(c->d_sdY, Kp, c->Rp, c->d_D, c->Kov, Kp, c->ext(c->d_sdY, 8),
+                      c->ext(c->d_D, 8), c->st));
+    GemmArgs b{};  // rho = Y T, T [k][s] (k-major for the product over k)
+    b.A = c->d_sdY; b.lda = Kp;
+    b.B = c->d_sdT; b.ldb = Kp;
+    b.C = c->d_sdRho; b.ldc = Kp;
+    b.M = c->Rp; b.N = Kp; b.K = Kp;
+    b.map = MAP_FULL; b.tiles_m = c->Rp / 64; b.tiles_n = Kp / 64;
+    b.n_tiles = b.tiles_m * b.tiles_n; b.batch = 1; b.splitk = 1;
+    RCHK(run_gemm(c, b, 3, KC, KM, EPI_STORE));
+  }
+  c->timing.sd_ms += tm.stop();
+  c->timing.sd_sweeps = sweeps;
+  c->sd_valid = true;
+  return 0;
+}
+
+// Re Sigma^c and its derivative from the pole form (requires build_sd).
+int eval_sigma_sd(gw_ctx* c, const std::vector<int>& states, const std::vector<double>& omega,
+                  std::vector<double>& sig, std::vector<double>& dsig) {
+  const int n = (int)states.size();
+  sig.assign(n, 0.0);
+  dsig.assign(n, 0.0);
+  if (n == 0) return 0;
+  RCHK(ensure_sig(c, n));
+  const int sc = c->sig_cap;
+  RCHK(ensure_stage(c, (size_t)sc * (3 * sizeof(double) + sizeof(int)) + 64));
+  double* h_om = (double*)c->h_stage;
+  int* h_row = (int*)(h_om + sc);
+  double* h_sig = (double*)(h_row + sc);
+  for (int j = 0; j < n; ++j) {
+    h_om[j] = omega[j];
+    h_row[j] = c->row_of[states[j]];
+  }
+  HIPCHK(rt_memcpy(c->d_omega, h_om, (size_t)sc * (sizeof(double) + sizeof(int)),
+                   hipMemcpyHostToDevice, c->st));
+  HIPCHK(sigma_sd(c->d_sdRho, c->Kp, c->n_mo, c->Kov, c->n_rows, c->d_rowsel,
+                  c->n_spin > 1 ? c->d_rowspin : nullptr, c->n_occ_s[0], c->n_occ_s[1],
+                  c->d_omega, c->d_eps, c->d_sdO, n, c->d_sig, c->d_dsig, c->d_sigpart,
+                  c->ext(c->d_sdRho, 8), c->ext(c->d_eps, 8), c->ext(c->d_sdO, 8),
+                  c->ext(c->d_sigpart, 8), c->st));
+  HIPCHK(rt_memcpy(h_sig, c->d_sig, 2 * (size_t)sc * sizeof(double), hipMemcpyDeviceToHost,
+                   c->st));
+  HIPCHK(rt_sync(c->st));
+  for (int j = 0; j < n; ++j) {
+    sig[j] = h_sig[j];
+    dsig[j] = h_sig[sc + j];
+  }
+  return 0;
+}
+
+// ---------------------------------------------------------------------------
 // Quasiparticle step tree (Implementation - Solution of the Quasiparticle
 // Equations, step-selection tree figure).  f(w) = eps_n + dsig_x_n +
 // Re Sigma^c(w) - w, Z = -1/f'(w).
@@ -1242,7 +1385,7 @@ int validate_states(gw_ctx* c, int n, const int* states) {
 // the iteration cap).  A state's trajectory depends only on its start, so the
 // schedule does not change results.
 int solve_qp(gw_ctx* c, int n_states, const int* states, std::vector<QPState>& qs, int* rounds,
-             const double* start = nullptr) {
+             const double* start = nullptr, bool sd = false) {
   qs.assign(n_states, QPState{});
   std::vector<double> e0(n_states);
   for (int j = 0; j < n_states; ++j) {
@@ -1281,7 +1424,12 @@ int solve_qp(gw_ctx* c, int n_states, const int* states, std::vector<QPState>& q
     if (act.empty()) break;   // (members are released as soon as their representative is done)
     std::vector<double> sg, dsg;
     std::vector<int> nres, flags;
-    RCHK(eval_sigma(c, st, om, sg, dsg, nres, flags, &tol));
+    if (sd) {
+      RCHK(eval_sigma_sd(c, st, om, sg, dsg));
+      flags.assign(st.size(), 0);
+    } else {
+      RCHK(eval_sigma(c, st, om, sg, dsg, nres, flags, &tol));
+    }
     (*rounds)++;
     for (size_t a = 0; a < act.size(); ++a) {
       QPState& q = qs[act[a]];
@@ -1713,6 +1861,7 @@ size_t gw_footprint(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, in
 int gw_reset_cache(gw_ctx* c) {
   if (!c) return fail(GW_EINVAL, "NULL ctx");
   c->wtab_valid = false;
+  c->sd_valid = false;
   return 0;
 }
 
@@ -1826,6 +1975,47 @@ int gw_qp(gw_ctx* c, int n_states, const int* states, const gw_grid* grid, doubl
   return finish();
 }
 
+int gw_qp_sd(gw_ctx* c, int n_states, const int* states, double* E_qp, double* sigma_c,
+             double* Z, int* status) {
+  if (!c || n_states < 0 || (n_states > 0 && (!E_qp || !sigma_c || !Z)))
+    return fail(GW_EINVAL, "bad arguments");
+  RCHK(validate_states(c, n_states, states));
+  c->timing = gw_timing{};
+  Timer total;
+  total.a = c->ev0b;
+  total.b = c->ev1b;
+  total.start(c->st);
+  int rc = build_sd(c);
+  if (rc) return rc;
+  std::vector<QPState> qs;
+  int rounds = 0;
+  rc = solve_qp(c, n_states, states, qs, &rounds, nullptr, true);
+  const double ms = total.stop();
+  if (rc) return rc;
+  c->timing.total_ms = ms;
+  c->timing.qp_rounds = rounds;
+  for (int j = 0; j < n_states; ++j) {
+    E_qp[j] = qs[j].E;
+    sigma_c[j] = qs[j].sig;
+    Z[j] = qs[j].Z;
+    if (status) status[j] = qs[j].status;
+  }
+  return finish();
+}
+
+int gw_rpa_excitations(gw_ctx* c, double* Omega) {
+  if (!c || !Omega) return fail(GW_EINVAL, "bad arguments");
+  c->timing = gw_timing{};
+  RCHK(build_sd(c));
+  std::vector<double> om(c->Kov);
+  HIPCHK(rt_memcpy(om.data(), c->d_sdO, (size_t)c->Kov * sizeof(double), hipMemcpyDeviceToHost,
+                   c->st));
+  HIPCHK(rt_sync(c->st));
+  std::sort(om.begin(), om.end());
+  std::copy(om.begin(), om.end(), Omega);
+  return finish();
+}
+
 int gw_evgw(gw_ctx* c, int mode, int n_cycles, double ev_tol, int n_states, const int* states,
             const gw_grid* grid, double* E_qp, double* sigma_c, double* Z, int* status,
             double* E_cycles, int* cycles_done) {
@@ -1851,6 +2041,7 @@ int gw_evgw(gw_ctx* c, int mode, int n_cycles, double ev_tol, int n_states, cons
                      hipMemcpyHostToDevice, c->st));
     if (w_moved) {
       c->wtab_valid = false;
+      c->sd_valid = false;
       HIPCHK(transition_energies(c->d_eps, c->n_spin, c->n_mo, c->n_occ_s, c->Kp, c->d_D,
                                  c->ext(c->d_eps, 8), c->ext(c->d_D, 8), c->st));
     }
@@ -1874,6 +2065,7 @@ int gw_evgw(gw_ctx* c, int mode, int n_cycles, double ev_tol, int n_states, cons
       if (rc) break;
       w_moved = true;
       c->wtab_valid = false;
+      c->sd_valid = false;
       if (transition_energies(c->d_eps, c->n_spin, c->n_mo, c->n_occ_s, c->Kp, c->d_D,
                               c->ext(c->d_eps, 8), c->ext(c->d_D, 8), c->st) != hipSuccess) {
         rc = fail(GW_EDEVICE, "transition energies failed");

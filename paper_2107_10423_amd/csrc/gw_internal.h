@@ -133,6 +133,25 @@ hipError_t sigma_quad(const double* wtab, int n_mo, int G, int ld, int w0, const
                       double* part, int n_rows, long nW, long nPart, long nEps,
                       hipStream_t st);
 
+// Spectral-decomposition route (sd.hip)
+hipError_t casida_matrix(double* C, long ld, const double* D, int n, int Kp, long nC, long nD,
+                         hipStream_t st);
+hipError_t set_identity(double* T, long ld, int Kp, long nT, hipStream_t st);
+// one round r (0 <= r < Kp/32 - 1) of block Jacobi on M with T <- T V; V: Kp/64 * 64 * 64
+hipError_t jacobi_round(double* M, double* T, long ld, int Kp, int r, double* V, int max_sweeps,
+                        long nM, long nT, long nV, hipStream_t st);
+hipError_t offnorm(const double* M, long ld, int n, double* part, int blocks, long nM,
+                   long nPart, hipStream_t st);
+hipError_t diag_sqrt(const double* M, long ld, int n, double* Omega, long nM, long nO,
+                     hipStream_t st);
+hipError_t pole_scale(double* Y, long ld, int rows, const double* D, int n, int Kp, long nY,
+                      long nD, hipStream_t st);
+hipError_t sigma_sd(const double* rho, long ld, int n_mo, int n, int n_rows, const int* rowsel,
+                    const int* rowspin, int n_occ0, int n_occ1, const double* omega,
+                    const double* eps, const double* Omega, int cnt, double* sig, double* dsig,
+                    double* part, long nRho, long nEps, long nOmega, long nPart,
+                    hipStream_t st);
+
 // MINRES
 struct MinresBufs {
   int k, kp, Np, Kp;       // systems, padded systems, padded aux, padded ov

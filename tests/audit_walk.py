@@ -46,7 +46,9 @@ def run_case(n_occ, n_virt, n_aux, rows, G, wb, cap):
                                             np.linspace(-1, 22, 70)),
                          lambda: c.qp(list(rows), g),
                          lambda: c.evgw(list(rows), g, mode="evgw0", n_cycles=2),
-                         lambda: c.evgw(list(rows), g, mode="evgw", n_cycles=2)):
+                         lambda: c.evgw(list(rows), g, mode="evgw", n_cycles=2)) + (
+                            (lambda: c.rpa_excitations(), lambda: c.qp_sd(list(rows)))
+                            if n_occ * n_virt <= 16384 else ()):
                 try:
                     call()
                 except gwl.GWError as e:
@@ -73,7 +75,7 @@ def run_uhf_case(n_occ, n_virt, n_aux, rows, G):
                      lambda: c.sigma([rows[0], rows[-1]], [inp.eps[0][1], -0.3], g),
                      lambda: c.residues([rows[-1]] * 5, [0, 1, 2, 3, n_mo - 1],
                                         np.linspace(-1, 2, 5)),
-                     lambda: c.qp(list(rows), g)):
+                     lambda: c.qp(list(rows), g), lambda: c.qp_sd(list(rows))):
             try:
                 call()
             except gwl.GWError as e:
