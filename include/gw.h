@@ -80,6 +80,11 @@ typedef struct gw_opts {
   int no_graphs;            /* nonzero: launch every MINRES iteration eagerly instead of
                                replaying it from a captured HIP graph (0: graphs; they
                                are also skipped on a stream that cannot be captured) */
+  int no_precond;           /* nonzero: plain MINRES.  0: residue systems with |omega|
+                               below 0.9 of the lowest transition energy run MINRES
+                               preconditioned by M = 1 - Pi(0) (SPD), factored as one more
+                               grid point (xi = 0) of the W^c build; their residual target
+                               is then relative in the M^-1 norm */
   double cluster_width;     /* > 0: the cluster initial-guess layer of [QP] in gw_qp and
                                every gw_evgw cycle (0: off).  The requested states,
                                sorted by their energy in G, form clusters wherever

@@ -34,7 +34,7 @@ class _Opts(ctypes.Structure):
                 ("qp_max_iter", ctypes.c_int), ("dsig_x", _dp), ("stream", ctypes.c_void_p),
                 ("mem_budget_bytes", ctypes.c_size_t), ("work_budget_bytes", ctypes.c_size_t),
                 ("minres_batch", ctypes.c_int), ("no_graphs", ctypes.c_int),
-                ("cluster_width", ctypes.c_double)]
+                ("no_precond", ctypes.c_int), ("cluster_width", ctypes.c_double)]
 
 
 class _Grid(ctypes.Structure):
@@ -188,7 +188,7 @@ class Context:
     def __init__(self, eps, n_occ, B_ov, row_ids, B_rows, pi_prec="fp64", minres_max_iter=0,
                  minres_rtol=0.0, qp_tol=0.0, qp_max_iter=0, dsig_x=None, stream=None,
                  mem_budget_bytes=0, work_budget_bytes=0, minres_batch=0, graphs=True,
-                 cluster_width=0.0):
+                 cluster_width=0.0, precond=True):
         eps = _d(eps)
         B_ov = _d(B_ov)
         rows = _i(row_ids)
@@ -201,7 +201,7 @@ class Context:
             raise ValueError("B_rows must be [n_rows][n_mo][n_aux]")
         o = self._make_opts(pi_prec, minres_max_iter, minres_rtol, qp_tol, qp_max_iter,
                             dsig_x, stream, mem_budget_bytes, work_budget_bytes, minres_batch,
-                            graphs, cluster_width)
+                            graphs, cluster_width, precond)
         h = _ctxp()
         _check(_lib.gw_setup(ctypes.byref(h), n_mo, int(n_occ), n_aux, _pd(eps), _pd(B_ov),
                              rows.size, _pi(rows), _pd(B_rows), ctypes.byref(o)))
@@ -211,13 +211,14 @@ class Context:
 
     def _make_opts(self, pi_prec="fp64", minres_max_iter=0, minres_rtol=0.0, qp_tol=0.0,
                    qp_max_iter=0, dsig_x=None, stream=None, mem_budget_bytes=0,
-                   work_budget_bytes=0, minres_batch=0, graphs=True, cluster_width=0.0):
+                   work_budget_bytes=0, minres_batch=0, graphs=True, cluster_width=0.0,
+                   precond=True):
         self._dsx = _d(dsig_x) if dsig_x is not None else None
         return _Opts(PREC[pi_prec] if isinstance(pi_prec, str) else int(pi_prec),
                      int(minres_max_iter), float(minres_rtol), float(qp_tol), int(qp_max_iter),
                      _pd(self._dsx), ctypes.c_void_p(stream) if stream else None,
                      int(mem_budget_bytes), int(work_budget_bytes), int(minres_batch),
-                     0 if graphs else 1, float(cluster_width))
+                     0 if graphs else 1, 0 if precond else 1, float(cluster_width))
 
     @classmethod
     def from_inputs(cls, inp, **kw):

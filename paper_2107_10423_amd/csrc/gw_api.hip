@@ -257,7 +257,14 @@ struct gw_ctx {
   double* d_wtab = nullptr;    // [nR][wtab_G]
   int wtab_G = 0;              // table columns
   int quad_G = 0;              // quadrature points (wtab_G, or wtab_G - 1 with wtab_w0)
-  int wtab_w0 = 0;             // last column is W^c(0) for the split quadrature
+  int wtab_w0 = 0;             // last column is W^c(0) (the table was built with xi = 0)
+  int quad_split = 0;          // the quadrature integrates the W^c(0) part exactly (evGW)
+  // MINRES preconditioner M^-1 = (1 - Pi(0))^-1, formed from the xi = 0 point
+  // of a table build; systems with |omega| < pre_w use it
+  bool no_precond = false;
+  bool pre_valid = false;
+  double* d_pre = nullptr;     // [Np][Np]
+  double pre_w = 0.0;
   bool wtab_valid = false;
   std::vector<double> wtab_xi, wtab_w;
   int wtab_prec = -1;
@@ -268,7 +275,8 @@ struct gw_ctx {
   double* d_sig = nullptr;
   double* d_dsig = nullptr;
   double* d_sigpart = nullptr;   // [n][16][2] quadrature partial sums
-  char* d_mrin = nullptr;        // MINRES parameters [omega | rtol | rhs index | warm], cap each
+  char* d_mrin = nullptr;        // MINRES parameters [omega | rtol | rhs index | warm |
+                                 // preconditioned], cap each
   char* d_mrout = nullptr;       // MINRES results [W^c | dW^c | convergence], cap each
   int sig_cap = 0;
   // MINRES workspace
@@ -646,6 +654,33 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
     }
     wt_ms += tm.stop();
   }
+  if (mode == 0 && with_w0 && !c->no_precond) {
+    // the xi = 0 point is the last one, still in the work buffer after the
+    // last chunk: its rows [Np, 2 Np) hold X = L0^-T, and M^-1 = X X^T
+    const int g_last = G - 1 - ((G - 1) / c->chunk) * c->chunk;
+    if (!c->d_pre) RCHK(c->alloc((void**)&c->d_pre, (size_t)c->Np * c->Np * sizeof(double)));
+    const double* X = c->d_work + (long)g_last * per_g + (long)c->Np * ldA;
+    GemmArgs a{};
+    a.A = X; a.lda = ldA; a.sA = 0;
+    a.B = X; a.ldb = ldA; a.sB = 0;
+    a.C = c->d_pre; a.ldc = c->Np; a.sC = 0;
+    a.M = c->Np; a.N = c->Np; a.K = c->Np;
+    a.map = MAP_FULL; a.tiles_m = c->Np / 128; a.tiles_n = c->Np / 128;
+    a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
+    a.alpha = 1.0; a.beta = 0.0;
+    RCHK(run_gemm(c, a, 0, KC, KC, EPI_AXPBY));
+    // preconditioned window: |omega| below 0.9 of the lowest transition
+    // energy, where 1 - Pi(omega) stays positive definite and close to M
+    double dmin = INFINITY;
+    for (int sp = 0; sp < c->n_spin; ++sp) {
+      const double* e = c->eps.data() + (size_t)sp * c->n_mo;
+      const int no = c->n_occ_s[sp];
+      dmin = std::min(dmin, *std::min_element(e + no, e + c->n_mo) -
+                                *std::max_element(e, e + no));
+    }
+    c->pre_w = 0.9 * dmin;
+    c->pre_valid = true;
+  }
   c->timing.pi_ms += pi_ms;
   c->timing.chol_ms += chol_ms;
   c->timing.wtab_ms += wt_ms;
@@ -688,9 +723,13 @@ int ensure_stage(gw_ctx* c, size_t bytes) {
   return 0;
 }
 
+// Split-K slabs of the preconditioner product r M^-1 (K = Np, a multiple of
+// 128, so each slab's K range is a multiple of 16)
+constexpr int PRE_SPLIT = 8;
+
 // Staging bytes of one MINRES batch of kp systems: rhs index, warm flag,
 // frequency, tolerance in; W^c, dW^c, convergence out.
-inline size_t mr_stage_bytes(int cap) { return (size_t)cap * (4 + 4 + 8 + 8 + 8 + 8 + 4); }
+inline size_t mr_stage_bytes(int cap) { return (size_t)cap * (4 + 4 + 4 + 8 + 8 + 8 + 8 + 4); }
 
 int ensure_minres(gw_ctx* c, int kp) {
   if (kp <= c->mr_cap) return 0;
@@ -710,17 +749,18 @@ int ensure_minres(gw_ctx* c, int kp) {
   c->mr_splitk = splitk;
   c->mr_splitk1 = splitk1;
   size_t part = std::max({(size_t)splitk * kp * c->Np, (size_t)(c->Kp / 64) * kp,
-                          (size_t)splitk1 * kp * c->Kp});
+                          (size_t)splitk1 * kp * c->Kp, (size_t)PRE_SPLIT * kp * c->Np});
   RCHK(c->alloc((void**)&m.part, part * sizeof(double)));
   c->part_cap = part;
   RCHK(c->alloc((void**)&m.active, 2 * sizeof(int)));
   RCHK(c->alloc((void**)&m.blk, 2 * (size_t)(kp / 16) * sizeof(int)));
   // parameters and results each in one block, moved by one copy per batch
-  RCHK(c->alloc((void**)&c->d_mrin, (size_t)kp * (2 * sizeof(double) + 2 * sizeof(int))));
+  RCHK(c->alloc((void**)&c->d_mrin, (size_t)kp * (2 * sizeof(double) + 3 * sizeof(int))));
   m.omega = (double*)c->d_mrin;
   m.rtol = m.omega + kp;
   c->d_rhs_idx = (int*)(m.rtol + kp);
   c->d_warm = c->d_rhs_idx + kp;
+  m.preflag = c->d_warm + kp;
   RCHK(c->alloc((void**)&c->d_mrout, (size_t)kp * (2 * sizeof(double) + sizeof(int))));
   c->d_wc = (double*)c->d_mrout;
   c->d_dwc = c->d_wc + kp;
@@ -770,11 +810,29 @@ int backproject_pass(gw_ctx* c, int kp, const int* mask = nullptr) {
   return 0;
 }
 
+// part[s] = X M^-1 over the K slab s (X [kp][Np], M^-1 symmetric, so its rows
+// serve as the B operand); mask as for the operator passes
+int precond_pass(gw_ctx* c, const double* X, int kp, const int* mask = nullptr) {
+  GemmArgs a{};
+  a.A = X; a.lda = c->Np; a.sA = 0;
+  a.B = c->d_pre; a.ldb = c->Np; a.sB = 0;
+  a.C = c->mr.part; a.ldc = c->Np; a.sC = 0;
+  a.M = kp; a.N = c->Np; a.K = c->Np;
+  a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Np / 128;
+  a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1;
+  a.splitk = PRE_SPLIT; a.sSplit = (long)kp * c->Np;
+  a.mrows = mask ? 0 : c->mr.k;
+  a.rowmask = mask; a.nMask = c->ext(mask, sizeof(int));
+  RCHK(run_gemm(c, a, 2, KC, KC, EPI_STORE));
+  return 0;
+}
+
 // One MINRES iteration: both operator passes (from the second iteration on
-// skipping the 16-system blocks the previous step found converged), the
-// apply and step kernels, and the copy of this iteration's count of active
-// systems to pinned host memory.  Its launches depend on the iteration only
-// through its parity.
+// skipping the 16-system blocks the previous step found converged), the apply
+// and step kernels (with a preconditioner, the product r2 M^-1 between two
+// step kernels), and the copy of this iteration's count of active systems to
+// pinned host memory.  Its launches depend on the iteration only through its
+// parity.
 int minres_iteration(gw_ctx* c, int kp, int itn) {
   MinresBufs& m = c->mr;
   const int par = itn & 1;
@@ -782,7 +840,13 @@ int minres_iteration(gw_ctx* c, int kp, int itn) {
   RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp, mask));
   RCHK(backproject_pass(c, kp, mask));
   HIPCHK(minres_apply(m, c->mr_splitk, c->st));
-  HIPCHK(minres_finish_step(m, par, c->st));
+  if (m.pre) {
+    HIPCHK(minres_pre_step_a(m, par, c->st));
+    RCHK(precond_pass(c, m.r2, kp, mask));
+    HIPCHK(minres_pre_step_b(m, par, c->st));
+  } else {
+    HIPCHK(minres_finish_step(m, par, c->st));
+  }
   HIPCHK(rt_memcpy(c->h_poll + par, m.active + par, sizeof(int), hipMemcpyDeviceToHost, c->st));
   return 0;
 }
@@ -791,7 +855,9 @@ int minres_iteration(gw_ctx* c, int kp, int itn) {
 // A stream that refuses capture switches the context to eager launches.
 int minres_iteration_graph(gw_ctx* c, int kp, int itn) {
   const int par = itn & 1;
-  auto& slot = c->mr_graphs[kp];   // value-initialised: no graphs yet
+  // value-initialised: no graphs yet; the launch sequence depends on whether
+  // a preconditioner is in use
+  auto& slot = c->mr_graphs[2 * kp + (c->mr.pre ? 1 : 0)];
   if (!slot[par]) {
     if (hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       (void)hipGetLastError();
@@ -865,6 +931,8 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   m.n_part = c->ext(m.part, 8);
   m.n_V = c->ext(m.V, 8);
   m.n_blk = c->ext(m.blk, sizeof(int));
+  m.pre = (c->pre_valid && !c->no_precond) ? c->d_pre : nullptr;
+  m.splitp = PRE_SPLIT;
   // host mirror of the device parameter and result blocks (same layout)
   const int cap = c->mr_cap;
   RCHK(ensure_stage(c, c->stage_off + mr_stage_bytes(cap)));
@@ -873,16 +941,19 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   double* tol = om + cap;
   int* idx = (int*)(tol + cap);
   int* warm = idx + cap;
-  char* h_out = (char*)(warm + cap);
+  int* pref = warm + cap;
+  char* h_out = (char*)(pref + cap);
   double* h_wc = (double*)h_out;
   double* h_dwc = h_wc + cap;
   int* h_conv = (int*)(h_dwc + cap);
-  const size_t in_bytes = (size_t)cap * (2 * sizeof(double) + 2 * sizeof(int));
+  const size_t in_bytes = (size_t)cap * (2 * sizeof(double) + 3 * sizeof(int));
   const size_t out_bytes = (size_t)cap * (2 * sizeof(double) + sizeof(int));
   for (int j = 0; j < kp; ++j) {
     idx[j] = j < k ? sys[j].q : 0;
     om[j] = j < k ? sys[j].w : 0.0;
     tol[j] = (j < k && sys[j].tol > 0) ? std::max(sys[j].tol, c->minres_rtol) : c->minres_rtol;
+    // preconditioned window (a device flag, so replayed graphs read the current one)
+    pref[j] = (m.pre && j < k && std::fabs(sys[j].w) < c->pre_w) ? 1 : 0;
   }
   Timer tm;
   tm.a = c->ev0; tm.b = c->ev1;
@@ -908,7 +979,16 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
     RCHK(backproject_pass(c, kp));
     HIPCHK(minres_apply(m, c->mr_splitk, c->st));
   }
-  HIPCHK(minres_init(m, c->d_R, c->d_rhs_idx, idx, c->Rp, n_warm > 0, c->st));
+  if (m.pre) {
+    // preconditioned start: r = b - A x0, |b| and beta1 in the M^-1 norm
+    HIPCHK(minres_pre_init_a(m, c->d_R, c->d_rhs_idx, idx, c->Rp, n_warm > 0, c->st));
+    RCHK(precond_pass(c, m.w, kp));
+    HIPCHK(minres_pre_init_b(m, c->st));
+    RCHK(precond_pass(c, m.r1, kp));
+    HIPCHK(minres_pre_init_c(m, c->st));
+  } else {
+    HIPCHK(minres_init(m, c->d_R, c->d_rhs_idx, idx, c->Rp, n_warm > 0, c->st));
+  }
   int itn = 0;
   // Each iteration's count of still-active systems is copied to pinned host
   // memory behind its step kernel; the host reads iteration i's count after
@@ -1081,7 +1161,7 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
     if (!audit_mode()) HIPCHK(hipEventRecord(c->ev_quad[0], c->st));
     HIPCHK(rt_memcpy(c->d_omega, h_om, (size_t)sc * (sizeof(double) + sizeof(int)),
                      hipMemcpyHostToDevice, c->st));
-    HIPCHK(sigma_quad(c->d_wtab, c->n_mo, c->quad_G, c->wtab_G, c->wtab_w0, c->d_rowsel,
+    HIPCHK(sigma_quad(c->d_wtab, c->n_mo, c->quad_G, c->wtab_G, c->quad_split, c->d_rowsel,
                       c->n_spin > 1 ? c->d_rowspin : nullptr, c->d_omega, c->d_eps, c->d_grid,
                       c->d_grid + c->grid_cap, n, c->d_sig, c->d_dsig, c->d_sigpart, c->n_rows,
                       c->ext(c->d_wtab, 8), c->ext(c->d_sigpart, 8), c->ext(c->d_eps, 8),
@@ -1465,9 +1545,10 @@ int solve_qp(gw_ctx* c, int n_states, const int* states, std::vector<QPState>& q
 // every allocation above (requested bytes).  n_states bounds the number of
 // residue systems per Sigma evaluation (n_states * n_mo, in batches of at
 // most minres_batch).
-size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, int G,
+size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, int G_in,
                        int pi_prec, size_t work_budget, int minres_batch) {
   const size_t d = sizeof(double);
+  const int G = G_in + 1;   // the xi = 0 point of the preconditioner (on by default)
   const int Np = round_up(n_aux, 128);
   const int Kov = n_occ * (n_mo - n_occ);
   const int Kp = round_up(Kov, 128);
@@ -1493,11 +1574,12 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   int splitk = 1, splitk1 = 1;
   minres_splits(kp, Np, Kp, &splitk, &splitk1);
   const size_t part = std::max({(size_t)splitk * kp * Np, (size_t)(Kp / 64) * kp,
-                                (size_t)splitk1 * kp * Kp});
+                                (size_t)splitk1 * kp * Kp, (size_t)PRE_SPLIT * kp * Np});
   b += 8 * (size_t)kp * Np * d + (size_t)kp * 16 * d + (size_t)kp * Kp * d + part * d +
        (size_t)kp * (2 * d + 2 * sizeof(int) + 2 * d + sizeof(int)) + 2 * sizeof(int) +
        2 * (size_t)(kp / 16) * sizeof(int);
   b += (size_t)Rp * Np * d;  // remembered residue solutions
+  b += (size_t)Np * Np * d;  // preconditioner
   // dense fallback
   b += (size_t)Np * Np * d + (size_t)Kp * d + (size_t)Np * d + sizeof(int);
   return b;
@@ -1731,6 +1813,7 @@ int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts) {
   if (o.work_budget_bytes > 0) c->work_budget = o.work_budget_bytes;
   if (o.minres_batch > 0) c->minres_batch = std::max(64, o.minres_batch);
   c->graphs_off = o.no_graphs != 0;
+  c->no_precond = o.no_precond != 0;
   c->cluster_width = o.cluster_width;
   const int n_so = n_spin * n_mo;   // spin-orbitals
   c->eps.assign(in.eps, in.eps + n_so);
@@ -1910,7 +1993,8 @@ int gw_sigma(gw_ctx* c, int n, const int* states, const double* omega, const gw_
     if (!std::isfinite(omega[j])) return fail(GW_EINVAL, "omega[%d] is not finite", j);
   forget_solutions(c);
   c->timing = gw_timing{};
-  RCHK(build_wtable(c, grid, 0));
+  RCHK(build_wtable(c, grid, 0, nullptr, !c->no_precond));
+  c->quad_split = 0;
   std::vector<int> st(states, states + n), nres, flags;
   std::vector<double> om(omega, omega + n), sg, dsg;
   RCHK(eval_sigma(c, st, om, sg, dsg, nres, flags));
@@ -1957,8 +2041,10 @@ int gw_qp(gw_ctx* c, int n_states, const int* states, const gw_grid* grid, doubl
   total.a = c->ev0b;
   total.b = c->ev1b;
   total.start(c->st);
-  int rc = build_wtable(c, grid, 0);
+  // (the xi = 0 point also gives the MINRES preconditioner)
+  int rc = build_wtable(c, grid, 0, nullptr, !c->no_precond);
   if (rc) return rc;
+  c->quad_split = 0;
   std::vector<QPState> qs;
   int rounds = 0;
   rc = solve_qp(c, n_states, states, qs, &rounds);
@@ -2036,6 +2122,7 @@ int gw_evgw(gw_ctx* c, int mode, int n_cycles, double ev_tol, int n_states, cons
   // G and W again; a W^c table built from moved energies is dropped.
   bool w_moved = false;
   auto restore = [&]() -> int {
+    c->quad_split = 0;
     c->eps = c->eps_ks;
     HIPCHK(rt_memcpy(c->d_eps, c->eps.data(), c->eps.size() * sizeof(double),
                      hipMemcpyHostToDevice, c->st));
@@ -2073,6 +2160,7 @@ int gw_evgw(gw_ctx* c, int mode, int n_cycles, double ev_tol, int n_states, cons
       }
     }
     if ((rc = build_wtable(c, grid, 0, nullptr, true))) break;
+    c->quad_split = 1;
     // each cycle starts its solves from the current energies in G
     std::vector<double> start(n_states);
     for (int j = 0; j < n_states; ++j) start[j] = c->eps[states[j]];

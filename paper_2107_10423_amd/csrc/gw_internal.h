@@ -166,6 +166,14 @@ struct MinresBufs {
   int *blk;                // [2][kp / 16] 1 where a block of 16 systems still has an
                            // unconverged one after an odd / even iteration
   long n_vec, n_scal, n_part, n_V, n_blk;   // extents in elements (per array)
+  // preconditioning by M = 1 - Pi(0) (symmetric positive definite): systems
+  // with preflag[j] != 0 run preconditioned MINRES; the product r M^-1 of all
+  // systems arrives as splitp split-K slabs in part.  (Kernels read only
+  // device data that a replayed graph sees current: the flags, not a
+  // by-value threshold.)
+  const double* pre;       // [Np][Np] M^-1, or nullptr (no system preconditioned)
+  const int* preflag;      // [kp]
+  int splitp;
 };
 // rhs_idx values must be < n_rhs_rows (rows of rhs_base, each Np long); the host
 // passes the index array it uploaded so the guard can check it
@@ -185,6 +193,16 @@ hipError_t minres_scale_sum(MinresBufs& m, int splits, const double* D, long nD,
 hipError_t minres_apply(MinresBufs& m, int splitk, hipStream_t st);
 // one MINRES step per unconverged system; par = global iteration parity
 hipError_t minres_finish_step(MinresBufs& m, int par, hipStream_t st);
+// Preconditioned variants (m.pre set).  Start: pre_init_a (r = b - A x0, b kept
+// in w), then the product b M^-1 into part, pre_init_b (|b|_M^-1), the product
+// r M^-1, pre_init_c (beta1, v).  Iteration: apply, pre_step_a (Lanczos
+// update of r1, r2), the product r2 M^-1, pre_step_b (beta, Givens, x).
+hipError_t minres_pre_init_a(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
+                             const int* host_idx, int n_rhs_rows, int use_y, hipStream_t st);
+hipError_t minres_pre_init_b(MinresBufs& m, hipStream_t st);
+hipError_t minres_pre_init_c(MinresBufs& m, hipStream_t st);
+hipError_t minres_pre_step_a(MinresBufs& m, int par, hipStream_t st);
+hipError_t minres_pre_step_b(MinresBufs& m, int par, hipStream_t st);
 hipError_t minres_results(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
                           int n_rhs_rows, int n_deriv_parts, double* wc, double* dwc, int* conv,
                           long n_out, hipStream_t st);

@@ -12,7 +12,7 @@ namespace gw {
 
 enum {
   S_BETA1 = 0, S_BETA, S_OLDB, S_DBAR, S_EPS, S_PHIBAR, S_CS, S_SN, S_DONE, S_ITERS, S_RATIO,
-  S_BNORM
+  S_BNORM, S_ALPHA
 };
 
 static hipError_t check_bufs(const MinresBufs& m, const char* kn) {
@@ -285,6 +285,260 @@ hipError_t minres_finish_step(MinresBufs& m, int par, hipStream_t st) {
   if (par != 0 && par != 1) return refuse("minres_step", "parity");
   GW_AUDIT_RETURN();
   hipLaunchKernelGGL(k_minres_step, dim3(m.kp), dim3(256), 0, st, m, par);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Preconditioned MINRES (Paige and Saunders with a symmetric positive definite
+// preconditioner M): the Lanczos vectors are built in the M^-1 inner product,
+// z = M^-1 r supplies the next direction and beta = sqrt(r . z); the Givens
+// recurrences are unchanged and phibar estimates |b - A x| in the M^-1 norm.
+// Systems outside the preconditioned frequency window take z = r, which is
+// the plain recurrence.
+
+__device__ __forceinline__ bool is_pre(const MinresBufs& m, int j) {
+  return m.pre != nullptr && m.preflag[j] != 0;
+}
+
+// z[p] of system j: the sum of the splitp slabs of r M^-1
+__device__ __forceinline__ double pre_z(const MinresBufs& m, long i) {
+  const long slab = (long)m.kp * m.Np;
+  double z = 0.0;
+  for (int s = 0; s < m.splitp; ++s) z += m.part[s * slab + i];
+  return z;
+}
+
+// r1 = r2 = b - A x0 (or b); w = b (input of the first product); x = w2 = 0;
+// |b| and |r| (the norms of unpreconditioned systems)
+__global__ __launch_bounds__(256) void k_minres_pre_init_a(MinresBufs m, const double* rhs_base,
+                                                           const int* rhs_idx, int use_y) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, t = threadIdx.x;
+  if (j == 0) {
+    if (t < 2) m.active[t] = 0;
+    for (int i = t; i < 2 * (m.kp / 16); i += 256) m.blk[i] = 0;
+  }
+  const long o = (long)j * m.Np;
+  const double* b = (j < m.k) ? rhs_base + (long)rhs_idx[j] * m.Np : nullptr;
+  double s = 0.0, sb = 0.0;
+  for (int p = t; p < m.Np; p += 256) {
+    const double bv = b ? b[p] : 0.0;
+    const double rv = use_y ? bv - m.y[o + p] : bv;
+    m.r1[o + p] = rv;
+    m.r2[o + p] = rv;
+    m.w[o + p] = bv;
+    m.x[o + p] = 0.0;
+    m.w2[o + p] = 0.0;
+    s += rv * rv;
+    sb += bv * bv;
+  }
+  const double rn = sqrt(block_sum(s, red));
+  const double bn = sqrt(block_sum(sb, red));
+  if (t == 0) {
+    double* sc = m.scal + j * 16;
+    sc[S_BETA1] = rn;
+    sc[S_BNORM] = bn;
+  }
+}
+
+// |b|_M^-1 = sqrt(b . b M^-1) for preconditioned systems
+__global__ __launch_bounds__(256) void k_minres_pre_init_b(MinresBufs m) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, t = threadIdx.x;
+  if (!is_pre(m, j)) return;
+  const long o = (long)j * m.Np;
+  double s = 0.0;
+  for (int p = t; p < m.Np; p += 256) s += m.w[o + p] * pre_z(m, o + p);
+  const double bn = sqrt(fmax(block_sum(s, red), 0.0));
+  if (t == 0) m.scal[j * 16 + S_BNORM] = bn;
+}
+
+// beta1 = sqrt(r . z), v = z / beta1 (z = r M^-1, or r), w = 0, scalars
+__global__ __launch_bounds__(256) void k_minres_pre_init_c(MinresBufs m) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const long o = (long)j * m.Np;
+  const bool pre = is_pre(m, j);
+  double s = 0.0;
+  for (int p = t; p < m.Np; p += 256) {
+    const double r = m.r1[o + p];
+    const double z = pre ? pre_z(m, o + p) : r;
+    m.y[o + p] = z;
+    m.w[o + p] = 0.0;
+    s += r * z;
+  }
+  const double beta1 = sqrt(fmax(block_sum(s, red), 0.0));
+  const double inv = beta1 > 0.0 ? 1.0 / beta1 : 0.0;
+  for (int p = t; p < m.Np; p += 256) m.v[o + p] = m.y[o + p] * inv;
+  if (t == 0) {
+    double* sc = m.scal + j * 16;
+    sc[S_BETA1] = beta1;
+    sc[S_BETA] = beta1;
+    sc[S_OLDB] = 0.0;
+    sc[S_DBAR] = 0.0;
+    sc[S_EPS] = 0.0;
+    sc[S_PHIBAR] = beta1;
+    sc[S_CS] = -1.0;
+    sc[S_SN] = 0.0;
+    sc[S_DONE] = (j < m.k && beta1 > 0.0) ? 0.0 : 1.0;
+    sc[S_ITERS] = 0.0;
+    sc[S_RATIO] = 0.0;
+    sc[S_ALPHA] = 0.0;
+  }
+}
+
+static hipError_t check_pre(const MinresBufs& m, const char* kn) {
+  if (hipError_t e = check_bufs(m, kn)) return e;
+  if (!m.pre || !m.preflag) return refuse(kn, "no preconditioner");
+  if (m.splitp < 1) return refuse(kn, "splitp");
+  GW_GUARD(kn, "part", (long)m.splitp * m.kp * m.Np - 1, m.n_part);
+  return hipSuccess;
+}
+
+hipError_t minres_pre_init_a(MinresBufs& m, const double* rhs_base, const int* rhs_idx,
+                             const int* host_idx, int n_rhs_rows, int use_y, hipStream_t st) {
+  if (hipError_t e = check_pre(m, "minres_pre_init_a")) return e;
+  GW_GUARD("minres_pre_init_a", "blk", 2L * (m.kp / 16) - 1, m.n_blk);
+  for (int j = 0; j < m.k; ++j)
+    if (host_idx[j] < 0 || host_idx[j] >= n_rhs_rows) return refuse("minres_pre_init_a", "rhs index");
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_minres_pre_init_a, dim3(m.kp), dim3(256), 0, st, m, rhs_base, rhs_idx,
+                     use_y);
+  return hipGetLastError();
+}
+
+hipError_t minres_pre_init_b(MinresBufs& m, hipStream_t st) {
+  if (hipError_t e = check_pre(m, "minres_pre_init_b")) return e;
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_minres_pre_init_b, dim3(m.kp), dim3(256), 0, st, m);
+  return hipGetLastError();
+}
+
+hipError_t minres_pre_init_c(MinresBufs& m, hipStream_t st) {
+  if (hipError_t e = check_pre(m, "minres_pre_init_c")) return e;
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_minres_pre_init_c, dim3(m.kp), dim3(256), 0, st, m);
+  return hipGetLastError();
+}
+
+// Lanczos update, given y = A v: y -= (beta/oldb) r1 (second iteration on),
+// alpha = v . y, y -= (alpha/beta) r2, r1 = r2, r2 = y.  (The other parity's
+// block flags are still the mask of this iteration's preconditioner product;
+// k_minres_pre_step_b clears them.)
+__global__ __launch_bounds__(256) void k_minres_pre_step_a(MinresBufs m, int par) {
+  __shared__ double red[4];
+  const int j = blockIdx.x, t = threadIdx.x;
+  (void)par;
+  double* sc = m.scal + j * 16;
+  if (sc[S_DONE] != 0.0) return;
+  const long o = (long)j * m.Np;
+  const double beta = sc[S_BETA], oldb = sc[S_OLDB];
+  const double itn = sc[S_ITERS] + 1.0;
+  const double c1 = (itn >= 2.0) ? beta / oldb : 0.0;
+  double sa = 0.0;
+  for (int p = t; p < m.Np; p += 256) {
+    double yv = m.y[o + p] - c1 * m.r1[o + p];
+    m.y[o + p] = yv;
+    sa += m.v[o + p] * yv;
+  }
+  const double alpha = block_sum(sa, red);
+  for (int p = t; p < m.Np; p += 256) {
+    const double yv = m.y[o + p] - (alpha / beta) * m.r2[o + p];
+    m.r1[o + p] = m.r2[o + p];
+    m.r2[o + p] = yv;
+  }
+  if (t == 0) sc[S_ALPHA] = alpha;
+}
+
+// beta_new = sqrt(r2 . z), Givens rotation, w / x update, v = z / beta_new.
+// Block 0 clears the other parity's counters as k_minres_step does.
+__global__ __launch_bounds__(256) void k_minres_pre_step_b(MinresBufs m, int par) {
+  __shared__ double red[4];
+  __shared__ double bc[5];
+  const int j = blockIdx.x, t = threadIdx.x;
+  const int nb = m.kp / 16;
+  if (j == 0 && t == 0) m.active[par ^ 1] = 0;
+  if (j == 0 && t < nb) m.blk[(par ^ 1) * nb + t] = 0;
+  double* sc = m.scal + j * 16;
+  if (sc[S_DONE] != 0.0) return;
+  const long o = (long)j * m.Np;
+  const bool pre = is_pre(m, j);
+  double sb = 0.0;
+  for (int p = t; p < m.Np; p += 256) {
+    const double r = m.r2[o + p];
+    const double z = pre ? pre_z(m, o + p) : r;
+    m.y[o + p] = z;
+    sb += r * z;
+  }
+  const double beta_new = sqrt(fmax(block_sum(sb, red), 0.0));
+  if (t == 0) {
+    const double beta = sc[S_BETA], alpha = sc[S_ALPHA];
+    const double itn = sc[S_ITERS] + 1.0;
+    const double oldeps = sc[S_EPS];
+    const double cs = sc[S_CS], sn = sc[S_SN], dbar = sc[S_DBAR];
+    const double delta = cs * dbar + sn * alpha;
+    const double gbar = sn * dbar - cs * alpha;
+    const double epsln = sn * beta_new;
+    const double dbar_n = -cs * beta_new;
+    double gamma = sqrt(gbar * gbar + beta_new * beta_new);
+    if (gamma < 1e-300) gamma = 1e-300;
+    const double cs_n = gbar / gamma, sn_n = beta_new / gamma;
+    const double phi = cs_n * sc[S_PHIBAR];
+    const double phibar = sn_n * sc[S_PHIBAR];
+    sc[S_OLDB] = beta;
+    sc[S_BETA] = beta_new;
+    sc[S_EPS] = epsln;
+    sc[S_DBAR] = dbar_n;
+    sc[S_CS] = cs_n;
+    sc[S_SN] = sn_n;
+    sc[S_PHIBAR] = phibar;
+    sc[S_ITERS] = itn;
+    // phibar: |b - A x| in the M^-1 norm (plain norm for unpreconditioned
+    // systems); the target is relative to |b| in the same norm
+    const double ratio = phibar / sc[S_BNORM];
+    sc[S_RATIO] = ratio;
+    const bool done = (ratio <= m.rtol[j]) || (beta_new <= 1e-300);
+    if (done) sc[S_DONE] = 1.0;
+    bc[0] = oldeps;
+    bc[1] = delta;
+    bc[2] = 1.0 / gamma;
+    bc[3] = phi;
+    bc[4] = done ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  const double oldeps = bc[0], delta = bc[1], ginv = bc[2], phi = bc[3];
+  const bool done = bc[4] != 0.0;
+  const double inv_b = (beta_new > 1e-300) ? 1.0 / beta_new : 0.0;
+  for (int p = t; p < m.Np; p += 256) {
+    double w1 = m.w2[o + p];
+    double w2 = m.w[o + p];
+    double wn = (m.v[o + p] - oldeps * w1 - delta * w2) * ginv;
+    m.w2[o + p] = w2;
+    m.w[o + p] = wn;
+    m.x[o + p] += phi * wn;
+    m.v[o + p] = done ? 0.0 : m.y[o + p] * inv_b;
+  }
+  if (t == 0 && !done) {
+    atomicAdd(m.active + par, 1);
+    m.blk[par * nb + j / 16] = 1;
+  }
+}
+
+hipError_t minres_pre_step_a(MinresBufs& m, int par, hipStream_t st) {
+  if (hipError_t e = check_pre(m, "minres_pre_step_a")) return e;
+  GW_GUARD("minres_pre_step_a", "blk", 2L * (m.kp / 16) - 1, m.n_blk);
+  if (par != 0 && par != 1) return refuse("minres_pre_step_a", "parity");
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_minres_pre_step_a, dim3(m.kp), dim3(256), 0, st, m, par);
+  return hipGetLastError();
+}
+
+hipError_t minres_pre_step_b(MinresBufs& m, int par, hipStream_t st) {
+  if (hipError_t e = check_pre(m, "minres_pre_step_b")) return e;
+  GW_GUARD("minres_pre_step_b", "blk", 2L * (m.kp / 16) - 1, m.n_blk);
+  if (par != 0 && par != 1) return refuse("minres_pre_step_b", "parity");
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_minres_pre_step_b, dim3(m.kp), dim3(256), 0, st, m, par);
   return hipGetLastError();
 }
 

@@ -350,3 +350,23 @@ def test_setup_from_the_full_tensor():
     ref = _oracle_qp(gwgen.make_config("monomer", states=[3, 6]), [3, 6], 64)
     for j, r in enumerate(ref):
         assert abs(E2[j] - r["E"]) <= 1e-10 * abs(r["E"])
+
+
+def test_preconditioned_minres_matches_plain_and_saves_iterations():
+    """Residue systems below the lowest transition energy run MINRES
+    preconditioned by 1 - Pi(0): the QP results agree with plain MINRES and
+    with the oracle, in fewer iterations."""
+    inp = ragged()
+    states = list(inp.row_ids)
+    g = gwl().Grid.gauss_legendre(64)
+    out = {}
+    for pre in (False, True):
+        with ctx(inp, qp_tol=1e-12, precond=pre) as c:
+            E, S, Z, st = c.qp(states, g)
+            out[pre] = (E, Z, c.timing()["minres_iters"])
+    assert np.all(np.abs(out[True][0] - out[False][0]) <= 1e-10 * np.abs(out[False][0]))
+    assert np.all(np.abs(out[True][1] - out[False][1]) <= 1e-9)
+    assert out[True][2] < out[False][2], (out[True][2], out[False][2])
+    ref = _oracle_qp(inp, states, 64)
+    for j, r in enumerate(ref):
+        assert abs(out[True][0][j] - r["E"]) <= 1e-10 * abs(r["E"])
