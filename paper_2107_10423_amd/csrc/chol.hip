@@ -289,6 +289,27 @@ __global__ void k_sigma_quad_sum(const double* part, int n, double* sig, double*
   dsig[j] = -inv_pi * d;
 }
 
+// A <- 2 I - A on the leading Np x Np block of every item (1 - Pi becomes
+// 1 + Pi): the failure-handling test hook of the Cholesky
+__global__ void k_reflect_unit(double* A, long ldA, long sA, int Np) {
+  double* a = A + (long)blockIdx.y * sA;
+  const long n = (long)Np * Np;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < n;
+       e += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(e / Np), j = (int)(e % Np);
+    double* x = a + (long)i * ldA + j;
+    *x = (i == j ? 2.0 : 0.0) - *x;
+  }
+}
+
+hipError_t reflect_unit(double* A, long ldA, long sA, int Np, int G, long nA, hipStream_t st) {
+  if (G <= 0) return hipSuccess;
+  GW_GUARD("reflect_unit", "A", (long)(G - 1) * sA + (long)(Np - 1) * ldA + Np - 1, nA);
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_reflect_unit, dim3(64, G), dim3(256), 0, st, A, ldA, sA, Np);
+  return hipGetLastError();
+}
+
 hipError_t sigma_quad(const double* wtab, int n_mo, int G, int ld, int w0, const int* rowsel,
                       const int* rowspin, const double* omega, const double* eps,
                       const double* xi, const double* z, int n, double* sig, double* dsig,

@@ -56,9 +56,21 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
+// GW_DEBUG_SYNC=1: every runtime call and launch is followed by a device
+// synchronisation, so an asynchronous fault is reported at the call that
+// caused it (graphs are then off: a capture cannot synchronise)
+bool debug_sync() {
+  static const bool on = [] {
+    const char* e = getenv("GW_DEBUG_SYNC");
+    return e && atoi(e) != 0;
+  }();
+  return on;
+}
+
 #define HIPCHK(expr)                                                                         \
   do {                                                                                       \
     hipError_t e_ = (expr);                                                                  \
+    if (e_ == hipSuccess && debug_sync() && !gw::audit_mode()) e_ = hipDeviceSynchronize();  \
     if (e_ != hipSuccess)                                                                    \
       return fail(GW_EDEVICE, "%s failed: %s [%s] (%s:%d)", #expr, hipGetErrorString(e_),    \
                   gw::launch_error(), __FILE__, __LINE__);                                   \
@@ -265,6 +277,7 @@ struct gw_ctx {
   bool pre_valid = false;
   double* d_pre = nullptr;     // [Np][Np]
   double pre_w = 0.0;
+  bool test_indefinite = false;
   bool wtab_valid = false;
   std::vector<double> wtab_xi, wtab_w;
   int wtab_prec = -1;
@@ -507,6 +520,8 @@ int ensure_mixed_operands(gw_ctx* c) {
 int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
   const int Np = c->Np;
   HIPCHK(rt_memset(c->d_info, 0, G * sizeof(int), c->st));
+  if (c->test_indefinite)
+    HIPCHK(reflect_unit(c->d_work, ldA, per_g, Np, G, c->ext(c->d_work, 8), c->st));
   HIPCHK(set_identity_rows(c->d_work, ldA, per_g, Np, Np, Np, G, c->ext(c->d_work, 8), c->st));
   // Left-looking (Crout) panels over the augmented rows: panel k is first
   // brought up to date with every factored column to its left (one GEMM with
@@ -1812,8 +1827,11 @@ int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts) {
   c->mem_budget = o.mem_budget_bytes;
   if (o.work_budget_bytes > 0) c->work_budget = o.work_budget_bytes;
   if (o.minres_batch > 0) c->minres_batch = std::max(64, o.minres_batch);
-  c->graphs_off = o.no_graphs != 0;
+  c->graphs_off = o.no_graphs != 0 || debug_sync();
   c->no_precond = o.no_precond != 0;
+  // test hook: GW_TEST_INDEFINITE=1 replaces 1 - Pi(i xi) by 1 + Pi(i xi) before
+  // the Cholesky, so that the factorisation meets a non-positive pivot
+  if (const char* e = getenv("GW_TEST_INDEFINITE")) c->test_indefinite = atoi(e) != 0;
   c->cluster_width = o.cluster_width;
   const int n_so = n_spin * n_mo;   // spin-orbitals
   c->eps.assign(in.eps, in.eps + n_so);
@@ -1879,6 +1897,7 @@ int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts) {
 #define SETUP_CHK(expr)                                                                     \
   do {                                                                                      \
     hipError_t e_ = (expr);                                                                 \
+    if (e_ == hipSuccess && debug_sync() && !audit_mode()) e_ = hipDeviceSynchronize();     \
     if (e_ != hipSuccess)                                                                   \
       return cleanup(fail(GW_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)));      \
   } while (0)

@@ -100,6 +100,8 @@ hipError_t split_bf16(const double* B, uint16_t* hi, uint16_t* lo, float* b32, l
 // Cholesky pieces
 hipError_t chol_diag(double* A, long ldA, long sA, double* Linv, int k, int G, int* info,
                      long nA, long nLinv, long nInfo, hipStream_t st);
+// test hook: A <- 2 I - A on the leading Np x Np block of G items
+hipError_t reflect_unit(double* A, long ldA, long sA, int Np, int G, long nA, hipStream_t st);
 // rows [row0, row0 + n) of every batch item <- identity rows e_0 .. e_{n-1}
 // (columns [0, ncol))
 hipError_t set_identity_rows(double* A, long ldA, long sA, int row0, int n, int ncol, int G,
