@@ -13,7 +13,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libgw.so")
+# GW_LIB_VARIANT=hostsan loads the host-sanitizer build (launch audit only)
+LIB_PATH = os.path.join(_HERE, "libgw_hostsan.so" if os.environ.get("GW_LIB_VARIANT") == "hostsan"
+                        else "libgw.so")
 
 GW_PI_FP64, GW_PI_FP32, GW_PI_BF16X3 = 0, 1, 2
 PREC = {"fp64": GW_PI_FP64, "fp32": GW_PI_FP32, "bf16x3": GW_PI_BF16X3}

@@ -3,6 +3,11 @@
 Every translation unit under csrc/ is compiled to an object in _build/ in
 parallel and linked into paper_2107_10423_amd/libgw.so.  Packed-FP32 VALU
 instructions are disabled for every device compile.
+
+`python build.py --host-sanitizers` builds libgw_hostsan.so instead: the same
+sources with AddressSanitizer and UndefinedBehaviorSanitizer on the host code
+only (device code is built as usual), for the launch audit on a machine
+without a GPU (tests/test_launch_audit.py).
 """
 import concurrent.futures as cf
 import os
@@ -28,31 +33,40 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.basename(src).replace(".hip", ".o"))
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+# host-only sanitizers (each -fsanitize= applies to the host pass alone)
+SAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=all"]
+SAN_LIB = os.path.join(HERE, "libgw_hostsan.so")
+
+
+def _compile(src, build_dir=BUILD, extra=()):
+    obj = os.path.join(build_dir, os.path.basename(src).replace(".hip", ".o"))
+    cmd = [HIPCC, *FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     return obj
 
 
-def build(verbose=False):
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose=False, host_sanitizers=False):
+    build_dir = BUILD + "_hostsan" if host_sanitizers else BUILD
+    lib = SAN_LIB if host_sanitizers else LIB
+    extra = SAN_FLAGS if host_sanitizers else ()
+    os.makedirs(build_dir, exist_ok=True)
     srcs = sources()
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+        objs = list(ex.map(lambda src: _compile(src, build_dir, extra), srcs))
+    tmp = lib + ".tmp"
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *extra, *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, host_sanitizers="--host-sanitizers" in sys.argv[1:])
     sys.exit(0)

@@ -1117,6 +1117,9 @@ double residue_weight(const gw_ctx* c, int spin, int m, double w) {
 
 int ensure_sig(gw_ctx* c, int n) {
   if (n <= c->sig_cap) return 0;
+  // a multiple of 8, so that the pinned mirror [omega | rows | sig | dsig]
+  // keeps its doubles 8-byte aligned after the int block
+  n = round_up(n, 8);
   c->release(c->d_omega);
   c->release(c->d_sig);
   c->release(c->d_sigpart);
@@ -1582,7 +1585,7 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   b += (size_t)chunk * (per_g * d + parts * d + PANEL * PANEL * d + sizeof(int) + (size_t)Kp * (d + 4));
   b += 2 * (size_t)G * d + (size_t)std::max(nR, 1) * G * d;
   // Sigma evaluation buffers
-  b += (size_t)n_states * (sizeof(int) + 3 * d + 32 * d);
+  b += (size_t)round_up(std::max(n_states, 1), 8) * (sizeof(int) + 3 * d + 32 * d);
   // MINRES workspace for the largest batch
   const int kmax = std::min(std::max(n_states, 1) * n_mo, minres_batch);
   const int kp = round_up(kmax, 64);
