@@ -379,8 +379,8 @@ def main():
                     help="run one plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the work would shard).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path.",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

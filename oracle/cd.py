@@ -11,7 +11,7 @@ Closed shell, Hartree units.  Occupied states are 0..n_occ-1, virtual states
 n_occ..n_mo-1, eps ascending.  B_ov[P, i*n_virt + a] = (P|ia) and
 b = B_rows[r, m, :] = (P|nm) for the state n = row_ids[r].
 
-Readings of the paper (each is listed in the design doc):
+Readings of the paper:
   * Pi carries the closed-shell spin sum (factor 2) and eta -> 0+, so at
     omega = i xi it is -4 sum_ia B_ia B_ia^T D/(D^2 + xi^2) and at real
     omega it is -4 sum_ia B_ia B_ia^T D/(D^2 - omega^2), D = eps_a - eps_i.

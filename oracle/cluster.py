@@ -7,7 +7,7 @@ one kind the QP energies of the requested states gather in a few narrow
 regions; once one state of a region is solved, its result gives the other
 states of that region a good start for the iterative solver.
 
-Readings (listed in DESIGN.md):
+Readings:
   * clusters are formed from the requested states' energies in G (the
     mean-field eigenvalues for G0W0): sorted ascending, a new cluster starts
     wherever the gap to the previous state exceeds `width` (Ha); width <= 0

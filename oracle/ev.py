@@ -6,7 +6,7 @@ eigenvalues and the next cycle recomputes the transition energies and W;
 the Introduction distinguishes updating the eigenvalues in G only (evGW0)
 from updating them in G and W (evGW).
 
-Readings (listed in DESIGN.md):
+Readings:
   * only the requested states' eigenvalues are replaced, all at the end of a
     cycle; the other states keep their reference values (the paper states no
     shift for them);

@@ -12,7 +12,7 @@ alternative solver and serves as the brute-force pin.
 Here f(w) = eps_n + dsig_x_n + Re Sigma^c_n(w) - w, where dsig_x_n stands
 for Sigma^x_nn - V^xc_nn (0 unless given).
 
-Readings (listed in DESIGN.md):
+Readings:
   * scaled residual: dw = alpha f with alpha = min(0.1, 0.1/|f|), so the
     step never exceeds 0.1 Ha;
   * iteration 0 is always a scaled residual (no derivative is used there);

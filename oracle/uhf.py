@@ -13,7 +13,7 @@ occupied levels, B_ov[s] [N_aux, n_occ_s * n_virt_s] with column
 i * n_virt_s + a.  A state is named by its spin-orbital index s * n_mo + n;
 its row b = (P|n m s) [n_mo, N_aux] runs over the orbitals m of spin s.
 
-Readings (listed in DESIGN.md):
+Readings:
   * Pi(i xi) = -2 sum_s B_s diag(D_s / (D_s^2 + xi^2)) B_s^T: the two
     time orderings of each spin's transitions give the 2; closed shell (both
     spins equal) gives the -4 of the closed-shell reading;
