@@ -387,6 +387,10 @@ hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, h
   // MINRES: part[s][sys][P] = sum_ia V[sys][ia] B_ov[P][ia], split-K partials, 64 x 128 tiles
   if (tile_kind == 2 && la == KC && lb == KC && epi == EPI_STORE && !scaled)
     return launch<1, 4, 2, KC, KC, EPI_STORE, false, false>(a, st);
+  // Cholesky panel solve and the preconditioner X X^T: short K or few tiles, so
+  // 64 x 128 tiles for twice the workgroups of the 128 x 128 form
+  if (tile_kind == 2 && la == KC && lb == KC && epi == EPI_AXPBY && !scaled)
+    return launch<1, 4, 2, KC, KC, EPI_AXPBY, false, false>(a, st);
   // W^c reduction: |R^T Linv^T|^2 per row, Linv^T k-major, triangular k range;
   // grid point slowest so that the tiles reading one L^-T panel run together
   if (tile_kind == 0 && la == KC && lb == KM && epi == EPI_SQNORM && !scaled)

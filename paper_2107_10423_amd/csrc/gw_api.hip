@@ -555,11 +555,11 @@ int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
       a.C = c->d_work + k; a.ldc = ldA; a.sC = per_g;
       a.K = PANEL; a.row0 = k + PANEL; a.col0 = 0; a.k0 = k; a.kb0 = 0;
       a.map = MAP_FULL;
-      a.tiles_m = (rows_below + 127) / 128; a.tiles_n = 1;
-      a.M = a.tiles_m * 128; a.N = PANEL;
+      a.tiles_m = (rows_below + 63) / 64; a.tiles_n = 1;
+      a.M = a.tiles_m * 64; a.N = PANEL;
       a.n_tiles = a.tiles_m; a.batch = G; a.splitk = 1;
       a.alpha = 1.0; a.beta = 0.0;
-      RCHK(run_gemm(c, a, 0, KC, KC, EPI_AXPBY));
+      RCHK(run_gemm(c, a, 2, KC, KC, EPI_AXPBY));
     }
   }
   std::vector<int> info(G);
@@ -680,10 +680,10 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
     a.B = X; a.ldb = ldA; a.sB = 0;
     a.C = c->d_pre; a.ldc = c->Np; a.sC = 0;
     a.M = c->Np; a.N = c->Np; a.K = c->Np;
-    a.map = MAP_FULL; a.tiles_m = c->Np / 128; a.tiles_n = c->Np / 128;
+    a.map = MAP_FULL; a.tiles_m = c->Np / 64; a.tiles_n = c->Np / 128;
     a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
     a.alpha = 1.0; a.beta = 0.0;
-    RCHK(run_gemm(c, a, 0, KC, KC, EPI_AXPBY));
+    RCHK(run_gemm(c, a, 2, KC, KC, EPI_AXPBY));
     // preconditioned window: |omega| below 0.9 of the lowest transition
     // energy, where 1 - Pi(omega) stays positive definite and close to M
     double dmin = INFINITY;
