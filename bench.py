@@ -449,7 +449,7 @@ def main():
                        "points / launch time (HIP events on the context stream); BF16x3 issues 3 "
                        "bf16 MFMA products per algorithmic product, so its issued rate is 3x"}
     n_rows_mo = len(states) * (cfg.shape.n_occ + cfg.shape.n_virt)
-    w_flops = float(n_rows_mo) * n_aux * n_aux * (cfg.grid_points + 1)
+    w_flops = float(n_rows_mo) * n_aux * n_aux * cfg.grid_points
     w_ms = h["stages"]["wtab_ms"]
     w_tf = w_flops / (w_ms / 1e3) / 1e12
     tr_w = recorded_traffic("w_gemm")
@@ -459,10 +459,9 @@ def main():
               "flops_per_launch": w_flops, "launch_ms": round(w_ms, 4),
               "traffic_gb_per_s": (round(tr_w / (w_ms / 1e3) / 1e9, 1) if tr_w else None),
               "note": "W^c_nm = |L^-1 b|^2 - |b|^2 for every supplied row and m: algorithmic "
-                      "flops n_rows n_mo N_aux^2 per grid point (a triangular solve per b) x 65 "
-                      "grid points (64 + the xi = 0 point of the MINRES preconditioner) / the W^c "
-                      "stage time (HIP events around the FP64 GEMM with its squared-norm "
-                      "epilogue and the 10-us reduction kernel after it)"}
+                      "flops n_rows n_mo N_aux^2 per grid point (a triangular solve per b) x 64 "
+                      "grid points / the W^c stage time (HIP events around the FP64 GEMM with "
+                      "its squared-norm epilogue and the 10-us reduction kernel after it)"}
     roof, other = (roof_w, roof_pi) if w_ms > h["pi_ms"] else (roof_pi, roof_w)
     roof = dict(roof)
     roof["other_kernel"] = other

@@ -269,7 +269,8 @@ struct gw_ctx {
   double* d_wtab = nullptr;    // [nR][wtab_G]
   int wtab_G = 0;              // table columns
   int quad_G = 0;              // quadrature points (wtab_G, or wtab_G - 1 with wtab_w0)
-  int wtab_w0 = 0;             // last column is W^c(0) (the table was built with xi = 0)
+  int wtab_w0 = 0;             // the table was built with xi = 0 as its last point
+  bool wtab_w0col = false;     // ... and its last column holds W^c(0)
   int quad_split = 0;          // the quadrature integrates the W^c(0) part exactly (evGW)
   // MINRES preconditioner M^-1 = (1 - Pi(0))^-1, formed from the xi = 0 point
   // of a table build; systems with |omega| < pre_w use it
@@ -590,8 +591,10 @@ int copy_out_blocks(gw_ctx* c, double* dst, int Gc, long per_g, long ldA) {
 // Build the W^c table for `grid` unless cached.  mode: 0 normal; 1/2 write
 // the dielectric matrix / Cholesky factor of each point to `dbg_out`.
 // with_w0 (mode 0): one more column, W^c at xi = 0, for the split quadrature.
+// need_w0_col: the W^c(0) column itself is read (evGW); otherwise the xi = 0
+// point serves the preconditioner only and its W^c GEMM is skipped.
 int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_out = nullptr,
-                 bool with_w0 = false) {
+                 bool with_w0 = false, bool need_w0_col = false) {
   RCHK(check_grid(grid_in));
   std::vector<double> ext_xi, ext_w;
   gw_grid ext = *grid_in;
@@ -607,7 +610,8 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
   const gw_grid* grid = &ext;
   const int G = grid->n;
   if (mode == 0 && c->wtab_valid && c->wtab_G == G && c->wtab_w0 == (int)with_w0 &&
-      c->wtab_prec == c->pi_prec && std::equal(grid->xi, grid->xi + G, c->wtab_xi.begin()) &&
+      (!need_w0_col || c->wtab_w0col) && c->wtab_prec == c->pi_prec &&
+      std::equal(grid->xi, grid->xi + G, c->wtab_xi.begin()) &&
       std::equal(grid->w, grid->w + G, c->wtab_w.begin())) {
     c->timing.wtab_cached = 1;
     return 0;
@@ -652,7 +656,10 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
       continue;
     }
     tm.start(c->st);
-    if (c->nR > 0) {
+    // items of this chunk whose W^c column is formed (the xi = 0 point, last,
+    // only when its column is read)
+    const int Gw = (with_w0 && !need_w0_col && g0 + Gc == G) ? Gc - 1 : Gc;
+    if (c->nR > 0 && Gw > 0) {
       // |L^-1 b|^2 for every b = (P|nm): rows of R times L^-T (k-major rows
       // Np.. of the work buffer), k limited to the lower triangle
       GemmArgs a{};
@@ -661,10 +668,10 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
       a.C = c->d_parts; a.ldc = parts_ld(c); a.sC = parts_per_g(c);
       a.M = c->Rp; a.N = c->Np; a.K = c->Np;
       a.map = MAP_FULL_J; a.tiles_m = c->Rp / 128; a.tiles_n = c->Np / 128;
-      a.n_tiles = a.tiles_m * a.tiles_n; a.batch = Gc; a.splitk = 1; a.ktri = 1;
+      a.n_tiles = a.tiles_m * a.tiles_n; a.batch = Gw; a.splitk = 1; a.ktri = 1;
       RCHK(run_gemm(c, a, 0, KC, KM, EPI_SQNORM));
       HIPCHK(wc_from_parts(c->d_parts, parts_per_g(c), c->Np / 128, parts_ld(c), c->d_bn, c->nR,
-                           Gc, G, g0, c->d_wtab, c->ext(c->d_parts, 8), c->ext(c->d_bn, 8),
+                           Gw, G, g0, c->d_wtab, c->ext(c->d_parts, 8), c->ext(c->d_bn, 8),
                            c->ext(c->d_wtab, 8), c->st));
     }
     wt_ms += tm.stop();
@@ -703,6 +710,7 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
     c->wtab_valid = true;
     c->wtab_G = G;
     c->wtab_w0 = with_w0 ? 1 : 0;
+    c->wtab_w0col = with_w0 && need_w0_col;
     c->quad_G = with_w0 ? G - 1 : G;
     c->wtab_prec = c->pi_prec;
     c->wtab_xi.assign(grid->xi, grid->xi + G);
@@ -2181,7 +2189,7 @@ int gw_evgw(gw_ctx* c, int mode, int n_cycles, double ev_tol, int n_states, cons
         break;
       }
     }
-    if ((rc = build_wtable(c, grid, 0, nullptr, true))) break;
+    if ((rc = build_wtable(c, grid, 0, nullptr, true, true))) break;
     c->quad_split = 1;
     // each cycle starts its solves from the current energies in G
     std::vector<double> start(n_states);
