@@ -54,8 +54,9 @@ extern "C" {
 #define GW_ST_SMALL_Z 2   /* Z < 0.1 at the returned point */
 #define GW_ST_FALLBACK 4  /* at least one residue used the dense fallback */
 
-/* precision of the Pi(i xi) build only; Cholesky, MINRES and the QP step
- * are always float64 */
+/* precision of the Pi(i xi) build (gw_opts.pi_prec) and, optionally, of the
+ * W^c contraction (gw_opts.wc_prec: FP64 or BF16X3 only); Cholesky, MINRES
+ * and the QP step are always float64 */
 #define GW_PI_FP64 0
 #define GW_PI_FP32 1    /* FP32 operands, FP32 MFMA accumulation, FP64 split-K sum */
 #define GW_PI_BF16X3 2  /* bf16 hi/lo split, 3 MFMA products, FP32 accumulation */
@@ -94,6 +95,15 @@ typedef struct gw_opts {
                                iteration cap).  States of different clusters advance
                                together; a member joins the batched rounds once its
                                representative is done. */
+  int wc_prec;              /* precision of the W^c contraction of the table build
+                               (W_{mn,mn}(i xi) in [CD-impl]; 0: GW_PI_FP64).
+                               GW_PI_BF16X3 forms W^c = 2 b^T y + |y|^2 with
+                               y = (L^-1 - I) b in BF16x3 products with FP32
+                               accumulation (L the Cholesky factor of 1 - Pi), so
+                               that its error is relative to W^c rather than to
+                               |b|^2; adds 4 Np^2 bytes of workspace per grid point
+                               of a chunk and 4 Rp Np bytes per context.  Other
+                               values: GW_EINVAL. */
 } gw_opts;
 
 /* Imaginary-frequency quadrature: nodes xi[n] > 0 and d-xi weights w[n]
@@ -310,6 +320,7 @@ typedef struct gw_server_opts {
   size_t mem_budget_bytes;  /* admission budget; 0: 80% of free device memory */
   int n_streams;            /* concurrent request pipelines, 1..4 (0: 2) */
   size_t work_budget_bytes; /* stage-A workspace cap per request (0: 2 GiB) */
+  int wc_prec;              /* as in gw_opts (0: FP64) */
 } gw_server_opts;
 
 typedef struct gw_request {

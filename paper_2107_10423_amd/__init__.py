@@ -19,6 +19,10 @@ LIB_PATH = os.path.join(_HERE, "libgw_hostsan.so" if os.environ.get("GW_LIB_VARI
 
 GW_PI_FP64, GW_PI_FP32, GW_PI_BF16X3 = 0, 1, 2
 PREC = {"fp64": GW_PI_FP64, "fp32": GW_PI_FP32, "bf16x3": GW_PI_BF16X3}
+
+
+def _prec(p):
+    return PREC[p] if isinstance(p, str) else int(p)
 ST_MAXITER, ST_SMALL_Z, ST_FALLBACK = 1, 2, 4
 
 if not os.path.exists(LIB_PATH):
@@ -36,7 +40,8 @@ class _Opts(ctypes.Structure):
                 ("qp_max_iter", ctypes.c_int), ("dsig_x", _dp), ("stream", ctypes.c_void_p),
                 ("mem_budget_bytes", ctypes.c_size_t), ("work_budget_bytes", ctypes.c_size_t),
                 ("minres_batch", ctypes.c_int), ("no_graphs", ctypes.c_int),
-                ("no_precond", ctypes.c_int), ("cluster_width", ctypes.c_double)]
+                ("no_precond", ctypes.c_int), ("cluster_width", ctypes.c_double),
+                ("wc_prec", ctypes.c_int)]
 
 
 class _Grid(ctypes.Structure):
@@ -61,7 +66,8 @@ class _ServerOpts(ctypes.Structure):
                 ("qp_max_iter", ctypes.c_int), ("minres_rtol", ctypes.c_double),
                 ("qp_tol", ctypes.c_double), ("grid_n", ctypes.c_int), ("grid_xi", _dp),
                 ("grid_w", _dp), ("mem_budget_bytes", ctypes.c_size_t),
-                ("n_streams", ctypes.c_int), ("work_budget_bytes", ctypes.c_size_t)]
+                ("n_streams", ctypes.c_int), ("work_budget_bytes", ctypes.c_size_t),
+                ("wc_prec", ctypes.c_int)]
 
 
 class _Request(ctypes.Structure):
@@ -190,7 +196,7 @@ class Context:
     def __init__(self, eps, n_occ, B_ov, row_ids, B_rows, pi_prec="fp64", minres_max_iter=0,
                  minres_rtol=0.0, qp_tol=0.0, qp_max_iter=0, dsig_x=None, stream=None,
                  mem_budget_bytes=0, work_budget_bytes=0, minres_batch=0, graphs=True,
-                 cluster_width=0.0, precond=True):
+                 cluster_width=0.0, precond=True, wc_prec="fp64"):
         eps = _d(eps)
         B_ov = _d(B_ov)
         rows = _i(row_ids)
@@ -203,7 +209,7 @@ class Context:
             raise ValueError("B_rows must be [n_rows][n_mo][n_aux]")
         o = self._make_opts(pi_prec, minres_max_iter, minres_rtol, qp_tol, qp_max_iter,
                             dsig_x, stream, mem_budget_bytes, work_budget_bytes, minres_batch,
-                            graphs, cluster_width, precond)
+                            graphs, cluster_width, precond, wc_prec)
         h = _ctxp()
         _check(_lib.gw_setup(ctypes.byref(h), n_mo, int(n_occ), n_aux, _pd(eps), _pd(B_ov),
                              rows.size, _pi(rows), _pd(B_rows), ctypes.byref(o)))
@@ -214,13 +220,14 @@ class Context:
     def _make_opts(self, pi_prec="fp64", minres_max_iter=0, minres_rtol=0.0, qp_tol=0.0,
                    qp_max_iter=0, dsig_x=None, stream=None, mem_budget_bytes=0,
                    work_budget_bytes=0, minres_batch=0, graphs=True, cluster_width=0.0,
-                   precond=True):
+                   precond=True, wc_prec="fp64"):
         self._dsx = _d(dsig_x) if dsig_x is not None else None
-        return _Opts(PREC[pi_prec] if isinstance(pi_prec, str) else int(pi_prec),
+        return _Opts(_prec(pi_prec),
                      int(minres_max_iter), float(minres_rtol), float(qp_tol), int(qp_max_iter),
                      _pd(self._dsx), ctypes.c_void_p(stream) if stream else None,
                      int(mem_budget_bytes), int(work_budget_bytes), int(minres_batch),
-                     0 if graphs else 1, 0 if precond else 1, float(cluster_width))
+                     0 if graphs else 1, 0 if precond else 1, float(cluster_width),
+                     _prec(wc_prec))
 
     @classmethod
     def from_inputs(cls, inp, **kw):
@@ -388,10 +395,10 @@ GW_EAUDIT = -5
 
 
 def footprint(n_mo, n_occ, n_aux, n_rows, n_states, grid_n, pi_prec="fp64", work_budget_bytes=0,
-              minres_batch=0):
+              minres_batch=0, wc_prec="fp64"):
     """gw_footprint: device bytes a context of these sizes uses."""
-    o = _Opts(PREC[pi_prec] if isinstance(pi_prec, str) else int(pi_prec), 0, 0.0, 0.0, 0, None,
-              None, 0, int(work_budget_bytes), int(minres_batch))
+    o = _Opts(_prec(pi_prec), 0, 0.0, 0.0, 0, None, None, 0, int(work_budget_bytes),
+              int(minres_batch), 0, 0, 0.0, _prec(wc_prec))
     return int(_lib.gw_footprint(n_mo, n_occ, n_aux, n_rows, n_states, grid_n, ctypes.byref(o)))
 
 
@@ -399,11 +406,12 @@ class Server:
     """Request server (gw_server_*): submit molecules, poll results."""
 
     def __init__(self, grid, pi_prec="fp64", mem_budget_bytes=0, n_streams=0,
-                 work_budget_bytes=0, qp_tol=0.0, minres_rtol=0.0):
+                 work_budget_bytes=0, qp_tol=0.0, minres_rtol=0.0, wc_prec="fp64"):
         self._grid = grid
-        o = _ServerOpts(PREC[pi_prec] if isinstance(pi_prec, str) else int(pi_prec), 0, 0,
+        o = _ServerOpts(_prec(pi_prec), 0, 0,
                         float(minres_rtol), float(qp_tol), grid.n, _pd(grid.xi), _pd(grid.w),
-                        int(mem_budget_bytes), int(n_streams), int(work_budget_bytes))
+                        int(mem_budget_bytes), int(n_streams), int(work_budget_bytes),
+                        _prec(wc_prec))
         h = ctypes.c_void_p()
         _check(_lib.gw_server_create(ctypes.byref(h), ctypes.byref(o)))
         self._h = h

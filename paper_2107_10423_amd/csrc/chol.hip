@@ -163,14 +163,15 @@ hipError_t set_identity_rows(double* A, long ldA, long sA, int row0, int n, int 
   return hipGetLastError();
 }
 
-// wtab[q][g0 + g] = sum_J part[g][J][q] - bnorm2[q]
+// wtab[q][g0 + g] = sum_J part[g][J][q] - bnorm2[q] (bnorm2 null: no subtraction,
+// the partials of the mixed contraction already are W^c)
 __global__ void k_wc_from_parts(const double* part, long sPart, int nJ, int ldp,
                                 const double* bnorm2, int nR, int Gtot, int g0, double* wtab) {
   const int g = blockIdx.y;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nR; q += gridDim.x * blockDim.x) {
     double s = 0.0;
     for (int J = 0; J < nJ; ++J) s += part[(long)g * sPart + (long)J * ldp + q];
-    wtab[(long)q * Gtot + g0 + g] = s - bnorm2[q];
+    wtab[(long)q * Gtot + g0 + g] = bnorm2 ? s - bnorm2[q] : s;
   }
 }
 
@@ -180,7 +181,7 @@ hipError_t wc_from_parts(const double* part, long sPart, int nJ, int ldp, const 
   if (nR <= 0 || G <= 0) return hipSuccess;
   if (g0 + G > Gtot || ldp < nR) return refuse("wc_from_parts", "shape");
   GW_GUARD("wc_from_parts", "part", (long)(G - 1) * sPart + (long)(nJ - 1) * ldp + nR - 1, nPart);
-  GW_GUARD("wc_from_parts", "bnorm2", nR - 1, nBn);
+  if (bnorm2) GW_GUARD("wc_from_parts", "bnorm2", nR - 1, nBn);
   GW_GUARD("wc_from_parts", "wtab", (long)(nR - 1) * Gtot + g0 + G - 1, nW);
   GW_AUDIT_RETURN();
   int blocks = std::min((nR + 255) / 256, 256);

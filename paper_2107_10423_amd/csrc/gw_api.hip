@@ -202,6 +202,7 @@ struct gw_ctx {
   int Rp = 0;      // nR padded to 128
   // options
   int pi_prec = GW_PI_FP64;
+  int wc_prec = GW_PI_FP64;    // W^c contraction: FP64 GEMM, or the BF16x3 form
   int minres_max_iter = 200;
   double minres_rtol = 1e-12;
   double qp_tol = 1e-10;
@@ -263,6 +264,10 @@ struct gw_ctx {
   double* d_scale = nullptr;   // [chunk][Kp]
   float* d_scale32 = nullptr;  // [chunk][Kp], the same scales rounded for the mixed builds
   double* d_parts = nullptr;   // [chunk][Np/128][Rp] squared-norm partials
+  // mixed W^c contraction: R split once, F = L^-1 - I split per grid point
+  uint16_t* d_Rh = nullptr;    // [Rp][Np] (hi; lo follows at Rp Np)
+  uint16_t* d_F = nullptr;     // [2][f_cap][Np][Np] (hi block, then lo block)
+  int f_cap = 0;
   double* d_grid = nullptr;    // [2][Gmax]
   int grid_cap = 0;
   // W^c table cache
@@ -282,6 +287,7 @@ struct gw_ctx {
   bool wtab_valid = false;
   std::vector<double> wtab_xi, wtab_w;
   int wtab_prec = -1;
+  int wtab_wcprec = -1;
   // Sigma quadrature buffers
   int* d_rowsel = nullptr;
   int* d_rowspin = nullptr;      // [n_rows] (open shell only)
@@ -424,6 +430,7 @@ int setup_work(gw_ctx* c, int G) {
   const long per_g = work_per_g(c);
   size_t per_bytes = (size_t)per_g * sizeof(double) + (size_t)c->Kp * (sizeof(double) + sizeof(float)) +
                      PANEL * PANEL * sizeof(double) + (size_t)parts_per_g(c) * sizeof(double);
+  if (c->wc_prec == GW_PI_BF16X3) per_bytes += (size_t)c->Np * c->Np * 2 * sizeof(uint16_t);
   int chunk = (int)std::max<size_t>(1, c->work_budget / per_bytes);
   if (chunk > G) chunk = G;
   if (c->d_work && c->chunk >= chunk) return 0;
@@ -500,6 +507,24 @@ int pi_build_chunk(gw_ctx* c, int G, long per_g, long ldA) {
   HIPCHK(pi_build_bf16x3(c->d_Bhi, c->d_Blo, c->Kp, c->d_B32, c->d_scale32, c->Kp, c->d_work,
                          ldA, per_g, c->Np, c->Kp, G, nB, c->ext(c->d_scale32, 4),
                          c->ext(c->d_work, 8), c->st));
+  return 0;
+}
+
+// Operands of the mixed W^c contraction: R split once per context, the F
+// buffer sized for the current chunk.
+int ensure_wc_mixed(gw_ctx* c) {
+  if (!c->d_Rh) {
+    const size_t n = (size_t)c->Rp * c->Np;
+    RCHK(c->alloc((void**)&c->d_Rh, 2 * n * sizeof(uint16_t)));
+    HIPCHK(split_bf16(c->d_R, c->d_Rh, c->d_Rh + n, nullptr, (long)n, c->st));
+  }
+  if (c->f_cap < c->chunk) {
+    if (c->d_F) c->release(c->d_F);
+    c->d_F = nullptr;
+    c->f_cap = 0;
+    RCHK(c->alloc((void**)&c->d_F, 2 * (size_t)c->chunk * c->Np * c->Np * sizeof(uint16_t)));
+    c->f_cap = c->chunk;
+  }
   return 0;
 }
 
@@ -611,6 +636,7 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
   const int G = grid->n;
   if (mode == 0 && c->wtab_valid && c->wtab_G == G && c->wtab_w0 == (int)with_w0 &&
       (!need_w0_col || c->wtab_w0col) && c->wtab_prec == c->pi_prec &&
+      c->wtab_wcprec == c->wc_prec &&
       std::equal(grid->xi, grid->xi + G, c->wtab_xi.begin()) &&
       std::equal(grid->w, grid->w + G, c->wtab_w.begin())) {
     c->timing.wtab_cached = 1;
@@ -659,7 +685,23 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
     // items of this chunk whose W^c column is formed (the xi = 0 point, last,
     // only when its column is read)
     const int Gw = (with_w0 && !need_w0_col && g0 + Gc == G) ? Gc - 1 : Gc;
-    if (c->nR > 0 && Gw > 0) {
+    if (c->nR > 0 && Gw > 0 && c->wc_prec == GW_PI_BF16X3) {
+      // 2 b^T y + |y|^2, y = (L^-1 - I) b, in BF16x3 products: F split from
+      // the k-major L^-T rows, then one contraction with the split R
+      RCHK(ensure_wc_mixed(c));
+      const long nRR = (long)c->Rp * c->Np;
+      const long sF = (long)c->Np * c->Np;
+      const long nF = (long)c->f_cap * sF;
+      uint16_t* Fh = c->d_F;
+      uint16_t* Fl = c->d_F + nF;
+      HIPCHK(split_linv(c->d_work + (long)c->Np * ldA, ldA, per_g, c->Np, Gw, Fh, Fl, sF,
+                        c->ext(c->d_work + (long)c->Np * ldA, 8), nF, c->st));
+      HIPCHK(wc_bf16x3(c->d_Rh, c->d_Rh + nRR, c->Np, c->Rp, Fh, Fl, sF, c->Np, Gw, c->d_parts,
+                       parts_ld(c), parts_per_g(c), nRR, nF, c->ext(c->d_parts, 8), c->st));
+      HIPCHK(wc_from_parts(c->d_parts, parts_per_g(c), c->Np / 128, parts_ld(c), nullptr, c->nR,
+                           Gw, G, g0, c->d_wtab, c->ext(c->d_parts, 8), 0, c->ext(c->d_wtab, 8),
+                           c->st));
+    } else if (c->nR > 0 && Gw > 0) {
       // |L^-1 b|^2 for every b = (P|nm): rows of R times L^-T (k-major rows
       // Np.. of the work buffer), k limited to the lower triangle
       GemmArgs a{};
@@ -713,6 +755,7 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
     c->wtab_w0col = with_w0 && need_w0_col;
     c->quad_G = with_w0 ? G - 1 : G;
     c->wtab_prec = c->pi_prec;
+    c->wtab_wcprec = c->wc_prec;
     c->wtab_xi.assign(grid->xi, grid->xi + G);
     c->wtab_w.assign(grid->w, grid->w + G);
   }
@@ -1572,7 +1615,7 @@ int solve_qp(gw_ctx* c, int n_states, const int* states, std::vector<QPState>& q
 // residue systems per Sigma evaluation (n_states * n_mo, in batches of at
 // most minres_batch).
 size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, int G_in,
-                       int pi_prec, size_t work_budget, int minres_batch) {
+                       int pi_prec, int wc_prec, size_t work_budget, int minres_batch) {
   const size_t d = sizeof(double);
   const int G = G_in + 1;   // the xi = 0 point of the preconditioner (on by default)
   const int Np = round_up(n_aux, 128);
@@ -1587,10 +1630,12 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   // stage A
   const size_t per_g = (size_t)(2L * Np + 128) * (Np + 128);
   const size_t parts = (size_t)(Np / 128) * Rp;
-  const size_t per_bytes = per_g * d + (size_t)Kp * (d + 4) + PANEL * PANEL * d + parts * d;
+  const size_t f_bytes = wc_prec == GW_PI_BF16X3 ? (size_t)Np * Np * 4 : 0;
+  const size_t per_bytes = per_g * d + (size_t)Kp * (d + 4) + PANEL * PANEL * d + parts * d + f_bytes;
   int chunk = (int)std::max<size_t>(1, work_budget / per_bytes);
   if (chunk > G) chunk = G;
   b += (size_t)chunk * (per_g * d + parts * d + PANEL * PANEL * d + sizeof(int) + (size_t)Kp * (d + 4));
+  if (wc_prec == GW_PI_BF16X3) b += (size_t)chunk * f_bytes + (size_t)Rp * Np * 4;
   b += 2 * (size_t)G * d + (size_t)std::max(nR, 1) * G * d;
   // Sigma evaluation buffers
   b += (size_t)round_up(std::max(n_states, 1), 8) * (sizeof(int) + 3 * d + 32 * d);
@@ -1814,6 +1859,8 @@ int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts) {
   gw_opts o{};
   if (opts) o = *opts;
   if (o.pi_prec < 0 || o.pi_prec > 2) return fail(GW_EINVAL, "unknown pi_prec %d", o.pi_prec);
+  if (o.wc_prec != GW_PI_FP64 && o.wc_prec != GW_PI_BF16X3)
+    return fail(GW_EINVAL, "wc_prec must be GW_PI_FP64 or GW_PI_BF16X3, not %d", o.wc_prec);
   if (o.minres_max_iter < 0 || o.qp_max_iter < 0 || o.minres_rtol < 0 || o.qp_tol < 0 ||
       !(o.cluster_width >= 0.0) || !std::isfinite(o.cluster_width))
     return fail(GW_EINVAL, "negative or non-finite option");
@@ -1831,6 +1878,7 @@ int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts) {
   c->nR = n_rows * n_mo;
   c->Rp = round_up(std::max(c->nR, 1), 128);
   c->pi_prec = o.pi_prec;
+  c->wc_prec = o.wc_prec;
   if (o.minres_max_iter > 0) c->minres_max_iter = o.minres_max_iter;
   if (o.minres_rtol > 0) c->minres_rtol = o.minres_rtol;
   if (o.qp_tol > 0) c->qp_tol = o.qp_tol;
@@ -1968,7 +2016,7 @@ size_t gw_footprint(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, in
   const size_t wb = o.work_budget_bytes ? o.work_budget_bytes : (16ull << 30);
   const int mb = o.minres_batch > 0 ? std::max(64, o.minres_batch) : 256;
   if (n_mo < 2 || n_occ < 1 || n_occ >= n_mo || n_aux < 1 || n_rows < 0 || grid_n < 1) return 0;
-  return footprint_bytes(n_mo, n_occ, n_aux, n_rows, n_states, grid_n, o.pi_prec, wb, mb);
+  return footprint_bytes(n_mo, n_occ, n_aux, n_rows, n_states, grid_n, o.pi_prec, o.wc_prec, wb, mb);
 }
 
 int gw_reset_cache(gw_ctx* c) {

@@ -96,6 +96,13 @@ hipError_t pi_build_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, long ld, co
                            const float* scale, long sS, double* A, long ldA, long sA, int Np,
                            int Kp, int G, long nB, long nS, long nA, hipStream_t st);
 hipError_t split_bf16(const double* B, uint16_t* hi, uint16_t* lo, float* b32, long n, hipStream_t st);
+// mixed W^c contraction: F = L^-1 - I split from X = L^-T (k-major), then
+// part[g][J][q] = sum over panel J of (2 b + y) y with y = F b (BF16x3)
+hipError_t split_linv(const double* X, long ldX, long sX, int Np, int G, uint16_t* Fh,
+                      uint16_t* Fl, long sF, long nX, long nF, hipStream_t st);
+hipError_t wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl, long ldR, int Rp, const uint16_t* Fh,
+                     const uint16_t* Fl, long sF, int Np, int G, double* part, long ldp, long sP,
+                     long nR, long nF, long nP, hipStream_t st);
 
 // Cholesky pieces
 hipError_t chol_diag(double* A, long ldA, long sA, double* Linv, int k, int G, int* info,

@@ -19,7 +19,7 @@
 #include "../../include/gw.h"
 
 size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, int G,
-                       int pi_prec, size_t work_budget, int minres_batch);
+                       int pi_prec, int wc_prec, size_t work_budget, int minres_batch);
 int validate_inputs(int n_mo, int n_occ, int n_aux, const double* eps, const double* B_ov,
                     int n_rows, const int* row_ids, const double* B_rows, bool check_arrays);
 long copy_check_finite(double* dst, const double* src, long n);
@@ -153,6 +153,7 @@ struct gw_server {
   void process(Req* r, int slot) {
     gw_opts o{};
     o.pi_prec = opts.pi_prec;
+    o.wc_prec = opts.wc_prec;
     o.minres_max_iter = opts.minres_max_iter;
     o.minres_rtol = opts.minres_rtol;
     o.qp_tol = opts.qp_tol;
@@ -189,6 +190,9 @@ extern "C" {
 
 int gw_server_create(gw_server** out, const gw_server_opts* opts) {
   if (!out || !opts || opts->grid_n < 1 || !opts->grid_xi || !opts->grid_w) return GW_EINVAL;
+  if (opts->pi_prec < 0 || opts->pi_prec > 2 ||
+      (opts->wc_prec != GW_PI_FP64 && opts->wc_prec != GW_PI_BF16X3))
+    return GW_EINVAL;
   *out = nullptr;
   gw_server* s = new gw_server();
   s->opts = *opts;
@@ -265,7 +269,8 @@ int gw_server_submit(gw_server* s, const gw_request* q, unsigned long long* tick
   o.pi_prec = s->opts.pi_prec;
   o.work_budget_bytes = s->opts.work_budget_bytes;
   r->footprint = footprint_bytes(q->n_mo, q->n_occ, q->n_aux, q->n_rows, q->n_states,
-                                 (int)s->xi.size(), s->opts.pi_prec, s->opts.work_budget_bytes, 256);
+                                 (int)s->xi.size(), s->opts.pi_prec, s->opts.wc_prec,
+                                 s->opts.work_budget_bytes, 256);
   if (r->footprint > s->budget) {
     if (r->pinned_bytes) s->pinned.release(r->B, r->pinned_bytes);
     delete r;

@@ -16,12 +16,19 @@
 // Tiles are 128 x 128 per 256-thread workgroup (2 x 2 wavefronts of 64 x 64),
 // lower-triangular tile map, grid point index fastest and XCD-swizzled as in
 // the FP64 kernel.
+//
+// The same BF16x3 products serve the optional mixed W^c contraction (end of
+// this file).  There W^c = |L^-1 b|^2 - |b|^2 is evaluated as
+// 2 b^T y + |y|^2 with y = (L^-1 - I) b: the difference of the two large norms
+// is never formed, so the error of the low-precision products stays relative
+// to W^c itself instead of to |b|^2.
 #include "gw_internal.h"
 
 namespace gw {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
 typedef short s8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -65,13 +72,14 @@ __global__ void k_split_bf16(const double* B, uint16_t* hi, uint16_t* lo, float*
     float r = x - bf16_to_f(h);
     hi[i] = h;
     lo[i] = bf16_rne(r);
-    b32[i] = x;
+    if (b32) b32[i] = x;
   }
 }
 
+// b32 may be null (only the bf16 pair is wanted)
 hipError_t split_bf16(const double* B, uint16_t* hi, uint16_t* lo, float* b32, long n,
                       hipStream_t st) {
-  GW_AUDIT_RETURN();  // all four arrays are allocated with n elements by the caller
+  GW_AUDIT_RETURN();  // the arrays are allocated with n elements by the caller
   int blocks = (int)std::min<long>((n + 255) / 256, 4096);
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_split_bf16, dim3(blocks), dim3(256), 0, st, B, hi, lo, b32, n);
@@ -407,6 +415,188 @@ hipError_t pi_build_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, long ld, co
   GW_AUDIT_RETURN();
   hipLaunchKernelGGL(k_pi_bf16x3, dim3((unsigned)total), dim3(256), 0, st, Bhi, Blo, ld, B32, scale,
                      sS, A, ldA, sA, T, Kp, G);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Mixed W^c contraction.
+//
+// k_split_linv: F = L^-1 - I of each grid point, from X = L^-T held k-major
+// (X[k][p] = (L^-1)[p][k]; row k of the work buffer's appended block), written
+// row-major [p][k] (k contiguous, zero for k > p) as a bf16 hi/lo pair, 64 x 64
+// tiles transposed through LDS.
+
+__global__ __launch_bounds__(256) void k_split_linv(const double* X, long ldX, long sX, int Np,
+                                                    uint16_t* Fh, uint16_t* Fl, long sF) {
+  __shared__ float T[64][65];
+  const int nt = Np / 64;
+  const int kt = blockIdx.x / nt, pt = blockIdx.x % nt;
+  const int g = blockIdx.y;
+  const int t = threadIdx.x;
+  const double* Xg = X + (long)g * sX;
+  if (kt <= pt) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = (t >> 4) + 16 * u, pp = (t & 15) * 4;
+      const int k = kt * 64 + kk;
+      const double* src = Xg + (long)k * ldX + pt * 64 + pp;
+      const d2 v0 = *reinterpret_cast<const d2*>(src);
+      const d2 v1 = *reinterpret_cast<const d2*>(src + 2);
+      const double v[4] = {v0.x, v0.y, v1.x, v1.y};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int p = pt * 64 + pp + e;
+        T[kk][pp + e] = k > p ? 0.f : (float)(k == p ? v[e] - 1.0 : v[e]);
+      }
+    }
+  }
+  __syncthreads();
+  // thread -> row p = pt*64 + t/4, 16 k values from kt*64 + 16 (t%4)
+  const int pr = t >> 2, kq = (t & 3) * 16;
+  unsigned h[8], l[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float x0 = kt <= pt ? T[kq + 2 * e][pr] : 0.f;
+    const float x1 = kt <= pt ? T[kq + 2 * e + 1][pr] : 0.f;
+    split_pair(x0, x1, h[e], l[e]);
+  }
+  const long o = (long)g * sF + (long)(pt * 64 + pr) * Np + kt * 64 + kq;
+  u32x4* dh = reinterpret_cast<u32x4*>(Fh + o);
+  u32x4* dl = reinterpret_cast<u32x4*>(Fl + o);
+  dh[0] = u32x4{h[0], h[1], h[2], h[3]};
+  dh[1] = u32x4{h[4], h[5], h[6], h[7]};
+  dl[0] = u32x4{l[0], l[1], l[2], l[3]};
+  dl[1] = u32x4{l[4], l[5], l[6], l[7]};
+}
+
+hipError_t split_linv(const double* X, long ldX, long sX, int Np, int G, uint16_t* Fh,
+                      uint16_t* Fl, long sF, long nX, long nF, hipStream_t st) {
+  const char* kn = "split_linv";
+  if (G <= 0) return hipSuccess;
+  if (Np % 128 != 0 || ldX < Np || (ldX & 1) || (sX & 1) || sF < (long)Np * Np || sF % 8 != 0)
+    return refuse(kn, "shape");
+  GW_GUARD(kn, "X", (long)(G - 1) * sX + (long)(Np - 1) * ldX + Np - 1, nX);
+  GW_GUARD(kn, "F", (long)(G - 1) * sF + (long)Np * Np - 1, nF);
+  GW_AUDIT_RETURN();
+  const int nt = Np / 64;
+  hipLaunchKernelGGL(k_split_linv, dim3(nt * nt, G), dim3(256), 0, st, X, ldX, sX, Np, Fh, Fl, sF);
+  return hipGetLastError();
+}
+
+// k_wc_bf16x3: for every grid point g, row q of R (b = (P|nm) of one
+// (state, m) pair) and 128-wide column panel J of the auxiliary index,
+//   part[g][J][q] = sum_{p in J} (2 b_p + y_p) y_p,   y = F_g b,
+// with the BF16x3 products and LDS layout of the Pi build.  F_g[p][k] is zero
+// for k > p, so panel J contracts k < 128 (J + 1) only.  b_p at the output
+// positions is re-read from the split R (hi + lo): the same values the last
+// K-steps of the tile have just staged, so the reads hit the cache.  Row tile
+// fastest, then panel, then grid point: the tiles of one F panel run together.
+__global__ __launch_bounds__(256) void k_wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl,
+                                                   long ldR, const uint16_t* Fh,
+                                                   const uint16_t* Fl, long sF, int Np,
+                                                   double* part, long ldp, long sP, int TM,
+                                                   int TN, int G) {
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Al[2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[2][SLAB];
+  __shared__ double red[2][128];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int total = TM * TN * G;
+  const int id = xcd_swizzle_m(blockIdx.x, total);
+  const int I = id % TM;
+  const int J = (id / TM) % TN;
+  const int g = id / (TM * TN);
+  const uint16_t* Fhg = Fh + (long)g * sF;
+  const uint16_t* Flg = Fl + (long)g * sF;
+  const int ar0 = I * 128, br0 = J * 128;
+  const int nk = (br0 + 128) / BKB;
+
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  // both sides pre-split: 128 rows x 32 k bf16 = 512 chunks of 16 B per array,
+  // 2 per thread
+  u32x4 rah[2], ral[2], rbh[2], rbl[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int row, ch;
+      a_item(t + 256 * u, row, ch);
+      const long oa = (long)(ar0 + row) * ldR + k0 + 8 * ch;
+      const long ob = (long)(br0 + row) * Np + k0 + 8 * ch;
+      rah[u] = *reinterpret_cast<const u32x4*>(Rh + oa);
+      ral[u] = *reinterpret_cast<const u32x4*>(Rl + oa);
+      rbh[u] = *reinterpret_cast<const u32x4*>(Fhg + ob);
+      rbl[u] = *reinterpret_cast<const u32x4*>(Flg + ob);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int row, ch;
+      a_item(t + 256 * u, row, ch);
+      const int s = lds_slot(row, ch);
+      *reinterpret_cast<u32x4*>(&Ah[buf][s]) = rah[u];
+      *reinterpret_cast<u32x4*>(&Al[buf][s]) = ral[u];
+      *reinterpret_cast<u32x4*>(&Bh[buf][s]) = rbh[u];
+      *reinterpret_cast<u32x4*>(&Bl[buf][s]) = rbl[u];
+    }
+  };
+  gload(0);
+  lstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * BKB);
+    bf_mfma_step(Ah[cur], Al[cur], Bh[cur], Bl[cur], lane, wm, wn, acc);
+    if (kt + 1 < nk) lstore(cur ^ 1);
+    __syncthreads();
+  }
+  // accumulator element (4 (l / 16) + r, l % 16) of block (i, j): R row
+  // ar0 + wm 64 + 16 i + mfma_row(4 (l / 16) + r), column br0 + wn 64 + 16 j +
+  // mfma_row(l % 16); the 16 lanes of one l / 16 group share the row
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int lrow = wm * 64 + i * 16 + mfma_row(4 * (lane >> 4) + r);
+      const long ro = (long)(ar0 + lrow) * ldR;
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = br0 + wn * 64 + j * 16 + mfma_row(lane & 15);
+        const double b = (double)bf16_to_f(Rh[ro + col]) + (double)bf16_to_f(Rl[ro + col]);
+        const double y = (double)acc[i][j][r];
+        s += (2.0 * b + y) * y;
+      }
+      for (int off = 8; off > 0; off >>= 1) s += __shfl_xor(s, off, 16);
+      if ((lane & 15) == 0) red[wn][lrow] = s;
+    }
+  __syncthreads();
+  if (t < 128) part[(long)g * sP + (long)J * ldp + ar0 + t] = red[0][t] + red[1][t];
+}
+
+hipError_t wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl, long ldR, int Rp, const uint16_t* Fh,
+                     const uint16_t* Fl, long sF, int Np, int G, double* part, long ldp, long sP,
+                     long nR, long nF, long nP, hipStream_t st) {
+  const char* kn = "wc_bf16x3";
+  const long total = (long)(Rp / 128) * (Np / 128) * G;
+  if (G <= 0 || Rp <= 0) return hipSuccess;
+  if (Rp % 128 != 0 || Np % 128 != 0 || ldR < Np || ldR % 8 != 0 || sF < (long)Np * Np ||
+      sF % 8 != 0 || ldp < Rp || total > 0x7fffffffL)
+    return refuse(kn, "shape");
+  if (((uintptr_t)Rh | (uintptr_t)Rl | (uintptr_t)Fh | (uintptr_t)Fl) & 15)
+    return refuse(kn, "operand pointer not 16-byte aligned");
+  GW_GUARD(kn, "R", (long)(Rp - 1) * ldR + Np - 1, nR);
+  GW_GUARD(kn, "F", (long)(G - 1) * sF + (long)(Np - 1) * Np + Np - 1, nF);
+  GW_GUARD(kn, "part", (long)(G - 1) * sP + (long)(Np / 128 - 1) * ldp + Rp - 1, nP);
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_wc_bf16x3, dim3((unsigned)total), dim3(256), 0, st, Rh, Rl, ldR, Fh, Fl, sF,
+                     Np, part, ldp, sP, Rp / 128, Np / 128, G);
   return hipGetLastError();
 }
 

@@ -34,8 +34,9 @@ def run_case(n_occ, n_virt, n_aux, rows, G, wb, cap):
     shape = gwgen.custom_shape(n_occ, n_virt, n_aux, n_core=1 if n_occ > 1 else 0)
     inp = gwgen.make_inputs(shape, 1, rows)
     g = gwl.Grid.gauss_legendre(G)
-    for prec in ("fp64", "fp32", "bf16x3"):
-        kw = dict(pi_prec=prec, work_budget_bytes=wb, minres_max_iter=cap)
+    for prec, wc in (("fp64", "fp64"), ("fp32", "fp64"), ("bf16x3", "fp64"),
+                     ("bf16x3", "bf16x3")):
+        kw = dict(pi_prec=prec, work_budget_bytes=wb, minres_max_iter=cap, wc_prec=wc)
         with gwl.Context.from_inputs(inp, **kw) as c:
             before = gwl.audit_launch_count()
             for call in (lambda: c.dielectric([0.1, 2.0]), lambda: c.cholesky([0.3]),
@@ -57,7 +58,7 @@ def run_case(n_occ, n_virt, n_aux, rows, G, wb, cap):
                 else:
                     raise AssertionError("audit mode returned results")
             n = gwl.audit_launch_count() - before
-        print(f"case {n_occ}/{n_virt}/{n_aux} rows={len(rows)} G={G} {prec}: {n} launches checked",
+        print(f"case {n_occ}/{n_virt}/{n_aux} rows={len(rows)} G={G} {prec}/wc {wc}: {n} launches checked",
               flush=True)
 
 
@@ -68,7 +69,7 @@ def run_uhf_case(n_occ, n_virt, n_aux, rows, G):
     g = gwl.Grid.gauss_legendre(G)
     n_mo = inp.n_mo
     for prec in ("fp64", "bf16x3"):
-        c = gwl.Context.from_inputs_uhf(inp, pi_prec=prec)
+        c = gwl.Context.from_inputs_uhf(inp, pi_prec=prec, wc_prec=prec)
         before = gwl.audit_launch_count()
         for call in (lambda: c.dielectric([0.1]), lambda: c.cholesky([0.3]),
                      lambda: c.wtable(g),

@@ -128,3 +128,23 @@ def test_full_setup_rejects_bad_input_before_device_work():
     with pytest.raises(gwl.GWError) as e:
         gwl.Context.full(a.eps, 8, B)
     assert e.value.code == -1 and "sizes" in str(e.value)
+
+
+def test_setup_rejects_unknown_wc_prec_before_device_work():
+    import paper_2107_10423_amd as gwl
+    inp = _small()
+    for bad in (1, 3, -1):   # only FP64 and the BF16x3 form exist for W^c
+        with pytest.raises(gwl.GWError) as e:
+            gwl.Context.from_inputs(inp, wc_prec=bad)
+        assert e.value.code == -1 and "wc_prec" in str(e.value)
+
+
+def test_footprint_counts_the_mixed_contraction_workspace():
+    """The mixed W^c form adds the split R (4 Rp Np bytes) and the split
+    F = L^-1 - I of every grid point of a chunk (4 Np^2 bytes each)."""
+    import paper_2107_10423_amd as gwl
+    n_mo, n_occ, n_aux, n_rows, G = 430, 50, 1120, 10, 64
+    Np, Rp = 1152, 4352
+    base = gwl.footprint(n_mo, n_occ, n_aux, n_rows, 10, G, pi_prec="bf16x3")
+    mixed = gwl.footprint(n_mo, n_occ, n_aux, n_rows, 10, G, pi_prec="bf16x3", wc_prec="bf16x3")
+    assert mixed - base == 4 * Rp * Np + (G + 1) * 4 * Np * Np
