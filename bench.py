@@ -8,9 +8,9 @@ One step = one gw_qp call with the W^c table cache dropped first, i.e. the
 whole hot path: Pi(i xi) build on every grid point, Cholesky of 1 - Pi,
 W^c table, imaginary-axis Sigma quadrature, batched MINRES residues and the
 QP step tree, for all 10 states.  The headline value is the mixed-precision
-(BF16x3 Pi build) path; the plain FP64 path and the FP32 Pi path are timed
-the same way and reported beside it, each with its error against the FP64
-oracle's stored QP energies.
+path (BF16x3 Pi build and BF16x3 W^c contraction); the BF16x3-Pi-only path,
+the plain FP64 path and the FP32 Pi path are timed the same way and reported
+beside it, each with its error against the FP64 oracle's stored QP energies.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -25,6 +25,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+# timed paths: name -> context options (Pi build precision, W^c contraction)
+PATHS = {"bf16x3w": dict(pi_prec="bf16x3", wc_prec="bf16x3"),
+         "bf16x3": dict(pi_prec="bf16x3", wc_prec="fp64"),
+         "fp64": dict(pi_prec="fp64", wc_prec="fp64"),
+         "fp32": dict(pi_prec="fp32", wc_prec="fp64")}
+DTYPES = {"bf16x3w": "bf16x3 Pi and W^c (fp32 acc) + f64", "bf16x3": "bf16x3 Pi (fp32 acc) + f64",
+          "fp64": "f64", "fp32": "f32 Pi + f64"}
 MEV = 1e-3 / 27.211386245988
 
 
@@ -53,12 +60,12 @@ def recorded_traffic(kernel):
     return rec["hbm_fetch_bytes"] + rec["hbm_write_bytes"]
 
 
-def time_path(gwl, inp, states, grid, prec, steps, warmup):
+def time_path(gwl, inp, states, grid, path, steps, warmup):
     import numpy as np
     import torch
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
-    c = gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=1e-10)
+    c = gwl.Context.from_inputs(inp, qp_tol=1e-10, **PATHS[path])
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t_setup)   # host -> HBM upload and setup
     with c:
@@ -94,14 +101,14 @@ def time_path(gwl, inp, states, grid, prec, steps, warmup):
                 stages={k: float(np.mean([s[k] for s in stages])) for k in stages[0]})
 
 
-def time_evgw(gwl, inp, states, grid, prec, reps=2, n_cycles=3):
+def time_evgw(gwl, inp, states, grid, path, reps=2, n_cycles=3):
     """evGW0 and evGW, n_cycles cycles each, on the same workload: wall time
     per call (W^c built inside the call), QP rounds, and the last cycle's
     energies."""
     import numpy as np
     import torch
     out = {}
-    with gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=1e-10) as c:
+    with gwl.Context.from_inputs(inp, qp_tol=1e-10, **PATHS[path]) as c:
         for mode in ("evgw0", "evgw"):
             each, rounds = [], []
             for _ in range(reps + 1):        # the first call warms up
@@ -119,7 +126,7 @@ def time_evgw(gwl, inp, states, grid, prec, reps=2, n_cycles=3):
     return out
 
 
-def time_core_spectrum(gwl, prec, reps=2):
+def time_core_spectrum(gwl, path, reps=2):
     """Every core level of the (H2O)20-shaped input (20 states, ~100 residue
     systems each per QP round), plain and with the cluster initial-guess
     layer; W^c table cached after the first call, so the calls time the QP
@@ -135,9 +142,10 @@ def time_core_spectrum(gwl, prec, reps=2):
     gold = json.load(open(os.path.join(ROOT, "tests", "golden", "h2o20_core.json")))
     out = {"workload": f"(H2O)20-shaped, all {n_core} core levels: n_occ={cfg.shape.n_occ}, "
                        f"n_virt={cfg.shape.n_virt}, N_aux={cfg.shape.n_aux}, "
-                       f"{cfg.grid_points}-point grid, seed {cfg.seed}", "pi_prec": prec}
+                       f"{cfg.grid_points}-point grid, seed {cfg.seed}", "path": path}
     for width in (0.0, 0.5):
-        with gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=1e-10, cluster_width=width) as c:
+        with gwl.Context.from_inputs(inp, qp_tol=1e-10, cluster_width=width,
+                                     **PATHS[path]) as c:
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             E, S, Z, st = c.qp(list(range(n_core)), grid)
@@ -253,7 +261,8 @@ def cpu_baseline(inp, states, G, gold):
 def serve_bench(args):
     """Serving workload: water clusters of k ~ U{1..24} molecules (HOMO-2..LUMO+2,
     64-point grid) through gw_server.  Phase 1: closed loop with 8 requests
-    outstanding, FP64 and BF16x3 -> saturated throughput of each.  Phase 2:
+    outstanding, FP64 and the mixed form (BF16x3 Pi and W^c) -> saturated
+    throughput of each.  Phase 2:
     Poisson arrivals at 0.8 x the FP64 saturated rate, for both paths ->
     throughput, p50 / p99 latency (done - submit) and the per-request energy
     difference between the paths."""
@@ -272,7 +281,7 @@ def serve_bench(args):
     grid = gwl.Grid.gauss_legendre(64)
 
     def run(prec, arrivals, window=None):
-        srv = gwl.Server(grid, pi_prec=prec, n_streams=args.streams)
+        srv = gwl.Server(grid, n_streams=args.streams, **PATHS[prec])
         tickets, E = {}, {}
         lat, done_t, sub_t = [], [], []
         lock = threading.Lock()
@@ -332,22 +341,22 @@ def serve_bench(args):
                     peak_reserved_gb=st["peak_reserved_bytes"] / 2**30)
 
     sat = {}
-    for prec in ("fp64", "bf16x3"):
+    for prec in ("fp64", "bf16x3w"):
         log(f"serve: phase 1, {prec} closed loop (8 outstanding)")
         sat[prec] = run(prec, None, window=8)
     lam = 0.8 * sat["fp64"]["req_per_s"]
     arr = np.array([r["arrival_s"] for r in stream]) / lam
     res = {}
-    for prec in ("fp64", "bf16x3"):
+    for prec in ("fp64", "bf16x3w"):
         log(f"serve: phase 2, {prec}, Poisson arrivals at {lam:.2f} req/s")
         res[prec] = run(prec, arr)
-    dE = max(float(np.max(np.abs(res["bf16x3"]["E"][i] - res["fp64"]["E"][i])))
+    dE = max(float(np.max(np.abs(res["bf16x3w"]["E"][i] - res["fp64"]["E"][i])))
              for i in range(len(stream)))
     pick = lambda r: {k: (round(v, 4) if isinstance(v, float) else v)
                       for k, v in r.items() if k != "E"}
     out = {"metric": "serving: QP energies/s (saturated) and p50/p99 latency at a fixed Poisson "
-                     "rate, BF16x3 vs FP64 Pi",
-           "value": round(sat["bf16x3"]["qp_per_s"], 3), "unit": "QP energies/s",
+                     "rate, mixed (BF16x3 Pi and W^c) vs FP64",
+           "value": round(sat["bf16x3w"]["qp_per_s"], 3), "unit": "QP energies/s",
            "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "config": {"workload": f"{len(stream)} water clusters, k ~ U{{1..{args.kmax}}}, "
                                   "HOMO-2..LUMO+2, 64-point grid",
@@ -356,7 +365,7 @@ def serve_bench(args):
            "poisson": {p: pick(r) for p, r in res.items()},
            "max_abs_dE_mixed_vs_fp64_mev": dE / MEV,
            "mixed_over_fp64_saturated_qp_per_s":
-               round(sat["bf16x3"]["qp_per_s"] / sat["fp64"]["qp_per_s"], 3)}
+               round(sat["bf16x3w"]["qp_per_s"] / sat["fp64"]["qp_per_s"], 3)}
     print(json.dumps(out))
 
 
@@ -370,7 +379,8 @@ def main():
     ap.add_argument("--no-core", action="store_true", help="skip the full core spectrum timing")
     ap.add_argument("--crossover", default=None,
                     help="comma-separated cluster sizes k: time the SD and CD routes instead")
-    ap.add_argument("--only", default=None, help="time only this Pi precision (profiling)")
+    ap.add_argument("--only", default=None, choices=list(PATHS),
+                    help="time only this path (profiling)")
     ap.add_argument("--serve", action="store_true", help="run the serving workload instead")
     ap.add_argument("--requests", type=int, default=128)
     ap.add_argument("--kmax", type=int, default=24)
@@ -420,7 +430,7 @@ def main():
     n_aux, n_ov = cfg.shape.n_aux, cfg.shape.n_ov
     flops = pi_flops(n_aux, n_ov, cfg.grid_points)
 
-    precs = [args.only] if args.only else ["bf16x3", "fp64", "fp32"]
+    precs = [args.only] if args.only else list(PATHS)
     res = {}
     for prec in precs:
         log(f"bench: timing {prec} path, {args.warmup} warmup + {args.steps} steps")
@@ -435,13 +445,14 @@ def main():
 
     head = precs[0]
     h = res[head]
-    # roofline of the Pi build and of the W^c GEMM (one launch each per step
-    # at this size); the dominant one, by measured launch time, heads the line
-    kname = {"bf16x3": "pi_bf16x3", "fp32": "pi_f32", "fp64": "pi_f64"}[head]
+    pi_prec, wc_prec = PATHS[head]["pi_prec"], PATHS[head]["wc_prec"]
+    # roofline of the Pi build and of the W^c contraction (one launch each per
+    # step at this size); the dominant one, by measured launch time, heads the line
+    kname = {"bf16x3": "pi_bf16x3", "fp32": "pi_f32", "fp64": "pi_f64"}[pi_prec]
     tr_pi = recorded_traffic(kname)
     roof_pi = {"kernel": kname, "bound": "mfma", "achieved": round(h["pi_tflops"], 2),
-               "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
-               "frac": round(h["pi_tflops"] / PEAK_TFLOPS[head], 4),
+               "peak": PEAK_TFLOPS[pi_prec], "unit": "TFLOP/s",
+               "frac": round(h["pi_tflops"] / PEAK_TFLOPS[pi_prec], 4),
                "traffic": tr_pi,
                "flops_per_launch": flops, "launch_ms": round(h["pi_ms"], 4),
                "traffic_gb_per_s": (round(tr_pi / (h["pi_ms"] / 1e3) / 1e9, 1) if tr_pi else None),
@@ -452,16 +463,19 @@ def main():
     w_flops = float(n_rows_mo) * n_aux * n_aux * cfg.grid_points
     w_ms = h["stages"]["wtab_ms"]
     w_tf = w_flops / (w_ms / 1e3) / 1e12
-    tr_w = recorded_traffic("w_gemm")
-    roof_w = {"kernel": "w_gemm", "bound": "mfma", "achieved": round(w_tf, 2),
-              "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
-              "frac": round(w_tf / PEAK_TFLOPS["fp64"], 4), "traffic": tr_w,
+    wname = "wc_bf16x3" if wc_prec == "bf16x3" else "w_gemm"
+    tr_w = recorded_traffic(wname)
+    roof_w = {"kernel": wname, "bound": "mfma", "achieved": round(w_tf, 2),
+              "peak": PEAK_TFLOPS[wc_prec], "unit": "TFLOP/s",
+              "frac": round(w_tf / PEAK_TFLOPS[wc_prec], 4), "traffic": tr_w,
               "flops_per_launch": w_flops, "launch_ms": round(w_ms, 4),
               "traffic_gb_per_s": (round(tr_w / (w_ms / 1e3) / 1e9, 1) if tr_w else None),
               "note": "W^c_nm = |L^-1 b|^2 - |b|^2 for every supplied row and m: algorithmic "
                       "flops n_rows n_mo N_aux^2 per grid point (a triangular solve per b) x 64 "
-                      "grid points / the W^c stage time (HIP events around the FP64 GEMM with "
-                      "its squared-norm epilogue and the 10-us reduction kernel after it)"}
+                      "grid points / the W^c stage time (HIP events around the stage: the FP64 "
+                      "GEMM with its squared-norm epilogue, or the F = L^-1 - I split and the "
+                      "BF16x3 contraction with its 2 b^T y + |y|^2 epilogue, then the 10-us "
+                      "reduction kernel)"}
     roof, other = (roof_w, roof_pi) if w_ms > h["pi_ms"] else (roof_pi, roof_w)
     roof = dict(roof)
     roof["other_kernel"] = other
@@ -473,8 +487,7 @@ def main():
         "value": round(h["qp_per_s"], 3), "unit": "QP energies/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(h["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"bf16x3": "bf16x3 Pi (fp32 acc) + f64", "fp64": "f64",
-                  "fp32": "f32 Pi + f64"}[head],
+        "dtype": DTYPES[head],
         "data": "synthetic",
         "config": {"workload": "(H2O)10-shaped G0W0: n_occ=50, n_virt=380, N_aux=1120, "
                                "64-point grid, HOMO-4..LUMO+4 (10 states), seed 2",
@@ -485,7 +498,7 @@ def main():
                       "setup_ms": round(r["setup_ms"], 1),
                       "cached_wtable_qp_per_s": round(len(states) / (r["cached_ms"] / 1e3), 3),
                       "pi_ms": round(r["pi_ms"], 3), "pi_tflops": round(r["pi_tflops"], 2),
-                      "pi_frac_of_peak": round(r["pi_tflops"] / PEAK_TFLOPS[p], 4),
+                      "pi_frac_of_peak": round(r["pi_tflops"] / PEAK_TFLOPS[PATHS[p]["pi_prec"]], 4),
                       "max_err_mev_vs_oracle": r["err_mev"],
                       "stages_ms": {k: round(v, 3) for k, v in r["stages"].items()}}
                   for p, r in res.items()},

@@ -489,8 +489,15 @@ hipError_t split_linv(const double* X, long ldX, long sX, int Np, int G, uint16_
 // with the BF16x3 products and LDS layout of the Pi build.  F_g[p][k] is zero
 // for k > p, so panel J contracts k < 128 (J + 1) only.  b_p at the output
 // positions is re-read from the split R (hi + lo): the same values the last
-// K-steps of the tile have just staged, so the reads hit the cache.  Row tile
-// fastest, then panel, then grid point: the tiles of one F panel run together.
+// K-steps of the tile have just staged, so the reads hit the cache.
+//
+// Tile order: blocks of 8 grid points (each XCD receives a contiguous range of
+// the order, i.e. about one such block), then the panel J, then groups of 8 row
+// tiles, and inside a group of 8 x 8 tiles the grid point fastest.  The 64
+// workgroups an XCD holds at a time then read 8 R panels and 8 F panels, each
+// shared by 8 of them through that XCD's L2, instead of one F panel and 64
+// distinct R panels (which stream the whole of R from outside L2 for every
+// grid point and panel).
 __global__ __launch_bounds__(256) void k_wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl,
                                                    long ldR, const uint16_t* Fh,
                                                    const uint16_t* Fl, long sF, int Np,
@@ -505,9 +512,16 @@ __global__ __launch_bounds__(256) void k_wc_bf16x3(const uint16_t* Rh, const uin
   const int wm = wave >> 1, wn = wave & 1;
   const int total = TM * TN * G;
   const int id = xcd_swizzle_m(blockIdx.x, total);
-  const int I = id % TM;
-  const int J = (id / TM) % TN;
-  const int g = id / (TM * TN);
+  // every block of 8 grid points but the last is full, and likewise every
+  // group of 8 row tiles of a panel, so block offsets are plain products
+  const int gb = id / (8 * TN * TM);
+  const int gs = min(8, G - 8 * gb);
+  const int rem = id - gb * 8 * TN * TM;
+  const int J = rem / (gs * TM);
+  const int rem2 = rem % (gs * TM);
+  const int r8 = rem2 % (8 * gs);
+  const int I = 8 * (rem2 / (8 * gs)) + r8 / gs;
+  const int g = 8 * gb + r8 % gs;
   const uint16_t* Fhg = Fh + (long)g * sF;
   const uint16_t* Flg = Fl + (long)g * sF;
   const int ar0 = I * 128, br0 = J * 128;
