@@ -240,8 +240,10 @@ __device__ __forceinline__ int mfma_row(int p) { return 4 * (p & 3) + (p >> 2); 
 
 // Staging of one 32-wide K-step: the unscaled side is loaded pre-split
 // (bf16 hi and lo, one 16-byte chunk per item, 2 items per thread); the scaled
-// side is loaded as FP32 (4 values per item, 4 items per thread), multiplied
-// by the grid point's scale and split into hi/lo while it is written to LDS.
+// side is loaded as FP32 (4 values per item, 4 items per thread) with its
+// scales, and multiplied and split into hi/lo only when it is written to LDS,
+// after the K-step's MFMAs, so that no arithmetic waits on the loads before
+// the MFMAs are issued.
 // Item maps: A item q -> row q / 4, chunk q % 4; B item q -> row q / 8, chunk
 // (q % 8) / 2, half q % 2.
 __device__ __forceinline__ void a_item(int q, int& row, int& ch) {
@@ -257,7 +259,7 @@ __device__ __forceinline__ void b_item(int q, int& row, int& ch, int& half) {
 __device__ __forceinline__ void bf_gload(const uint16_t* Bhi, const uint16_t* Blo,
                                          const float* B32, const float* S, long ld, int ar0,
                                          int br0, int k0, int t, u32x4 (&rah)[2],
-                                         u32x4 (&ral)[2], f32x4 (&rb)[4]) {
+                                         u32x4 (&ral)[2], f32x4 (&rb)[4], f32x4 (&rs)[4]) {
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     int row, ch;
@@ -270,8 +272,8 @@ __device__ __forceinline__ void bf_gload(const uint16_t* Bhi, const uint16_t* Bl
     int row, ch, half;
     b_item(t + 256 * u, row, ch, half);
     const int k = k0 + 8 * ch + 4 * half;
-    const f32x4 v = *reinterpret_cast<const f32x4*>(B32 + (long)(br0 + row) * ld + k);
-    rb[u] = v * *reinterpret_cast<const f32x4*>(S + k);
+    rb[u] = *reinterpret_cast<const f32x4*>(B32 + (long)(br0 + row) * ld + k);
+    rs[u] = *reinterpret_cast<const f32x4*>(S + k);
   }
 }
 
@@ -290,7 +292,8 @@ __device__ __forceinline__ void split_pair(float x0, float x1, unsigned& hi, uns
 
 __device__ __forceinline__ void bf_lstore(uint16_t* Ah, uint16_t* Al, uint16_t* Bh,
                                           uint16_t* Bl, int t, const u32x4 (&rah)[2],
-                                          const u32x4 (&ral)[2], const f32x4 (&rb)[4]) {
+                                          const u32x4 (&ral)[2], const f32x4 (&rb)[4],
+                                          const f32x4 (&rs)[4]) {
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     int row, ch;
@@ -303,8 +306,9 @@ __device__ __forceinline__ void bf_lstore(uint16_t* Ah, uint16_t* Al, uint16_t* 
     int row, ch, half;
     b_item(t + 256 * u, row, ch, half);
     unsigned h01, l01, h23, l23;
-    split_pair(rb[u].x, rb[u].y, h01, l01);
-    split_pair(rb[u].z, rb[u].w, h23, l23);
+    const f32x4 v = rb[u] * rs[u];
+    split_pair(v.x, v.y, h01, l01);
+    split_pair(v.z, v.w, h23, l23);
     u32x2 hv, lv;
     hv.x = h01;
     hv.y = h23;
@@ -379,16 +383,22 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
   // A side: 128 rows x 32 k bf16 = 512 chunks of 8 (16 B) per array -> 2 per thread
   // B side: 128 rows x 32 k fp32 = 1024 float4 -> 4 per thread
   u32x4 rah[2], ral[2];
-  f32x4 rb[4];
+  f32x4 rb[4], rs[4];
   const int nk = Kp / BKB;
-  bf_gload(Bhi, Blo, B32, S, ld, ar0, br0, 0, t, rah, ral, rb);
-  bf_lstore(Ah[0], Al[0], Bh[0], Bl[0], t, rah, ral, rb);
+  bf_gload(Bhi, Blo, B32, S, ld, ar0, br0, 0, t, rah, ral, rb, rs);
+  bf_lstore(Ah[0], Al[0], Bh[0], Bl[0], t, rah, ral, rb, rs);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) bf_gload(Bhi, Blo, B32, S, ld, ar0, br0, (kt + 1) * BKB, t, rah, ral, rb);
+    // The last K-step reloads its own slab and stores it into the idle buffer
+    // (nothing reads it again): with the load and the store unconditional the
+    // loads are not sunk into a branch after the MFMAs, and the barrier below
+    // keeps the scheduler from moving them there either.
+    const int knext = (kt + 1 < nk ? kt + 1 : kt) * BKB;
+    bf_gload(Bhi, Blo, B32, S, ld, ar0, br0, knext, t, rah, ral, rb, rs);
+    __builtin_amdgcn_sched_barrier(0);
     bf_mfma_step(Ah[cur], Al[cur], Bh[cur], Bl[cur], lane, wm, wn, acc);
-    if (kt + 1 < nk) bf_lstore(Ah[cur ^ 1], Al[cur ^ 1], Bh[cur ^ 1], Bl[cur ^ 1], t, rah, ral, rb);
+    bf_lstore(Ah[cur ^ 1], Al[cur ^ 1], Bh[cur ^ 1], Bl[cur ^ 1], t, rah, ral, rb, rs);
     __syncthreads();
   }
   double* Ag = A + (long)g * sA;
@@ -565,9 +575,10 @@ __global__ __launch_bounds__(256) void k_wc_bf16x3(const uint16_t* Rh, const uin
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * BKB);
+    gload((kt + 1 < nk ? kt + 1 : kt) * BKB);   // unconditional, as in the Pi build
+    __builtin_amdgcn_sched_barrier(0);
     bf_mfma_step(Ah[cur], Al[cur], Bh[cur], Bl[cur], lane, wm, wn, acc);
-    if (kt + 1 < nk) lstore(cur ^ 1);
+    lstore(cur ^ 1);
     __syncthreads();
   }
   // accumulator element (4 (l / 16) + r, l % 16) of block (i, j): R row
