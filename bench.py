@@ -95,7 +95,8 @@ def time_path(gwl, inp, states, grid, path, steps, warmup):
             cached.append(1e3 * (time.perf_counter() - t1))
     E = out[0]
     return dict(E=E, Z=out[2], status=out[3], wall_s=wall, ms_per_step=1e3 * wall / steps,
-                median_ms=float(np.median(each)), setup_ms=setup_ms,
+                median_ms=float(np.median(each)), p99_ms=float(np.percentile(each, 99)),
+                setup_ms=setup_ms,
                 cached_ms=float(np.median(cached)),
                 pi_ms=float(np.mean(pi_ms)), total_ms=float(np.mean(tot_ms)),
                 stages={k: float(np.mean([s[k] for s in stages])) for k in stages[0]})
@@ -493,6 +494,11 @@ def main():
                                "64-point grid, HOMO-4..LUMO+4 (10 states), seed 2",
                    "n_occ": 50, "n_virt": 380, "n_aux": 1120, "grid_points": 64, "states": 10},
         "roofline": roof,
+        # one molecule's request latency on an idle GPU (W^c table rebuilt, all
+        # 10 states): the timed steps' distribution; loaded p50/p99 latency is
+        # the --serve line's
+        "latency_ms": {"p50": round(h["median_ms"], 3), "p99": round(h["p99_ms"], 3),
+                       "samples": args.steps},
         "paths": {p: {"qp_per_s": round(r["qp_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
                       "median_ms_per_step": round(r["median_ms"], 3),
                       "setup_ms": round(r["setup_ms"], 1),
