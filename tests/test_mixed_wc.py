@@ -147,3 +147,27 @@ def test_serving_results_alone_and_in_the_mix():
             np.testing.assert_allclose(E, E0, rtol=0, atol=1e-9)
     finally:
         srv.close()
+
+
+@pytest.mark.parametrize("n_occ,n_virt,n_aux,rows", [
+    (1, 1, 1, (0, 1)),          # one auxiliary function: a single padded tile
+    (3, 20, 64, (1, 2)),        # N_aux below one 128-wide panel
+    (2, 3, 130, (1,)),          # N_aux just past a panel (second panel of 2 rows)
+    (11, 60, 300, tuple(range(0, 71))),   # 71 x 71 rows: 40 row tiles, 5 groups of 8
+])
+def test_wtable_edge_shapes(n_occ, n_virt, n_aux, rows):
+    """FP64 Pi, so that only the contraction's error is measured (with BF16x3
+    Pi the N_aux = 130 case, whose W^c is 0.97 of |b|^2, amplifies the Pi
+    error to 6e-5).  Bound: with a single auxiliary function W^c is one
+    product (2 b + y) y, y = F b; y carries up to 2 x 2^-17 + 2^-18 = 1.9e-5
+    relative error and 2 b + y up to 2 x 2^-17 (|2 b| <= 2 |2 b + y| since
+    -1 < F <= 0), so 3.4e-5; the bound is 4e-5 (measured 1.0e-5)."""
+    shape = gwgen.custom_shape(n_occ, n_virt, n_aux, n_core=1 if n_occ > 1 else 0)
+    inp = gwgen.make_inputs(shape, 1, rows)
+    xi = np.array([1e-3, 0.7, 40.0])
+    g = gwl().Grid(xi, np.ones_like(xi))
+    ref = cd.w_table(inp.eps, inp.n_occ, inp.B_ov, inp.B_rows, xi)
+    with gwl().Context.from_inputs(inp, wc_prec="bf16x3") as c:
+        got = c.wtable(g)
+    rel = np.abs(got - ref) / np.abs(ref)
+    assert rel.max() <= 4e-5, rel.max()
