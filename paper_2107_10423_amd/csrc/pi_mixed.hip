@@ -508,15 +508,22 @@ hipError_t split_linv(const double* X, long ldX, long sX, int Np, int G, uint16_
 // shared by 8 of them through that XCD's L2, instead of one F panel and 64
 // distinct R panels (which stream the whole of R from outside L2 for every
 // grid point and panel).
+//
+// One LDS slab set (34 KB with the reduction buffer) instead of the Pi build's
+// two: a K-step reads the slabs, waits at a barrier, overwrites them with the
+// prefetched next slabs and waits again.  At 166 VGPRs three workgroups then
+// share a CU (the double-buffered 66 KB form fits two), and the third
+// workgroup's MFMAs cover the extra barrier: 1.26 ms instead of 1.46 ms at
+// (H2O)10.
 __global__ __launch_bounds__(256) void k_wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl,
                                                    long ldR, const uint16_t* Fh,
                                                    const uint16_t* Fl, long sF, int Np,
                                                    double* part, long ldp, long sP, int TM,
                                                    int TN, int G) {
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][SLAB];
-  __shared__ __attribute__((aligned(16))) uint16_t Al[2][SLAB];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][SLAB];
-  __shared__ __attribute__((aligned(16))) uint16_t Bl[2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[1][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Al[1][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[1][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[1][SLAB];
   __shared__ double red[2][128];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -574,12 +581,12 @@ __global__ __launch_bounds__(256) void k_wc_bf16x3(const uint16_t* Rh, const uin
   lstore(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
     gload((kt + 1 < nk ? kt + 1 : kt) * BKB);   // unconditional, as in the Pi build
     __builtin_amdgcn_sched_barrier(0);
-    bf_mfma_step(Ah[cur], Al[cur], Bh[cur], Bl[cur], lane, wm, wn, acc);
-    lstore(cur ^ 1);
-    __syncthreads();
+    bf_mfma_step(Ah[0], Al[0], Bh[0], Bl[0], lane, wm, wn, acc);
+    __syncthreads();   // every wave has read its fragments of this K-step
+    lstore(0);
+    __syncthreads();   // the next K-step's slabs are in place
   }
   // accumulator element (4 (l / 16) + r, l % 16) of block (i, j): R row
   // ar0 + wm 64 + 16 i + mfma_row(4 (l / 16) + r), column br0 + wn 64 + 16 j +
