@@ -241,9 +241,7 @@ __device__ __forceinline__ int mfma_row(int p) { return 4 * (p & 3) + (p >> 2); 
 // Staging of one 32-wide K-step: the unscaled side is loaded pre-split
 // (bf16 hi and lo, one 16-byte chunk per item, 2 items per thread); the scaled
 // side is loaded as FP32 (4 values per item, 4 items per thread) with its
-// scales, and multiplied and split into hi/lo only when it is written to LDS,
-// after the K-step's MFMAs, so that no arithmetic waits on the loads before
-// the MFMAs are issued.
+// scales, and multiplied and split into hi/lo when it is written to LDS.
 // Item maps: A item q -> row q / 4, chunk q % 4; B item q -> row q / 8, chunk
 // (q % 8) / 2, half q % 2.
 __device__ __forceinline__ void a_item(int q, int& row, int& ch) {
@@ -321,13 +319,15 @@ __device__ __forceinline__ void bf_lstore(uint16_t* Ah, uint16_t* Al, uint16_t* 
 
 // One K-step of the 64 x 64 wave tile: 4 x 4 blocks, three bf16 MFMAs each
 // (lo x hi, hi x lo, hi x hi; the lo x lo term is below the split's error).
+// Operand fragments: lane l reads MFMA row l % 16 (physical row
+// mfma_row(l % 16) of the block), k = 8 (l / 16) .. +7.  The A fragments are
+// read first, then the B fragments one block column at a time with its 12
+// MFMAs, so that only 8 B-fragment registers are live at once.
 __device__ __forceinline__ void bf_mfma_step(const uint16_t* Ah, const uint16_t* Al,
-                                             const uint16_t* Bh, const uint16_t* Bl, int lane,
-                                             int wm, int wn, f4 (&acc)[4][4]) {
-  // operand fragments: lane l reads MFMA row l % 16 (physical row
-  // mfma_row(l % 16) of the block), k = 8 (l / 16) .. +7
+                                                  const uint16_t* Bh, const uint16_t* Bl,
+                                                  int lane, int wm, int wn, f4 (&acc)[4][4]) {
   const int ko = 8 * ((lane >> 4) * 128 + ((lane & 15) ^ (lane >> 4)));
-  s8 ah[4], al[4], bh[4], bl[4];
+  s8 ah[4], al[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     const int o = ko + (wm * 4 + i) * 128;
@@ -337,34 +337,36 @@ __device__ __forceinline__ void bf_mfma_step(const uint16_t* Ah, const uint16_t*
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int o = ko + (wn * 4 + j) * 128;
-    bh[j] = *reinterpret_cast<const s8*>(&Bh[o]);
-    bl[j] = *reinterpret_cast<const s8*>(&Bl[o]);
-  }
+    const s8 bh = *reinterpret_cast<const s8*>(&Bh[o]);
+    const s8 bl = *reinterpret_cast<const s8*>(&Bl[o]);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int i = 0; i < 4; ++i) {
       acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-          __builtin_bit_cast(bf8, al[i]), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+          __builtin_bit_cast(bf8, al[i]), __builtin_bit_cast(bf8, bh), acc[i][j], 0, 0, 0);
       acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-          __builtin_bit_cast(bf8, ah[i]), __builtin_bit_cast(bf8, bl[j]), acc[i][j], 0, 0, 0);
+          __builtin_bit_cast(bf8, ah[i]), __builtin_bit_cast(bf8, bl), acc[i][j], 0, 0, 0);
       acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-          __builtin_bit_cast(bf8, ah[i]), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+          __builtin_bit_cast(bf8, ah[i]), __builtin_bit_cast(bf8, bh), acc[i][j], 0, 0, 0);
     }
+  }
 }
 
 // 128 x 128 tile per workgroup (2 x 2 waves of 64 x 64), FP32 accumulation
-// over the whole K; global loads run one K-step ahead of the MFMAs and LDS is
-// double-buffered.  (Two register stages would cost the second workgroup per
-// CU, which measures slower.)
+// over the whole K.  One LDS slab set (32 KB): a K-step issues its MFMAs from
+// LDS, then loads the next slabs into registers, waits at a barrier until
+// every wave has read its fragments, stores the slabs and waits again.  No
+// staging register is live across the MFMAs, so the kernel takes 144 VGPRs
+// and three workgroups share a CU, covering each other's load latency and
+// barriers (5.36 ms at (H2O)10, against 5.8 ms for a double-buffered form
+// that loads a K-step ahead at 197 VGPRs and two workgroups per CU).
 __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const uint16_t* Blo,
                                                    long ld, const float* B32,
                                                    const float* scale, long sS, double* A,
                                                    long ldA, long sA, int T, int Kp, int G) {
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][SLAB];
-  __shared__ __attribute__((aligned(16))) uint16_t Al[2][SLAB];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][SLAB];
-  __shared__ __attribute__((aligned(16))) uint16_t Bl[2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[1][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Al[1][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[1][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[1][SLAB];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int total = T * (T + 1) / 2 * G;
@@ -389,17 +391,16 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
   bf_lstore(Ah[0], Al[0], Bh[0], Bl[0], t, rah, ral, rb, rs);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    // The last K-step reloads its own slab and stores it into the idle buffer
-    // (nothing reads it again): with the load and the store unconditional the
-    // loads are not sunk into a branch after the MFMAs, and the barrier below
-    // keeps the scheduler from moving them there either.
+    bf_mfma_step(Ah[0], Al[0], Bh[0], Bl[0], lane, wm, wn, acc);
+    // loads after the MFMAs (the scheduling barrier keeps them there, out of
+    // the fragment registers' live range); the last K-step reloads its own
+    // slab, so that loads and stores stay unconditional
+    __builtin_amdgcn_sched_barrier(0);
     const int knext = (kt + 1 < nk ? kt + 1 : kt) * BKB;
     bf_gload(Bhi, Blo, B32, S, ld, ar0, br0, knext, t, rah, ral, rb, rs);
-    __builtin_amdgcn_sched_barrier(0);
-    bf_mfma_step(Ah[cur], Al[cur], Bh[cur], Bl[cur], lane, wm, wn, acc);
-    bf_lstore(Ah[cur ^ 1], Al[cur ^ 1], Bh[cur ^ 1], Bl[cur ^ 1], t, rah, ral, rb, rs);
-    __syncthreads();
+    __syncthreads();   // every wave has read its fragments of this K-step
+    bf_lstore(Ah[0], Al[0], Bh[0], Bl[0], t, rah, ral, rb, rs);
+    __syncthreads();   // the next K-step's slabs are in place
   }
   double* Ag = A + (long)g * sA;
 #pragma unroll
@@ -509,13 +510,11 @@ hipError_t split_linv(const double* X, long ldX, long sX, int Np, int G, uint16_
 // distinct R panels (which stream the whole of R from outside L2 for every
 // grid point and panel).
 //
-// One LDS slab set (34 KB with the reduction buffer) instead of the Pi build's
-// two: a K-step reads the slabs, waits at a barrier, overwrites them with the
-// prefetched next slabs and waits again.  At 166 VGPRs three workgroups then
-// share a CU (the double-buffered 66 KB form fits two), and the third
-// workgroup's MFMAs cover the extra barrier: 1.26 ms instead of 1.46 ms at
-// (H2O)10.
-__global__ __launch_bounds__(256) void k_wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl,
+// The K-loop is the Pi build's (one LDS slab set, 34 KB with the reduction
+// buffer; loads after the MFMAs; two barriers per K-step).  At 126 VGPRs four
+// workgroups share a CU: 1.25 ms at (H2O)10, against 1.46 ms for the
+// double-buffered form with loads a K-step ahead (two workgroups per CU).
+__global__ __launch_bounds__(256, 4) void k_wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl,
                                                    long ldR, const uint16_t* Fh,
                                                    const uint16_t* Fl, long sF, int Np,
                                                    double* part, long ldp, long sP, int TM,
@@ -581,9 +580,9 @@ __global__ __launch_bounds__(256) void k_wc_bf16x3(const uint16_t* Rh, const uin
   lstore(0);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
-    gload((kt + 1 < nk ? kt + 1 : kt) * BKB);   // unconditional, as in the Pi build
-    __builtin_amdgcn_sched_barrier(0);
     bf_mfma_step(Ah[0], Al[0], Bh[0], Bl[0], lane, wm, wn, acc);
+    __builtin_amdgcn_sched_barrier(0);
+    gload((kt + 1 < nk ? kt + 1 : kt) * BKB);   // unconditional, as in the Pi build
     __syncthreads();   // every wave has read its fragments of this K-step
     lstore(0);
     __syncthreads();   // the next K-step's slabs are in place
