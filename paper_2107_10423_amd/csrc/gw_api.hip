@@ -565,11 +565,11 @@ int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
       a.K = k; a.row0 = k; a.col0 = k; a.k0 = 0; a.kb0 = 0;
       a.klo_from = Np;
       a.map = MAP_FULL;
-      a.tiles_m = Np / 128; a.tiles_n = 1;
+      a.tiles_m = Np / 64; a.tiles_n = 1;
       a.M = Np; a.N = PANEL;
       a.n_tiles = a.tiles_m; a.batch = G; a.splitk = 1;
       a.alpha = -1.0; a.beta = 1.0;
-      RCHK(run_gemm(c, a, 0, KC, KC, EPI_AXPBY));
+      RCHK(run_gemm(c, a, 2, KC, KC, EPI_AXPBY));
     }
     HIPCHK(chol_diag(c->d_work, ldA, per_g, c->d_Linv, k, G, c->d_info, c->ext(c->d_work, 8),
                      c->ext(c->d_Linv, 8), c->ext(c->d_info, 4), c->st));
