@@ -503,12 +503,12 @@ hipError_t split_linv(const double* X, long ldX, long sX, int Np, int G, uint16_
 // K-steps of the tile have just staged, so the reads hit the cache.
 //
 // Tile order: blocks of 8 grid points (each XCD receives a contiguous range of
-// the order, i.e. about one such block), then the panel J, then groups of 8 row
-// tiles, and inside a group of 8 x 8 tiles the grid point fastest.  The 64
-// workgroups an XCD holds at a time then read 8 R panels and 8 F panels, each
-// shared by 8 of them through that XCD's L2, instead of one F panel and 64
-// distinct R panels (which stream the whole of R from outside L2 for every
-// grid point and panel).
+// the order, i.e. about one such block), then the panel J, then groups of 16
+// row tiles, and inside a group of 16 x 8 tiles the grid point fastest.  The
+// 128 workgroups an XCD holds at a time (four per CU) then read 16 R panels
+// and 8 F panels, shared by 8 and 16 of them through that XCD's L2, instead
+// of one F panel and 128 distinct R panels (which stream the whole of R from
+// outside L2 for every grid point and panel).
 //
 // The K-loop is the Pi build's (one LDS slab set, 34 KB with the reduction
 // buffer; loads after the MFMAs; two barriers per K-step).  At 126 VGPRs four
@@ -529,15 +529,15 @@ __global__ __launch_bounds__(256, 4) void k_wc_bf16x3(const uint16_t* Rh, const 
   const int total = TM * TN * G;
   const int id = xcd_swizzle_m(blockIdx.x, total);
   // every block of 8 grid points but the last is full, and likewise every
-  // group of 8 row tiles of a panel, so block offsets are plain products
+  // group of 16 row tiles of a panel, so block offsets are plain products
   const int gb = id / (8 * TN * TM);
   const int gs = min(8, G - 8 * gb);
   const int rem = id - gb * 8 * TN * TM;
   const int J = rem / (gs * TM);
   const int rem2 = rem % (gs * TM);
-  const int r8 = rem2 % (8 * gs);
-  const int I = 8 * (rem2 / (8 * gs)) + r8 / gs;
-  const int g = 8 * gb + r8 % gs;
+  const int r16 = rem2 % (16 * gs);
+  const int I = 16 * (rem2 / (16 * gs)) + r16 / gs;
+  const int g = 8 * gb + r16 % gs;
   const uint16_t* Fhg = Fh + (long)g * sF;
   const uint16_t* Flg = Fl + (long)g * sF;
   const int ar0 = I * 128, br0 = J * 128;
