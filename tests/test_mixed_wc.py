@@ -171,3 +171,26 @@ def test_wtable_edge_shapes(n_occ, n_virt, n_aux, rows):
         got = c.wtable(g)
     rel = np.abs(got - ref) / np.abs(ref)
     assert rel.max() <= 4e-5, rel.max()
+
+
+def test_full_tensor_context():
+    """gw_setup_full (every state's rows resident) with the mixed contraction:
+    the requested states' energies equal those of a row-supplied context
+    (each W^c entry is contracted in the same order whatever other rows the
+    context holds), and a state outside that context is within 1 meV of the
+    oracle."""
+    inp = gwgen.make_config("monomer")
+    B = gwgen.full_B(inp.shape, inp.seed)
+    g = gwl().Grid.gauss_legendre(64)
+    with gwl().Context.from_inputs(inp, wc_prec="bf16x3", qp_tol=1e-12) as c:
+        E0, _, _, _ = c.qp([4, 5], g)
+    with gwl().Context.full(inp.eps, inp.n_occ, B, wc_prec="bf16x3", qp_tol=1e-12) as c:
+        E1, _, _, _ = c.qp([4, 5], g)
+        E2, _, _, _ = c.qp([3, 6], g)
+    np.testing.assert_allclose(E1, E0, rtol=1e-12, atol=0)
+    other = gwgen.make_config("monomer", states=[3, 6])
+    xi, z = grid.gauss_legendre(64)
+    ref = qp.solve(other.eps, other.n_occ, other.B_ov, other.row_ids, other.B_rows, [3, 6], xi,
+                   z, tol=1e-12)
+    for j, r in enumerate(ref):
+        assert abs(E2[j] - r["E"]) <= MEV
