@@ -853,7 +853,8 @@ int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long l
     // split over N_aux for parallelism: partials, then a deterministic sum + scale
     a.C = c->mr.part; a.ldc = c->Kp; a.splitk = c->mr_splitk1; a.sSplit = (long)kp * c->Kp;
     RCHK(run_gemm(c, a, 3, KC, KM, EPI_STORE));
-    HIPCHK(minres_scale_sum(c->mr, c->mr_splitk1, c->d_D, c->ext(c->d_D, 8), c->st));
+    HIPCHK(minres_scale_sum(c->mr, c->mr_splitk1, c->d_D, c->ext(c->d_D, 8), mask,
+                            c->ext(mask, sizeof(int)), c->st));
     return 0;
   }
   RCHK(run_gemm(c, a, 3, KC, KM, epi));
@@ -905,7 +906,7 @@ int minres_iteration(gw_ctx* c, int kp, int itn) {
   const int* mask = itn > 1 ? m.blk + (par ^ 1) * (kp / 16) : nullptr;
   RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp, mask));
   RCHK(backproject_pass(c, kp, mask));
-  HIPCHK(minres_apply(m, c->mr_splitk, c->st));
+  HIPCHK(minres_apply(m, c->mr_splitk, mask, c->ext(mask, sizeof(int)), c->st));
   if (m.pre) {
     HIPCHK(minres_pre_step_a(m, par, c->st));
     RCHK(precond_pass(c, m.r2, kp, mask));
@@ -1043,7 +1044,7 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   if (n_warm > 0) {
     RCHK(matvec_pass(c, m.v, kp, EPI_RES_SCALE, m.V, c->Kp));
     RCHK(backproject_pass(c, kp));
-    HIPCHK(minres_apply(m, c->mr_splitk, c->st));
+    HIPCHK(minres_apply(m, c->mr_splitk, nullptr, 0, c->st));
   }
   if (m.pre) {
     // preconditioned start: r = b - A x0, |b| and beta1 in the M^-1 norm

@@ -196,10 +196,13 @@ hipError_t minres_init(MinresBufs& m, const double* rhs_base, const int* rhs_idx
 // x_j += x0_j, and xcache[rhs_idx_j] = x_j
 hipError_t minres_finalize(MinresBufs& m, double* xcache, const int* rhs_idx,
                            const int* host_idx, int n_rows, long n_cache, hipStream_t st);
-// V[j][ia] = D/(D^2 - w_j^2) * sum_s part[s][j][ia] (split partials of B_ov^T v)
-hipError_t minres_scale_sum(MinresBufs& m, int splits, const double* D, long nD, hipStream_t st);
-// y = v + 4 sum_s part[s] (the operator applied to v), one thread per element
-hipError_t minres_apply(MinresBufs& m, int splitk, hipStream_t st);
+// V[j][ia] = D/(D^2 - w_j^2) * sum_s part[s][j][ia] (split partials of B_ov^T v);
+// mask (nullable): per 16-system block, 0 where the block's systems are skipped
+hipError_t minres_scale_sum(MinresBufs& m, int splits, const double* D, long nD,
+                            const int* mask, long nMask, hipStream_t st);
+// y = v + 4 sum_s part[s] (the operator applied to v), one block row per system;
+// mask as for minres_scale_sum
+hipError_t minres_apply(MinresBufs& m, int splitk, const int* mask, long nMask, hipStream_t st);
 // one MINRES step per unconverged system; par = global iteration parity
 hipError_t minres_finish_step(MinresBufs& m, int par, hipStream_t st);
 // Preconditioned variants (m.pre set).  Start: pre_init_a (r = b - A x0, b kept

@@ -145,51 +145,59 @@ hipError_t minres_finalize(MinresBufs& m, double* xcache, const int* rhs_idx,
 }
 
 // V[j][ia] = D_ia/(D_ia^2 - w_j^2) sum_s part[s][j][ia]: finishes the first
-// operator pass from its partials over N_aux, in a fixed order.
-__global__ void k_minres_scale_sum(MinresBufs m, int splits, const double* D) {
+// operator pass from its partials over N_aux, in a fixed order.  One block row
+// per system; with a mask, systems of 16-system blocks flagged converged are
+// skipped (the second pass does not multiply their rows of V).
+__global__ void k_minres_scale_sum(MinresBufs m, int splits, const double* D, const int* mask) {
+  const int j = blockIdx.y;
+  if (mask && mask[j >> 4] == 0) return;
   const long n = (long)m.kp * m.Kp;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long)gridDim.x * blockDim.x) {
+  const double w = m.omega[j];
+  for (int ia = blockIdx.x * blockDim.x + threadIdx.x; ia < m.Kp; ia += gridDim.x * blockDim.x) {
+    const long i = (long)j * m.Kp + ia;
     double acc = 0.0;
     for (int s = 0; s < splits; ++s) acc += m.part[s * n + i];
-    const int j = (int)(i / m.Kp), ia = (int)(i % m.Kp);
-    const double w = m.omega[j], d = D[ia];
+    const double d = D[ia];
     m.V[i] = acc * (d / (d * d - w * w));
   }
 }
 
-hipError_t minres_scale_sum(MinresBufs& m, int splits, const double* D, long nD, hipStream_t st) {
+hipError_t minres_scale_sum(MinresBufs& m, int splits, const double* D, long nD,
+                            const int* mask, long nMask, hipStream_t st) {
   if (hipError_t e = check_bufs(m, "minres_scale_sum")) return e;
   GW_GUARD("minres_scale_sum", "part", (long)splits * m.kp * m.Kp - 1, m.n_part);
   GW_GUARD("minres_scale_sum", "V", (long)m.kp * m.Kp - 1, m.n_V);
   GW_GUARD("minres_scale_sum", "D", m.Kp - 1, nD);
+  if (mask) GW_GUARD("minres_scale_sum", "mask", (m.kp - 1) / 16, nMask);
   GW_AUDIT_RETURN();
-  const long n = (long)m.kp * m.Kp;
-  int blocks = (int)std::min<long>((n + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_minres_scale_sum, dim3(blocks), dim3(256), 0, st, m, splits, D);
+  const int bx = std::min((m.Kp + 255) / 256, 64);
+  hipLaunchKernelGGL(k_minres_scale_sum, dim3(bx, m.kp), dim3(256), 0, st, m, splits, D, mask);
   return hipGetLastError();
 }
 
 // y = v + 4 sum_s part[s] for every element of every system: the matrix-vector
-// product (1 - Pi(w)) v finished from the split-K partials of B_ov V^T.
-__global__ void k_minres_apply(MinresBufs m, int splitk) {
-  const long n = (long)m.kp * m.Np;
-  const long slab = n;
-  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (long)gridDim.x * blockDim.x) {
+// product (1 - Pi(w)) v finished from the split-K partials of B_ov V^T.  One
+// block row per system; with a mask, systems of converged 16-system blocks
+// are skipped (their step is skipped too).
+__global__ void k_minres_apply(MinresBufs m, int splitk, const int* mask) {
+  const int j = blockIdx.y;
+  if (mask && mask[j >> 4] == 0) return;
+  const long slab = (long)m.kp * m.Np;
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m.Np; p += gridDim.x * blockDim.x) {
+    const long i = (long)j * m.Np + p;
     double av = 0.0;
     for (int s = 0; s < splitk; ++s) av += m.part[s * slab + i];
     m.y[i] = m.v[i] + 4.0 * av;
   }
 }
 
-hipError_t minres_apply(MinresBufs& m, int splitk, hipStream_t st) {
+hipError_t minres_apply(MinresBufs& m, int splitk, const int* mask, long nMask, hipStream_t st) {
   if (hipError_t e = check_bufs(m, "minres_apply")) return e;
   GW_GUARD("minres_apply", "part", (long)splitk * m.kp * m.Np - 1, m.n_part);
+  if (mask) GW_GUARD("minres_apply", "mask", (m.kp - 1) / 16, nMask);
   GW_AUDIT_RETURN();
-  const long n = (long)m.kp * m.Np;
-  int blocks = (int)std::min<long>((n + 255) / 256, 2048);
-  hipLaunchKernelGGL(k_minres_apply, dim3(blocks), dim3(256), 0, st, m, splitk);
+  const int bx = (m.Np + 255) / 256;
+  hipLaunchKernelGGL(k_minres_apply, dim3(bx, m.kp), dim3(256), 0, st, m, splitk, mask);
   return hipGetLastError();
 }
 
