@@ -137,7 +137,7 @@ void minres_splits(int kp, int Np, int Kp, int* splitk, int* splitk1) {
   // K chunks of about `chunk2` (pass 2) and `chunk1` (pass 1) elements bound the
   // latency chain of each workgroup; GW_TUNE_MINRES="chunk1,chunk2" replaces
   // the rule below by those chunks
-  int chunk1 = 288, chunk2 = 512;
+  int chunk1 = 384, chunk2 = 512;
   const int t2 = (kp / 64) * (Np / 128);
   if (const char* e = getenv("GW_TUNE_MINRES")) {
     if (sscanf(e, "%d,%d", &chunk1, &chunk2) == 2) {
