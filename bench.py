@@ -456,6 +456,9 @@ def main():
                "frac": round(h["pi_tflops"] / PEAK_TFLOPS[pi_prec], 4),
                "traffic": tr_pi,
                "flops_per_launch": flops, "launch_ms": round(h["pi_ms"], 4),
+               # BF16x3 issues three bf16 products per algorithmic one
+               "issued_frac": round(h["pi_tflops"] * (3 if pi_prec == "bf16x3" else 1)
+                                    / PEAK_TFLOPS[pi_prec], 4),
                "traffic_gb_per_s": (round(tr_pi / (h["pi_ms"] / 1e3) / 1e9, 1) if tr_pi else None),
                "note": "achieved = algorithmic flops N_aux(N_aux+1)N_ov per grid point x 64 grid "
                        "points / launch time (HIP events on the context stream); BF16x3 issues 3 "
@@ -470,6 +473,8 @@ def main():
               "peak": PEAK_TFLOPS[wc_prec], "unit": "TFLOP/s",
               "frac": round(w_tf / PEAK_TFLOPS[wc_prec], 4), "traffic": tr_w,
               "flops_per_launch": w_flops, "launch_ms": round(w_ms, 4),
+              "issued_frac": round(w_tf * (3 if wc_prec == "bf16x3" else 1)
+                                   / PEAK_TFLOPS[wc_prec], 4),
               "traffic_gb_per_s": (round(tr_w / (w_ms / 1e3) / 1e9, 1) if tr_w else None),
               "note": "W^c_nm = |L^-1 b|^2 - |b|^2 for every supplied row and m: algorithmic "
                       "flops n_rows n_mo N_aux^2 per grid point (a triangular solve per b) x 64 "
