@@ -55,10 +55,13 @@ def dpi_real_quadratic(eps, n_occ, B_ov, w, x):
 
 
 def screened_from_pi(Pi, b):
-    """W^c = b^T [(1 - Pi)^-1 - 1] b with an explicit inverse.  b: [..., N_aux]."""
+    """W^c = b^T [(1 - Pi)^-1 - 1] b with an explicit inverse.  b: [..., N_aux].
+
+    The quadratic form is the row sum of (b X) * b: one matrix product with
+    X = (1 - Pi)^-1 - 1, then a dot product of each row with its own b."""
     n = Pi.shape[0]
     X = np.linalg.inv(np.eye(n) - Pi) - np.eye(n)
-    return np.einsum("...p,pq,...q->...", b, X, b)
+    return np.sum((b @ X) * b, axis=-1)
 
 
 def w_table(eps, n_occ, B_ov, B_rows, xi):
