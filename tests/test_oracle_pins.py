@@ -289,6 +289,30 @@ def test_step_tree_branches_on_model_functions():
     assert np.all(np.abs(steps[:kinds.index("golden")]) <= 0.1 + 1e-15)
 
 
+def test_step_tree_iteration_cap_returns_last_evaluated_point():
+    """Reading of the paper's iterative QP solution at an iteration cap (the
+    paper gives none): the answer is the last point at which f was evaluated,
+    with f and Z from that evaluation, flagged.  Hand-computed sequence for
+    f(w) = -20 (w - 0.47) from w = 0 (Z = 0.05 < 0.1, no bracket, so every
+    step is a scaled residual alpha f with alpha = min(0.1, 0.1/|f|), i.e.
+    exactly 0.1 Ha while |f| > 1): evaluations at 0, 0.1, 0.2; the step to 0.3
+    computed after the third is not taken."""
+    f = lambda w: (-20.0 * (w - 0.47), -20.0)
+    r = qp.step_tree(f, 0.0, tol=1e-10, max_iter=3)
+    assert [t[0] for t in r["trace"]] == pytest.approx([0.0, 0.1, 0.2], abs=1e-15)
+    assert r["E"] == pytest.approx(0.2, abs=1e-15)
+    assert r["f"] == pytest.approx(5.4, abs=1e-13)
+    assert r["Z"] == pytest.approx(0.05, abs=1e-15)
+    assert r["status"] == qp.STATUS_MAXITER | qp.STATUS_SMALL_Z and r["iters"] == 3
+    # a cap of one evaluation returns the starting point itself
+    r = qp.step_tree(f, 0.0, tol=1e-10, max_iter=1)
+    assert r["E"] == 0.0 and r["f"] == pytest.approx(9.4, abs=1e-13)
+    # Newton (Z = 1) converges on its second evaluation; with the cap there
+    # the converged point is returned without the cap flag
+    r = qp.step_tree(lambda w: (-(w - 0.3), -1.0), 0.0, tol=1e-12, max_iter=3)
+    assert r["status"] == 0 and r["E"] == pytest.approx(0.3, abs=1e-15)
+
+
 def test_bracket_rules():
     # proper sign change (f > 0 on the left end): a root bracket, s = end of smaller |f|
     assert qp._make_bracket(0.1, 0.5, 0.3, -0.2) == (0.3, -0.2, 0.1, 0.5)
