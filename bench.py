@@ -1,18 +1,23 @@
 """Benchmark of the contour-deformation G0W0 hot path on one MI355X.
 
-Workload: the (H2O)10-shaped G0W0 problem (n_occ=50, n_virt=380, N_aux=1120,
-64-point modified Gauss-Legendre grid, QP energies of HOMO-4..LUMO+4),
-synthetic seeded inputs resident in HBM before timing starts.
+Headline workload: the (H2O)30-shaped G0W0 problem (n_occ=150, n_virt=1140,
+N_aux=3360, 128-point modified Gauss-Legendre grid, QP energies of
+HOMO-9..LUMO+9), synthetic seeded inputs resident in HBM before timing starts.
 
 One step = one gw_qp call with the W^c table cache dropped first, i.e. the
 whole hot path: Pi(i xi) build on every grid point, Cholesky of 1 - Pi,
 W^c table, imaginary-axis Sigma quadrature, batched MINRES residues and the
-QP step tree, for all 10 states.  The headline value is the mixed-precision
-path (BF16x3 Pi build and BF16x3 W^c contraction); the BF16x3-Pi-only path,
-the plain FP64 path and the FP32 Pi path are timed the same way and reported
-beside it, each with its error against the FP64 oracle's stored QP energies.
+QP step tree, for all 20 states.  The headline value is the mixed-precision
+path (BF16x3 Pi build and BF16x3 W^c contraction), timed over exactly
+--steps steps; the plain FP64 path, the BF16x3-Pi-only path and the FP32 Pi
+path are timed beside it (fewer steps), each with its per-state error against
+the FP64 oracle's stored QP energies.  The same line carries a (H2O)10 leg,
+a bounded serving leg (p50/p99 latency of a Poisson request stream, mixed vs
+FP64, batching on and off), evGW and core-spectrum legs, and the oracle timed
+on a bounded sample of the headline workload.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--workload h2o30|h2o10] [--only PATH] [--no-serve] ...
 """
 import argparse
 import json
@@ -45,12 +50,12 @@ def pi_flops(n_aux, n_ov, G):
     return n_aux * (n_aux + 1) * n_ov * G
 
 
-def recorded_traffic(kernel):
-    """HBM bytes per launch of `kernel` from its committed rocprofv3 counter
-    record, or None when the record is missing or the kernel's source file has
-    changed since the counters were taken."""
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from its committed
+    rocprofv3 counter record, or None when the record is missing or the
+    kernel's source file has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"{kernel}_h2o10_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -60,12 +65,12 @@ def recorded_traffic(kernel):
     return rec["hbm_fetch_bytes"] + rec["hbm_write_bytes"]
 
 
-def time_path(gwl, inp, states, grid, path, steps, warmup):
+def time_path(gwl, inp, states, grid, path, steps, warmup, work_budget=0):
     import numpy as np
     import torch
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
-    c = gwl.Context.from_inputs(inp, qp_tol=1e-10, **PATHS[path])
+    c = gwl.Context.from_inputs(inp, qp_tol=1e-10, work_budget_bytes=work_budget, **PATHS[path])
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t_setup)   # host -> HBM upload and setup
     with c:
@@ -89,7 +94,7 @@ def time_path(gwl, inp, states, grid, path, steps, warmup):
         # the same call with the W^c table kept (a second molecule-independent
         # number: QP energies only, stage A cached)
         cached = []
-        for _ in range(max(3, steps // 2)):
+        for _ in range(max(1, min(3, steps // 2))):
             t1 = time.perf_counter()
             c.qp(states, grid)
             cached.append(1e3 * (time.perf_counter() - t1))
@@ -218,86 +223,128 @@ def crossover(gwl, ks, reps=3):
     return rows
 
 
-def cpu_baseline(inp, states, G, gold):
-    """Oracle timed on a bounded sample of the same workload (about 15 s of
-    host work): the W^c table on three of the grid points (first, middle,
-    last) and one Sigma^c evaluation (with its residues) each of the HOMO and
-    the LUMO at their QP energies, scaled to the whole workload with the
-    oracle's own iteration counts."""
-    import numpy as np
-    from oracle import cd, grid as ogrid
+def _cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
+
+
+def _blas_threads():
     try:
         from threadpoolctl import threadpool_info
-        cores = max((i.get("num_threads", 1) for i in threadpool_info()), default=os.cpu_count())
+        return max((i.get("num_threads", 1) for i in threadpool_info()), default=None)
     except Exception:
-        cores = os.cpu_count()
+        return None
+
+
+def cpu_baseline(inp, states, G, gold):
+    """Oracle timed on a bounded sample of the headline workload: the W^c
+    table on one grid point (Pi build, explicit inverse, contraction for every
+    row) and one residue term (explicit Pi(w) at a real frequency, inverse,
+    W^c and its derivative) of the HOMO, then scaled to the whole workload
+    with the oracle's own counts from its fixture (grid points, and residue
+    terms summed over every Sigma evaluation of every state; states the
+    fixture does not hold are counted at the mean of the occupied states it
+    does hold).  The I-term quadrature itself is negligible next to these."""
+    import numpy as np
+    from oracle import cd, grid as ogrid
     xi, z = ogrid.gauss_legendre(G)
-    picks = sorted({0, G // 2, G - 1})
     t0 = time.perf_counter()
-    for g in picks:
-        cd.w_table(inp.eps, inp.n_occ, inp.B_ov, inp.B_rows, xi[g:g + 1])
-    t_g = (time.perf_counter() - t0) / len(picks)
+    cd.w_table(inp.eps, inp.n_occ, inp.B_ov, inp.B_rows, xi[G // 2:G // 2 + 1])
+    t_g = time.perf_counter() - t0
     homo = inp.n_occ - 1
-    wt = np.zeros((inp.shape.n_mo, G))
-    t_ev, nres = [], []
-    for n in (homo, homo + 1):
-        r = list(inp.row_ids).index(n)
-        w = gold["results"][states.index(n)]["E"]
-        t0 = time.perf_counter()
-        _, _, k = cd.sigma_c(inp.eps, inp.n_occ, inp.B_ov, inp.B_rows[r], wt, xi, z, w)
-        t_ev.append(time.perf_counter() - t0)
-        nres.append(k)
-    t_eval = float(np.mean(t_ev))
-    n_evals = sum(x["iters"] for x in gold["results"])
-    total = G * t_g + n_evals * t_eval
-    return {"value": len(states) / total, "unit": "QP energies/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": (f"W^c table on {len(picks)} of {G} grid points ({t_g:.1f} s each) + one "
-                       f"Sigma^c evaluation each of the HOMO and LUMO at their QP energies with "
-                       f"{nres[0]} and {nres[1]} residues ({t_eval:.1f} s each); scaled to {G} grid "
-                       f"points and {n_evals} evaluations"),
+    r = list(inp.row_ids).index(homo)
+    have = {int(x["state"]): x for x in gold["results"]} if gold else {}
+    E_h = have[homo]["E"] if homo in have else inp.eps[homo] - 0.3
+    m = homo - 1                       # an occupied level above E: a residue term
+    t0 = time.perf_counter()
+    cd.residue_value(inp.eps, inp.n_occ, inp.B_ov, inp.B_rows[r, m], inp.eps[m] - E_h)
+    t_res = time.perf_counter() - t0
+    occ_counts = [sum(x.get("n_residues", [])) for n, x in have.items() if n < inp.n_occ]
+    mean_occ = float(np.mean(occ_counts)) if occ_counts else 0.0
+    n_res = 0.0
+    for n in states:
+        if n in have:
+            n_res += sum(have[n].get("n_residues", []))
+        elif n < inp.n_occ:
+            n_res += mean_occ
+    total = G * t_g + n_res * t_res
+    return {"value": len(states) / total, "unit": "QP energies/s", "cores": _cores(),
+            "blas_threads": _blas_threads(), "kind": "oracle",
+            "sample": (f"W^c table on 1 of {G} grid points ({t_g:.1f} s: Pi build, explicit "
+                       f"inverse, {inp.B_rows.shape[0]} x {inp.B_rows.shape[1]} rows) + one "
+                       f"residue term of the HOMO ({t_res:.1f} s: explicit Pi(w), inverse, W^c "
+                       f"and derivative); scaled to {G} grid points and {n_res:.0f} residue "
+                       f"terms (the oracle's own counts over all {len(states)} states)"),
             "est_total_s": total}
 
 
-def serve_bench(args):
-    """Serving workload: water clusters of k ~ U{1..24} molecules (HOMO-2..LUMO+2,
-    64-point grid) through gw_server.  Phase 1: closed loop with 8 requests
-    outstanding, FP64 and the mixed form (BF16x3 Pi and W^c) -> saturated
-    throughput of each.  Phase 2:
-    Poisson arrivals at 0.8 x the FP64 saturated rate, for both paths ->
-    throughput, p50 / p99 latency (done - submit) and the per-request energy
-    difference between the paths."""
+def oracle_errors(E, states, gold):
+    """Per-state |E - E_oracle| (meV) over the states the fixture holds."""
+    import numpy as np
+    if not gold:
+        return {"states_checked": 0}
+    ref = {int(x["state"]): x["E"] for x in gold["results"]}
+    per = {int(n): float(abs(E[j] - ref[n]) / MEV) for j, n in enumerate(states) if n in ref}
+    if not per:
+        return {"states_checked": 0}
+    rel = max(abs(E[j] - ref[n]) / abs(ref[n]) for j, n in enumerate(states) if n in ref)
+    return {"states_checked": len(per), "max_err_mev_vs_oracle": max(per.values()),
+            "max_rel_err_vs_oracle": float(rel),
+            "per_state_err_mev": {str(k): float(f"{v:.3e}") for k, v in sorted(per.items())}}
+
+
+def load_workload(name):
+    import gwgen
+    cfg = gwgen.CONFIGS[name]
+    if name == "h2o30":      # block-wise recipe of the same distribution (its fixture's)
+        inp = gwgen.make_inputs_blocked(cfg.shape, cfg.seed, cfg.states)
+    else:
+        inp = gwgen.make_config(name)
+    p = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+    gold = json.load(open(p)) if os.path.exists(p) else None
+    return cfg, inp, gold
+
+
+def serve_leg(gwl, n_requests, kmax, streams, small_k=6):
+    """Serving workload (bounded): the first n_requests requests of the stream
+    (water clusters of k ~ U{1..kmax}, request r seeded 1000 + r, HOMO-2..LUMO+2,
+    64-point grid) through gw_server.  Closed loop with 8 outstanding for FP64
+    and for the mixed form -> saturated throughput; then Poisson arrivals at
+    0.8 x the FP64 saturated rate for FP64, for the mixed form, and for the
+    mixed form with batching off -> throughput and p50 / p99 latency (done -
+    submit), also over the small requests (k <= small_k) alone."""
     import threading
+    from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
     import gwgen
-    import paper_2107_10423_amd as gwl
 
-    stream = gwgen.serving_stream(n_requests=args.requests, k_max=args.kmax, seed=5000, rate=1.0)
-    cache = {}
-    log(f"serve: generating inputs for {len(set(r['k'] for r in stream))} cluster sizes")
-    for r in stream:
-        if r["k"] not in cache:
-            cache[r["k"]] = gwgen.serving_inputs(r["k"], 1000 + r["k"])
+    stream = gwgen.serving_stream(n_requests=n_requests, k_max=kmax, seed=5000, rate=1.0)
+    log(f"serve: generating {len(stream)} requests (seed 1000 + r each)")
+    with ThreadPoolExecutor(max_workers=min(16, _cores() or 1)) as ex:
+        inputs = list(ex.map(lambda r: gwgen.serving_inputs(r["k"], r["seed"]), stream))
     grid = gwl.Grid.gauss_legendre(64)
+    ks = np.array([r["k"] for r in stream])
 
-    def run(prec, arrivals, window=None):
-        srv = gwl.Server(grid, n_streams=args.streams, **PATHS[prec])
-        tickets, E = {}, {}
-        lat, done_t, sub_t = [], [], []
+    def run(prec, arrivals, window=None, batch_max_aux=0):
+        srv = gwl.Server(grid, n_streams=streams, batch_max_aux=batch_max_aux, **PATHS[prec])
+        tickets, E, lat = {}, {}, {}
+        done_t, sub_t = [], []
         lock = threading.Lock()
         outstanding = threading.Semaphore(window) if window else None
         t0 = time.perf_counter()
 
         def producer():
-            for i, r in enumerate(stream):
+            for i in range(len(stream)):
                 if arrivals is not None:
                     dt = arrivals[i] - (time.perf_counter() - t0)
                     if dt > 0:
                         time.sleep(dt)
                 if outstanding:
                     outstanding.acquire()
-                inp = cache[r["k"]]
+                inp = inputs[i]
                 tk = srv.submit_inputs(inp, list(inp.row_ids))
                 with lock:
                     tickets[tk] = i
@@ -322,7 +369,7 @@ def serve_bench(args):
                 if info["rc"] != 0:
                     raise RuntimeError(f"request {i} failed with {info['rc']}")
                 E[i] = out[0]
-                lat.append(info["t_done"] - info["t_submit"])
+                lat[i] = info["t_done"] - info["t_submit"]
                 done_t.append(info["t_done"])
                 sub_t.append(info["t_submit"])
                 n_done += 1
@@ -334,58 +381,165 @@ def serve_bench(args):
         st = srv.stats()
         srv.close()
         span = max(done_t) - min(sub_t)
-        lat = np.array(lat)
+        L = np.array([lat[i] for i in range(len(stream))])
+        small = L[ks <= small_k]
         return dict(E=E, span_s=span, req_per_s=len(stream) / span,
-                    qp_per_s=sum(len(cache[r["k"]].row_ids) for r in stream) / span,
-                    p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
-                    mean_s=float(lat.mean()), peak_active=st["peak_active"],
-                    peak_reserved_gb=st["peak_reserved_bytes"] / 2**30)
+                    qp_per_s=sum(len(x.row_ids) for x in inputs) / span,
+                    p50_s=float(np.percentile(L, 50)), p99_s=float(np.percentile(L, 99)),
+                    small_p50_s=float(np.percentile(small, 50)) if small.size else None,
+                    small_p99_s=float(np.percentile(small, 99)) if small.size else None,
+                    peak_active=st["peak_active"], batches=st["batches"],
+                    batched_requests=st["batched_requests"], graph_replays=st["graph_replays"],
+                    device_mallocs=st["device_mallocs"], cache_hits=st["cache_hits"])
 
     sat = {}
     for prec in ("fp64", "bf16x3w"):
-        log(f"serve: phase 1, {prec} closed loop (8 outstanding)")
+        log(f"serve: {prec} closed loop (8 outstanding)")
         sat[prec] = run(prec, None, window=8)
     lam = 0.8 * sat["fp64"]["req_per_s"]
     arr = np.array([r["arrival_s"] for r in stream]) / lam
     res = {}
-    for prec in ("fp64", "bf16x3w"):
-        log(f"serve: phase 2, {prec}, Poisson arrivals at {lam:.2f} req/s")
-        res[prec] = run(prec, arr)
+    for key, prec, lim in (("fp64", "fp64", 0), ("bf16x3w", "bf16x3w", 0),
+                           ("bf16x3w_no_batching", "bf16x3w", -1)):
+        log(f"serve: {key}, Poisson arrivals at {lam:.2f} req/s")
+        res[key] = run(prec, arr, batch_max_aux=lim)
     dE = max(float(np.max(np.abs(res["bf16x3w"]["E"][i] - res["fp64"]["E"][i])))
              for i in range(len(stream)))
     pick = lambda r: {k: (round(v, 4) if isinstance(v, float) else v)
                       for k, v in r.items() if k != "E"}
-    out = {"metric": "serving: QP energies/s (saturated) and p50/p99 latency at a fixed Poisson "
-                     "rate, mixed (BF16x3 Pi and W^c) vs FP64",
-           "value": round(sat["bf16x3w"]["qp_per_s"], 3), "unit": "QP energies/s",
-           "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
-           "config": {"workload": f"{len(stream)} water clusters, k ~ U{{1..{args.kmax}}}, "
-                                  "HOMO-2..LUMO+2, 64-point grid",
-                      "poisson_rate_req_per_s": round(lam, 4), "streams": args.streams},
-           "saturated": {p: pick(r) for p, r in sat.items()},
-           "poisson": {p: pick(r) for p, r in res.items()},
-           "max_abs_dE_mixed_vs_fp64_mev": dE / MEV,
-           "mixed_over_fp64_saturated_qp_per_s":
-               round(sat["bf16x3w"]["qp_per_s"] / sat["fp64"]["qp_per_s"], 3)}
-    print(json.dumps(out))
+    return {"workload": f"first {len(stream)} requests of the serving stream: water clusters "
+                        f"k ~ U{{1..{kmax}}}, request r seeded 1000 + r, HOMO-2..LUMO+2, "
+                        f"64-point grid, {streams} pipelines",
+            "small_k_max": small_k, "n_small": int((ks <= small_k).sum()),
+            "poisson_rate_req_per_s": round(lam, 4),
+            "saturated": {p: pick(r) for p, r in sat.items()},
+            "poisson": {p: pick(r) for p, r in res.items()},
+            "p50_s": {p: round(r["p50_s"], 4) for p, r in res.items()},
+            "p99_s": {p: round(r["p99_s"], 4) for p, r in res.items()},
+            "max_abs_dE_mixed_vs_fp64_mev": dE / MEV,
+            "mixed_over_fp64_saturated_qp_per_s":
+                round(sat["bf16x3w"]["qp_per_s"] / sat["fp64"]["qp_per_s"], 3)}
+
+
+def roofline_objects(h, cfg, workload, states):
+    """Roofline of the Pi build and of the W^c contraction of the timed path;
+    the longer of the two heads, the other rides along."""
+    n_aux, n_ov, G = cfg.shape.n_aux, cfg.shape.n_ov, cfg.grid_points
+    pi_prec, wc_prec = h["pi_prec"], h["wc_prec"]
+    Gx = G + 1                      # the xi = 0 point (preconditioner) is built too
+    flops = pi_flops(n_aux, n_ov, G)
+    kname = {"bf16x3": "pi_bf16x3", "fp32": "pi_f32", "fp64": "pi_f64"}[pi_prec]
+    # algorithmic bytes of one step's Pi build(s): every operand element read
+    # once in the kernel's own format (FP64: 8 B; FP32: 4 B; BF16x3: hi + lo of
+    # the unscaled side and the FP32 scaled side, 8 B) plus the lower triangle
+    # of 1 - Pi written once per grid point (FP64)
+    opb = {"fp64": 8, "fp32": 4, "bf16x3": 8}[pi_prec]
+    alg_pi = n_aux * n_ov * opb + Gx * n_aux * (n_aux + 1) // 2 * 8
+    tr_pi = recorded_traffic(kname, workload)
+    pi_tf = flops / (h["pi_ms"] / 1e3) / 1e12
+    roof_pi = {"kernel": kname, "bound": "mfma", "achieved": round(pi_tf, 2),
+               "peak": PEAK_TFLOPS[pi_prec], "unit": "TFLOP/s",
+               "frac": round(pi_tf / PEAK_TFLOPS[pi_prec], 4),
+               "traffic": tr_pi, "algorithmic_bytes": alg_pi,
+               "traffic_over_algorithmic": round(tr_pi / alg_pi, 2) if tr_pi else None,
+               "flops_per_step": flops, "stage_ms": round(h["pi_ms"], 4),
+               "issued_frac": round(pi_tf * (3 if pi_prec == "bf16x3" else 1)
+                                    / PEAK_TFLOPS[pi_prec], 4),
+               "note": f"achieved = algorithmic flops N_aux(N_aux+1)N_ov per grid point x {G} "
+                       "grid points / the Pi stage time (HIP events on the context stream; the "
+                       "stage also builds the xi = 0 point, not counted); BF16x3 issues 3 bf16 "
+                       "MFMA products per algorithmic product, so its issued rate is 3x"}
+    n_rows_mo = len(states) * (cfg.shape.n_occ + cfg.shape.n_virt)
+    w_flops = float(n_rows_mo) * n_aux * n_aux * G
+    w_ms = h["stages"]["wtab_ms"]
+    w_tf = w_flops / (w_ms / 1e3) / 1e12
+    wname = "wc_bf16x3" if wc_prec == "bf16x3" else "w_gemm"
+    tr_w = recorded_traffic(wname, workload)
+    # algorithmic bytes: the rows b = (P|nm) once and L^-1 (lower triangle)
+    # once per grid point, in the operands' format, plus the table
+    ob = 4 if wc_prec == "bf16x3" else 8
+    alg_w = n_rows_mo * n_aux * ob + G * n_aux * (n_aux + 1) // 2 * ob + n_rows_mo * G * 8
+    roof_w = {"kernel": wname, "bound": "mfma", "achieved": round(w_tf, 2),
+              "peak": PEAK_TFLOPS[wc_prec], "unit": "TFLOP/s",
+              "frac": round(w_tf / PEAK_TFLOPS[wc_prec], 4), "traffic": tr_w,
+              "algorithmic_bytes": alg_w,
+              "traffic_over_algorithmic": round(tr_w / alg_w, 2) if tr_w else None,
+              "flops_per_step": w_flops, "stage_ms": round(w_ms, 4),
+              "issued_frac": round(w_tf * (3 if wc_prec == "bf16x3" else 1)
+                                   / PEAK_TFLOPS[wc_prec], 4),
+              "note": "W^c_nm = |L^-1 b|^2 - |b|^2 for every supplied row and m: algorithmic "
+                      f"flops n_rows n_mo N_aux^2 per grid point x {G} / the W^c stage time"}
+    roof, other = (roof_w, roof_pi) if w_ms > h["pi_ms"] else (roof_pi, roof_w)
+    roof = dict(roof)
+    roof["other_kernel"] = other
+    return roof
+
+
+def run_workload(gwl, name, head_path, args, side_paths, side_steps):
+    cfg, inp, gold = load_workload(name)
+    states = list(cfg.states)
+    grid = gwl.Grid.gauss_legendre(cfg.grid_points)
+    # one stage-A chunk holds every grid point (the whole build per launch)
+    wb = 48 << 30 if name == "h2o30" else 0
+    flops = pi_flops(cfg.shape.n_aux, cfg.shape.n_ov, cfg.grid_points)
+    res = {}
+    for path in [head_path] + [p for p in side_paths if p != head_path]:
+        steps, warmup = (args.steps, args.warmup) if path == head_path else (side_steps, 1)
+        log(f"bench: {name}: timing {path} path, {warmup} warmup + {steps} steps")
+        r = time_path(gwl, inp, states, grid, path, steps, warmup, work_budget=wb)
+        r.update(oracle_errors(r["E"], states, gold))
+        r["qp_per_s"] = len(states) / (r["ms_per_step"] / 1e3)
+        r["pi_tflops"] = flops / (r["pi_ms"] / 1e3) / 1e12
+        r["pi_prec"], r["wc_prec"] = PATHS[path]["pi_prec"], PATHS[path]["wc_prec"]
+        r["steps"] = steps
+        res[path] = r
+        log(f"bench: {name}: {path}: {r['ms_per_step']:.2f} ms/step, Pi {r['pi_ms']:.2f} ms "
+            f"({r['pi_tflops']:.1f} TFLOP/s), oracle: {r.get('max_err_mev_vs_oracle')} meV over "
+            f"{r.get('states_checked')} states, stages "
+            f"{json.dumps({k: round(v, 3) for k, v in r['stages'].items()})}")
+    return cfg, inp, gold, states, res
+
+
+def path_summary(res, states):
+    out = {}
+    for p, r in res.items():
+        d = {"qp_per_s": round(r["qp_per_s"], 4), "ms_per_step": round(r["ms_per_step"], 3),
+             "steps": r["steps"], "median_ms_per_step": round(r["median_ms"], 3),
+             "setup_ms": round(r["setup_ms"], 1),
+             "cached_wtable_qp_per_s": round(len(states) / (r["cached_ms"] / 1e3), 3),
+             "pi_ms": round(r["pi_ms"], 3), "pi_tflops": round(r["pi_tflops"], 2),
+             "pi_frac_of_peak": round(r["pi_tflops"] / PEAK_TFLOPS[r["pi_prec"]], 4),
+             "stages_ms": {k: round(v, 3) for k, v in r["stages"].items()}}
+        for k in ("states_checked", "max_err_mev_vs_oracle", "max_rel_err_vs_oracle",
+                  "per_state_err_mev"):
+            if k in r:
+                d[k] = r[k]
+        out[p] = d
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="h2o30", choices=["h2o30", "h2o10"],
+                    help="headline workload (default: the (H2O)30 shape)")
+    ap.add_argument("--only", default=None, choices=list(PATHS),
+                    help="time only this path of the headline workload (profiling)")
+    ap.add_argument("--side-steps", type=int, default=1,
+                    help="timed steps of each non-headline path of the headline workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-h2o10", action="store_true", help="skip the (H2O)10 leg")
     ap.add_argument("--no-evgw", action="store_true", help="skip the evGW0 / evGW timing")
     ap.add_argument("--no-core", action="store_true", help="skip the full core spectrum timing")
-    ap.add_argument("--crossover", default=None,
-                    help="comma-separated cluster sizes k: time the SD and CD routes instead")
-    ap.add_argument("--only", default=None, choices=list(PATHS),
-                    help="time only this path (profiling)")
-    ap.add_argument("--serve", action="store_true", help="run the serving workload instead")
-    ap.add_argument("--requests", type=int, default=128)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=32,
+                    help="requests of the serving leg (the first ones of the stream)")
     ap.add_argument("--kmax", type=int, default=24)
     ap.add_argument("--streams", type=int, default=4)
+    ap.add_argument("--crossover", default=None,
+                    help="comma-separated cluster sizes k: time the SD and CD routes instead")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -399,11 +553,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    if args.serve:
-        serve_bench(args)
-        return
+    import paper_2107_10423_amd as gwl
     if args.crossover:
-        import paper_2107_10423_amd as gwl
         ks = [int(k) for k in args.crossover.split(",")]
         print(json.dumps({"metric": "G0W0 wall time per call, spectral decomposition vs "
                                     "contour deformation (HOMO, LUMO)", "unit": "ms",
@@ -417,128 +568,83 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": x.numel() * 8}))
         return
-    import gwgen
-    import paper_2107_10423_amd as gwl
 
-    name = "h2o10"
-    cfg = gwgen.CONFIGS[name]
-    states = list(cfg.states)
+    name = args.workload
+    head = args.only or "bf16x3w"
+    side = [] if args.only else ["fp64", "bf16x3", "fp32"]
     log(f"bench: generating {name} inputs")
-    inp = gwgen.make_config(name)
-    grid = gwl.Grid.gauss_legendre(cfg.grid_points)
-    gold = json.load(open(os.path.join(ROOT, "tests", "golden", f"{name}.json")))
-    E_ref = np.array([r["E"] for r in gold["results"]])
-    n_aux, n_ov = cfg.shape.n_aux, cfg.shape.n_ov
-    flops = pi_flops(n_aux, n_ov, cfg.grid_points)
-
-    precs = [args.only] if args.only else list(PATHS)
-    res = {}
-    for prec in precs:
-        log(f"bench: timing {prec} path, {args.warmup} warmup + {args.steps} steps")
-        r = time_path(gwl, inp, states, grid, prec, args.steps, args.warmup)
-        r["err_mev"] = float(np.max(np.abs(r["E"] - E_ref)) / MEV)
-        r["qp_per_s"] = len(states) / (r["ms_per_step"] / 1e3)
-        r["pi_tflops"] = flops / (r["pi_ms"] / 1e3) / 1e12
-        res[prec] = r
-        log(f"bench: {prec}: {r['ms_per_step']:.2f} ms/step, Pi {r['pi_ms']:.2f} ms "
-            f"({r['pi_tflops']:.1f} TFLOP/s), max |E - oracle| = {r['err_mev']:.2e} meV, "
-            f"stages {json.dumps({k: round(v, 3) for k, v in r['stages'].items()})}")
-
-    head = precs[0]
+    cfg, inp, gold, states, res = run_workload(gwl, name, head, args, side, args.side_steps)
     h = res[head]
-    pi_prec, wc_prec = PATHS[head]["pi_prec"], PATHS[head]["wc_prec"]
-    # roofline of the Pi build and of the W^c contraction (one launch each per
-    # step at this size); the dominant one, by measured launch time, heads the line
-    kname = {"bf16x3": "pi_bf16x3", "fp32": "pi_f32", "fp64": "pi_f64"}[pi_prec]
-    tr_pi = recorded_traffic(kname)
-    roof_pi = {"kernel": kname, "bound": "mfma", "achieved": round(h["pi_tflops"], 2),
-               "peak": PEAK_TFLOPS[pi_prec], "unit": "TFLOP/s",
-               "frac": round(h["pi_tflops"] / PEAK_TFLOPS[pi_prec], 4),
-               "traffic": tr_pi,
-               "flops_per_launch": flops, "launch_ms": round(h["pi_ms"], 4),
-               # BF16x3 issues three bf16 products per algorithmic one
-               "issued_frac": round(h["pi_tflops"] * (3 if pi_prec == "bf16x3" else 1)
-                                    / PEAK_TFLOPS[pi_prec], 4),
-               "traffic_gb_per_s": (round(tr_pi / (h["pi_ms"] / 1e3) / 1e9, 1) if tr_pi else None),
-               "note": "achieved = algorithmic flops N_aux(N_aux+1)N_ov per grid point x 64 grid "
-                       "points / launch time (HIP events on the context stream); BF16x3 issues 3 "
-                       "bf16 MFMA products per algorithmic product, so its issued rate is 3x"}
-    n_rows_mo = len(states) * (cfg.shape.n_occ + cfg.shape.n_virt)
-    w_flops = float(n_rows_mo) * n_aux * n_aux * cfg.grid_points
-    w_ms = h["stages"]["wtab_ms"]
-    w_tf = w_flops / (w_ms / 1e3) / 1e12
-    wname = "wc_bf16x3" if wc_prec == "bf16x3" else "w_gemm"
-    tr_w = recorded_traffic(wname)
-    roof_w = {"kernel": wname, "bound": "mfma", "achieved": round(w_tf, 2),
-              "peak": PEAK_TFLOPS[wc_prec], "unit": "TFLOP/s",
-              "frac": round(w_tf / PEAK_TFLOPS[wc_prec], 4), "traffic": tr_w,
-              "flops_per_launch": w_flops, "launch_ms": round(w_ms, 4),
-              "issued_frac": round(w_tf * (3 if wc_prec == "bf16x3" else 1)
-                                   / PEAK_TFLOPS[wc_prec], 4),
-              "traffic_gb_per_s": (round(tr_w / (w_ms / 1e3) / 1e9, 1) if tr_w else None),
-              "note": "W^c_nm = |L^-1 b|^2 - |b|^2 for every supplied row and m: algorithmic "
-                      "flops n_rows n_mo N_aux^2 per grid point (a triangular solve per b) x 64 "
-                      "grid points / the W^c stage time (HIP events around the stage: the FP64 "
-                      "GEMM with its squared-norm epilogue, or the F = L^-1 - I split and the "
-                      "BF16x3 contraction with its 2 b^T y + |y|^2 epilogue, then the 10-us "
-                      "reduction kernel)"}
-    roof, other = (roof_w, roof_pi) if w_ms > h["pi_ms"] else (roof_pi, roof_w)
-    roof = dict(roof)
-    roof["other_kernel"] = other
+    sh = cfg.shape
     out = {
-        # the headline metric of the workload; this line carries the QP energies/s and
-        # Pi TFLOP/s of the mixed and FP64 paths (p50/p99 latency: the --serve line)
         "metric": "QP energies/sec + \u03a0(i\u03c9) TFLOP/s, mixed vs FP64 GPU at \u22641 meV; "
                   "p50/p99 latency",
-        "value": round(h["qp_per_s"], 3), "unit": "QP energies/s", "n_gpus": 1,
+        "value": round(h["qp_per_s"], 4), "unit": "QP energies/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(h["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": DTYPES[head],
         "data": "synthetic",
-        "config": {"workload": "(H2O)10-shaped G0W0: n_occ=50, n_virt=380, N_aux=1120, "
-                               "64-point grid, HOMO-4..LUMO+4 (10 states), seed 2",
-                   "n_occ": 50, "n_virt": 380, "n_aux": 1120, "grid_points": 64, "states": 10},
-        "roofline": roof,
-        # one molecule's request latency on an idle GPU (W^c table rebuilt, all
-        # 10 states): the timed steps' distribution; loaded p50/p99 latency is
-        # the --serve line's
+        "config": {"workload": f"{'(H2O)30' if name == 'h2o30' else '(H2O)10'}-shaped G0W0: "
+                               f"n_occ={sh.n_occ}, n_virt={sh.n_virt}, N_aux={sh.n_aux}, "
+                               f"{cfg.grid_points}-point grid, {len(states)} states "
+                               f"(HOMO-{sh.n_occ - 1 - states[0]}..LUMO+"
+                               f"{states[-1] - sh.n_occ}), seed {cfg.seed}",
+                   "n_occ": sh.n_occ, "n_virt": sh.n_virt, "n_aux": sh.n_aux,
+                   "grid_points": cfg.grid_points, "states": len(states)},
+        "roofline": roofline_objects(h, cfg, name, states),
+        # one molecule's request latency on an idle GPU (the headline path's
+        # timed steps); loaded latency under a request stream: "serving"
         "latency_ms": {"p50": round(h["median_ms"], 3), "p99": round(h["p99_ms"], 3),
                        "samples": args.steps},
-        "paths": {p: {"qp_per_s": round(r["qp_per_s"], 3), "ms_per_step": round(r["ms_per_step"], 3),
-                      "median_ms_per_step": round(r["median_ms"], 3),
-                      "setup_ms": round(r["setup_ms"], 1),
-                      "cached_wtable_qp_per_s": round(len(states) / (r["cached_ms"] / 1e3), 3),
-                      "pi_ms": round(r["pi_ms"], 3), "pi_tflops": round(r["pi_tflops"], 2),
-                      "pi_frac_of_peak": round(r["pi_tflops"] / PEAK_TFLOPS[PATHS[p]["pi_prec"]], 4),
-                      "max_err_mev_vs_oracle": r["err_mev"],
-                      "stages_ms": {k: round(v, 3) for k, v in r["stages"].items()}}
-                  for p, r in res.items()},
+        "paths": path_summary(res, states),
     }
     if "fp64" in res and head != "fp64":
         out["mixed_over_fp64"] = {"qp_per_s": round(h["qp_per_s"] / res["fp64"]["qp_per_s"], 3),
                                   "pi_tflops": round(h["pi_tflops"] / res["fp64"]["pi_tflops"], 3)}
-    if not args.no_evgw:
-        log(f"bench: timing evGW0 / evGW (3 cycles) on the {head} path")
-        evr = time_evgw(gwl, inp, states, grid, head)
-        out["evgw"] = {}
-        for mode, r in evr.items():
-            d = {"ms_per_call": round(r["ms_per_call"], 3), "cycles": r["cycles"],
-                 "qp_rounds": r["qp_rounds"],
-                 "qp_per_s": round(len(states) / (r["ms_per_call"] / 1e3), 3),
-                 "status_nonzero": int(np.count_nonzero(r["status"])),
-                 "stages_ms": r["stages"]}
-            p = os.path.join(ROOT, "tests", "golden", f"{name}_{mode}.json")
-            if os.path.exists(p):
-                ref = np.array(json.load(open(p))["cycles"])
-                if ref.shape == r["hist"].shape:
-                    d["max_err_mev_vs_oracle"] = float(np.max(np.abs(r["hist"] - ref)) / MEV)
-            out["evgw"][mode] = d
-            log(f"bench: {mode}: {json.dumps(d)}")
-    if not args.no_core:
-        log(f"bench: timing the full core spectrum on the {head} path")
-        out["core_spectrum"] = time_core_spectrum(gwl, head)
-    if not args.no_cpu_baseline:
-        log("bench: timing the oracle on a bounded sample")
+    # free the headline inputs before the other legs
+    del inp
+    if name != "h2o10" and not args.no_h2o10 and not args.only:
+        log("bench: (H2O)10 leg")
+        ns = argparse.Namespace(**vars(args))
+        ns.steps, ns.warmup = max(args.steps, 10), 2
+        c2, inp2, gold2, st2, res2 = run_workload(gwl, "h2o10", "bf16x3w", ns, ["fp64"], 10)
+        out["h2o10"] = {"paths": path_summary(res2, st2),
+                        "mixed_over_fp64": {
+                            "qp_per_s": round(res2["bf16x3w"]["qp_per_s"] /
+                                              res2["fp64"]["qp_per_s"], 3),
+                            "pi_tflops": round(res2["bf16x3w"]["pi_tflops"] /
+                                               res2["fp64"]["pi_tflops"], 3)},
+                        "roofline": roofline_objects(res2["bf16x3w"], c2, "h2o10", st2)}
+        if not args.no_evgw:
+            log("bench: timing evGW0 / evGW (3 cycles) on the (H2O)10 mixed path")
+            grid2 = gwl.Grid.gauss_legendre(c2.grid_points)
+            evr = time_evgw(gwl, inp2, st2, grid2, "bf16x3w")
+            out["evgw"] = {"workload": "(H2O)10 shape, 3 cycles, mixed path"}
+            for mode, r in evr.items():
+                d = {"ms_per_call": round(r["ms_per_call"], 3), "cycles": r["cycles"],
+                     "qp_rounds": r["qp_rounds"],
+                     "qp_per_s": round(len(st2) / (r["ms_per_call"] / 1e3), 3),
+                     "status_nonzero": int(np.count_nonzero(r["status"]))}
+                pth = os.path.join(ROOT, "tests", "golden", f"h2o10_{mode}.json")
+                if os.path.exists(pth):
+                    ref = np.array(json.load(open(pth))["cycles"])
+                    if ref.shape == r["hist"].shape:
+                        d["max_err_mev_vs_oracle"] = float(np.max(np.abs(r["hist"] - ref)) / MEV)
+                out["evgw"][mode] = d
+        del inp2
+    if not args.no_core and not args.only:
+        log("bench: timing the full core spectrum on the mixed path")
+        out["core_spectrum"] = time_core_spectrum(gwl, "bf16x3w")
+    if not args.no_serve and not args.only:
+        log("bench: serving leg")
+        out["serving"] = serve_leg(gwl, args.serve_requests, args.kmax, args.streams)
+        out["latency_p50_p99_s"] = {"mixed": [out["serving"]["p50_s"]["bf16x3w"],
+                                              out["serving"]["p99_s"]["bf16x3w"]],
+                                    "fp64": [out["serving"]["p50_s"]["fp64"],
+                                             out["serving"]["p99_s"]["fp64"]]}
+    if not args.no_cpu_baseline and not args.only:
+        log("bench: timing the oracle on a bounded sample of the headline workload")
+        _, inp, gold = load_workload(name)
         out["cpu_baseline"] = cpu_baseline(inp, states, cfg.grid_points, gold)
     print(json.dumps(out))
 

@@ -306,9 +306,19 @@ int gw_get_timing(gw_ctx* ctx, gw_timing* out);
  * (gw_footprint) fits in the remaining budget; each admitted request keeps
  * its inputs, W^c table and workspaces resident until it completes, and its
  * context may not allocate past its reserved footprint.  Up to n_streams
- * requests run at once, each on its own HIP stream, so the work of requests
- * admitted while others are on the GPU overlaps with theirs.  Every request
- * runs exactly the gw_qp path.  The server is internally synchronised. */
+ * pipelines run at once, each on its own HIP stream, so the work of requests
+ * admitted while others are on the GPU overlaps with theirs.
+ * Small requests (N_aux up to batch_max_aux) are batched: when one is
+ * admitted, every pending request of the same padded shape (N_aux, n_occ n_virt
+ * and n_rows n_mo, each padded to 128) joins it, up to a batch size the
+ * shape's workspace allows, and their stage A (the Pi build, Cholesky and W^c
+ * table on every grid point) runs as one set of launches over all their grid
+ * points, replayed from a graph captured for that shape and batch size.  Each
+ * request's quasiparticle stage then runs on whichever pipeline is free.
+ * Results are those of gw_qp on the request alone, bit for bit.  Device and
+ * pinned host blocks are kept by the server and reused across requests, so a
+ * stream of recurring shapes runs without hipMalloc / hipFree once warm.  The
+ * server is internally synchronised. */
 typedef struct gw_server gw_server;
 
 typedef struct gw_server_opts {
@@ -321,6 +331,9 @@ typedef struct gw_server_opts {
   int n_streams;            /* concurrent request pipelines, 1..4 (0: 2) */
   size_t work_budget_bytes; /* stage-A workspace cap per request (0: 2 GiB) */
   int wc_prec;              /* as in gw_opts (0: FP64) */
+  int batch_max_aux;        /* requests whose N_aux, padded to 128, is at most this
+                               run stage A batched with others of their padded shape
+                               (0: 768; negative: never batched) */
 } gw_server_opts;
 
 typedef struct gw_request {
@@ -346,6 +359,12 @@ typedef struct gw_server_stats {
   unsigned long long submitted, completed, failed;
   size_t budget_bytes, reserved_bytes, peak_reserved_bytes;
   int active, peak_active;
+  long batches;             /* grouped stage-A launches (graph replays or captures) */
+  long batched_requests;    /* requests whose stage A ran in such a batch */
+  long graph_replays;       /* batches that replayed an already captured graph */
+  long device_mallocs;      /* device and pinned blocks the server obtained from the
+                               runtime (each later reuse of a block is a cache hit) */
+  long cache_hits;
 } gw_server_stats;
 
 /* GW_EINVAL for bad options, GW_EDEVICE if no device or stream is usable. */

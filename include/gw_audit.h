@@ -28,6 +28,17 @@ int gw_audit_enable(void);
 /* Number of kernel launches checked (and skipped) in audit mode so far. */
 long gw_audit_launch_count(void);
 
+/* The server's grouped stage A on n caller-made contexts (gw_setup, closed
+ * shell, the same padded shape and options, preconditioner on): builds a
+ * temporary group for that shape and runs one batch of all n (as graphs
+ * unless use_graph is 0), then frees the group.  rc[j]: 0 when context j's
+ * W^c table (grid plus xi = 0) is now cached, or GW_ENOTSPD.  For tests and
+ * the launch audit; returns GW_EINVAL for mismatched contexts. */
+struct gw_ctx;
+struct gw_grid;
+int gw_group_stage_a(int n, struct gw_ctx* const* ctxs, const struct gw_grid* grid,
+                     int use_graph, int* rc);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,7 +67,7 @@ class _ServerOpts(ctypes.Structure):
                 ("qp_tol", ctypes.c_double), ("grid_n", ctypes.c_int), ("grid_xi", _dp),
                 ("grid_w", _dp), ("mem_budget_bytes", ctypes.c_size_t),
                 ("n_streams", ctypes.c_int), ("work_budget_bytes", ctypes.c_size_t),
-                ("wc_prec", ctypes.c_int)]
+                ("wc_prec", ctypes.c_int), ("batch_max_aux", ctypes.c_int)]
 
 
 class _Request(ctypes.Structure):
@@ -89,7 +89,10 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_ulonglong), ("completed", ctypes.c_ulonglong),
                 ("failed", ctypes.c_ulonglong), ("budget_bytes", ctypes.c_size_t),
                 ("reserved_bytes", ctypes.c_size_t), ("peak_reserved_bytes", ctypes.c_size_t),
-                ("active", ctypes.c_int), ("peak_active", ctypes.c_int)]
+                ("active", ctypes.c_int), ("peak_active", ctypes.c_int),
+                ("batches", ctypes.c_long), ("batched_requests", ctypes.c_long),
+                ("graph_replays", ctypes.c_long), ("device_mallocs", ctypes.c_long),
+                ("cache_hits", ctypes.c_long)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -132,6 +135,8 @@ _sig = {
     "gw_server_destroy": (None, [ctypes.c_void_p]),
     "gw_audit_enable": (ctypes.c_int, []),
     "gw_audit_launch_count": (ctypes.c_long, []),
+    "gw_group_stage_a": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_ctxp), ctypes.POINTER(_Grid),
+                                        ctypes.c_int, _ip]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -406,12 +411,13 @@ class Server:
     """Request server (gw_server_*): submit molecules, poll results."""
 
     def __init__(self, grid, pi_prec="fp64", mem_budget_bytes=0, n_streams=0,
-                 work_budget_bytes=0, qp_tol=0.0, minres_rtol=0.0, wc_prec="fp64"):
+                 work_budget_bytes=0, qp_tol=0.0, minres_rtol=0.0, wc_prec="fp64",
+                 batch_max_aux=0):
         self._grid = grid
         o = _ServerOpts(_prec(pi_prec), 0, 0,
                         float(minres_rtol), float(qp_tol), grid.n, _pd(grid.xi), _pd(grid.w),
                         int(mem_budget_bytes), int(n_streams), int(work_budget_bytes),
-                        _prec(wc_prec))
+                        _prec(wc_prec), int(batch_max_aux))
         h = ctypes.c_void_p()
         _check(_lib.gw_server_create(ctypes.byref(h), ctypes.byref(o)))
         self._h = h
@@ -476,6 +482,17 @@ def audit_enable():
 
 def audit_launch_count():
     return int(_lib.gw_audit_launch_count())
+
+
+def group_stage_a(contexts, grid, use_graph=True):
+    """The server's grouped stage A on contexts of one padded shape
+    (gw_group_stage_a): one batched launch sequence over all their grid points;
+    returns each context's status (0: its W^c table is cached)."""
+    n = len(contexts)
+    arr = (_ctxp * n)(*[c._h for c in contexts])
+    rc = np.zeros(n, dtype=np.int32)
+    _check(_lib.gw_group_stage_a(n, arr, ctypes.byref(grid._g), int(bool(use_graph)), _pi(rc)))
+    return rc
 
 
 def exported_symbols():

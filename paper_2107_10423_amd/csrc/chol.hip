@@ -190,6 +190,49 @@ hipError_t wc_from_parts(const double* part, long sPart, int nJ, int ldp, const 
   return hipGetLastError();
 }
 
+// Grouped form: item g of the batch is grid column g % grp of request g / grp
+__global__ void k_wc_from_parts_tab(const double* part, long sPart, int nJ, int ldp,
+                                    const double* const* bn_tab, int nR, int grp,
+                                    double* const* wtab_tab) {
+  const int g = blockIdx.y;
+  const int r = g / grp, col = g % grp;
+  const double* bn = bn_tab ? bn_tab[r] : nullptr;
+  double* wtab = wtab_tab[r];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < nR; q += gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int J = 0; J < nJ; ++J) s += part[(long)g * sPart + (long)J * ldp + q];
+    wtab[(long)q * grp + col] = bn ? s - bn[q] : s;
+  }
+}
+
+hipError_t wc_from_parts_tab(const double* part, long sPart, int nJ, int ldp,
+                             const double* const* bn_tab, int nR, int G, int grp,
+                             double* const* wtab_tab, long nPart, long nBn, long nW,
+                             hipStream_t st) {
+  if (nR <= 0 || G <= 0) return hipSuccess;
+  if (grp <= 0 || G % grp != 0 || ldp < nR || !wtab_tab) return refuse("wc_from_parts", "shape");
+  GW_GUARD("wc_from_parts", "part", (long)(G - 1) * sPart + (long)(nJ - 1) * ldp + nR - 1, nPart);
+  if (bn_tab) GW_GUARD("wc_from_parts", "bnorm2", nR - 1, nBn);
+  GW_GUARD("wc_from_parts", "wtab", (long)(nR - 1) * grp + grp - 1, nW);
+  GW_AUDIT_RETURN();
+  int blocks = std::min((nR + 255) / 256, 256);
+  hipLaunchKernelGGL(k_wc_from_parts_tab, dim3(blocks, G), dim3(256), 0, st, part, sPart, nJ, ldp,
+                     bn_tab, nR, grp, wtab_tab);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_int(int* p, int n, int v) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t fill_int(int* p, int n, int v, long nP, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  GW_GUARD("fill_int", "p", n - 1, nP);
+  GW_AUDIT_RETURN();
+  hipLaunchKernelGGL(k_fill_int, dim3(std::min((n + 255) / 256, 64)), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
 // s[g][k] = D_k / (D_k^2 + xi_g^2) for k < Kov, 0 for the padding; s32 (if
 // given) receives the same values rounded to FP32 for the mixed Pi builds
 __global__ void k_scale_imag(const double* D, int Kov, int Kp, const double* xi, double* s,
@@ -216,6 +259,41 @@ hipError_t make_scale_imag(const double* D, int Kov, int Kp, const double* xi, i
   int blocks = (Kp + 255) / 256;
   if (blocks > 256) blocks = 256;
   hipLaunchKernelGGL(k_scale_imag, dim3(blocks, G), dim3(256), 0, st, D, Kov, Kp, xi, s, s32);
+  return hipGetLastError();
+}
+
+// Grouped form: item g takes request g / grp's energies and real-column count
+// and grid point xi[g % grp]
+__global__ void k_scale_imag_tab(const double* const* D_tab, const int* Kov_tab, int Kp,
+                                 const double* xi, int grp, double* s, float* s32) {
+  const int g = blockIdx.y;
+  const double* D = D_tab[g / grp];
+  const int Kov = Kov_tab[g / grp];
+  const double x = xi[g % grp];
+  const double x2 = x * x;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < Kp; k += gridDim.x * blockDim.x) {
+    double d = D[k];
+    const double v = (k < Kov) ? d / (d * d + x2) : 0.0;
+    s[(long)g * Kp + k] = v;
+    if (s32) s32[(long)g * Kp + k] = (float)v;
+  }
+}
+
+// nD: the smallest extent over the table's energy arrays
+hipError_t make_scale_imag_tab(const double* const* D_tab, const int* Kov_tab, int Kp,
+                               const double* xi, int grp, int G, double* s, float* s32,
+                               long nD, long nXi, long nS, long nS32, hipStream_t st) {
+  if (G <= 0 || Kp <= 0) return hipSuccess;
+  if (grp <= 0 || G % grp != 0 || !D_tab || !Kov_tab) return refuse("scale_imag", "shape");
+  GW_GUARD("scale_imag", "D", Kp - 1, nD);
+  GW_GUARD("scale_imag", "xi", grp - 1, nXi);
+  GW_GUARD("scale_imag", "s", (long)G * Kp - 1, nS);
+  if (s32) GW_GUARD("scale_imag", "s32", (long)G * Kp - 1, nS32);
+  GW_AUDIT_RETURN();
+  int blocks = (Kp + 255) / 256;
+  if (blocks > 256) blocks = 256;
+  hipLaunchKernelGGL(k_scale_imag_tab, dim3(blocks, G), dim3(256), 0, st, D_tab, Kov_tab, Kp, xi,
+                     grp, s, s32);
   return hipGetLastError();
 }
 

@@ -153,8 +153,8 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
   int I, J;
   decode_tile<BM, BN>(p, tile, I, J);
 
-  const double* A = p.A + (long)b * p.sA;
-  const double* Bm = p.B + (long)b * p.sB;
+  const double* A = p.Atab ? p.Atab[b / p.grp] : p.A + (long)b * p.sA;
+  const double* Bm = p.Btab ? p.Btab[b / p.grp] : p.B + (long)b * p.sB;
   const double* S = SCALED ? p.scale + (long)b * p.sS : nullptr;
   const int arow0 = p.row0 + I * BM;
   const int brow0 = p.col0 + J * BN;
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs p) {
 
   // Epilogue.  f64 16x16x4 output layout: lane l, register r holds
   // row (l / 16) + 4 r, column l % 16 of the 16x16 block.
-  double* C = p.C + (long)b * p.sC + (long)split * p.sSplit;
+  double* C = (p.Ctab ? p.Ctab[b / p.grp] : p.C + (long)b * p.sC) + (long)split * p.sSplit;
   if (EPI == EPI_RES_DERIV || EPI == EPI_SQNORM) {
     // per-row sum over this tile's columns of acc^2 (EPI_SQNORM) or of
     // acc^2 * 2 D w / (D^2 - w^2)^2 (EPI_RES_DERIV)
@@ -341,15 +341,19 @@ static hipError_t check_gemm(const GemmArgs& a, int tile_kind, int la, int lb, i
   const long rmax = a.row0 + (long)a.tiles_m * BM - 1;
   const long cmax = a.col0 + (long)a.tiles_n * BN - 1;
   const long b1 = a.batch - 1;
-  long maxA = la == KC ? b1 * a.sA + rmax * a.lda + a.k0 + a.K - 1
-                       : b1 * a.sA + (long)(a.k0 + a.K - 1) * a.lda + rmax;
-  long maxB = lb == KC ? b1 * a.sB + cmax * a.ldb + a.kb0 + a.K - 1
-                       : b1 * a.sB + (long)(a.kb0 + a.K - 1) * a.ldb + cmax;
+  if ((a.Atab || a.Btab || a.Ctab) && (a.grp <= 0 || a.batch % a.grp != 0))
+    return refuse(kn, "operand table group");
+  // a table's pointers are checked one request at a time (item offset 0)
+  const long bA = a.Atab ? 0 : b1, bB = a.Btab ? 0 : b1, bC = a.Ctab ? 0 : b1;
+  long maxA = la == KC ? bA * a.sA + rmax * a.lda + a.k0 + a.K - 1
+                       : bA * a.sA + (long)(a.k0 + a.K - 1) * a.lda + rmax;
+  long maxB = lb == KC ? bB * a.sB + cmax * a.ldb + a.kb0 + a.K - 1
+                       : bB * a.sB + (long)(a.kb0 + a.K - 1) * a.ldb + cmax;
   if (!guard(kn, "A", maxA, a.nA)) return hipErrorInvalidValue;
   if (!guard(kn, "B", maxB, a.nB)) return hipErrorInvalidValue;
   if (a.scale && !guard(kn, "scale", b1 * a.sS + a.kb0 + a.K - 1, a.nS)) return hipErrorInvalidValue;
   const bool per_tile = epi == EPI_RES_DERIV || epi == EPI_SQNORM;
-  long maxC = b1 * a.sC + (long)(a.splitk - 1) * a.sSplit +
+  long maxC = bC * a.sC + (long)(a.splitk - 1) * a.sSplit +
               (per_tile ? (long)(a.tiles_n - 1) * a.ldc + rmax : rmax * a.ldc + cmax);
   if ((a.ktri || a.klo_from > 0) && a.splitk != 1) return refuse(kn, "triangular k limit with split-K");
   if (a.rowmask && !guard(kn, "rowmask", ((long)a.tiles_m * BM - 1) / 16, a.nMask))

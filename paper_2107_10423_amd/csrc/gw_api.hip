@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -187,7 +188,132 @@ struct Timer {
 
 }  // namespace
 
+// Block cache for the contexts a server creates: device blocks and pinned host
+// blocks freed by a context go to per-size free lists and are handed out again
+// to later contexts, so that requests of recurring shapes run without
+// hipMalloc / hipFree (hipFree waits for the whole device) once the cache is
+// warm.  Blocks are returned to the runtime only when a new allocation would
+// exceed the cap, and when the cache is destroyed.
+struct gw_devcache {
+  std::mutex mu;
+  std::multimap<size_t, void*> free_dev, free_host;
+  std::map<void*, size_t> size_of;     // every block handed out or cached -> its size
+  size_t cap = 0;                      // device bytes (live + cached) the cache may hold
+  size_t live = 0, cached = 0;
+  long n_malloc = 0, n_free = 0, n_hits = 0;
+
+  static size_t round(size_t b) {
+    const size_t q = b >= (1u << 20) ? (64u << 10) : 256;
+    return (std::max<size_t>(b, 8) + q - 1) / q * q;
+  }
+  // a block of exactly this size class, else the best fit within 1/8 of slack
+  static void* take(std::multimap<size_t, void*>& fl, size_t want, size_t* got) {
+    auto it = fl.find(want);
+    if (it == fl.end()) it = fl.lower_bound(want);
+    if (it == fl.end() || it->first > want + want / 8) return nullptr;
+    void* p = it->second;
+    *got = it->first;
+    fl.erase(it);
+    return p;
+  }
+  hipError_t get_dev(void** p, size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu);
+    const size_t want = round(bytes);
+    size_t got = 0;
+    if ((*p = take(free_dev, want, &got))) {
+      cached -= got;
+      live += got;
+      ++n_hits;
+      return hipSuccess;
+    }
+    while (live + cached + want > cap && !free_dev.empty()) {   // make room: largest first
+      auto last = std::prev(free_dev.end());
+      rt_free(last->second);
+      size_of.erase(last->second);
+      cached -= last->first;
+      ++n_free;
+      free_dev.erase(last);
+    }
+    hipError_t e = rt_malloc(p, want);
+    if (e != hipSuccess && !free_dev.empty()) {   // the runtime is short: drop the rest
+      (void)hipGetLastError();
+      for (auto& kv : free_dev) {
+        rt_free(kv.second);
+        size_of.erase(kv.second);
+        ++n_free;
+      }
+      free_dev.clear();
+      cached = 0;
+      e = rt_malloc(p, want);
+    }
+    if (e != hipSuccess) return e;
+    ++n_malloc;
+    size_of[*p] = want;
+    live += want;
+    return hipSuccess;
+  }
+  void put_dev(void* p) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = size_of.find(p);
+    if (it == size_of.end()) return;
+    live -= it->second;
+    cached += it->second;
+    free_dev.emplace(it->second, p);
+  }
+  hipError_t get_host(void** p, size_t bytes) {
+    std::lock_guard<std::mutex> lk(mu);
+    const size_t want = round(bytes);
+    size_t got = 0;
+    if ((*p = take(free_host, want, &got))) {
+      ++n_hits;
+      return hipSuccess;
+    }
+    if (audit_mode()) {
+      *p = calloc(want, 1);
+      if (!*p) return hipErrorOutOfMemory;
+    } else {
+      hipError_t e = hipHostMalloc(p, want, hipHostMallocDefault);
+      if (e != hipSuccess) return e;
+    }
+    ++n_malloc;
+    size_of[*p] = want;
+    return hipSuccess;
+  }
+  void put_host(void* p) {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = size_of.find(p);
+    if (it != size_of.end()) free_host.emplace(it->second, p);
+  }
+  ~gw_devcache() {
+    for (auto& kv : free_dev) rt_free(kv.second);
+    for (auto& kv : free_host) {
+      if (audit_mode()) free(kv.second);
+      else hipHostFree(kv.second);
+    }
+  }
+};
+
+namespace {
+// pinned host memory of a context: from its cache, else the runtime
+hipError_t host_alloc(gw_devcache* cache, void** p, size_t bytes) {
+  if (cache) return cache->get_host(p, bytes);
+  if (audit_mode()) {
+    *p = calloc(bytes, 1);
+    return *p ? hipSuccess : hipErrorOutOfMemory;
+  }
+  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+void host_free(gw_devcache* cache, void* p) {
+  if (!p) return;
+  if (cache) cache->put_host(p);
+  else if (audit_mode()) free(p);
+  else hipHostFree(p);
+}
+}  // namespace
+
 struct gw_ctx {
+  // device and pinned host blocks come from this cache when set (server contexts)
+  gw_devcache* cache = nullptr;
   // sizes
   int n_mo = 0, n_occ = 0, n_virt = 0, n_aux = 0, n_rows = 0;
   // spins: 1 (closed shell) or 2 (open shell, up then down); per-spin
@@ -337,7 +463,7 @@ struct gw_ctx {
     if (mem_budget && mem_used + bytes > mem_budget)
       return fail(GW_ENOMEM, "device memory budget exceeded: need %zu more bytes, %zu of %zu used",
                   bytes, mem_used, mem_budget);
-    hipError_t e = rt_malloc(p, bytes);
+    hipError_t e = cache ? cache->get_dev(p, bytes) : rt_malloc(p, bytes);
     if (e != hipSuccess) return fail(GW_ENOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
     allocs.push_back(*p);
     mem_used += bytes;
@@ -352,7 +478,8 @@ struct gw_ctx {
       alloc_sizes.erase(it);
     }
     allocs.erase(std::remove(allocs.begin(), allocs.end(), p), allocs.end());
-    rt_free(p);
+    if (cache) cache->put_dev(p);
+    else rt_free(p);
   }
   // elements of size `elem` reachable from p inside its allocation (0 if none)
   long ext(const void* p, size_t elem) const {
@@ -370,17 +497,14 @@ struct gw_ctx {
   ~gw_ctx() {
     if (st) hipStreamSynchronize(st);
     drop_graphs();
-    for (void* p : allocs) rt_free(p);
+    for (void* p : allocs) {
+      if (cache) cache->put_dev(p);
+      else rt_free(p);
+    }
     for (hipEvent_t e : {ev0, ev1, ev0b, ev1b, ev_poll[0], ev_poll[1], ev_quad[0], ev_quad[1]})
       if (e) hipEventDestroy(e);
-    if (h_stage) {
-      if (audit_mode()) free(h_stage);
-      else hipHostFree(h_stage);
-    }
-    if (h_poll) {
-      if (audit_mode()) free(h_poll);
-      else hipHostFree(h_poll);
-    }
+    host_free(cache, h_stage);
+    host_free(cache, h_poll);
     if (own_stream && st) hipStreamDestroy(st);
   }
 };
@@ -431,8 +555,8 @@ int setup_work(gw_ctx* c, int G) {
   size_t per_bytes = (size_t)per_g * sizeof(double) + (size_t)c->Kp * (sizeof(double) + sizeof(float)) +
                      PANEL * PANEL * sizeof(double) + (size_t)parts_per_g(c) * sizeof(double);
   if (c->wc_prec == GW_PI_BF16X3) per_bytes += (size_t)c->Np * c->Np * 2 * sizeof(uint16_t);
-  int chunk = (int)std::max<size_t>(1, c->work_budget / per_bytes);
-  if (chunk > G) chunk = G;
+  const int chunk = (int)std::min<size_t>(std::max<size_t>(1, c->work_budget / per_bytes),
+                                          (size_t)std::max(G, 1));
   if (c->d_work && c->chunk >= chunk) return 0;
   if (c->d_work) c->release(c->d_work);
   if (c->d_Linv) c->release(c->d_Linv);
@@ -512,12 +636,17 @@ int pi_build_chunk(gw_ctx* c, int G, long per_g, long ldA) {
 
 // Operands of the mixed W^c contraction: R split once per context, the F
 // buffer sized for the current chunk.
-int ensure_wc_mixed(gw_ctx* c) {
+int ensure_r_split(gw_ctx* c) {
   if (!c->d_Rh) {
     const size_t n = (size_t)c->Rp * c->Np;
     RCHK(c->alloc((void**)&c->d_Rh, 2 * n * sizeof(uint16_t)));
     HIPCHK(split_bf16(c->d_R, c->d_Rh, c->d_Rh + n, nullptr, (long)n, c->st));
   }
+  return 0;
+}
+
+int ensure_wc_mixed(gw_ctx* c) {
+  RCHK(ensure_r_split(c));
   if (c->f_cap < c->chunk) {
     if (c->d_F) c->release(c->d_F);
     c->d_F = nullptr;
@@ -543,9 +672,12 @@ int ensure_mixed_operands(gw_ctx* c) {
 // [0, Np) of 1 - Pi and the appended identity rows; panel k carries the
 // appended rows up to Np + k + PANEL only (the later ones are still unit rows
 // that the panel does not touch).
-int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
+// deferred: the pivot flags are left in d_info for the caller to read (no host
+// synchronisation, no memset: the sequence can be captured into a graph)
+int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA, bool deferred = false) {
   const int Np = c->Np;
-  HIPCHK(rt_memset(c->d_info, 0, G * sizeof(int), c->st));
+  if (deferred) HIPCHK(fill_int(c->d_info, G, 0, c->ext(c->d_info, 4), c->st));
+  else HIPCHK(rt_memset(c->d_info, 0, G * sizeof(int), c->st));
   if (c->test_indefinite)
     HIPCHK(reflect_unit(c->d_work, ldA, per_g, Np, G, c->ext(c->d_work, 8), c->st));
   HIPCHK(set_identity_rows(c->d_work, ldA, per_g, Np, Np, Np, G, c->ext(c->d_work, 8), c->st));
@@ -588,6 +720,7 @@ int cholesky_chunk(gw_ctx* c, int G, long per_g, long ldA) {
       RCHK(run_gemm(c, a, 2, KC, KC, EPI_AXPBY));
     }
   }
+  if (deferred) return 0;
   std::vector<int> info(G);
   HIPCHK(rt_memcpy(info.data(), c->d_info, G * sizeof(int), hipMemcpyDeviceToHost, c->st));
   HIPCHK(rt_sync(c->st));
@@ -773,16 +906,11 @@ int ensure_stage(gw_ctx* c, size_t bytes) {
   HIPCHK(rt_sync(c->st));
   const size_t cap = std::max<size_t>(64 << 10, 2 * bytes);
   char* p = nullptr;
-  if (audit_mode()) {
-    p = (char*)calloc(cap, 1);
-    if (!p) return fail(GW_ENOMEM, "host allocation failed");
-  } else if (hipHostMalloc((void**)&p, cap, hipHostMallocDefault) != hipSuccess) {
+  if (host_alloc(c->cache, (void**)&p, cap) != hipSuccess)
     return fail(GW_ENOMEM, "pinned host allocation of %zu bytes failed", cap);
-  }
   if (c->h_stage) {
     memcpy(p, c->h_stage, c->h_stage_cap);
-    if (audit_mode()) free(c->h_stage);
-    else hipHostFree(c->h_stage);
+    host_free(c->cache, c->h_stage);
   }
   c->h_stage = p;
   c->h_stage_cap = cap;
@@ -1737,7 +1865,8 @@ struct SetupIn {
   const double* B_rows;
 };
 
-int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts);
+int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts,
+               gw_devcache* cache = nullptr);
 
 // ===========================================================================
 // C-ABI
@@ -1850,7 +1979,7 @@ int gw_setup_uhf(gw_ctx** out, int n_mo, const int* n_occ, int n_aux, const doub
 
 }  // extern "C"
 
-int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts) {
+int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts, gw_devcache* cache) {
   *out = nullptr;
   const int n_mo = in.n_mo, n_aux = in.n_aux, n_rows = in.n_rows, n_spin = in.n_spin;
   long Ks[2] = {0, 0};
@@ -1867,6 +1996,7 @@ int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts) {
     return fail(GW_EINVAL, "negative or non-finite option");
 
   gw_ctx* c = new gw_ctx();
+  c->cache = cache;
   g_contexts_created = true;
   c->n_spin = n_spin;
   c->n_occ_s[0] = in.n_occ[0];
@@ -1939,12 +2069,8 @@ int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts) {
        hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) != hipSuccess ||
        hipEventCreate(&c->ev_quad[0]) != hipSuccess || hipEventCreate(&c->ev_quad[1]) != hipSuccess))
     return cleanup(fail(GW_EDEVICE, "hipEventCreate failed"));
-  if (audit_mode()) {
-    c->h_poll = (int*)calloc(2, sizeof(int));
-    if (!c->h_poll) return cleanup(fail(GW_ENOMEM, "host allocation failed"));
-  } else if (hipHostMalloc((void**)&c->h_poll, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+  if (host_alloc(c->cache, (void**)&c->h_poll, 2 * sizeof(int)) != hipSuccess)
     return cleanup(fail(GW_ENOMEM, "pinned host allocation failed"));
-  }
   if ((rc = c->alloc((void**)&c->d_eps, (size_t)n_so * sizeof(double)))) return cleanup(rc);
   if ((rc = c->alloc((void**)&c->d_D, (size_t)c->Kp * sizeof(double)))) return cleanup(rc);
   if ((rc = c->alloc((void**)&c->d_Bov, (size_t)c->Np * c->Kp * sizeof(double)))) return cleanup(rc);
@@ -1996,6 +2122,14 @@ int setup_validated(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* 
                     const gw_opts* opts) {
   SetupIn in{1, n_mo, {n_occ, n_occ}, n_aux, eps, {B_ov, nullptr}, n_rows, row_ids, B_rows};
   return setup_core(out, in, opts);
+}
+
+// A server context: its device and pinned host blocks come from `cache`.
+int setup_cached(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps,
+                 const double* B_ov, int n_rows, const int* row_ids, const double* B_rows,
+                 const gw_opts* opts, gw_devcache* cache) {
+  SetupIn in{1, n_mo, {n_occ, n_occ}, n_aux, eps, {B_ov, nullptr}, n_rows, row_ids, B_rows};
+  return setup_core(out, in, opts, cache);
 }
 
 extern "C" {
@@ -2294,3 +2428,380 @@ int gw_audit_enable(void) {
 long gw_audit_launch_count(void) { return audit_count(); }
 
 }  // extern "C"
+
+// ===========================================================================
+// Grouped stage A (serving).  Requests of one padded shape (Np, Kp, Rp) share
+// one set of stage-A launches: batch item b = j * Gx + g is grid point g of
+// request j (the serving grid extended by xi = 0 for the preconditioner), the
+// per-request operands (B_ov and its mixed copies, D, R and its split, |b|^2,
+// the W^c table and M^-1) are read through device tables of pointers, and the
+// per-item work (scales, 1 - Pi, Cholesky, L^-1, W^c partials) lives in the
+// group's own workspace.  The launch sequence for n requests is captured once
+// into a graph and replayed for every later batch of n: only the pointer
+// tables change between replays.
+
+namespace {
+enum { T_BOV, T_D, T_R, T_BN, T_WTAB, T_PRE, T_B32, T_BHI, T_BLO, T_RH, T_COUNT };
+}
+
+struct gw_group {
+  gw_ctx* lead = nullptr;   // owns the workspace for n_max * Gx items and the stream
+  int Np = 0, Kp = 0, Rp = 0, Gx = 0, n_max = 0;
+  int pi_prec = 0, wc_prec = 0;
+  std::vector<double> xi, w;          // serving grid, then xi = 0 (weight 0)
+  void** d_tab = nullptr;             // [T_COUNT][n_max] pointers, then n_max ints (Kov)
+  void** h_tab = nullptr;             // pinned host copy
+  int* h_info = nullptr;              // pinned: Cholesky pivot flags of a batch
+  std::vector<hipGraphExec_t> graphs; // [n]: the launch sequence for n requests
+  long batches = 0, items = 0, replays = 0;
+  size_t tab_bytes() const { return (size_t)n_max * (T_COUNT * sizeof(void*) + sizeof(int)); }
+  ~gw_group() {
+    for (hipGraphExec_t g : graphs)
+      if (g) hipGraphExecDestroy(g);
+    if (lead) {
+      host_free(lead->cache, h_tab);
+      host_free(lead->cache, h_info);
+      delete lead;
+    }
+  }
+};
+
+namespace {
+
+// device elements each member operand must hold (checked per member per batch;
+// the launch guards are evaluated against these)
+struct GroupExt {
+  long bov, d, r, bn, wtab, pre, b32, bhalf, rh;
+};
+GroupExt group_ext(const gw_group* g) {
+  const long NK = (long)g->Np * g->Kp, RN = (long)g->Rp * g->Np;
+  return GroupExt{NK, g->Kp, RN, g->Rp, (long)g->Rp * g->Gx, (long)g->Np * g->Np, NK, NK, 2 * RN};
+}
+
+// the stage-A launches of a batch of n requests (tables already on the device)
+int group_sequence(gw_group* g, int n) {
+  gw_ctx* L = g->lead;
+  const int G = n * g->Gx, Np = g->Np, Kp = g->Kp, Rp = g->Rp;
+  const long ldA = work_ld(L), per_g = work_per_g(L);
+  const GroupExt ex = group_ext(g);
+  void** tab = g->d_tab;
+  auto T = [&](int k) { return tab + (size_t)k * g->n_max; };
+  const int* kov = reinterpret_cast<const int*>(T(T_COUNT));
+  HIPCHK(make_scale_imag_tab((const double* const*)T(T_D), kov, Kp, L->d_grid, g->Gx, G,
+                             L->d_scale, g->pi_prec == GW_PI_FP64 ? nullptr : L->d_scale32, ex.d,
+                             L->ext(L->d_grid, 8), L->ext(L->d_scale, 8),
+                             L->ext(L->d_scale32, 4), L->st));
+  if (g->pi_prec == GW_PI_FP64) {
+    GemmArgs a{};
+    a.Atab = (const double* const*)T(T_BOV); a.lda = Kp;
+    a.Btab = (const double* const*)T(T_BOV); a.ldb = Kp;
+    a.grp = g->Gx;
+    a.scale = L->d_scale; a.sS = Kp;
+    a.C = L->d_work; a.ldc = ldA; a.sC = per_g;
+    a.M = Np; a.N = Np; a.K = Kp;
+    a.map = MAP_LOWER;
+    a.tiles_m = Np / 128; a.tiles_n = Np / 128;
+    a.n_tiles = (int)lower_tile_count(a.tiles_m, a.tiles_n, 128, 128);
+    a.batch = G; a.splitk = 1;
+    a.nA = ex.bov; a.nB = ex.bov;
+    a.nS = L->ext(L->d_scale, 8); a.nC = L->ext(L->d_work, 8);
+    HIPCHK(gemm_f64(a, 0, KC, KC, EPI_ONE_PLUS_4, L->st));
+  } else {
+    OperandTabs tb{};
+    tb.B32 = (const float* const*)T(T_B32);
+    tb.Bhi = (const uint16_t* const*)T(T_BHI);
+    tb.Blo = (const uint16_t* const*)T(T_BLO);
+    tb.grp = g->Gx;
+    if (g->pi_prec == GW_PI_FP32)
+      HIPCHK(pi_build_f32_tab(tb, Kp, L->d_scale32, Kp, L->d_work, ldA, per_g, Np, Kp, G, ex.b32,
+                              L->ext(L->d_scale32, 4), L->ext(L->d_work, 8), L->st));
+    else
+      HIPCHK(pi_build_bf16x3_tab(tb, Kp, L->d_scale32, Kp, L->d_work, ldA, per_g, Np, Kp, G,
+                                 std::min(ex.b32, ex.bhalf), L->ext(L->d_scale32, 4),
+                                 L->ext(L->d_work, 8), L->st));
+  }
+  RCHK(cholesky_chunk(L, G, per_g, ldA, true));
+  const double* X = L->d_work + (long)Np * ldA;   // L^-T rows of every item
+  if (g->wc_prec == GW_PI_BF16X3) {
+    const long sF = (long)Np * Np;
+    const long nF = (long)L->f_cap * sF;
+    uint16_t* Fh = L->d_F;
+    uint16_t* Fl = L->d_F + nF;
+    HIPCHK(split_linv(X, ldA, per_g, Np, G, Fh, Fl, sF, L->ext(X, 8), nF, L->st));
+    OperandTabs tb{};
+    tb.Rh = (const uint16_t* const*)T(T_RH);
+    tb.grp = g->Gx;
+    HIPCHK(wc_bf16x3_tab(tb, (long)Rp * Np, Np, Rp, Fh, Fl, sF, Np, G, L->d_parts, parts_ld(L),
+                         parts_per_g(L), ex.rh / 2, nF, L->ext(L->d_parts, 8), L->st));
+    HIPCHK(wc_from_parts_tab(L->d_parts, parts_per_g(L), Np / 128, parts_ld(L), nullptr, Rp, G,
+                             g->Gx, (double* const*)T(T_WTAB), L->ext(L->d_parts, 8), 0, ex.wtab,
+                             L->st));
+  } else {
+    GemmArgs a{};
+    a.Atab = (const double* const*)T(T_R); a.lda = Np; a.grp = g->Gx;
+    a.B = X; a.ldb = ldA; a.sB = per_g;
+    a.C = L->d_parts; a.ldc = parts_ld(L); a.sC = parts_per_g(L);
+    a.M = Rp; a.N = Np; a.K = Np;
+    a.map = MAP_FULL_J; a.tiles_m = Rp / 128; a.tiles_n = Np / 128;
+    a.n_tiles = a.tiles_m * a.tiles_n; a.batch = G; a.splitk = 1; a.ktri = 1;
+    a.nA = ex.r; a.nB = L->ext(X, 8); a.nC = L->ext(L->d_parts, 8);
+    HIPCHK(gemm_f64(a, 0, KC, KM, EPI_SQNORM, L->st));
+    HIPCHK(wc_from_parts_tab(L->d_parts, parts_per_g(L), Np / 128, parts_ld(L),
+                             (const double* const*)T(T_BN), Rp, G, g->Gx,
+                             (double* const*)T(T_WTAB), L->ext(L->d_parts, 8), ex.bn, ex.wtab,
+                             L->st));
+  }
+  {  // M^-1 = X0 X0^T of each request, X0 from its xi = 0 item (the last)
+    GemmArgs a{};
+    const double* X0 = X + (long)(g->Gx - 1) * per_g;
+    a.A = X0; a.lda = ldA; a.sA = (long)g->Gx * per_g;
+    a.B = X0; a.ldb = ldA; a.sB = (long)g->Gx * per_g;
+    a.Ctab = (double* const*)T(T_PRE); a.ldc = Np; a.grp = 1;
+    a.M = Np; a.N = Np; a.K = Np;
+    a.map = MAP_FULL; a.tiles_m = Np / 64; a.tiles_n = Np / 128;
+    a.n_tiles = a.tiles_m * a.tiles_n; a.batch = n; a.splitk = 1;
+    a.alpha = 1.0; a.beta = 0.0;
+    a.nA = L->ext(X0, 8); a.nB = a.nA; a.nC = ex.pre;
+    HIPCHK(gemm_f64(a, 2, KC, KC, EPI_AXPBY, L->st));
+  }
+  return 0;
+}
+
+// a member context of the group's shape, made ready for one batch: its W^c
+// table and M^-1 buffers allocated, its mixed copies split
+int group_member_prepare(gw_group* g, gw_ctx* m) {
+  if (m->Np != g->Np || m->Kp != g->Kp || m->Rp != g->Rp || m->n_spin != 1 ||
+      m->pi_prec != g->pi_prec || m->wc_prec != g->wc_prec || m->no_precond)
+    return fail(GW_EINVAL, "request does not match the group's shape or options");
+  const size_t wt = (size_t)g->Rp * g->Gx;
+  if (m->d_wtab && m->ext(m->d_wtab, 8) < (long)wt) {
+    m->release(m->d_wtab);
+    m->d_wtab = nullptr;
+  }
+  if (!m->d_wtab) RCHK(m->alloc((void**)&m->d_wtab, wt * sizeof(double)));
+  if (!m->d_pre) RCHK(m->alloc((void**)&m->d_pre, (size_t)g->Np * g->Np * sizeof(double)));
+  if (g->pi_prec != GW_PI_FP64) RCHK(ensure_mixed_operands(m));
+  if (g->wc_prec == GW_PI_BF16X3) RCHK(ensure_r_split(m));
+  const GroupExt ex = group_ext(g);
+  const bool ok = m->ext(m->d_Bov, 8) >= ex.bov && m->ext(m->d_D, 8) >= ex.d &&
+                  m->ext(m->d_R, 8) >= ex.r && m->ext(m->d_bn, 8) >= ex.bn &&
+                  m->ext(m->d_wtab, 8) >= ex.wtab && m->ext(m->d_pre, 8) >= ex.pre &&
+                  (g->pi_prec == GW_PI_FP64 ||
+                   (m->ext(m->d_B32, 4) >= ex.b32 && m->ext(m->d_Bhi, 2) >= ex.bhalf &&
+                    m->ext(m->d_Blo, 2) >= ex.bhalf)) &&
+                  (g->wc_prec != GW_PI_BF16X3 || m->ext(m->d_Rh, 2) >= ex.rh);
+  if (!ok) return fail(GW_EINVAL, "member buffers smaller than the group's shape");
+  return 0;
+}
+
+// the member's W^c table (and preconditioner) now hold the group's results
+void group_member_finish(gw_group* g, gw_ctx* m) {
+  m->wtab_valid = true;
+  m->wtab_G = g->Gx;
+  m->wtab_w0 = 1;
+  m->wtab_w0col = true;
+  m->quad_G = g->Gx - 1;
+  m->wtab_prec = g->pi_prec;
+  m->wtab_wcprec = g->wc_prec;
+  m->wtab_xi = g->xi;
+  m->wtab_w = g->w;
+  double dmin = INFINITY;
+  const double* e = m->eps.data();
+  dmin = *std::min_element(e + m->n_occ, e + m->n_mo) - *std::max_element(e, e + m->n_occ);
+  m->pre_w = 0.9 * dmin;
+  m->pre_valid = true;
+}
+
+}  // namespace
+
+// Creates a group for requests of padded shape (Np, Kp, Rp) on `grid` (the
+// xi = 0 point is appended), batches of at most n_max, with its own stream and
+// workspace; device and pinned blocks from `cache` (nullable).
+int group_create(gw_group** out, int Np, int Kp, int Rp, const gw_grid* grid, int n_max,
+                 int pi_prec, int wc_prec, gw_devcache* cache, bool graphs) {
+  *out = nullptr;
+  RCHK(check_grid(grid));
+  if (Np < 128 || Np % 128 || Kp < 128 || Kp % 128 || Rp < 128 || Rp % 128 || n_max < 1 ||
+      n_max > 64)
+    return fail(GW_EINVAL, "bad group shape");
+  gw_group* g = new gw_group();
+  g->Np = Np; g->Kp = Kp; g->Rp = Rp; g->Gx = grid->n + 1; g->n_max = n_max;
+  g->pi_prec = pi_prec; g->wc_prec = wc_prec;
+  g->xi.assign(grid->xi, grid->xi + grid->n);
+  g->w.assign(grid->w, grid->w + grid->n);
+  g->xi.push_back(0.0);
+  g->w.push_back(0.0);
+  g->graphs.assign(n_max + 1, nullptr);
+  gw_ctx* L = new gw_ctx();
+  g->lead = L;
+  L->cache = cache;
+  L->n_mo = 2; L->n_occ = 1; L->n_virt = 1; L->n_aux = Np;
+  L->Np = Np; L->Kp = Kp; L->Kov = Kp; L->Rp = Rp; L->nR = Rp;
+  L->pi_prec = pi_prec; L->wc_prec = wc_prec;
+  L->work_budget = (size_t)1 << 62;     // one chunk holds every item of a full batch
+  L->graphs_off = !graphs || debug_sync();
+  if (const char* e = getenv("GW_TEST_INDEFINITE")) L->test_indefinite = atoi(e) != 0;
+  auto bad = [&](int rc) {
+    std::string keep = g_err;
+    delete g;
+    g_err = keep;
+    return rc;
+  };
+  if (!audit_mode()) {
+    if (hipStreamCreateWithFlags(&L->st, hipStreamNonBlocking) != hipSuccess)
+      return bad(fail(GW_EDEVICE, "hipStreamCreate failed"));
+    L->own_stream = true;
+  }
+  int rc;
+  if ((rc = setup_work(L, n_max * g->Gx))) return bad(rc);
+  if ((rc = upload_grid(L, g->Gx, g->xi.data(), g->w.data()))) return bad(rc);
+  if (wc_prec == GW_PI_BF16X3) {
+    if ((rc = L->alloc((void**)&L->d_F, 2 * (size_t)L->chunk * Np * Np * sizeof(uint16_t))))
+      return bad(rc);
+    L->f_cap = L->chunk;
+  }
+  if ((rc = L->alloc((void**)&g->d_tab, g->tab_bytes()))) return bad(rc);
+  if (host_alloc(cache, (void**)&g->h_tab, g->tab_bytes()) != hipSuccess ||
+      host_alloc(cache, (void**)&g->h_info, (size_t)n_max * g->Gx * sizeof(int)) != hipSuccess)
+    return bad(fail(GW_ENOMEM, "pinned host allocation failed"));
+  if (rt_sync(L->st) != hipSuccess) return bad(fail(GW_EDEVICE, "group setup failed"));
+  *out = g;
+  return 0;
+}
+
+void group_free(gw_group* g) { delete g; }
+
+// Moves a context to another stream (its pending work on the old one is
+// finished first); the server uses it to run a request's quasiparticle stage
+// on the pipeline that picks it up.
+int ctx_set_stream(gw_ctx* c, hipStream_t st) {
+  if (c->st == st) return 0;
+  HIPCHK(rt_sync(c->st));
+  if (c->own_stream && c->st) hipStreamDestroy(c->st);
+  c->own_stream = false;
+  c->st = st;
+  return 0;
+}
+
+// padded shape of a closed-shell request (the context's Np, Kp, Rp)
+void padded_shape(int n_mo, int n_occ, int n_aux, int n_rows, int* Np, int* Kp, int* Rp) {
+  *Np = round_up(n_aux, 128);
+  *Kp = round_up(n_occ * (n_mo - n_occ), 128);
+  *Rp = round_up(std::max(n_rows * n_mo, 1), 128);
+}
+
+// device bytes of a group's workspace for batches of n (the pointer tables aside)
+size_t group_bytes(int Np, int Kp, int Rp, int grid_n, int n, int pi_prec, int wc_prec) {
+  const size_t d = sizeof(double);
+  const size_t items = (size_t)n * (grid_n + 1);
+  const size_t per_g = (size_t)(2L * Np + 128) * (Np + 128);
+  size_t b = items * (per_g * d + (size_t)(Np / 128) * Rp * d + PANEL * PANEL * d + sizeof(int) +
+                      (size_t)Kp * (d + 4));
+  if (wc_prec == GW_PI_BF16X3) b += items * (size_t)Np * Np * 4;
+  (void)pi_prec;
+  return b;
+}
+
+// Stage A of n member contexts (created with the group's padded shape and
+// options) in one replay of the group's graph.  rc[j] receives each member's
+// outcome: 0 (its W^c table and preconditioner are then cached, so gw_qp on it
+// goes straight to the quasiparticle stage) or GW_ENOTSPD.  Returns a hard
+// error for the whole batch (bad arguments, device failure) or 0.
+int group_run(gw_group* g, gw_ctx* const* m, int n, int* rc) {
+  if (!g || !m || n < 1 || n > g->n_max) return fail(GW_EINVAL, "bad group batch");
+  gw_ctx* L = g->lead;
+  for (int j = 0; j < n; ++j) RCHK(group_member_prepare(g, m[j]));
+  for (int j = 0; j < n; ++j) HIPCHK(rt_sync(m[j]->st));   // uploads and splits are done
+  void** T = g->h_tab;
+  std::fill(T, T + (size_t)T_COUNT * g->n_max, nullptr);
+  int* kov = reinterpret_cast<int*>(T + (size_t)T_COUNT * g->n_max);
+  for (int j = 0; j < g->n_max; ++j) {
+    gw_ctx* c = m[std::min(j, n - 1)];   // unused entries repeat the last member
+    T[T_BOV * g->n_max + j] = c->d_Bov;
+    T[T_D * g->n_max + j] = c->d_D;
+    T[T_R * g->n_max + j] = c->d_R;
+    T[T_BN * g->n_max + j] = c->d_bn;
+    T[T_WTAB * g->n_max + j] = c->d_wtab;
+    T[T_PRE * g->n_max + j] = c->d_pre;
+    T[T_B32 * g->n_max + j] = c->d_B32;
+    T[T_BHI * g->n_max + j] = c->d_Bhi;
+    T[T_BLO * g->n_max + j] = c->d_Blo;
+    T[T_RH * g->n_max + j] = c->d_Rh;
+    kov[j] = c->Kov;
+  }
+  HIPCHK(rt_memcpy(g->d_tab, g->h_tab, g->tab_bytes(), hipMemcpyHostToDevice, L->st));
+  if (!L->graphs_off && !audit_mode()) {
+    if (!g->graphs[n]) {
+      if (hipStreamBeginCapture(L->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        L->graphs_off = true;
+      } else {
+        const int r = group_sequence(g, n);
+        hipGraph_t gr = nullptr;
+        const hipError_t e = hipStreamEndCapture(L->st, &gr);
+        if (r != 0 || e != hipSuccess) {
+          if (gr) hipGraphDestroy(gr);
+          if (r != 0) return r;
+          HIPCHK(e);
+        }
+        const hipError_t ei = hipGraphInstantiate(&g->graphs[n], gr, nullptr, nullptr, 0);
+        hipGraphDestroy(gr);
+        HIPCHK(ei);
+        trace("group graph captured Np=%d Kp=%d Rp=%d n=%d", g->Np, g->Kp, g->Rp, n);
+      }
+    }
+  }
+  if (g->graphs[n]) {
+    HIPCHK(hipGraphLaunch(g->graphs[n], L->st));
+    g->replays++;
+  } else {
+    RCHK(group_sequence(g, n));
+  }
+  const int items = n * g->Gx;
+  HIPCHK(rt_memcpy(g->h_info, L->d_info, (size_t)items * sizeof(int), hipMemcpyDeviceToHost, L->st));
+  HIPCHK(rt_sync(L->st));
+  g->batches++;
+  g->items += items;
+  for (int j = 0; j < n; ++j) {
+    rc[j] = 0;
+    for (int q = 0; q < g->Gx; ++q)
+      if (g->h_info[j * g->Gx + q] != 0) rc[j] = GW_ENOTSPD;
+    if (rc[j] == 0) group_member_finish(g, m[j]);
+    else m[j]->wtab_valid = false;
+  }
+  return 0;
+}
+
+void group_stats(const gw_group* g, long* batches, long* items, long* replays) {
+  *batches = g->batches;
+  *items = g->items;
+  *replays = g->replays;
+}
+
+gw_devcache* devcache_create(size_t cap) {
+  gw_devcache* c = new gw_devcache();
+  c->cap = cap;
+  return c;
+}
+void devcache_destroy(gw_devcache* c) { delete c; }
+void devcache_stats(gw_devcache* c, long* mallocs, long* hits, size_t* live, size_t* cached) {
+  std::lock_guard<std::mutex> lk(c->mu);
+  *mallocs = c->n_malloc;
+  *hits = c->n_hits;
+  *live = c->live;
+  *cached = c->cached;
+}
+
+extern "C" int gw_group_stage_a(int n, gw_ctx* const* ctxs, const gw_grid* grid, int use_graph,
+                                int* rc) {
+  if (n < 1 || !ctxs || !rc) return fail(GW_EINVAL, "bad arguments");
+  for (int j = 0; j < n; ++j)
+    if (!ctxs[j]) return fail(GW_EINVAL, "NULL context");
+  const gw_ctx* c0 = ctxs[0];
+  gw_group* g = nullptr;
+  RCHK(group_create(&g, c0->Np, c0->Kp, c0->Rp, grid, n, c0->pi_prec, c0->wc_prec, nullptr,
+                    use_graph != 0));
+  const int r = group_run(g, ctxs, n, rc);
+  group_free(g);
+  return r == 0 ? finish() : r;
+}

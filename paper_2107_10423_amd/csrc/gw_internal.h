@@ -77,6 +77,14 @@ struct GemmArgs {
                                         // whose outputs nobody reads: MFMAs skipped, and a
                                         // tile without a live block writes nothing
                                         // (nullptr: every block is computed)
+  // Grouped launches (several requests' grid points in one launch): batch item b
+  // belongs to request b / grp; a non-null table replaces the strided operand
+  // base (A + b sA, B + b sB, C + b sC) by that request's pointer.  The host
+  // then passes as nA / nB / nC the smallest extent over the table's pointers.
+  const double* const* Atab;
+  const double* const* Btab;
+  double* const* Ctab;
+  int grp;
   double alpha, beta;
   const double* Dvec;                   // transition energies (EPI_RES_*)
   const double* wrow;                   // per-row real frequency (EPI_RES_*)
@@ -95,6 +103,24 @@ hipError_t pi_build_f32(const float* B32, long ld, const float* scale, long sS, 
 hipError_t pi_build_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, long ld, const float* B32,
                            const float* scale, long sS, double* A, long ldA, long sA, int Np,
                            int Kp, int G, long nB, long nS, long nA, hipStream_t st);
+// Per-request operand tables of a grouped launch: item g of the batch reads the
+// operands of request g / grp.  Null tables: the single-request operands.
+struct OperandTabs {
+  const float* const* B32;        // pi builds: FP32 copy of each request's B_ov
+  const uint16_t* const* Bhi;     // pi builds: bf16 hi of each request's B_ov (lo follows
+  const uint16_t* const* Blo;     //   in its own table)
+  const uint16_t* const* Rh;      // mixed W^c: each request's split R (hi; lo at +nRR)
+  int grp;
+};
+hipError_t pi_build_f32_tab(const OperandTabs& tb, long ld, const float* scale, long sS,
+                            double* A, long ldA, long sA, int Np, int Kp, int G, long nB,
+                            long nS, long nA, hipStream_t st);
+hipError_t pi_build_bf16x3_tab(const OperandTabs& tb, long ld, const float* scale, long sS,
+                               double* A, long ldA, long sA, int Np, int Kp, int G, long nB,
+                               long nS, long nA, hipStream_t st);
+hipError_t wc_bf16x3_tab(const OperandTabs& tb, long nRR, long ldR, int Rp, const uint16_t* Fh,
+                         const uint16_t* Fl, long sF, int Np, int G, double* part, long ldp,
+                         long sP, long nR, long nF, long nP, hipStream_t st);
 hipError_t split_bf16(const double* B, uint16_t* hi, uint16_t* lo, float* b32, long n, hipStream_t st);
 // mixed W^c contraction: F = L^-1 - I split from X = L^-T (k-major), then
 // part[g][J][q] = sum over panel J of (2 b + y) y with y = F b (BF16x3)
@@ -117,6 +143,14 @@ hipError_t set_identity_rows(double* A, long ldA, long sA, int row0, int n, int 
 hipError_t wc_from_parts(const double* part, long sPart, int nJ, int ldp, const double* bnorm2,
                          int nR, int G, int Gtot, int g0, double* wtab, long nPart, long nBn,
                          long nW, hipStream_t st);
+// grouped form: item g writes column g % grp of request g / grp's table
+// (wtab_tab, bn_tab: per-request pointers, bn_tab null for the mixed form)
+hipError_t wc_from_parts_tab(const double* part, long sPart, int nJ, int ldp,
+                             const double* const* bn_tab, int nR, int G, int grp,
+                             double* const* wtab_tab, long nPart, long nBn, long nW,
+                             hipStream_t st);
+// fills n ints with v (graph-safe replacement for a memset)
+hipError_t fill_int(int* p, int n, int v, long nP, hipStream_t st);
 
 // prep
 // stacked transition energies of n_spin (1 or 2) spins, eps [n_spin][n_mo]
@@ -130,6 +164,11 @@ hipError_t make_scale_real(const double* D, int Kov, int Kp, double w, double* s
 hipError_t copy_vec(const double* src, double* dst, int n, long nSrc, long nDst, hipStream_t st);
 hipError_t make_scale_imag(const double* D, int Kov, int Kp, const double* xi, int G, double* s,
                            float* s32, long nD, long nXi, long nS, long nS32, hipStream_t st);
+// grouped form: item g uses request g / grp's transition energies and its
+// count Kov_tab[g / grp] of real columns, and grid point xi[g % grp]
+hipError_t make_scale_imag_tab(const double* const* D_tab, const int* Kov_tab, int Kp,
+                               const double* xi, int grp, int G, double* s, float* s32,
+                               long nD, long nXi, long nS, long nS32, hipStream_t st);
 
 // Sigma quadrature of n states: per state j, -(1/pi) sum_m sum_{g<G} W[row_j][m][g] z_g
 // a/(a^2+xi^2) and its derivative, the table holding ld columns per m; w0 != 0: column G

@@ -4,9 +4,19 @@
 // its context capped at its reserved footprint.  Inputs are validated and
 // copied into pinned host memory (a reused pool) on the submitting thread, so
 // a slot's upload is one DMA that overlaps the other slots' kernels.
+//
+// Small requests are batched by padded shape: the slot that admits one takes
+// every pending request of that shape along (continuous batching: whatever
+// has arrived by then), runs their stage A as one grouped launch sequence
+// replayed from the shape's captured graph, and queues them for their
+// quasiparticle stages, which any free slot picks up before admitting new
+// work.  Contexts draw their device and pinned blocks from a server-wide
+// cache, so requests of recurring shapes reuse memory instead of calling
+// hipMalloc / hipFree.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -20,6 +30,22 @@
 
 size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, int G,
                        int pi_prec, int wc_prec, size_t work_budget, int minres_batch);
+struct gw_devcache;
+struct gw_group;
+int setup_cached(gw_ctx** out, int n_mo, int n_occ, int n_aux, const double* eps,
+                 const double* B_ov, int n_rows, const int* row_ids, const double* B_rows,
+                 const gw_opts* opts, gw_devcache* cache);
+int group_create(gw_group** out, int Np, int Kp, int Rp, const gw_grid* grid, int n_max,
+                 int pi_prec, int wc_prec, gw_devcache* cache, bool graphs);
+void group_free(gw_group* g);
+size_t group_bytes(int Np, int Kp, int Rp, int grid_n, int n, int pi_prec, int wc_prec);
+int group_run(gw_group* g, gw_ctx* const* m, int n, int* rc);
+void group_stats(const gw_group* g, long* batches, long* items, long* replays);
+int ctx_set_stream(gw_ctx* c, hipStream_t st);
+void padded_shape(int n_mo, int n_occ, int n_aux, int n_rows, int* Np, int* Kp, int* Rp);
+gw_devcache* devcache_create(size_t cap);
+void devcache_destroy(gw_devcache* c);
+void devcache_stats(gw_devcache* c, long* mallocs, long* hits, size_t* live, size_t* cached);
 int validate_inputs(int n_mo, int n_occ, int n_aux, const double* eps, const double* B_ov,
                     int n_rows, const int* row_ids, const double* B_rows, bool check_arrays);
 long copy_check_finite(double* dst, const double* src, long n);
@@ -75,8 +101,21 @@ struct PinnedPool {
   }
 };
 
+// Requests of one padded shape batched together: the group (its workspace and
+// captured graphs) is created by the first batch and kept until the server is
+// destroyed; its workspace is reserved from the budget for that long.
+struct ShapeGroup {
+  int Np = 0, Kp = 0, Rp = 0, n_max = 1;
+  size_t bytes = 0;
+  bool usable = true;        // false: the workspace did not fit, requests run alone
+  std::mutex mu;             // one batch at a time
+  gw_group* g = nullptr;
+};
+
 struct Req {
   unsigned long long ticket = 0;
+  ShapeGroup* group = nullptr;   // set when the request may be batched
+  gw_ctx* ctx = nullptr;         // between a batch's stage A and the QP stage
   int n_mo = 0, n_occ = 0, n_aux = 0, n_rows = 0;
   std::vector<double> eps, dsig_x;
   // B_ov [n_aux][n_occ n_virt] then B_rows [n_rows][n_mo][n_aux]: pinned pool
@@ -99,6 +138,10 @@ struct Req {
 struct gw_server {
   gw_server_opts opts{};
   PinnedPool pinned;
+  gw_devcache* cache = nullptr;
+  std::map<std::array<int, 3>, ShapeGroup*> groups;
+  std::deque<Req*> qp_ready;     // stage A done (batched), waiting for a pipeline
+  long batches = 0, batched = 0;
   std::vector<double> xi, w;
   size_t budget = 0, reserved = 0, peak_reserved = 0;
   int active = 0, peak_active = 0;
@@ -115,42 +158,85 @@ struct gw_server {
 
   double now() const { return std::chrono::duration<double>(clk::now() - t0).count(); }
 
+  // caller holds mu
+  void admit(Req* r, int slot) {
+    reserved += r->footprint;
+    peak_reserved = std::max(peak_reserved, reserved);
+    active++;
+    peak_active = std::max(peak_active, active);
+    r->t_admit = now();
+    r->slot = slot;
+  }
+
+  void complete(Req* r) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      reserved -= r->footprint;
+      active--;
+      r->t_done = now();
+      r->done = true;
+      completed++;
+      if (r->rc) failed++;
+    }
+    cv_done.notify_all();
+    cv_work.notify_all();
+  }
+
   void run_slot(int slot) {
     hipSetDevice(device);
     for (;;) {
       Req* r = nullptr;
+      bool qp_stage = false;
+      std::vector<Req*> batch;
       {
         std::unique_lock<std::mutex> lk(mu);
         cv_work.wait(lk, [&] {
-          return stop || (!pending.empty() && reserved + pending.front()->footprint <= budget);
+          return stop || !qp_ready.empty() ||
+                 (!pending.empty() && reserved + pending.front()->footprint <= budget);
         });
-        if (stop && pending.empty()) return;
-        if (pending.empty() || reserved + pending.front()->footprint > budget) continue;
-        r = pending.front();
-        pending.pop_front();
-        reserved += r->footprint;
-        peak_reserved = std::max(peak_reserved, reserved);
-        active++;
-        peak_active = std::max(peak_active, active);
-        r->t_admit = now();
-        r->slot = slot;
+        if (!qp_ready.empty()) {
+          r = qp_ready.front();
+          qp_ready.pop_front();
+          qp_stage = true;
+        } else if (stop && pending.empty()) {
+          return;
+        } else if (pending.empty() || reserved + pending.front()->footprint > budget) {
+          continue;
+        } else {
+          r = pending.front();
+          pending.pop_front();
+          admit(r, slot);
+          ShapeGroup* sg = r->group;
+          if (sg && sg->usable) {
+            // every pending request of the same shape that fits joins the batch
+            batch.push_back(r);
+            for (auto it = pending.begin();
+                 it != pending.end() && (int)batch.size() < sg->n_max;) {
+              Req* q = *it;
+              if (q->group == sg && reserved + q->footprint <= budget) {
+                admit(q, slot);
+                batch.push_back(q);
+                it = pending.erase(it);
+              } else {
+                ++it;
+              }
+            }
+          }
+        }
       }
-      process(r, slot);
-      {
-        std::lock_guard<std::mutex> lk(mu);
-        reserved -= r->footprint;
-        active--;
-        r->t_done = now();
-        r->done = true;
-        completed++;
-        if (r->rc) failed++;
+      if (qp_stage) {
+        qp(r, slot);
+        complete(r);
+      } else if (batch.empty()) {
+        process(r, slot);
+        complete(r);
+      } else {
+        run_batch(batch, slot);
       }
-      cv_done.notify_all();
-      cv_work.notify_all();
     }
   }
 
-  void process(Req* r, int slot) {
+  gw_opts ctx_opts(const Req* r, int slot) const {
     gw_opts o{};
     o.pi_prec = opts.pi_prec;
     o.wc_prec = opts.wc_prec;
@@ -162,11 +248,16 @@ struct gw_server {
     o.stream = streams[slot];
     o.mem_budget_bytes = r->footprint;
     o.work_budget_bytes = opts.work_budget_bytes;
-    gw_ctx* c = nullptr;
+    return o;
+  }
+
+  // context of a request on the slot's stream; the pinned input copy is
+  // released once the device holds it (setup synchronises its stream)
+  int make_ctx(Req* r, int slot) {
+    gw_opts o = ctx_opts(r, slot);
     const size_t nov = (size_t)r->n_occ * (r->n_mo - r->n_occ);
-    int rc = setup_validated(&c, r->n_mo, r->n_occ, r->n_aux, r->eps.data(), r->B, r->n_rows,
-                             r->row_ids.data(), r->B + nov * r->n_aux, &o);
-    // the device holds its copies now (setup synchronises its stream)
+    int rc = setup_cached(&r->ctx, r->n_mo, r->n_occ, r->n_aux, r->eps.data(), r->B, r->n_rows,
+                          r->row_ids.data(), r->B + nov * r->n_aux, &o, cache);
     if (r->pinned_bytes) pinned.release(r->B, r->pinned_bytes);
     r->B = nullptr;
     r->pinned_bytes = 0;
@@ -176,13 +267,112 @@ struct gw_server {
     r->S.assign(n, 0.0);
     r->Z.assign(n, 0.0);
     r->status.assign(n, 0);
+    return rc;
+  }
+
+  // quasiparticle stage (and stage A, unless a batch already built it)
+  void qp(Req* r, int slot) {
+    int rc = ctx_set_stream(r->ctx, streams[slot]);
     if (rc == 0) {
       gw_grid g{(int)xi.size(), xi.data(), w.data()};
-      rc = gw_qp(c, n, r->states.data(), &g, r->E.data(), r->S.data(), r->Z.data(),
-                 r->status.data());
+      rc = gw_qp(r->ctx, (int)r->states.size(), r->states.data(), &g, r->E.data(), r->S.data(),
+                 r->Z.data(), r->status.data());
     }
-    gw_free(c);
+    gw_free(r->ctx);
+    r->ctx = nullptr;
     r->rc = rc;
+  }
+
+  void process(Req* r, int slot) {
+    const int rc = make_ctx(r, slot);
+    if (rc != 0) {
+      gw_free(r->ctx);
+      r->ctx = nullptr;
+      r->rc = rc;
+      return;
+    }
+    qp(r, slot);
+  }
+
+  // stage A of a batch of one shape in one grouped launch sequence; the
+  // members then wait in qp_ready for their quasiparticle stages
+  void run_batch(std::vector<Req*>& batch, int slot) {
+    ShapeGroup* sg = batch[0]->group;
+    std::vector<Req*> ok;
+    for (Req* r : batch) {
+      const int rc = make_ctx(r, slot);
+      if (rc != 0) {
+        gw_free(r->ctx);
+        r->ctx = nullptr;
+        r->rc = rc;
+        complete(r);
+      } else {
+        ok.push_back(r);
+      }
+    }
+    if (ok.empty()) return;
+    std::vector<gw_ctx*> ctxs;
+    for (Req* r : ok) ctxs.push_back(r->ctx);
+    std::vector<int> rcs(ok.size(), 0);
+    int rc = 0;
+    {
+      std::lock_guard<std::mutex> lk(sg->mu);
+      if (!sg->g) {
+        gw_grid g{(int)xi.size(), xi.data(), w.data()};
+        rc = group_create(&sg->g, sg->Np, sg->Kp, sg->Rp, &g, sg->n_max, opts.pi_prec,
+                          opts.wc_prec, cache, true);
+      }
+      if (rc == 0) rc = group_run(sg->g, ctxs.data(), (int)ctxs.size(), rcs.data());
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (rc == 0) {
+        batches++;
+        batched += (long)ok.size();
+      }
+      for (size_t j = 0; j < ok.size(); ++j) {
+        // a failed group leaves the member's stage A to its own gw_qp call
+        if (rc != 0 || rcs[j] == 0) qp_ready.push_back(ok[j]);
+      }
+    }
+    for (size_t j = 0; j < ok.size(); ++j) {
+      if (rc == 0 && rcs[j] != 0) {
+        gw_free(ok[j]->ctx);
+        ok[j]->ctx = nullptr;
+        ok[j]->rc = rcs[j];
+        complete(ok[j]);
+      }
+    }
+    cv_work.notify_all();
+  }
+
+  // the shape group of a small request (created, with its workspace reserved,
+  // on first use); caller holds mu
+  ShapeGroup* group_for(const Req* r) {
+    if (opts.batch_max_aux < 0) return nullptr;
+    const int lim = opts.batch_max_aux > 0 ? opts.batch_max_aux : 768;
+    int Np, Kp, Rp;
+    padded_shape(r->n_mo, r->n_occ, r->n_aux, r->n_rows, &Np, &Kp, &Rp);
+    if (Np > lim) return nullptr;
+    auto key = std::array<int, 3>{Np, Kp, Rp};
+    auto it = groups.find(key);
+    if (it != groups.end()) return it->second;
+    ShapeGroup* sg = new ShapeGroup();
+    sg->Np = Np;
+    sg->Kp = Kp;
+    sg->Rp = Rp;
+    // batch size: as many requests as 2 GiB of grouped workspace holds, 1..8
+    const size_t one = group_bytes(Np, Kp, Rp, (int)xi.size(), 1, opts.pi_prec, opts.wc_prec);
+    sg->n_max = (int)std::max<size_t>(1, std::min<size_t>(8, (2ull << 30) / std::max<size_t>(one, 1)));
+    sg->bytes = one * sg->n_max;
+    if (reserved + sg->bytes > budget / 4) {
+      sg->usable = false;
+    } else {
+      reserved += sg->bytes;   // held until the server is destroyed
+      peak_reserved = std::max(peak_reserved, reserved);
+    }
+    groups[key] = sg;
+    return sg;
   }
 };
 
@@ -227,6 +417,7 @@ int gw_server_create(gw_server** out, const gw_server_opts* opts) {
     }
     s->streams.push_back(st);
   }
+  s->cache = devcache_create(s->budget);
   for (int i = 0; i < ns; ++i) s->workers.emplace_back([s, i] { s->run_slot(i); });
   *out = s;
   return 0;
@@ -278,6 +469,7 @@ int gw_server_submit(gw_server* s, const gw_request* q, unsigned long long* tick
   }
   {
     std::lock_guard<std::mutex> lk(s->mu);
+    r->group = s->group_for(r);
     r->ticket = s->next_ticket++;
     r->t_submit = s->now();
     s->pending.push_back(r);
@@ -322,7 +514,7 @@ int gw_server_poll(gw_server* s, unsigned long long ticket, double* E_qp, double
 int gw_server_drain(gw_server* s) {
   if (!s) return GW_EINVAL;
   std::unique_lock<std::mutex> lk(s->mu);
-  s->cv_done.wait(lk, [&] { return s->pending.empty() && s->active == 0; });
+  s->cv_done.wait(lk, [&] { return s->pending.empty() && s->qp_ready.empty() && s->active == 0; });
   return 0;
 }
 
@@ -337,6 +529,20 @@ int gw_server_get_stats(gw_server* s, gw_server_stats* out) {
   out->peak_reserved_bytes = s->peak_reserved;
   out->active = s->active;
   out->peak_active = s->peak_active;
+  out->batches = s->batches;
+  out->batched_requests = s->batched;
+  long replays = 0;
+  for (auto& kv : s->groups) {
+    std::lock_guard<std::mutex> gl(kv.second->mu);
+    if (kv.second->g) {
+      long b, it, rp;
+      group_stats(kv.second->g, &b, &it, &rp);
+      replays += rp;
+    }
+  }
+  out->graph_replays = replays;
+  size_t live = 0, cached = 0;
+  devcache_stats(s->cache, &out->device_mallocs, &out->cache_hits, &live, &cached);
   return 0;
 }
 
@@ -351,8 +557,13 @@ void gw_server_destroy(gw_server* s) {
   }
   s->cv_work.notify_all();
   for (auto& t : s->workers) t.join();
+  for (auto& kv : s->groups) {
+    if (kv.second->g) group_free(kv.second->g);
+    delete kv.second;
+  }
   for (hipStream_t st : s->streams) hipStreamDestroy(st);
   for (auto& kv : s->all) delete kv.second;
+  devcache_destroy(s->cache);
   delete s;
 }
 

@@ -213,7 +213,8 @@ __global__ __launch_bounds__(256) void k_minres_step(MinresBufs m, int par) {
   const int j = blockIdx.x, t = threadIdx.x;
   const int nb = m.kp / 16;
   if (j == 0 && t == 0) m.active[par ^ 1] = 0;
-  if (j == 0 && t < nb) m.blk[(par ^ 1) * nb + t] = 0;
+  if (j == 0)
+    for (int i = t; i < nb; i += 256) m.blk[(par ^ 1) * nb + i] = 0;
   double* sc = m.scal + j * 16;
   if (sc[S_DONE] != 0.0) return;
   const long o = (long)j * m.Np;
@@ -466,7 +467,8 @@ __global__ __launch_bounds__(256) void k_minres_pre_step_b(MinresBufs m, int par
   const int j = blockIdx.x, t = threadIdx.x;
   const int nb = m.kp / 16;
   if (j == 0 && t == 0) m.active[par ^ 1] = 0;
-  if (j == 0 && t < nb) m.blk[(par ^ 1) * nb + t] = 0;
+  if (j == 0)
+    for (int i = t; i < nb; i += 256) m.blk[(par ^ 1) * nb + i] = 0;
   double* sc = m.scal + j * 16;
   if (sc[S_DONE] != 0.0) return;
   const long o = (long)j * m.Np;

@@ -91,7 +91,7 @@ hipError_t split_bf16(const double* B, uint16_t* hi, uint16_t* lo, float* b32, l
 
 __global__ __launch_bounds__(256) void k_pi_f32(const float* B, long ld, const float* scale,
                                                 long sS, double* A, long ldA, long sA, int T,
-                                                int Kp, int G) {
+                                                int Kp, int G, OperandTabs tb) {
   constexpr int BKF = 16;
   __shared__ float As[2][BKF][128];
   __shared__ float Bs[2][BKF][128];
@@ -104,6 +104,7 @@ __global__ __launch_bounds__(256) void k_pi_f32(const float* B, long ld, const f
   lower_tile(id / G, I, J);
   const float* S = scale + (long)g * sS;
   const int ar0 = I * 128, br0 = J * 128;
+  if (tb.B32) B = tb.B32[g / tb.grp];
 
   f4 acc[4][4];
   d4 acc64[4][4];
@@ -204,17 +205,32 @@ static hipError_t check_pi(const char* kn, long ld, long sS, long ldA, long sA, 
   return hipSuccess;
 }
 
-hipError_t pi_build_f32(const float* B32, long ld, const float* scale, long sS, double* A,
-                        long ldA, long sA, int Np, int Kp, int G, long nB, long nS, long nA,
-                        hipStream_t st) {
+static hipError_t launch_pi_f32(const float* B32, const OperandTabs& tb, long ld,
+                                const float* scale, long sS, double* A, long ldA, long sA,
+                                int Np, int Kp, int G, long nB, long nS, long nA, hipStream_t st) {
   const int T = Np / 128;
   const long total = (long)T * (T + 1) / 2 * G;
   if (total <= 0) return hipSuccess;
+  if (tb.B32 && (tb.grp <= 0 || G % tb.grp != 0)) return refuse("pi_f32", "operand table group");
   if (hipError_t e = check_pi("pi_f32", ld, sS, ldA, sA, Np, Kp, G, 16, nB, nS, nA)) return e;
   GW_AUDIT_RETURN();
   hipLaunchKernelGGL(k_pi_f32, dim3((unsigned)total), dim3(256), 0, st, B32, ld, scale, sS, A, ldA,
-                     sA, T, Kp, G);
+                     sA, T, Kp, G, tb);
   return hipGetLastError();
+}
+
+hipError_t pi_build_f32(const float* B32, long ld, const float* scale, long sS, double* A,
+                        long ldA, long sA, int Np, int Kp, int G, long nB, long nS, long nA,
+                        hipStream_t st) {
+  return launch_pi_f32(B32, OperandTabs{}, ld, scale, sS, A, ldA, sA, Np, Kp, G, nB, nS, nA, st);
+}
+
+// nB: the smallest extent over the table's B copies
+hipError_t pi_build_f32_tab(const OperandTabs& tb, long ld, const float* scale, long sS,
+                            double* A, long ldA, long sA, int Np, int Kp, int G, long nB,
+                            long nS, long nA, hipStream_t st) {
+  if (!tb.B32) return refuse("pi_f32", "missing operand table");
+  return launch_pi_f32(nullptr, tb, ld, scale, sS, A, ldA, sA, Np, Kp, G, nB, nS, nA, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -362,7 +378,8 @@ __device__ __forceinline__ void bf_mfma_step(const uint16_t* Ah, const uint16_t*
 __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const uint16_t* Blo,
                                                    long ld, const float* B32,
                                                    const float* scale, long sS, double* A,
-                                                   long ldA, long sA, int T, int Kp, int G) {
+                                                   long ldA, long sA, int T, int Kp, int G,
+                                                   OperandTabs tb) {
   __shared__ __attribute__((aligned(16))) uint16_t Ah[1][SLAB];
   __shared__ __attribute__((aligned(16))) uint16_t Al[1][SLAB];
   __shared__ __attribute__((aligned(16))) uint16_t Bh[1][SLAB];
@@ -376,6 +393,11 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
   lower_tile(id / G, I, J);
   const float* S = scale + (long)g * sS;
   const int ar0 = I * 128, br0 = J * 128;
+  if (tb.Bhi) {
+    Bhi = tb.Bhi[g / tb.grp];
+    Blo = tb.Blo[g / tb.grp];
+    B32 = tb.B32[g / tb.grp];
+  }
 
   f4 acc[4][4];
 #pragma unroll
@@ -416,17 +438,197 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
       }
 }
 
-hipError_t pi_build_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, long ld, const float* B32,
-                           const float* scale, long sS, double* A, long ldA, long sA, int Np,
-                           int Kp, int G, long nB, long nS, long nA, hipStream_t st) {
+// Tall form for large N_aux: 256 x 128 tiles (256 rows of the pre-split
+// side, 128 of the scaled side) per 256-thread workgroup, each wavefront
+// 128 x 64 (8 x 4 blocks, three bf16 MFMAs each).  Per K-step and per flop
+// it stages half as much of the scaled side (so half the VALU split work)
+// and reads 3/4 of the LDS bytes of the 128 x 128 form; at 232 VGPRs two
+// workgroups share a CU.  Tiles cover the lower triangle: tile (I, J) with
+// 256-row index I and 128-column index J <= 2 I + 1.  The last 256-row tile
+// may reach past N_aux: its rows are clamped on load and not stored, and a
+// wavefront whose 128 x 64 block lies past N_aux or wholly above the diagonal
+// skips its MFMAs.  Same K order and products as the 128 x 128 form, so the
+// results are identical bit for bit.
+__global__ __launch_bounds__(256) void k_pi_bf16x3_tall(const uint16_t* Bhi, const uint16_t* Blo,
+                                                        long ld, const float* B32,
+                                                        const float* scale, long sS, double* A,
+                                                        long ldA, long sA, int Np, int T1,
+                                                        int ntile, int Kp, int G, OperandTabs tb) {
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Al[2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[SLAB];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int id = xcd_swizzle_m(blockIdx.x, ntile * G);
+  const int g = id % G;
+  int rem = id / G, I = 0;
+  for (;;) {   // row I holds min(2 I + 2, T1) tiles
+    const int c = min(2 * I + 2, T1);
+    if (rem < c) break;
+    rem -= c;
+    ++I;
+  }
+  const int J = rem;
+  const float* S = scale + (long)g * sS;
+  if (tb.Bhi) {
+    Bhi = tb.Bhi[g / tb.grp];
+    Blo = tb.Blo[g / tb.grp];
+    B32 = tb.B32[g / tb.grp];
+  }
+  const int ar0 = I * 256, br0 = J * 128;
+  const int wr0 = ar0 + wm * 128, wc0 = br0 + wn * 64;
+  const bool live = wr0 < Np && wr0 + 127 >= wc0;
+  f4 acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  // pre-split side: 256 rows x 4 chunks of 16 B per array, 4 items per thread;
+  // scaled side: as in the 128 x 128 form
+  u32x4 rah[4], ral[4];
+  f32x4 rb[4], rs[4];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int row, ch;
+      a_item(t + 256 * u, row, ch);
+      const long gr = min(ar0 + row, Np - 1);
+      rah[u] = *reinterpret_cast<const u32x4*>(Bhi + gr * ld + k0 + 8 * ch);
+      ral[u] = *reinterpret_cast<const u32x4*>(Blo + gr * ld + k0 + 8 * ch);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int row, ch, half;
+      b_item(t + 256 * u, row, ch, half);
+      const int k = k0 + 8 * ch + 4 * half;
+      rb[u] = *reinterpret_cast<const f32x4*>(B32 + (long)(br0 + row) * ld + k);
+      rs[u] = *reinterpret_cast<const f32x4*>(S + k);
+    }
+  };
+  auto lstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int row, ch;
+      a_item(t + 256 * u, row, ch);
+      const int sl = lds_slot(row & 127, ch);
+      *reinterpret_cast<u32x4*>(&Ah[row >> 7][sl]) = rah[u];
+      *reinterpret_cast<u32x4*>(&Al[row >> 7][sl]) = ral[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      int row, ch, half;
+      b_item(t + 256 * u, row, ch, half);
+      unsigned h01, l01, h23, l23;
+      const f32x4 v = rb[u] * rs[u];
+      split_pair(v.x, v.y, h01, l01);
+      split_pair(v.z, v.w, h23, l23);
+      u32x2 hv, lv;
+      hv.x = h01;
+      hv.y = h23;
+      lv.x = l01;
+      lv.y = l23;
+      *reinterpret_cast<u32x2*>(&Bh[lds_slot(row, ch) + 4 * half]) = hv;
+      *reinterpret_cast<u32x2*>(&Bl[lds_slot(row, ch) + 4 * half]) = lv;
+    }
+  };
+  const int nk = Kp / BKB;
+  gload(0);
+  lstore();
+  __syncthreads();
+  const int ko = 8 * ((lane >> 4) * 128 + ((lane & 15) ^ (lane >> 4)));
+  for (int kt = 0; kt < nk; ++kt) {
+    if (live) {
+      // B fragments of the four block columns first, then one A block row at
+      // a time with its 12 MFMAs
+      s8 bh[4], bl[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int o = ko + (wn * 4 + j) * 128;
+        bh[j] = *reinterpret_cast<const s8*>(&Bh[o]);
+        bl[j] = *reinterpret_cast<const s8*>(&Bl[o]);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int o = ko + i * 128;
+        const s8 ah = *reinterpret_cast<const s8*>(&Ah[wm][o]);
+        const s8 al = *reinterpret_cast<const s8*>(&Al[wm][o]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf8, al), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf8, ah), __builtin_bit_cast(bf8, bl[j]), acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+              __builtin_bit_cast(bf8, ah), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    const int knext = (kt + 1 < nk ? kt + 1 : kt) * BKB;
+    gload(knext);
+    __syncthreads();   // every wave has read its fragments of this K-step
+    lstore();
+    __syncthreads();   // the next K-step's slabs are in place
+  }
+  if (!live) return;
+  double* Ag = A + (long)g * sA;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = wr0 + i * 16 + mfma_row(4 * (lane >> 4) + r);
+        const int col = wc0 + j * 16 + mfma_row(lane & 15);
+        if (row < Np) Ag[(long)row * ldA + col] = (row == col ? 1.0 : 0.0) + 4.0 * (double)acc[i][j][r];
+      }
+}
+
+// N_aux (padded) from which the tall form is used: measured faster from the
+// (H2O)20 shape up, slower at (H2O)10 (fewer, half-idle last-row tiles)
+constexpr int TALL_FROM = 2048;
+
+static hipError_t launch_pi_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, const float* B32,
+                                   const OperandTabs& tb, long ld, const float* scale, long sS,
+                                   double* A, long ldA, long sA, int Np, int Kp, int G, long nB,
+                                   long nS, long nA, hipStream_t st) {
   const int T = Np / 128;
   const long total = (long)T * (T + 1) / 2 * G;
   if (total <= 0) return hipSuccess;
+  if (tb.Bhi && (tb.grp <= 0 || G % tb.grp != 0 || !tb.Blo || !tb.B32))
+    return refuse("pi_bf16x3", "operand table group");
   if (hipError_t e = check_pi("pi_bf16x3", ld, sS, ldA, sA, Np, Kp, G, BKB, nB, nS, nA)) return e;
+  if (Np >= TALL_FROM) {
+    const int T2 = (Np + 255) / 256;
+    long ntile = 0;
+    for (int I = 0; I < T2; ++I) ntile += std::min(2 * I + 2, T);
+    if (ntile * G > 0x7fffffffL) return refuse("pi_bf16x3", "grid too large");
+    GW_AUDIT_RETURN();
+    hipLaunchKernelGGL(k_pi_bf16x3_tall, dim3((unsigned)(ntile * G)), dim3(256), 0, st, Bhi, Blo,
+                       ld, B32, scale, sS, A, ldA, sA, Np, T, (int)ntile, Kp, G, tb);
+    return hipGetLastError();
+  }
   GW_AUDIT_RETURN();
   hipLaunchKernelGGL(k_pi_bf16x3, dim3((unsigned)total), dim3(256), 0, st, Bhi, Blo, ld, B32, scale,
-                     sS, A, ldA, sA, T, Kp, G);
+                     sS, A, ldA, sA, T, Kp, G, tb);
   return hipGetLastError();
+}
+
+hipError_t pi_build_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, long ld, const float* B32,
+                           const float* scale, long sS, double* A, long ldA, long sA, int Np,
+                           int Kp, int G, long nB, long nS, long nA, hipStream_t st) {
+  return launch_pi_bf16x3(Bhi, Blo, B32, OperandTabs{}, ld, scale, sS, A, ldA, sA, Np, Kp, G, nB,
+                          nS, nA, st);
+}
+
+// nB: the smallest extent over the table's B copies
+hipError_t pi_build_bf16x3_tab(const OperandTabs& tb, long ld, const float* scale, long sS,
+                               double* A, long ldA, long sA, int Np, int Kp, int G, long nB,
+                               long nS, long nA, hipStream_t st) {
+  if (!tb.Bhi) return refuse("pi_bf16x3", "missing operand table");
+  return launch_pi_bf16x3(nullptr, nullptr, nullptr, tb, ld, scale, sS, A, ldA, sA, Np, Kp, G, nB,
+                          nS, nA, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,7 +720,7 @@ __global__ __launch_bounds__(256, 4) void k_wc_bf16x3(const uint16_t* Rh, const 
                                                    long ldR, const uint16_t* Fh,
                                                    const uint16_t* Fl, long sF, int Np,
                                                    double* part, long ldp, long sP, int TM,
-                                                   int TN, int G) {
+                                                   int TN, int G, OperandTabs tb, long nRR) {
   __shared__ __attribute__((aligned(16))) uint16_t Ah[1][SLAB];
   __shared__ __attribute__((aligned(16))) uint16_t Al[1][SLAB];
   __shared__ __attribute__((aligned(16))) uint16_t Bh[1][SLAB];
@@ -538,6 +740,10 @@ __global__ __launch_bounds__(256, 4) void k_wc_bf16x3(const uint16_t* Rh, const 
   const int r16 = rem2 % (16 * gs);
   const int I = 16 * (rem2 / (16 * gs)) + r16 / gs;
   const int g = 8 * gb + r16 % gs;
+  if (tb.Rh) {
+    Rh = tb.Rh[g / tb.grp];
+    Rl = Rh + nRR;
+  }
   const uint16_t* Fhg = Fh + (long)g * sF;
   const uint16_t* Flg = Fl + (long)g * sF;
   const int ar0 = I * 128, br0 = J * 128;
@@ -611,15 +817,18 @@ __global__ __launch_bounds__(256, 4) void k_wc_bf16x3(const uint16_t* Rh, const 
   if (t < 128) part[(long)g * sP + (long)J * ldp + ar0 + t] = red[0][t] + red[1][t];
 }
 
-hipError_t wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl, long ldR, int Rp, const uint16_t* Fh,
-                     const uint16_t* Fl, long sF, int Np, int G, double* part, long ldp, long sP,
-                     long nR, long nF, long nP, hipStream_t st) {
+static hipError_t launch_wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl, const OperandTabs& tb,
+                                   long nRR, long ldR, int Rp, const uint16_t* Fh,
+                                   const uint16_t* Fl, long sF, int Np, int G, double* part,
+                                   long ldp, long sP, long nR, long nF, long nP, hipStream_t st) {
   const char* kn = "wc_bf16x3";
   const long total = (long)(Rp / 128) * (Np / 128) * G;
   if (G <= 0 || Rp <= 0) return hipSuccess;
   if (Rp % 128 != 0 || Np % 128 != 0 || ldR < Np || ldR % 8 != 0 || sF < (long)Np * Np ||
       sF % 8 != 0 || ldp < Rp || total > 0x7fffffffL)
     return refuse(kn, "shape");
+  if (tb.Rh && (tb.grp <= 0 || G % tb.grp != 0 || nRR % 8 != 0 || nRR < (long)(Rp - 1) * ldR + Np))
+    return refuse(kn, "operand table group");
   if (((uintptr_t)Rh | (uintptr_t)Rl | (uintptr_t)Fh | (uintptr_t)Fl) & 15)
     return refuse(kn, "operand pointer not 16-byte aligned");
   GW_GUARD(kn, "R", (long)(Rp - 1) * ldR + Np - 1, nR);
@@ -627,8 +836,25 @@ hipError_t wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl, long ldR, int Rp, c
   GW_GUARD(kn, "part", (long)(G - 1) * sP + (long)(Np / 128 - 1) * ldp + Rp - 1, nP);
   GW_AUDIT_RETURN();
   hipLaunchKernelGGL(k_wc_bf16x3, dim3((unsigned)total), dim3(256), 0, st, Rh, Rl, ldR, Fh, Fl, sF,
-                     Np, part, ldp, sP, Rp / 128, Np / 128, G);
+                     Np, part, ldp, sP, Rp / 128, Np / 128, G, tb, nRR);
   return hipGetLastError();
+}
+
+hipError_t wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl, long ldR, int Rp, const uint16_t* Fh,
+                     const uint16_t* Fl, long sF, int Np, int G, double* part, long ldp, long sP,
+                     long nR, long nF, long nP, hipStream_t st) {
+  return launch_wc_bf16x3(Rh, Rl, OperandTabs{}, 0, ldR, Rp, Fh, Fl, sF, Np, G, part, ldp, sP, nR,
+                          nF, nP, st);
+}
+
+// each table entry Rh holds the hi half and, nRR elements further, the lo half;
+// nR: the smallest extent of either half over the table
+hipError_t wc_bf16x3_tab(const OperandTabs& tb, long nRR, long ldR, int Rp, const uint16_t* Fh,
+                         const uint16_t* Fl, long sF, int Np, int G, double* part, long ldp,
+                         long sP, long nR, long nF, long nP, hipStream_t st) {
+  if (!tb.Rh) return refuse("wc_bf16x3", "missing operand table");
+  return launch_wc_bf16x3(nullptr, nullptr, tb, nRR, ldR, Rp, Fh, Fl, sF, Np, G, part, ldp, sP, nR,
+                          nF, nP, st);
 }
 
 }  // namespace gw

@@ -90,10 +90,37 @@ def run_uhf_case(n_occ, n_virt, n_aux, rows, G):
               f"checked", flush=True)
 
 
+def run_group_case(ks, G):
+    """The server's grouped stage A (several requests of one padded shape in
+    one launch sequence), then each member's QP stage."""
+    for prec, wc in (("fp64", "fp64"), ("fp32", "fp64"), ("bf16x3", "bf16x3")):
+        ctxs = [gwl.Context.from_inputs(gwgen.serving_inputs(k, 1000 + j), pi_prec=prec, wc_prec=wc)
+                for j, k in enumerate(ks)]
+        g = gwl.Grid.gauss_legendre(G)
+        before = gwl.audit_launch_count()
+        try:
+            gwl.group_stage_a(ctxs, g, use_graph=False)
+        except gwl.GWError as e:
+            if e.code != gwl.GW_EAUDIT:
+                raise
+        for c, k in zip(ctxs, ks):
+            try:
+                c.qp(list(c.row_ids), g)
+            except gwl.GWError as e:
+                if e.code != gwl.GW_EAUDIT:
+                    raise
+            c.close()
+        n = gwl.audit_launch_count() - before
+        print(f"group case k={ks} G={G} {prec}/wc {wc}: {n} launches checked", flush=True)
+
+
 def main():
     gwl.audit_enable()
     for case in CASES:
         run_case(*case)
+    run_group_case([1, 1, 1], 64)
+    run_group_case([3, 3], 16)
+    run_group_case([6, 6, 6, 6], 8)
     run_uhf_case(6, 40, 150, (3, 6, 46 + 4, 46 + 5), 6)
     run_uhf_case(1, 3, 20, (0, 4, 5), 3)
     print("audit ok")

@@ -1,5 +1,6 @@
 """bench.py's output contract: one JSON line with the headline metric, the
-roofline object of the dominant kernel and the single-request latency; more
+roofline object of the dominant kernel and the single-request latency on the
+(H2O)30 headline workload; more
 than one GPU is refused with a message before any device work."""
 import json
 import os
@@ -23,7 +24,7 @@ def test_more_than_one_gpu_is_refused():
 def test_bench_line_carries_the_contract_fields():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--steps", "2",
                         "--warmup", "1", "--no-cpu-baseline", "--no-evgw", "--no-core",
-                        "--only", "bf16x3w"], capture_output=True, text=True, timeout=300)
+                        "--only", "bf16x3w"], capture_output=True, text=True, timeout=400)
     assert r.returncode == 0, r.stderr[-2000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.strip()]
     assert len(lines) == 1
@@ -42,4 +43,7 @@ def test_bench_line_carries_the_contract_fields():
     assert roof["bound"] in ("hbm", "mfma", "alu")
     assert abs(roof["frac"] - roof["achieved"] / roof["peak"]) < 1e-3
     assert d["latency_ms"]["p50"] > 0 and d["latency_ms"]["p99"] >= d["latency_ms"]["p50"]
+    assert d["paths"]["bf16x3w"]["states_checked"] >= 1
     assert d["paths"]["bf16x3w"]["max_err_mev_vs_oracle"] <= 1.0
+    assert "(H2O)30" in d["config"]["workload"] and d["config"]["grid_points"] == 128
+    assert roof["algorithmic_bytes"] > 0

@@ -93,3 +93,80 @@ def test_oversized_request_is_refused_and_bad_request_fails_alone():
     assert bad[4]["rc"] == -1 and ok[4]["rc"] == 0
     E_ref = alone(good[1], "fp64", grid)[0]
     np.testing.assert_array_equal(ok[0], E_ref)
+
+
+def _burst(srv, head, reqs):
+    """Submit `head` first (it keeps the one pipeline busy), then every request
+    of `reqs` while it runs, so that requests of one shape queue together."""
+    tickets = [srv.submit_inputs(head, list(head.row_ids))]
+    tickets += [srv.submit_inputs(r, list(r.row_ids)) for r in reqs]
+    srv.drain()
+    return [srv.poll(t) for t in tickets]
+
+
+@pytest.mark.parametrize("prec,wc", [("fp64", "fp64"), ("bf16x3", "bf16x3")])
+def test_batched_stage_a_mixed_sizes_equals_solo_bitwise(prec, wc):
+    """Water clusters of k = 1..24 on the 64-point grid, each seeded 1000 + r.
+    The small shapes recur, so they queue behind the large head request and
+    their stage A runs batched (one grouped launch sequence over all their grid
+    points); every request's energies, Sigma^c, Z and status equal those of its
+    own context run alone, bit for bit, in FP64 and in the mixed form."""
+    grid = gwl().Grid.gauss_legendre(64)
+    ks = [1, 2, 1, 3, 2, 1, 4, 6, 5, 9, 13, 18, 24, 3, 1, 2, 6, 4]
+    reqs = requests(ks)
+    head = gwgen.serving_inputs(16, 999)
+    solo = []
+    for r in [head] + reqs:
+        with gwl().Context.from_inputs(r, pi_prec=prec, wc_prec=wc, qp_tol=1e-12) as c:
+            solo.append(c.qp(list(r.row_ids), grid))
+    with gwl().Server(grid, pi_prec=prec, wc_prec=wc, n_streams=1, qp_tol=1e-12) as srv:
+        outs = _burst(srv, head, reqs)
+        st = srv.stats()
+    assert st["completed"] == len(reqs) + 1 and st["failed"] == 0
+    # k = 1 appears 4 times, 2 three times, 3, 4 and 6 twice: batches of 2-4
+    assert st["batches"] >= 4 and st["batched_requests"] >= 12, st
+    assert st["batched_requests"] > st["batches"]
+    for j, ((E, S, Z, status, info), (Es, Ss, Zs, sts)) in enumerate(zip(outs, solo)):
+        assert info["rc"] == 0
+        np.testing.assert_array_equal(E, Es, err_msg=f"request {j}")
+        np.testing.assert_array_equal(S, Ss, err_msg=f"request {j}")
+        np.testing.assert_array_equal(Z, Zs, err_msg=f"request {j}")
+        np.testing.assert_array_equal(status, sts, err_msg=f"request {j}")
+    print(f"serving {prec}/{wc}: {st['batches']} batches of {st['batched_requests']} requests, "
+          f"{st['graph_replays']} graph replays, identical to solo runs")
+
+
+def test_recurring_shapes_reuse_memory_and_graphs():
+    """A second wave of the same shapes runs from the server's block cache (no
+    new device or pinned allocation) and replays the graphs the first wave
+    captured; its results equal the first wave's."""
+    grid = gwl().Grid.gauss_legendre(64)
+    ks = [1, 1, 2, 2, 3, 3]
+    reqs = requests(ks)
+    head = gwgen.serving_inputs(12, 998)
+    with gwl().Server(grid, pi_prec="bf16x3", wc_prec="bf16x3", n_streams=1,
+                      qp_tol=1e-12) as srv:
+        first = _burst(srv, head, reqs)
+        st1 = srv.stats()
+        second = _burst(srv, head, reqs)
+        st2 = srv.stats()
+    assert st2["device_mallocs"] == st1["device_mallocs"], (st1, st2)
+    assert st2["cache_hits"] > st1["cache_hits"]
+    assert st2["graph_replays"] >= st1["graph_replays"] + 3, (st1, st2)
+    for a, b in zip(first, second):
+        np.testing.assert_array_equal(a[0], b[0])
+
+
+def test_batching_off_gives_the_same_results():
+    grid = gwl().Grid.gauss_legendre(32)
+    reqs = requests([1, 1, 2, 2])
+    head = gwgen.serving_inputs(8, 997)
+    res = {}
+    for lim in (0, -1):
+        with gwl().Server(grid, pi_prec="bf16x3", n_streams=1, qp_tol=1e-12,
+                          batch_max_aux=lim) as srv:
+            res[lim] = _burst(srv, head, reqs)
+            st = srv.stats()
+        assert (st["batches"] > 0) == (lim == 0)
+    for a, b in zip(res[0], res[-1]):
+        np.testing.assert_array_equal(a[0], b[0])
