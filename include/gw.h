@@ -262,6 +262,7 @@ int gw_reset_cache(gw_ctx* ctx);
  * written (the strict upper triangle is set to 0). */
 int gw_dielectric(gw_ctx* ctx, int n_xi, const double* xi, double* out);
 
+
 /* Cholesky factors L_g of 1 - Pi(i xi_g): out [n_xi][n_aux][n_aux] lower
  * triangular (upper set to 0). */
 int gw_cholesky(gw_ctx* ctx, int n_xi, const double* xi, double* out);

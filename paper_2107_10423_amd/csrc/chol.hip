@@ -392,10 +392,12 @@ hipError_t reflect_unit(double* A, long ldA, long sA, int Np, int G, long nA, hi
 hipError_t sigma_quad(const double* wtab, int n_mo, int G, int ld, int w0, const int* rowsel,
                       const int* rowspin, const double* omega, const double* eps,
                       const double* xi, const double* z, int n, double* sig, double* dsig,
-                      double* part, int n_rows, long nW, long nPart, long nEps,
-                      hipStream_t st) {
+                      double* part, int n_rows, long nW, long nPart, long nEps, long nXi,
+                      long nZ, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   if (G < 1 || ld < G + (w0 ? 1 : 0)) return hipErrorInvalidValue;
+  GW_GUARD("sigma_quad", "xi", G - 1, nXi);
+  GW_GUARD("sigma_quad", "z", G - 1, nZ);
   // (row spins are 0 or 1, set by the context from validated row ids)
   GW_GUARD("sigma_quad", "eps", (rowspin ? 2L : 1L) * n_mo - 1, nEps);
   // row indices come from the context's validated state -> row map (< n_rows)

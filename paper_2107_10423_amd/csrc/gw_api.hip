@@ -206,11 +206,12 @@ struct gw_devcache {
     const size_t q = b >= (1u << 20) ? (64u << 10) : 256;
     return (std::max<size_t>(b, 8) + q - 1) / q * q;
   }
-  // a block of exactly this size class, else the best fit within 1/8 of slack
+  // a block of exactly this size class: a recurring sequence of allocations
+  // (the same request shapes again) then finds every block it needs, which a
+  // best fit that lets one class take another's block does not guarantee
   static void* take(std::multimap<size_t, void*>& fl, size_t want, size_t* got) {
     auto it = fl.find(want);
-    if (it == fl.end()) it = fl.lower_bound(want);
-    if (it == fl.end() || it->first > want + want / 8) return nullptr;
+    if (it == fl.end()) return nullptr;
     void* p = it->second;
     *got = it->first;
     fl.erase(it);
@@ -224,6 +225,7 @@ struct gw_devcache {
       cached -= got;
       live += got;
       ++n_hits;
+      if (audit_mode()) memset(*p, 0, got);   // as fresh audit-mode memory (no kernel runs)
       return hipSuccess;
     }
     while (live + cached + want > cap && !free_dev.empty()) {   // make room: largest first
@@ -234,6 +236,7 @@ struct gw_devcache {
       ++n_free;
       free_dev.erase(last);
     }
+    trace("block cache: new device block of %zu bytes", want);
     hipError_t e = rt_malloc(p, want);
     if (e != hipSuccess && !free_dev.empty()) {   // the runtime is short: drop the rest
       (void)hipGetLastError();
@@ -268,6 +271,7 @@ struct gw_devcache {
       ++n_hits;
       return hipSuccess;
     }
+    trace("block cache: new pinned block of %zu bytes", want);
     if (audit_mode()) {
       *p = calloc(want, 1);
       if (!*p) return hipErrorOutOfMemory;
@@ -1363,7 +1367,7 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
                       c->n_spin > 1 ? c->d_rowspin : nullptr, c->d_omega, c->d_eps, c->d_grid,
                       c->d_grid + c->grid_cap, n, c->d_sig, c->d_dsig, c->d_sigpart, c->n_rows,
                       c->ext(c->d_wtab, 8), c->ext(c->d_sigpart, 8), c->ext(c->d_eps, 8),
-                      c->st));
+                      c->ext(c->d_grid, 8), c->ext(c->d_grid + c->grid_cap, 8), c->st));
     HIPCHK(rt_memcpy(h_sig, c->d_sig, 2 * (size_t)sc * sizeof(double), hipMemcpyDeviceToHost,
                      c->st));
     if (!audit_mode()) HIPCHK(hipEventRecord(c->ev_quad[1], c->st));
@@ -2580,6 +2584,9 @@ int group_member_prepare(gw_group* g, gw_ctx* m) {
   }
   if (!m->d_wtab) RCHK(m->alloc((void**)&m->d_wtab, wt * sizeof(double)));
   if (!m->d_pre) RCHK(m->alloc((void**)&m->d_pre, (size_t)g->Np * g->Np * sizeof(double)));
+  // the grid (nodes and weights) the member's quadrature reads, as its own
+  // stage A would have left it
+  RCHK(upload_grid(m, g->Gx, g->xi.data(), g->w.data()));
   if (g->pi_prec != GW_PI_FP64) RCHK(ensure_mixed_operands(m));
   if (g->wc_prec == GW_PI_BF16X3) RCHK(ensure_r_split(m));
   const GroupExt ex = group_ext(g);

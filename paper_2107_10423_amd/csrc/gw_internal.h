@@ -178,8 +178,8 @@ hipError_t make_scale_imag_tab(const double* const* D_tab, const int* Kov_tab, i
 hipError_t sigma_quad(const double* wtab, int n_mo, int G, int ld, int w0, const int* rowsel,
                       const int* rowspin, const double* omega, const double* eps,
                       const double* xi, const double* z, int n, double* sig, double* dsig,
-                      double* part, int n_rows, long nW, long nPart, long nEps,
-                      hipStream_t st);
+                      double* part, int n_rows, long nW, long nPart, long nEps, long nXi,
+                      long nZ, hipStream_t st);
 
 // Spectral-decomposition route (sd.hip)
 hipError_t casida_matrix(double* C, long ld, const double* D, int n, int Kp, long nC, long nD,

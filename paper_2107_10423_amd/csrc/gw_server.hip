@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "../../include/gw.h"
+#include "gw_internal.h"
 
 size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, int G,
                        int pi_prec, int wc_prec, size_t work_budget, int minres_batch);
@@ -183,7 +184,7 @@ struct gw_server {
   }
 
   void run_slot(int slot) {
-    hipSetDevice(device);
+    if (!gw::audit_mode()) hipSetDevice(device);
     for (;;) {
       Req* r = nullptr;
       bool qp_stage = false;
@@ -393,13 +394,18 @@ int gw_server_create(gw_server** out, const gw_server_opts* opts) {
   if (s->opts.work_budget_bytes == 0) s->opts.work_budget_bytes = 2ull << 30;
   int ns = opts->n_streams > 0 ? opts->n_streams : 2;
   if (ns > 4) ns = 4;
-  if (hipGetDevice(&s->device) != hipSuccess) {
+  // launch-audit mode (no GPU): contexts walk their launch guards only, on
+  // null streams, and the budget is the stated one or 64 GiB
+  const bool audit = gw::audit_mode();
+  if (!audit && hipGetDevice(&s->device) != hipSuccess) {
     delete s;
     return GW_EDEVICE;
   }
   size_t free_b = 0, total_b = 0;
   if (opts->mem_budget_bytes) {
     s->budget = opts->mem_budget_bytes;
+  } else if (audit) {
+    s->budget = 64ull << 30;
   } else {
     if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
       delete s;
@@ -409,8 +415,8 @@ int gw_server_create(gw_server** out, const gw_server_opts* opts) {
   }
   s->pinned.cap = 64ull << 30;
   for (int i = 0; i < ns; ++i) {
-    hipStream_t st;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+    hipStream_t st = nullptr;
+    if (!audit && hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
       for (hipStream_t x : s->streams) hipStreamDestroy(x);
       delete s;
       return GW_EDEVICE;
@@ -561,7 +567,8 @@ void gw_server_destroy(gw_server* s) {
     if (kv.second->g) group_free(kv.second->g);
     delete kv.second;
   }
-  for (hipStream_t st : s->streams) hipStreamDestroy(st);
+  for (hipStream_t st : s->streams)
+    if (st) hipStreamDestroy(st);
   for (auto& kv : s->all) delete kv.second;
   devcache_destroy(s->cache);
   delete s;

@@ -114,8 +114,36 @@ def run_group_case(ks, G):
         print(f"group case k={ks} G={G} {prec}/wc {wc}: {n} launches checked", flush=True)
 
 
+def run_server_case(reqs, G, prec, wc, streams):
+    """The request server in audit mode: admission, batching by shape (grouped
+    stage A through the block cache), QP stages; every request must end with
+    GW_EAUDIT (all its launches checked), none with a refused launch."""
+    g = gwl.Grid.gauss_legendre(G)
+    before = gwl.audit_launch_count()
+    with gwl.Server(g, pi_prec=prec, wc_prec=wc, n_streams=streams) as srv:
+        ts = [srv.submit_inputs(r, list(r.row_ids)) for r in reqs]
+        srv.drain()
+        st = srv.stats()
+        rcs = [srv.poll(t)[4]["rc"] for t in ts]
+    bad = [rc for rc in rcs if rc != gwl.GW_EAUDIT]
+    if bad:
+        raise AssertionError(f"server case {prec}/{wc}: request codes {rcs}: "
+                             f"{gwl._lib.gw_last_error().decode()}")
+    n = gwl.audit_launch_count() - before
+    print(f"server case {len(reqs)} requests G={G} {prec}/wc {wc}: {n} launches checked, "
+          f"{st['batches']} batches of {st['batched_requests']} requests", flush=True)
+
+
 def main():
     gwl.audit_enable()
+    small = []
+    for k, seed in ((1, 11), (3, 12), (2, 13)):
+        shape = gwgen.custom_shape(5 * k, 38 * k, 112 * k, n_core=k)
+        small.append(gwgen.make_inputs(shape, seed, [5 * k - 1, 5 * k]))
+    for prec, wc in (("bf16x3", "bf16x3"), ("fp64", "fp64")):
+        run_server_case(small, 32, prec, wc, 2)
+        run_server_case([gwgen.serving_inputs(k, 1000 + j) for j, k in
+                         enumerate([1, 2, 1, 3, 1, 2, 9])], 16, prec, wc, 1)
     for case in CASES:
         run_case(*case)
     run_group_case([1, 1, 1], 64)
