@@ -438,61 +438,58 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
       }
 }
 
-// Tall form for large N_aux: 256 x 128 tiles (256 rows of the pre-split
-// side, 128 of the scaled side) per 256-thread workgroup, each wavefront
-// 128 x 64 (8 x 4 blocks, three bf16 MFMAs each).  Per K-step and per flop
-// it stages half as much of the scaled side (so half the VALU split work)
-// and reads 3/4 of the LDS bytes of the 128 x 128 form; at 232 VGPRs two
-// workgroups share a CU.  Tiles cover the lower triangle: tile (I, J) with
-// 256-row index I and 128-column index J <= 2 I + 1.  The last 256-row tile
-// may reach past N_aux: its rows are clamped on load and not stored, and a
-// wavefront whose 128 x 64 block lies past N_aux or wholly above the diagonal
-// skips its MFMAs.  Same K order and products as the 128 x 128 form, so the
-// results are identical bit for bit.
-__global__ __launch_bounds__(256) void k_pi_bf16x3_tall(const uint16_t* Bhi, const uint16_t* Blo,
+// Wide form for large N_aux: 256 x 256 tiles per 512-thread workgroup (eight
+// wavefronts, each 128 x 64: 8 x 4 blocks of three bf16 MFMAs, the B
+// fragments of its four block columns held while the A block rows stream
+// through) with a double-buffered LDS (128 KB) and one barrier per K-step:
+// after the barrier the staged slabs of step k+1 are split and stored into the
+// other buffer and the loads of step k+2 are issued, then the MFMAs of step k
+// run.  Per flop it stages half of the global bytes and 7/8 of the LDS bytes
+// of a 256 x 128 tile, and half of the scaled side's split work of the
+// 128 x 128 form.  At up to 256 VGPRs one workgroup (two wavefronts per SIMD)
+// holds a CU.  Lower tiles (I, J), J <= I, of 256; the last tile row and
+// column may reach past N_aux: rows are clamped on load and not stored, and
+// a wavefront whose block lies past N_aux or wholly above the diagonal skips
+// its MFMAs.  Same K order and products as the 128 x 128 form, so the results
+// are identical bit for bit.
+__global__ __launch_bounds__(512) void k_pi_bf16x3_wide(const uint16_t* Bhi, const uint16_t* Blo,
                                                         long ld, const float* B32,
                                                         const float* scale, long sS, double* A,
-                                                        long ldA, long sA, int Np, int T1,
-                                                        int ntile, int Kp, int G, OperandTabs tb) {
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][SLAB];
-  __shared__ __attribute__((aligned(16))) uint16_t Al[2][SLAB];
-  __shared__ __attribute__((aligned(16))) uint16_t Bh[SLAB];
-  __shared__ __attribute__((aligned(16))) uint16_t Bl[SLAB];
+                                                        long ldA, long sA, int Np, int T, int Kp,
+                                                        int G, OperandTabs tb) {
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][2][SLAB];   // [buffer][128-row half]
+  __shared__ __attribute__((aligned(16))) uint16_t Al[2][2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[2][2][SLAB];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int id = xcd_swizzle_m(blockIdx.x, ntile * G);
+  const int wm = wave >> 2, wn = wave & 3;
+  const int id = xcd_swizzle_m(blockIdx.x, T * (T + 1) / 2 * G);
   const int g = id % G;
-  int rem = id / G, I = 0;
-  for (;;) {   // row I holds min(2 I + 2, T1) tiles
-    const int c = min(2 * I + 2, T1);
-    if (rem < c) break;
-    rem -= c;
-    ++I;
-  }
-  const int J = rem;
+  int I, J;
+  lower_tile(id / G, I, J);
   const float* S = scale + (long)g * sS;
   if (tb.Bhi) {
     Bhi = tb.Bhi[g / tb.grp];
     Blo = tb.Blo[g / tb.grp];
     B32 = tb.B32[g / tb.grp];
   }
-  const int ar0 = I * 256, br0 = J * 128;
+  const int ar0 = I * 256, br0 = J * 256;
   const int wr0 = ar0 + wm * 128, wc0 = br0 + wn * 64;
-  const bool live = wr0 < Np && wr0 + 127 >= wc0;
+  const bool live = wr0 < Np && wc0 < Np && wr0 + 127 >= wc0;
   f4 acc[8][4];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-  // pre-split side: 256 rows x 4 chunks of 16 B per array, 4 items per thread;
-  // scaled side: as in the 128 x 128 form
-  u32x4 rah[4], ral[4];
+  // staging, per thread: pre-split side 256 rows x 4 chunks per array = 2
+  // items; scaled side 256 rows x 8 float4 = 4 items
+  u32x4 rah[2], ral[2];
   f32x4 rb[4], rs[4];
   auto gload = [&](int k0) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 2; ++u) {
       int row, ch;
-      a_item(t + 256 * u, row, ch);
+      a_item(t + 512 * u, row, ch);
       const long gr = min(ar0 + row, Np - 1);
       rah[u] = *reinterpret_cast<const u32x4*>(Bhi + gr * ld + k0 + 8 * ch);
       ral[u] = *reinterpret_cast<const u32x4*>(Blo + gr * ld + k0 + 8 * ch);
@@ -500,25 +497,26 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3_tall(const uint16_t* Bhi, con
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       int row, ch, half;
-      b_item(t + 256 * u, row, ch, half);
+      b_item(t + 512 * u, row, ch, half);
       const int k = k0 + 8 * ch + 4 * half;
-      rb[u] = *reinterpret_cast<const f32x4*>(B32 + (long)(br0 + row) * ld + k);
+      const long gr = min(br0 + row, Np - 1);
+      rb[u] = *reinterpret_cast<const f32x4*>(B32 + gr * ld + k);
       rs[u] = *reinterpret_cast<const f32x4*>(S + k);
     }
   };
-  auto lstore = [&]() {
+  auto lstore = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 2; ++u) {
       int row, ch;
-      a_item(t + 256 * u, row, ch);
+      a_item(t + 512 * u, row, ch);
       const int sl = lds_slot(row & 127, ch);
-      *reinterpret_cast<u32x4*>(&Ah[row >> 7][sl]) = rah[u];
-      *reinterpret_cast<u32x4*>(&Al[row >> 7][sl]) = ral[u];
+      *reinterpret_cast<u32x4*>(&Ah[buf][row >> 7][sl]) = rah[u];
+      *reinterpret_cast<u32x4*>(&Al[buf][row >> 7][sl]) = ral[u];
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       int row, ch, half;
-      b_item(t + 256 * u, row, ch, half);
+      b_item(t + 512 * u, row, ch, half);
       unsigned h01, l01, h23, l23;
       const f32x4 v = rb[u] * rs[u];
       split_pair(v.x, v.y, h01, l01);
@@ -528,31 +526,37 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3_tall(const uint16_t* Bhi, con
       hv.y = h23;
       lv.x = l01;
       lv.y = l23;
-      *reinterpret_cast<u32x2*>(&Bh[lds_slot(row, ch) + 4 * half]) = hv;
-      *reinterpret_cast<u32x2*>(&Bl[lds_slot(row, ch) + 4 * half]) = lv;
+      const int sl = lds_slot(row & 127, ch) + 4 * half;
+      *reinterpret_cast<u32x2*>(&Bh[buf][row >> 7][sl]) = hv;
+      *reinterpret_cast<u32x2*>(&Bl[buf][row >> 7][sl]) = lv;
     }
   };
   const int nk = Kp / BKB;
   gload(0);
-  lstore();
-  __syncthreads();
+  lstore(0);
+  gload(nk > 1 ? BKB : 0);
   const int ko = 8 * ((lane >> 4) * 128 + ((lane & 15) ^ (lane >> 4)));
+  const int bhalf = wn >> 1, bq = (wn & 1) * 4;
   for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    __syncthreads();   // step kt's slabs are in place; nobody reads buffer cur ^ 1 any more
+    if (kt + 1 < nk) {
+      lstore(cur ^ 1);                                      // step kt + 1
+      gload((kt + 2 < nk ? kt + 2 : kt) * BKB);             // step kt + 2
+    }
     if (live) {
-      // B fragments of the four block columns first, then one A block row at
-      // a time with its 12 MFMAs
       s8 bh[4], bl[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int o = ko + (wn * 4 + j) * 128;
-        bh[j] = *reinterpret_cast<const s8*>(&Bh[o]);
-        bl[j] = *reinterpret_cast<const s8*>(&Bl[o]);
+        const int o = ko + (bq + j) * 128;
+        bh[j] = *reinterpret_cast<const s8*>(&Bh[cur][bhalf][o]);
+        bl[j] = *reinterpret_cast<const s8*>(&Bl[cur][bhalf][o]);
       }
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
         const int o = ko + i * 128;
-        const s8 ah = *reinterpret_cast<const s8*>(&Ah[wm][o]);
-        const s8 al = *reinterpret_cast<const s8*>(&Al[wm][o]);
+        const s8 ah = *reinterpret_cast<const s8*>(&Ah[cur][wm][o]);
+        const s8 al = *reinterpret_cast<const s8*>(&Al[cur][wm][o]);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
@@ -564,12 +568,6 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3_tall(const uint16_t* Bhi, con
         }
       }
     }
-    __builtin_amdgcn_sched_barrier(0);
-    const int knext = (kt + 1 < nk ? kt + 1 : kt) * BKB;
-    gload(knext);
-    __syncthreads();   // every wave has read its fragments of this K-step
-    lstore();
-    __syncthreads();   // the next K-step's slabs are in place
   }
   if (!live) return;
   double* Ag = A + (long)g * sA;
@@ -581,13 +579,15 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3_tall(const uint16_t* Bhi, con
       for (int r = 0; r < 4; ++r) {
         const int row = wr0 + i * 16 + mfma_row(4 * (lane >> 4) + r);
         const int col = wc0 + j * 16 + mfma_row(lane & 15);
-        if (row < Np) Ag[(long)row * ldA + col] = (row == col ? 1.0 : 0.0) + 4.0 * (double)acc[i][j][r];
+        if (row < Np && col < Np)
+          Ag[(long)row * ldA + col] = (row == col ? 1.0 : 0.0) + 4.0 * (double)acc[i][j][r];
       }
 }
 
-// N_aux (padded) from which the tall form is used: measured faster from the
-// (H2O)20 shape up, slower at (H2O)10 (fewer, half-idle last-row tiles)
-constexpr int TALL_FROM = 2048;
+// N_aux (padded) from which the wide form is used: measured faster from the
+// (H2O)20 shape up; at (H2O)10 the two forms tie (15 wide tile pairs per grid
+// point leave the last round of workgroups short of the CUs)
+constexpr int WIDE_FROM = 2048;
 
 static hipError_t launch_pi_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, const float* B32,
                                    const OperandTabs& tb, long ld, const float* scale, long sS,
@@ -599,14 +599,13 @@ static hipError_t launch_pi_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, con
   if (tb.Bhi && (tb.grp <= 0 || G % tb.grp != 0 || !tb.Blo || !tb.B32))
     return refuse("pi_bf16x3", "operand table group");
   if (hipError_t e = check_pi("pi_bf16x3", ld, sS, ldA, sA, Np, Kp, G, BKB, nB, nS, nA)) return e;
-  if (Np >= TALL_FROM) {
+  if (Np >= WIDE_FROM) {
     const int T2 = (Np + 255) / 256;
-    long ntile = 0;
-    for (int I = 0; I < T2; ++I) ntile += std::min(2 * I + 2, T);
-    if (ntile * G > 0x7fffffffL) return refuse("pi_bf16x3", "grid too large");
+    const long wtotal = (long)T2 * (T2 + 1) / 2 * G;
+    if (wtotal > 0x7fffffffL) return refuse("pi_bf16x3", "grid too large");
     GW_AUDIT_RETURN();
-    hipLaunchKernelGGL(k_pi_bf16x3_tall, dim3((unsigned)(ntile * G)), dim3(256), 0, st, Bhi, Blo,
-                       ld, B32, scale, sS, A, ldA, sA, Np, T, (int)ntile, Kp, G, tb);
+    hipLaunchKernelGGL(k_pi_bf16x3_wide, dim3((unsigned)wtotal), dim3(512), 0, st, Bhi, Blo, ld,
+                       B32, scale, sS, A, ldA, sA, Np, T2, Kp, G, tb);
     return hipGetLastError();
   }
   GW_AUDIT_RETURN();

@@ -1,9 +1,9 @@
 """Every device kernel of the library compiles without register spills
 (no scratch memory), with the library's own compile flags for gfx950.  The
-BF16x3 kernels' occupancy (three, two and four workgroups per CU for the
-Pi build's 128 x 128 and 256 x 128 forms and the W^c contraction) depends on
-their register counts staying below 168, 256 and 128 VGPRs; those are
-checked too.  Cross-compiles with hipcc; no GPU needed."""
+BF16x3 kernels' occupancy (three 256-thread workgroups, one 512-thread
+workgroup and four 256-thread workgroups per CU for the Pi build's 128 x 128
+and 256 x 256 forms and the W^c contraction) depends on their register
+counts staying below 168, 256 and 128 VGPRs; those are checked too.  Cross-compiles with hipcc; no GPU needed."""
 import concurrent.futures as cf
 import importlib.util
 import os
@@ -65,10 +65,10 @@ def test_no_kernel_uses_scratch(kernels):
 
 def test_bf16x3_kernels_keep_their_occupancy(kernels):
     vg = {k: v["VGPRs"] for k, v in kernels.items() if "bf16x3" in k}
-    pi = [v for k, v in vg.items() if "k_pi_bf16x3" in k and "tall" not in k]
-    tall = [v for k, v in vg.items() if "k_pi_bf16x3_tall" in k]
+    pi = [v for k, v in vg.items() if "k_pi_bf16x3" in k and "wide" not in k]
+    wide = [v for k, v in vg.items() if "k_pi_bf16x3_wide" in k]
     wc = [v for k, v in vg.items() if "k_wc_bf16x3" in k]
-    assert pi and wc and tall
+    assert pi and wc and wide
     assert max(pi) <= 168, vg      # three 256-thread workgroups per CU
-    assert max(tall) <= 256, vg    # two
+    assert max(wide) <= 256, vg    # one 512-thread workgroup (two wavefronts per SIMD)
     assert max(wc) <= 128, vg      # four
