@@ -262,6 +262,23 @@ int gw_reset_cache(gw_ctx* ctx);
  * written (the strict upper triangle is set to 0). */
 int gw_dielectric(gw_ctx* ctx, int n_xi, const double* xi, double* out);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc): gw_dielectric without any
+ * allocation, asynchronous on the context's stream.  d_xi: [n_xi] device
+ * array; d_out: caller's device buffer, matrix g at d_out + g * out_stride
+ * with rows of ld_out doubles (ld_out >= N_aux padded to 128, even;
+ * out_stride >= that padded N_aux times ld_out); the lower triangle of the
+ * padded matrix 1 - Pi(i xi_g) is written (rows and columns past N_aux are
+ * the identity's), the strict upper triangle is left as it was.  The scale
+ * vectors go into a 32 MiB device array of the library, one per GPU, held
+ * until the process ends: n_xi * Kp * 8 bytes (12 for the FP32 and BF16x3
+ * builds, Kp = n_occ n_virt padded to 128) must fit, else GW_EINVAL names
+ * the limit.  The FP32 / BF16x3 builds need the context's split copies of
+ * B_ov, made by a first gw_dielectric, gw_wtable or gw_qp (GW_EINVAL
+ * otherwise).  Calls on one GPU share that array, so calls that overlap in
+ * time on one GPU (different streams) race; serialise them. */
+int gw_dielectric_noalloc(gw_ctx* ctx, int n_xi, const double* d_xi, double* d_out,
+                          long ld_out, long out_stride);
 
 /* Cholesky factors L_g of 1 - Pi(i xi_g): out [n_xi][n_aux][n_aux] lower
  * triangular (upper set to 0). */

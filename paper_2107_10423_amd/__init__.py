@@ -116,6 +116,8 @@ _sig = {
     "gw_free": (None, [_ctxp]),
     "gw_set_pi_prec": (ctypes.c_int, [_ctxp, ctypes.c_int]),
     "gw_dielectric": (ctypes.c_int, [_ctxp, ctypes.c_int, _dp, _dp]),
+    "gw_dielectric_noalloc": (ctypes.c_int, [_ctxp, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_long, ctypes.c_long]),
     "gw_cholesky": (ctypes.c_int, [_ctxp, ctypes.c_int, _dp, _dp]),
     "gw_wtable": (ctypes.c_int, [_ctxp, ctypes.POINTER(_Grid), _dp]),
     "gw_sigma": (ctypes.c_int, [_ctxp, ctypes.c_int, _ip, _dp, ctypes.POINTER(_Grid), _dp, _dp, _ip]),
@@ -360,6 +362,12 @@ class Context:
         out = np.empty((xi.size, self.n_aux, self.n_aux))
         _check(_lib.gw_dielectric(self._h, xi.size, _pd(xi), _pd(out)))
         return out
+
+    def dielectric_noalloc(self, d_xi, n_xi, d_out, ld_out, out_stride):
+        """gw_dielectric_noalloc: device pointers (ints) in and out, nothing
+        allocated; asynchronous on the context's stream."""
+        _check(_lib.gw_dielectric_noalloc(self._h, int(n_xi), ctypes.c_void_p(d_xi),
+                                          ctypes.c_void_p(d_out), int(ld_out), int(out_stride)))
 
     def cholesky(self, xi):
         xi = _d(np.atleast_1d(xi))

@@ -2812,3 +2812,85 @@ extern "C" int gw_group_stage_a(int n, gw_ctx* const* ctxs, const gw_grid* grid,
   group_free(g);
   return r == 0 ? finish() : r;
 }
+
+// ===========================================================================
+// Allocation-free form of gw_dielectric (include/gw.h): the scale vectors live
+// in a file-scope device array instead of the context's stage-A workspace, and
+// the matrices go straight into the caller's device buffer.
+
+namespace {
+constexpr size_t NOALLOC_SCRATCH_BYTES = 32ull << 20;
+__device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+// per-device address of `scratch` (the array's name is no device address in
+// host code), looked up once per device with that device current
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_ptr(char** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(GW_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(GW_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (char*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+}  // namespace
+
+extern "C" int gw_dielectric_noalloc(gw_ctx* c, int n_xi, const double* d_xi, double* d_out,
+                                     long ld_out, long out_stride) {
+  if (!c || n_xi < 1 || !d_xi || !d_out) return fail(GW_EINVAL, "bad arguments");
+  if (audit_mode()) return fail(GW_EINVAL, "gw_dielectric_noalloc has no launch-audit form");
+  if (ld_out < c->Np || out_stride < (long)c->Np * ld_out || (ld_out & 1))
+    return fail(GW_EINVAL, "output layout: need ld_out >= %d (even) and out_stride >= %d * ld_out",
+                c->Np, c->Np);
+  const bool mixed = c->pi_prec != GW_PI_FP64;
+  const size_t need = (size_t)n_xi * c->Kp * (sizeof(double) + (mixed ? sizeof(float) : 0));
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(GW_EINVAL, "n_xi = %d needs %zu bytes of scratch, more than its %zu (at most %zu "
+                "grid points for this context)", n_xi, need, NOALLOC_SCRATCH_BYTES,
+                NOALLOC_SCRATCH_BYTES / ((size_t)c->Kp * (sizeof(double) + (mixed ? 4 : 0))));
+  if (mixed && !c->d_B32)
+    return fail(GW_EINVAL, "the context's split copies of B_ov are not built yet (a first "
+                "gw_dielectric, gw_wtable or gw_qp call builds them)");
+  char* base = nullptr;
+  RCHK(scratch_ptr(&base));
+  double* s64 = reinterpret_cast<double*>(base);
+  float* s32 = mixed ? reinterpret_cast<float*>(base + (size_t)n_xi * c->Kp * sizeof(double))
+                     : nullptr;
+  const long nS = (long)n_xi * c->Kp;
+  const long nOut = (long)(n_xi - 1) * out_stride + (long)(c->Np - 1) * ld_out + c->Np;
+  // every scale entry the builds read is written here first (no clearing needed)
+  HIPCHK(make_scale_imag(c->d_D, c->Kov, c->Kp, d_xi, n_xi, s64, s32, c->ext(c->d_D, 8), n_xi, nS,
+                         nS, c->st));
+  if (!mixed) {
+    GemmArgs a{};
+    a.A = c->d_Bov; a.lda = c->Kp; a.sA = 0;
+    a.B = c->d_Bov; a.ldb = c->Kp; a.sB = 0;
+    a.scale = s64; a.sS = c->Kp;
+    a.C = d_out; a.ldc = ld_out; a.sC = out_stride;
+    a.M = c->Np; a.N = c->Np; a.K = c->Kp;
+    a.map = MAP_LOWER;
+    a.tiles_m = c->Np / 128; a.tiles_n = c->Np / 128;
+    a.n_tiles = (int)lower_tile_count(a.tiles_m, a.tiles_n, 128, 128);
+    a.batch = n_xi; a.splitk = 1;
+    a.nA = c->ext(c->d_Bov, 8); a.nB = a.nA; a.nS = nS; a.nC = nOut;
+    HIPCHK(gemm_f64(a, 0, KC, KC, EPI_ONE_PLUS_4, c->st));
+  } else if (c->pi_prec == GW_PI_FP32) {
+    HIPCHK(pi_build_f32(c->d_B32, c->Kp, s32, c->Kp, d_out, ld_out, out_stride, c->Np, c->Kp, n_xi,
+                        c->ext(c->d_B32, 4), nS, nOut, c->st));
+  } else {
+    const long nB = std::min({c->ext(c->d_Bhi, 2), c->ext(c->d_Blo, 2), c->ext(c->d_B32, 4)});
+    HIPCHK(pi_build_bf16x3(c->d_Bhi, c->d_Blo, c->Kp, c->d_B32, s32, c->Kp, d_out, ld_out,
+                           out_stride, c->Np, c->Kp, n_xi, nB, nS, nOut, c->st));
+  }
+  return 0;
+}
