@@ -436,23 +436,30 @@ def roofline_objects(h, cfg, workload, states):
     opb = {"fp64": 8, "fp32": 4, "bf16x3": 8}[pi_prec]
     alg_pi = n_aux * n_ov * opb + Gx * n_aux * (n_aux + 1) // 2 * 8
     tr_pi = recorded_traffic(kname, workload)
-    pi_tf = flops / (h["pi_ms"] / 1e3) / 1e12
+    st = h["stages"]
+    n_pi = max(1, round(st.get("pi_launches", 1)))
+    pi_kms = st.get("pi_kernel_ms") or h["pi_ms"]       # the kernel's own launches
+    pi_tf = flops / (pi_kms / 1e3) / 1e12
     roof_pi = {"kernel": kname, "bound": "mfma", "achieved": round(pi_tf, 2),
                "peak": PEAK_TFLOPS[pi_prec], "unit": "TFLOP/s",
                "frac": round(pi_tf / PEAK_TFLOPS[pi_prec], 4),
-               "traffic": tr_pi, "algorithmic_bytes": alg_pi,
-               "traffic_over_algorithmic": round(tr_pi / alg_pi, 2) if tr_pi else None,
-               "flops_per_step": flops, "stage_ms": round(h["pi_ms"], 4),
+               "traffic": tr_pi, "algorithmic_bytes": alg_pi // n_pi,
+               "traffic_over_algorithmic": round(tr_pi / (alg_pi / n_pi), 2) if tr_pi else None,
+               "flops_per_launch": flops / n_pi, "launches_per_step": n_pi,
+               "launch_ms": round(pi_kms / n_pi, 4), "stage_ms": round(h["pi_ms"], 4),
                "issued_frac": round(pi_tf * (3 if pi_prec == "bf16x3" else 1)
                                     / PEAK_TFLOPS[pi_prec], 4),
                "note": f"achieved = algorithmic flops N_aux(N_aux+1)N_ov per grid point x {G} "
-                       "grid points / the Pi stage time (HIP events on the context stream; the "
-                       "stage also builds the xi = 0 point, not counted); BF16x3 issues 3 bf16 "
-                       "MFMA products per algorithmic product, so its issued rate is 3x"}
+                       "grid points per step / the Pi kernel's launch time (HIP events around "
+                       "its launches on the context stream; the launch also builds the xi = 0 "
+                       "point, not counted); BF16x3 issues 3 bf16 MFMA products per "
+                       "algorithmic product, so its issued rate is 3x"}
     n_rows_mo = len(states) * (cfg.shape.n_occ + cfg.shape.n_virt)
     w_flops = float(n_rows_mo) * n_aux * n_aux * G
     w_ms = h["stages"]["wtab_ms"]
-    w_tf = w_flops / (w_ms / 1e3) / 1e12
+    n_w = max(1, round(st.get("wc_launches", 1)))
+    w_kms = st.get("wc_kernel_ms") or w_ms
+    w_tf = w_flops / (w_kms / 1e3) / 1e12
     wname = "wc_bf16x3" if wc_prec == "bf16x3" else "w_gemm"
     tr_w = recorded_traffic(wname, workload)
     # algorithmic bytes: the rows b = (P|nm) once and L^-1 (lower triangle)
@@ -462,14 +469,16 @@ def roofline_objects(h, cfg, workload, states):
     roof_w = {"kernel": wname, "bound": "mfma", "achieved": round(w_tf, 2),
               "peak": PEAK_TFLOPS[wc_prec], "unit": "TFLOP/s",
               "frac": round(w_tf / PEAK_TFLOPS[wc_prec], 4), "traffic": tr_w,
-              "algorithmic_bytes": alg_w,
-              "traffic_over_algorithmic": round(tr_w / alg_w, 2) if tr_w else None,
-              "flops_per_step": w_flops, "stage_ms": round(w_ms, 4),
+              "algorithmic_bytes": alg_w // n_w,
+              "traffic_over_algorithmic": round(tr_w / (alg_w / n_w), 2) if tr_w else None,
+              "flops_per_launch": w_flops / n_w, "launches_per_step": n_w,
+              "launch_ms": round(w_kms / n_w, 4), "stage_ms": round(w_ms, 4),
               "issued_frac": round(w_tf * (3 if wc_prec == "bf16x3" else 1)
                                    / PEAK_TFLOPS[wc_prec], 4),
               "note": "W^c_nm = |L^-1 b|^2 - |b|^2 for every supplied row and m: algorithmic "
-                      f"flops n_rows n_mo N_aux^2 per grid point x {G} / the W^c stage time"}
-    roof, other = (roof_w, roof_pi) if w_ms > h["pi_ms"] else (roof_pi, roof_w)
+                      f"flops n_rows n_mo N_aux^2 per grid point x {G} / the launch time of "
+                      "the FP64 GEMM or BF16x3 contraction (HIP events around its launches)"}
+    roof, other = (roof_w, roof_pi) if w_kms > pi_kms else (roof_pi, roof_w)
     roof = dict(roof)
     roof["other_kernel"] = other
     return roof

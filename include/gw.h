@@ -313,6 +313,11 @@ typedef struct gw_timing {
   int qp_rounds, minres_iters, minres_systems, fallback_systems, wtab_cached;
   double sd_ms;     /* spectral-decomposition build (Casida matrix, Jacobi, pole strengths) */
   int sd_sweeps;    /* block-Jacobi sweeps of that build */
+  /* the Pi-build kernel and the W^c kernel (FP64 GEMM or BF16x3 contraction)
+   * alone, summed over their launches, and the number of launches of each
+   * (one per stage-A chunk) */
+  double pi_kernel_ms, wc_kernel_ms;
+  int pi_launches, wc_launches;
 } gw_timing;
 int gw_get_timing(gw_ctx* ctx, gw_timing* out);
 

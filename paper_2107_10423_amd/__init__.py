@@ -55,7 +55,9 @@ class Timing(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("qp_rounds", ctypes.c_int),
                 ("minres_iters", ctypes.c_int), ("minres_systems", ctypes.c_int),
                 ("fallback_systems", ctypes.c_int), ("wtab_cached", ctypes.c_int),
-                ("sd_ms", ctypes.c_double), ("sd_sweeps", ctypes.c_int)]
+                ("sd_ms", ctypes.c_double), ("sd_sweeps", ctypes.c_int),
+                ("pi_kernel_ms", ctypes.c_double), ("wc_kernel_ms", ctypes.c_double),
+                ("pi_launches", ctypes.c_int), ("wc_launches", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -354,6 +354,7 @@ struct gw_ctx {
   bool own_stream = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;    // stage timers
   hipEvent_t ev0b = nullptr, ev1b = nullptr;  // whole-call timer
+  hipEvent_t evk[4] = {nullptr, nullptr, nullptr, nullptr};  // Pi / W^c kernel launches
   // MINRES convergence polling: per-iteration active counts land in pinned
   // host memory and are read one iteration late, so the host never idles the GPU
   hipEvent_t ev_poll[2] = {nullptr, nullptr};
@@ -505,7 +506,8 @@ struct gw_ctx {
       if (cache) cache->put_dev(p);
       else rt_free(p);
     }
-    for (hipEvent_t e : {ev0, ev1, ev0b, ev1b, ev_poll[0], ev_poll[1], ev_quad[0], ev_quad[1]})
+    for (hipEvent_t e : {ev0, ev1, ev0b, ev1b, ev_poll[0], ev_poll[1], ev_quad[0], ev_quad[1],
+                         evk[0], evk[1], evk[2], evk[3]})
       if (e) hipEventDestroy(e);
     host_free(cache, h_stage);
     host_free(cache, h_poll);
@@ -805,8 +807,16 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
     HIPCHK(make_scale_imag(c->d_D, c->Kov, c->Kp, c->d_grid + g0, Gc, c->d_scale,
                            c->pi_prec == GW_PI_FP64 ? nullptr : c->d_scale32, c->ext(c->d_D, 8),
                            G - g0, c->ext(c->d_scale, 8), c->ext(c->d_scale32, 4), c->st));
+    if (!audit_mode()) HIPCHK(hipEventRecord(c->evk[0], c->st));
     RCHK(pi_build_chunk(c, Gc, per_g, ldA));
+    if (!audit_mode()) HIPCHK(hipEventRecord(c->evk[1], c->st));
     pi_ms += tm.stop();
+    if (!audit_mode()) {
+      float kms = 0.f;
+      HIPCHK(hipEventElapsedTime(&kms, c->evk[0], c->evk[1]));
+      c->timing.pi_kernel_ms += kms;
+    }
+    c->timing.pi_launches++;
     if (mode == 1) {
       RCHK(copy_out_blocks(c, dbg_out + (size_t)g0 * c->n_aux * c->n_aux, Gc, per_g, ldA));
       continue;
@@ -833,8 +843,10 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
       uint16_t* Fl = c->d_F + nF;
       HIPCHK(split_linv(c->d_work + (long)c->Np * ldA, ldA, per_g, c->Np, Gw, Fh, Fl, sF,
                         c->ext(c->d_work + (long)c->Np * ldA, 8), nF, c->st));
+      if (!audit_mode()) HIPCHK(hipEventRecord(c->evk[2], c->st));
       HIPCHK(wc_bf16x3(c->d_Rh, c->d_Rh + nRR, c->Np, c->Rp, Fh, Fl, sF, c->Np, Gw, c->d_parts,
                        parts_ld(c), parts_per_g(c), nRR, nF, c->ext(c->d_parts, 8), c->st));
+      if (!audit_mode()) HIPCHK(hipEventRecord(c->evk[3], c->st));
       HIPCHK(wc_from_parts(c->d_parts, parts_per_g(c), c->Np / 128, parts_ld(c), nullptr, c->nR,
                            Gw, G, g0, c->d_wtab, c->ext(c->d_parts, 8), 0, c->ext(c->d_wtab, 8),
                            c->st));
@@ -848,12 +860,22 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
       a.M = c->Rp; a.N = c->Np; a.K = c->Np;
       a.map = MAP_FULL_J; a.tiles_m = c->Rp / 128; a.tiles_n = c->Np / 128;
       a.n_tiles = a.tiles_m * a.tiles_n; a.batch = Gw; a.splitk = 1; a.ktri = 1;
+      if (!audit_mode()) HIPCHK(hipEventRecord(c->evk[2], c->st));
       RCHK(run_gemm(c, a, 0, KC, KM, EPI_SQNORM));
+      if (!audit_mode()) HIPCHK(hipEventRecord(c->evk[3], c->st));
       HIPCHK(wc_from_parts(c->d_parts, parts_per_g(c), c->Np / 128, parts_ld(c), c->d_bn, c->nR,
                            Gw, G, g0, c->d_wtab, c->ext(c->d_parts, 8), c->ext(c->d_bn, 8),
                            c->ext(c->d_wtab, 8), c->st));
     }
     wt_ms += tm.stop();
+    if (c->nR > 0 && Gw > 0) {
+      if (!audit_mode()) {
+        float kms = 0.f;
+        HIPCHK(hipEventElapsedTime(&kms, c->evk[2], c->evk[3]));
+        c->timing.wc_kernel_ms += kms;
+      }
+      c->timing.wc_launches++;
+    }
   }
   if (mode == 0 && with_w0 && !c->no_precond) {
     // the xi = 0 point is the last one, still in the work buffer after the
@@ -2071,7 +2093,9 @@ int setup_core(gw_ctx** out, const SetupIn& in, const gw_opts* opts, gw_devcache
        hipEventCreate(&c->ev0b) != hipSuccess || hipEventCreate(&c->ev1b) != hipSuccess ||
        hipEventCreateWithFlags(&c->ev_poll[0], hipEventDisableTiming) != hipSuccess ||
        hipEventCreateWithFlags(&c->ev_poll[1], hipEventDisableTiming) != hipSuccess ||
-       hipEventCreate(&c->ev_quad[0]) != hipSuccess || hipEventCreate(&c->ev_quad[1]) != hipSuccess))
+       hipEventCreate(&c->ev_quad[0]) != hipSuccess || hipEventCreate(&c->ev_quad[1]) != hipSuccess ||
+       hipEventCreate(&c->evk[0]) != hipSuccess || hipEventCreate(&c->evk[1]) != hipSuccess ||
+       hipEventCreate(&c->evk[2]) != hipSuccess || hipEventCreate(&c->evk[3]) != hipSuccess))
     return cleanup(fail(GW_EDEVICE, "hipEventCreate failed"));
   if (host_alloc(c->cache, (void**)&c->h_poll, 2 * sizeof(int)) != hipSuccess)
     return cleanup(fail(GW_ENOMEM, "pinned host allocation failed"));
