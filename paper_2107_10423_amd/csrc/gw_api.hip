@@ -847,7 +847,8 @@ int build_wtable(gw_ctx* c, const gw_grid* grid_in, int mode = 0, double* dbg_ou
       HIPCHK(wc_bf16x3(c->d_Rh, c->d_Rh + nRR, c->Np, c->Rp, Fh, Fl, sF, c->Np, Gw, c->d_parts,
                        parts_ld(c), parts_per_g(c), nRR, nF, c->ext(c->d_parts, 8), c->st));
       if (!audit_mode()) HIPCHK(hipEventRecord(c->evk[3], c->st));
-      HIPCHK(wc_from_parts(c->d_parts, parts_per_g(c), c->Np / 128, parts_ld(c), nullptr, c->nR,
+      HIPCHK(wc_from_parts(c->d_parts, parts_per_g(c), wc_bf16x3_panels(c->Np), parts_ld(c),
+                           nullptr, c->nR,
                            Gw, G, g0, c->d_wtab, c->ext(c->d_parts, 8), 0, c->ext(c->d_wtab, 8),
                            c->st));
     } else if (c->nR > 0 && Gw > 0) {
@@ -2561,7 +2562,8 @@ int group_sequence(gw_group* g, int n) {
     tb.grp = g->Gx;
     HIPCHK(wc_bf16x3_tab(tb, (long)Rp * Np, Np, Rp, Fh, Fl, sF, Np, G, L->d_parts, parts_ld(L),
                          parts_per_g(L), ex.rh / 2, nF, L->ext(L->d_parts, 8), L->st));
-    HIPCHK(wc_from_parts_tab(L->d_parts, parts_per_g(L), Np / 128, parts_ld(L), nullptr, Rp, G,
+    HIPCHK(wc_from_parts_tab(L->d_parts, parts_per_g(L), wc_bf16x3_panels(Np), parts_ld(L),
+                             nullptr, Rp, G,
                              g->Gx, (double* const*)T(T_WTAB), L->ext(L->d_parts, 8), 0, ex.wtab,
                              L->st));
   } else {

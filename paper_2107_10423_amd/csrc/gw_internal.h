@@ -118,6 +118,9 @@ hipError_t pi_build_f32_tab(const OperandTabs& tb, long ld, const float* scale, 
 hipError_t pi_build_bf16x3_tab(const OperandTabs& tb, long ld, const float* scale, long sS,
                                double* A, long ldA, long sA, int Np, int Kp, int G, long nB,
                                long nS, long nA, hipStream_t st);
+// panels of W^c partial sums the contraction writes per grid point (its
+// reduction sums this many: 128-wide panels, or 256-wide for large N_aux)
+int wc_bf16x3_panels(int Np);
 hipError_t wc_bf16x3_tab(const OperandTabs& tb, long nRR, long ldR, int Rp, const uint16_t* Fh,
                          const uint16_t* Fl, long sF, int Np, int G, double* part, long ldp,
                          long sP, long nR, long nF, long nP, hipStream_t st);

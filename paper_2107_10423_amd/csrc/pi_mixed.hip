@@ -443,14 +443,14 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
 // fragments of its four block columns held while the A block rows stream
 // through) with a double-buffered LDS (128 KB) and one barrier per K-step:
 // after the barrier the staged slabs of step k+1 are split and stored into the
-// other buffer and the loads of step k+2 are issued, then the MFMAs of step k
-// run.  Per flop it stages half of the global bytes and 7/8 of the LDS bytes
+// other buffer and the loads of step k+2 are issued, in one basic block with
+// the MFMAs of step k so that the scheduler interleaves them.  Per flop it stages half of the global bytes and 7/8 of the LDS bytes
 // of a 256 x 128 tile, and half of the scaled side's split work of the
 // 128 x 128 form.  At up to 256 VGPRs one workgroup (two wavefronts per SIMD)
 // holds a CU.  Lower tiles (I, J), J <= I, of 256; the last tile row and
 // column may reach past N_aux: rows are clamped on load and not stored, and
-// a wavefront whose block lies past N_aux or wholly above the diagonal skips
-// its MFMAs.  Same K order and products as the 128 x 128 form, so the results
+// a wavefront whose block lies past N_aux or wholly above the diagonal stores
+// nothing.  Same K order and products as the 128 x 128 form, so the results
 // are identical bit for bit.
 __global__ __launch_bounds__(512) void k_pi_bf16x3_wide(const uint16_t* Bhi, const uint16_t* Blo,
                                                         long ld, const float* B32,
@@ -540,32 +540,34 @@ __global__ __launch_bounds__(512) void k_pi_bf16x3_wide(const uint16_t* Bhi, con
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     __syncthreads();   // step kt's slabs are in place; nobody reads buffer cur ^ 1 any more
-    if (kt + 1 < nk) {
-      lstore(cur ^ 1);                                      // step kt + 1
-      gload((kt + 2 < nk ? kt + 2 : kt) * BKB);             // step kt + 2
+    // one basic block per K-step (no branches), so that the scheduler weaves
+    // the next step's split, stores and loads into this step's MFMA stream:
+    // the B fragments of this step, the slabs of step kt + 1 into the other
+    // buffer (the last step's store goes to a buffer nobody reads again), the
+    // loads of step kt + 2, then the MFMAs (wavefronts with no live block
+    // compute too and store nothing)
+    s8 bh[4], bl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = ko + (bq + j) * 128;
+      bh[j] = *reinterpret_cast<const s8*>(&Bh[cur][bhalf][o]);
+      bl[j] = *reinterpret_cast<const s8*>(&Bl[cur][bhalf][o]);
     }
-    if (live) {
-      s8 bh[4], bl[4];
+    lstore(cur ^ 1);
+    gload((kt + 2 < nk ? kt + 2 : nk - 1) * BKB);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int o = ko + i * 128;
+      const s8 ah = *reinterpret_cast<const s8*>(&Ah[cur][wm][o]);
+      const s8 al = *reinterpret_cast<const s8*>(&Al[cur][wm][o]);
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int o = ko + (bq + j) * 128;
-        bh[j] = *reinterpret_cast<const s8*>(&Bh[cur][bhalf][o]);
-        bl[j] = *reinterpret_cast<const s8*>(&Bl[cur][bhalf][o]);
-      }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int o = ko + i * 128;
-        const s8 ah = *reinterpret_cast<const s8*>(&Ah[cur][wm][o]);
-        const s8 al = *reinterpret_cast<const s8*>(&Al[cur][wm][o]);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf8, al), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf8, ah), __builtin_bit_cast(bf8, bl[j]), acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-              __builtin_bit_cast(bf8, ah), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
-        }
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf8, al), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf8, ah), __builtin_bit_cast(bf8, bl[j]), acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf8, ah), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
       }
     }
   }
@@ -816,6 +818,142 @@ __global__ __launch_bounds__(256, 4) void k_wc_bf16x3(const uint16_t* Rh, const 
   if (t < 128) part[(long)g * sP + (long)J * ldp + ar0 + t] = red[0][t] + red[1][t];
 }
 
+// Wide form for large N_aux: 256 x 256 tiles (256 rows of R, a 256-wide panel
+// J of F) on 512-thread workgroups, eight wavefronts of 128 x 64, with the
+// double-buffered LDS and single-block K-step of the wide Pi build (both
+// operands arrive pre-split, so the stores are plain copies); K runs over
+// k < min(256 (J + 1), N_aux).  part[g][J][q] holds the panel sums over the
+// 256-wide panels (J < ceil(N_aux / 256)).  Order: blocks of 8 grid points,
+// then the panel, then groups of 4 row tiles, grid point fastest, so the 32
+// workgroups an XCD holds share 4 R tiles and 8 F panels through its L2.
+// Rows past the padded R and columns past N_aux are clamped on load and
+// neither stored nor summed.
+__global__ __launch_bounds__(512) void k_wc_bf16x3_wide(const uint16_t* Rh, const uint16_t* Rl,
+                                                        long ldR, const uint16_t* Fh,
+                                                        const uint16_t* Fl, long sF, int Np,
+                                                        int Rp, double* part, long ldp, long sP,
+                                                        int TM, int TN, int G, OperandTabs tb,
+                                                        long nRR) {
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[2][2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Al[2][2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bh[2][2][SLAB];
+  __shared__ __attribute__((aligned(16))) uint16_t Bl[2][2][SLAB];
+  __shared__ double red[4][256];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int wm = wave >> 2, wn = wave & 3;
+  const int id = xcd_swizzle_m(blockIdx.x, TM * TN * G);
+  const int gb = id / (8 * TN * TM);
+  const int gs = min(8, G - 8 * gb);
+  const int rem = id - gb * 8 * TN * TM;
+  const int J = rem / (gs * TM);
+  const int rem2 = rem % (gs * TM);
+  const int r4 = rem2 % (4 * gs);
+  const int I = 4 * (rem2 / (4 * gs)) + r4 / gs;
+  const int g = 8 * gb + r4 % gs;
+  if (tb.Rh) {
+    Rh = tb.Rh[g / tb.grp];
+    Rl = Rh + nRR;
+  }
+  const uint16_t* Fhg = Fh + (long)g * sF;
+  const uint16_t* Flg = Fl + (long)g * sF;
+  const int ar0 = I * 256, br0 = J * 256;
+  const int nk = min(br0 + 256, Np) / BKB;
+  const bool live = br0 + wn * 64 < Np && ar0 + wm * 128 < Rp;
+  f4 acc[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  // 256 rows x 4 chunks per array and operand: 2 items per thread
+  u32x4 rah[2], ral[2], rbh[2], rbl[2];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int row, ch;
+      a_item(t + 512 * u, row, ch);
+      const long oa = (long)min(ar0 + row, Rp - 1) * ldR + k0 + 8 * ch;
+      const long ob = (long)min(br0 + row, Np - 1) * Np + k0 + 8 * ch;
+      rah[u] = *reinterpret_cast<const u32x4*>(Rh + oa);
+      ral[u] = *reinterpret_cast<const u32x4*>(Rl + oa);
+      rbh[u] = *reinterpret_cast<const u32x4*>(Fhg + ob);
+      rbl[u] = *reinterpret_cast<const u32x4*>(Flg + ob);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      int row, ch;
+      a_item(t + 512 * u, row, ch);
+      const int sl = lds_slot(row & 127, ch);
+      *reinterpret_cast<u32x4*>(&Ah[buf][row >> 7][sl]) = rah[u];
+      *reinterpret_cast<u32x4*>(&Al[buf][row >> 7][sl]) = ral[u];
+      *reinterpret_cast<u32x4*>(&Bh[buf][row >> 7][sl]) = rbh[u];
+      *reinterpret_cast<u32x4*>(&Bl[buf][row >> 7][sl]) = rbl[u];
+    }
+  };
+  gload(0);
+  lstore(0);
+  gload(nk > 1 ? BKB : 0);
+  const int ko = 8 * ((lane >> 4) * 128 + ((lane & 15) ^ (lane >> 4)));
+  const int bhalf = wn >> 1, bq = (wn & 1) * 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    __syncthreads();   // step kt's slabs are in place; nobody reads buffer cur ^ 1 any more
+    s8 bh[4], bl[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int o = ko + (bq + j) * 128;
+      bh[j] = *reinterpret_cast<const s8*>(&Bh[cur][bhalf][o]);
+      bl[j] = *reinterpret_cast<const s8*>(&Bl[cur][bhalf][o]);
+    }
+    lstore(cur ^ 1);   // the last step's store goes to a buffer nobody reads again
+    gload((kt + 2 < nk ? kt + 2 : nk - 1) * BKB);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int o = ko + i * 128;
+      const s8 ah = *reinterpret_cast<const s8*>(&Ah[cur][wm][o]);
+      const s8 al = *reinterpret_cast<const s8*>(&Al[cur][wm][o]);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf8, al), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf8, ah), __builtin_bit_cast(bf8, bl[j]), acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+            __builtin_bit_cast(bf8, ah), __builtin_bit_cast(bf8, bh[j]), acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+  // per row, the sum over this wavefront's 64 columns (p < N_aux) of
+  // (2 b_p + y_p) y_p, then over the four wavefronts of the row half
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int lrow = wm * 128 + i * 16 + mfma_row(4 * (lane >> 4) + r);
+      const long ro = (long)min(ar0 + lrow, Rp - 1) * ldR;
+      double sum = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = br0 + wn * 64 + j * 16 + mfma_row(lane & 15);
+        if (live && col < Np) {
+          const double b = (double)bf16_to_f(Rh[ro + col]) + (double)bf16_to_f(Rl[ro + col]);
+          const double y = (double)acc[i][j][r];
+          sum += (2.0 * b + y) * y;
+        }
+      }
+      for (int off = 8; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 16);
+      if ((lane & 15) == 0) red[wn][lrow] = sum;
+    }
+  __syncthreads();
+  if (t < 256 && ar0 + t < Rp)
+    part[(long)g * sP + (long)J * ldp + ar0 + t] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+}
+
+// Panels of the W^c partial sums the contraction writes per grid point
+// (128 wide, or 256 wide for the wide form); the reduction sums this many.
+int wc_bf16x3_panels(int Np) { return Np >= WIDE_FROM ? (Np + 255) / 256 : Np / 128; }
+
 static hipError_t launch_wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl, const OperandTabs& tb,
                                    long nRR, long ldR, int Rp, const uint16_t* Fh,
                                    const uint16_t* Fl, long sF, int Np, int G, double* part,
@@ -834,6 +972,14 @@ static hipError_t launch_wc_bf16x3(const uint16_t* Rh, const uint16_t* Rl, const
   GW_GUARD(kn, "F", (long)(G - 1) * sF + (long)(Np - 1) * Np + Np - 1, nF);
   GW_GUARD(kn, "part", (long)(G - 1) * sP + (long)(Np / 128 - 1) * ldp + Rp - 1, nP);
   GW_AUDIT_RETURN();
+  if (Np >= WIDE_FROM) {
+    const int TM = (Rp + 255) / 256, TN = (Np + 255) / 256;
+    const long wtotal = (long)TM * TN * G;
+    if (wtotal > 0x7fffffffL) return refuse(kn, "grid too large");
+    hipLaunchKernelGGL(k_wc_bf16x3_wide, dim3((unsigned)wtotal), dim3(512), 0, st, Rh, Rl, ldR, Fh,
+                       Fl, sF, Np, Rp, part, ldp, sP, TM, TN, G, tb, nRR);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(k_wc_bf16x3, dim3((unsigned)total), dim3(256), 0, st, Rh, Rl, ldR, Fh, Fl, sF,
                      Np, part, ldp, sP, Rp / 128, Np / 128, G, tb, nRR);
   return hipGetLastError();

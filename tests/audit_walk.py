@@ -27,6 +27,7 @@ CASES = [
     (12, 70, 220, (0, 11), 32, 2 << 20, 0),    # chunked stage A
     (50, 380, 1120, tuple(range(45, 55)), 64, 0, 0),  # (H2O)10 shape
     (17, 63, 129, (16, 17, 40), 7, 0, 2),
+    (3, 20, 2100, (1, 2), 4, 0, 0),            # N_aux past the wide tiles' threshold, ragged
 ]
 
 

@@ -67,8 +67,9 @@ def test_bf16x3_kernels_keep_their_occupancy(kernels):
     vg = {k: v["VGPRs"] for k, v in kernels.items() if "bf16x3" in k}
     pi = [v for k, v in vg.items() if "k_pi_bf16x3" in k and "wide" not in k]
     wide = [v for k, v in vg.items() if "k_pi_bf16x3_wide" in k]
-    wc = [v for k, v in vg.items() if "k_wc_bf16x3" in k]
-    assert pi and wc and wide
+    wc = [v for k, v in vg.items() if "k_wc_bf16x3" in k and "wide" not in k]
+    wcw = [v for k, v in vg.items() if "k_wc_bf16x3_wide" in k]
+    assert pi and wc and wide and wcw
     assert max(pi) <= 168, vg      # three 256-thread workgroups per CU
-    assert max(wide) <= 256, vg    # one 512-thread workgroup (two wavefronts per SIMD)
+    assert max(wide + wcw) <= 256, vg   # one 512-thread workgroup (two wavefronts per SIMD)
     assert max(wc) <= 128, vg      # four
