@@ -334,9 +334,10 @@ int gw_get_timing(gw_ctx* ctx, gw_timing* out);
  * Small requests (N_aux up to batch_max_aux) are batched: when one is
  * admitted, every pending request of the same padded shape (N_aux, n_occ n_virt
  * and n_rows n_mo, each padded to 128) joins it, up to a batch size the
- * shape's workspace allows, and their stage A (the Pi build, Cholesky and W^c
- * table on every grid point) runs as one set of launches over all their grid
- * points, replayed from a graph captured for that shape and batch size.  Each
+ * shape's workspace allows, and when that makes two or more, their stage A
+ * (the Pi build, Cholesky and W^c table on every grid point) runs as one set
+ * of launches over all their grid points, replayed from a graph captured for
+ * that shape and batch size.  Each
  * request's quasiparticle stage then runs on whichever pipeline is free.
  * Results are those of gw_qp on the request alone, bit for bit.  Device and
  * pinned host blocks are kept by the server and reused across requests, so a

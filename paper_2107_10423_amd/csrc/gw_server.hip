@@ -228,7 +228,9 @@ struct gw_server {
       if (qp_stage) {
         qp(r, slot);
         complete(r);
-      } else if (batch.empty()) {
+      } else if (batch.size() < 2) {
+        // nothing to share a launch with: the solo path, which needs no
+        // group workspace and no captured graph
         process(r, slot);
         complete(r);
       } else {
