@@ -138,7 +138,8 @@ void minres_splits(int kp, int Np, int Kp, int* splitk, int* splitk1) {
   // K chunks of about `chunk2` (pass 2) and `chunk1` (pass 1) elements bound the
   // latency chain of each workgroup; GW_TUNE_MINRES="chunk1,chunk2" replaces
   // the rule below by those chunks
-  int chunk1 = 384, chunk2 = 512;
+  int chunk1 = 384, chunk2 = 4096;
+  const int t1 = (kp / 64) * (Kp / 64);
   const int t2 = (kp / 64) * (Np / 128);
   if (const char* e = getenv("GW_TUNE_MINRES")) {
     if (sscanf(e, "%d,%d", &chunk1, &chunk2) == 2) {
@@ -149,8 +150,11 @@ void minres_splits(int kp, int Np, int Kp, int* splitk, int* splitk1) {
       return;
     }
   }
+  // pass 2 (kp x N_aux outputs): about 1024 workgroups, or K chunks of about
+  // chunk2 where that makes more; pass 1 is split only when its kp x N_ov
+  // outputs make fewer than 2048 tiles
   *splitk = std::max(1, std::min(std::max(1024 / std::max(t2, 1), Kp / chunk2), Kp / 64));
-  *splitk1 = std::max(1, std::min(Np / chunk1, Np / 16));
+  *splitk1 = t1 >= 2048 ? 1 : std::max(1, std::min(Np / chunk1, Np / 16));
 }
 
 long lower_tile_count(int tiles_m, int tiles_n, int BM, int BN) {
@@ -993,13 +997,15 @@ int ensure_minres(gw_ctx* c, int kp) {
 // mask (nullable): per 16-system block, 0 where every system's vector is zero
 int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long ldc,
                 const int* mask = nullptr) {
-  // out = scale(X B_ov): rows = systems, cols = ia
+  // out = scale(X B_ov): rows = systems, cols = ia.  The system tiles that
+  // read one B_ov column panel are adjacent in the launch order (and so run
+  // together on one XCD), so the panel comes from HBM once, not kp / 64 times
   GemmArgs a{};
   a.A = X; a.lda = c->Np; a.sA = 0;
   a.B = c->d_Bov; a.ldb = c->Kp; a.sB = 0;
   a.C = out; a.ldc = ldc; a.sC = 0;
   a.M = kp; a.N = c->Kp; a.K = c->Np;
-  a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Kp / 64;
+  a.map = MAP_FULL_J; a.tiles_m = kp / 64; a.tiles_n = c->Kp / 64;
   a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
   a.mrows = mask ? 0 : c->mr.k;   // a mask also marks the padding systems
   a.rowmask = mask; a.nMask = c->ext(mask, sizeof(int));
