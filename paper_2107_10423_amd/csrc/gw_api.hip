@@ -54,6 +54,13 @@ int fail(int code, const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   g_err = buf;
+  // GW_TRACE_ERRORS=1: every error is also printed where it arises (worker
+  // threads of the request server included)
+  static const bool show = [] {
+    const char* e = getenv("GW_TRACE_ERRORS");
+    return e && *e && *e != '0';
+  }();
+  if (show || trace_on()) fprintf(stderr, "gw: error %d: %s\n", code, buf);
   return code;
 }
 
@@ -155,6 +162,25 @@ void minres_splits(int kp, int Np, int Kp, int* splitk, int* splitk1) {
   // outputs make fewer than 2048 tiles
   *splitk = std::max(1, std::min(std::max(1024 / std::max(t2, 1), Kp / chunk2), Kp / 64));
   *splitk1 = t1 >= 2048 ? 1 : std::max(1, std::min(Np / chunk1, Np / 16));
+}
+
+// Split-K slabs of the preconditioner product r M^-1 (K = Np, a multiple of
+// 128, so each slab's K range is a multiple of 16)
+constexpr int PRE_SPLIT = 8;
+
+// Elements of the MINRES partial-product buffer for a capacity of kp systems.
+// The splits follow the capacity, and a smaller capacity can need more (the
+// first pass is split over N_aux only while it has few tiles), so the buffer
+// and the footprint take the largest need of every capacity up to kp.
+size_t minres_part_elems(int kp, int Np, int Kp) {
+  size_t part = 0;
+  for (int q = 64; q <= std::max(kp, 64); q += 64) {
+    int splitk = 1, splitk1 = 1;
+    minres_splits(q, Np, Kp, &splitk, &splitk1);
+    part = std::max({part, (size_t)splitk * q * Np, (size_t)(Kp / 64) * q,
+                     (size_t)splitk1 * q * Kp, (size_t)PRE_SPLIT * q * Np});
+  }
+  return part;
 }
 
 long lower_tile_count(int tiles_m, int tiles_n, int BM, int BN) {
@@ -948,9 +974,6 @@ int ensure_stage(gw_ctx* c, size_t bytes) {
   return 0;
 }
 
-// Split-K slabs of the preconditioner product r M^-1 (K = Np, a multiple of
-// 128, so each slab's K range is a multiple of 16)
-constexpr int PRE_SPLIT = 8;
 
 // Staging bytes of one MINRES batch of kp systems: rhs index, warm flag,
 // frequency, tolerance in; W^c, dW^c, convergence out.
@@ -973,8 +996,7 @@ int ensure_minres(gw_ctx* c, int kp) {
   minres_splits(kp, c->Np, c->Kp, &splitk, &splitk1);
   c->mr_splitk = splitk;
   c->mr_splitk1 = splitk1;
-  size_t part = std::max({(size_t)splitk * kp * c->Np, (size_t)(c->Kp / 64) * kp,
-                          (size_t)splitk1 * kp * c->Kp, (size_t)PRE_SPLIT * kp * c->Np});
+  const size_t part = minres_part_elems(kp, c->Np, c->Kp);
   RCHK(c->alloc((void**)&m.part, part * sizeof(double)));
   c->part_cap = part;
   RCHK(c->alloc((void**)&m.active, 2 * sizeof(int)));
@@ -1804,10 +1826,7 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   // MINRES workspace for the largest batch
   const int kmax = std::min(std::max(n_states, 1) * n_mo, minres_batch);
   const int kp = round_up(kmax, 64);
-  int splitk = 1, splitk1 = 1;
-  minres_splits(kp, Np, Kp, &splitk, &splitk1);
-  const size_t part = std::max({(size_t)splitk * kp * Np, (size_t)(Kp / 64) * kp,
-                                (size_t)splitk1 * kp * Kp, (size_t)PRE_SPLIT * kp * Np});
+  const size_t part = minres_part_elems(kp, Np, Kp);
   b += 8 * (size_t)kp * Np * d + (size_t)kp * 16 * d + (size_t)kp * Kp * d + part * d +
        (size_t)kp * (2 * d + 2 * sizeof(int) + 2 * d + sizeof(int)) + 2 * sizeof(int) +
        2 * (size_t)(kp / 16) * sizeof(int);

@@ -63,6 +63,30 @@ def run_case(n_occ, n_virt, n_aux, rows, G, wb, cap):
               flush=True)
 
 
+def run_budget_case(n_occ, n_virt, n_aux, G):
+    """A context held to exactly its footprint: residue batches of 70, 150 and
+    200 systems (MINRES capacities of 128, 192 and 256, whose split rules
+    differ) must all stay inside it."""
+    shape = gwgen.custom_shape(n_occ, n_virt, n_aux, n_core=1)
+    rows = (n_occ - 1, n_occ)
+    inp = gwgen.make_inputs(shape, 2, rows)
+    n_mo = n_occ + n_virt
+    fp = gwl.footprint(n_mo, n_occ, n_aux, len(rows), 1, G)
+    g = gwl.Grid.gauss_legendre(G)
+    with gwl.Context.from_inputs(inp, mem_budget_bytes=fp) as c:
+        calls = [lambda: c.wtable(g)] + [
+            (lambda k=k: c.residues([rows[0]] * k, [m % n_mo for m in range(k)],
+                                    np.linspace(-1, 22, k))) for k in (70, 150, 200)]
+        for call in calls:   # the W^c table's workspace first, as in a QP call
+            try:
+                call()
+            except gwl.GWError as e:
+                if e.code != gwl.GW_EAUDIT:
+                    raise
+    print(f"budget case {n_occ}/{n_virt}/{n_aux}: MINRES capacities 128, 192, 256 within "
+          f"the footprint ({fp / 2**20:.0f} MiB)", flush=True)
+
+
 def run_uhf_case(n_occ, n_virt, n_aux, rows, G):
     """Open-shell context: both spins' transitions stacked in one operator."""
     shape = gwgen.custom_shape(n_occ, n_virt, n_aux, n_core=1)
@@ -150,6 +174,7 @@ def main():
     run_group_case([1, 1, 1], 64)
     run_group_case([3, 3], 16)
     run_group_case([6, 6, 6, 6], 8)
+    run_budget_case(40, 900, 1152, 4)
     run_uhf_case(6, 40, 150, (3, 6, 46 + 4, 46 + 5), 6)
     run_uhf_case(1, 3, 20, (0, 4, 5), 3)
     print("audit ok")
