@@ -307,90 +307,38 @@ def load_workload(name):
     return cfg, inp, gold
 
 
-def serve_leg(gwl, n_requests, kmax, streams, small_k=6):
+def serve_leg(gwl, n_requests, kmax, streams, small_k=6, n_burst=48):
     """Serving workload (bounded): the first n_requests requests of the stream
     (water clusters of k ~ U{1..kmax}, request r seeded 1000 + r, HOMO-2..LUMO+2,
     64-point grid) through gw_server.  Closed loop with 8 outstanding for FP64
     and for the mixed form -> saturated throughput; then Poisson arrivals at
     0.8 x the FP64 saturated rate for FP64, for the mixed form, and for the
     mixed form with batching off -> throughput and p50 / p99 latency (done -
-    submit), also over the small requests (k <= small_k) alone."""
-    import threading
+    submit), also over the small requests (k <= small_k) alone.
+
+    Small-request leg: the first n_burst requests of the same stream with
+    k <= small_k (the sizes whose stage A is batched), mixed form, with and
+    without batching: closed loop with 16 outstanding, then Poisson arrivals
+    at 0.8 x the unbatched closed-loop rate."""
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
     import gwgen
 
-    stream = gwgen.serving_stream(n_requests=n_requests, k_max=kmax, seed=5000, rate=1.0)
-    log(f"serve: generating {len(stream)} requests (seed 1000 + r each)")
+    full = gwgen.serving_stream(n_requests=max(n_requests, 1024), k_max=kmax, seed=5000,
+                                rate=1.0)
+    stream = full[:n_requests]
+    burst = [r for r in full if r["k"] <= small_k][:n_burst]
+    log(f"serve: generating {len(stream)} + {len(burst)} requests (seed 1000 + r each)")
     with ThreadPoolExecutor(max_workers=min(16, _cores() or 1)) as ex:
         inputs = list(ex.map(lambda r: gwgen.serving_inputs(r["k"], r["seed"]), stream))
+        b_inputs = list(ex.map(lambda r: gwgen.serving_inputs(r["k"], r["seed"]), burst))
     grid = gwl.Grid.gauss_legendre(64)
-    ks = np.array([r["k"] for r in stream])
 
-    def run(prec, arrivals, window=None, batch_max_aux=0):
-        srv = gwl.Server(grid, n_streams=streams, batch_max_aux=batch_max_aux, **PATHS[prec])
-        tickets, E, lat = {}, {}, {}
-        done_t, sub_t = [], []
-        lock = threading.Lock()
-        outstanding = threading.Semaphore(window) if window else None
-        t0 = time.perf_counter()
-
-        def producer():
-            for i in range(len(stream)):
-                if arrivals is not None:
-                    dt = arrivals[i] - (time.perf_counter() - t0)
-                    if dt > 0:
-                        time.sleep(dt)
-                if outstanding:
-                    outstanding.acquire()
-                inp = inputs[i]
-                tk = srv.submit_inputs(inp, list(inp.row_ids))
-                with lock:
-                    tickets[tk] = i
-
-        th = threading.Thread(target=producer)
-        th.start()
-        n_done = 0
-        while n_done < len(stream):
-            with lock:
-                items = list(tickets.items())
-            progressed = False
-            for tk, i in items:
-                out = srv.poll(tk)
-                if out is None:
-                    continue
-                progressed = True
-                with lock:
-                    del tickets[tk]
-                if outstanding:
-                    outstanding.release()
-                info = out[4]
-                if info["rc"] != 0:
-                    raise RuntimeError(f"request {i} failed with {info['rc']}")
-                E[i] = out[0]
-                lat[i] = info["t_done"] - info["t_submit"]
-                done_t.append(info["t_done"])
-                sub_t.append(info["t_submit"])
-                n_done += 1
-                if n_done % 16 == 0:
-                    log(f"serve: {prec}: {n_done}/{len(stream)} done")
-            if not progressed:
-                time.sleep(0.002)
-        th.join()
-        st = srv.stats()
-        srv.close()
-        span = max(done_t) - min(sub_t)
-        L = np.array([lat[i] for i in range(len(stream))])
-        small = L[ks <= small_k]
-        return dict(E=E, span_s=span, req_per_s=len(stream) / span,
-                    qp_per_s=sum(len(x.row_ids) for x in inputs) / span,
-                    p50_s=float(np.percentile(L, 50)), p99_s=float(np.percentile(L, 99)),
-                    small_p50_s=float(np.percentile(small, 50)) if small.size else None,
-                    small_p99_s=float(np.percentile(small, 99)) if small.size else None,
-                    peak_active=st["peak_active"], batches=st["batches"],
-                    batched_requests=st["batched_requests"], graph_replays=st["graph_replays"],
-                    device_mallocs=st["device_mallocs"], cache_hits=st["cache_hits"])
+    def run(prec, arrivals, window=None, batch_max_aux=0, reqs=None):
+        stream_, inputs_ = reqs if reqs is not None else (stream, inputs)
+        return _serve_run(gwl, grid, streams, stream_, inputs_, small_k, prec, arrivals,
+                          window, batch_max_aux)
 
     sat = {}
     for prec in ("fp64", "bf16x3w"):
@@ -405,12 +353,26 @@ def serve_leg(gwl, n_requests, kmax, streams, small_k=6):
         res[key] = run(prec, arr, batch_max_aux=lim)
     dE = max(float(np.max(np.abs(res["bf16x3w"]["E"][i] - res["fp64"]["E"][i])))
              for i in range(len(stream)))
+    # small requests alone: batching on and off
+    b_sat, b_res = {}, {}
+    for key, lim in (("batching", 0), ("no_batching", -1)):
+        log(f"serve: small requests, mixed, {key}, closed loop (16 outstanding)")
+        b_sat[key] = run("bf16x3w", None, window=16, batch_max_aux=lim, reqs=(burst, b_inputs))
+    lam_b = 0.8 * b_sat["no_batching"]["req_per_s"]
+    # arrival gaps of the burst requests' own Poisson process, rescaled
+    gaps = np.diff([r["arrival_s"] for r in burst], prepend=burst[0]["arrival_s"])
+    arr_b = np.cumsum(gaps) / np.mean(gaps[1:]) / lam_b
+    for key, lim in (("batching", 0), ("no_batching", -1)):
+        log(f"serve: small requests, mixed, {key}, Poisson arrivals at {lam_b:.1f} req/s")
+        b_res[key] = run("bf16x3w", arr_b, batch_max_aux=lim, reqs=(burst, b_inputs))
+    dEb = max(float(np.max(np.abs(b_res["batching"]["E"][i] - b_res["no_batching"]["E"][i])))
+              for i in range(len(burst)))
     pick = lambda r: {k: (round(v, 4) if isinstance(v, float) else v)
                       for k, v in r.items() if k != "E"}
     return {"workload": f"first {len(stream)} requests of the serving stream: water clusters "
                         f"k ~ U{{1..{kmax}}}, request r seeded 1000 + r, HOMO-2..LUMO+2, "
                         f"64-point grid, {streams} pipelines",
-            "small_k_max": small_k, "n_small": int((ks <= small_k).sum()),
+            "small_k_max": small_k, "n_small": int(sum(r["k"] <= small_k for r in stream)),
             "poisson_rate_req_per_s": round(lam, 4),
             "saturated": {p: pick(r) for p, r in sat.items()},
             "poisson": {p: pick(r) for p, r in res.items()},
@@ -418,7 +380,88 @@ def serve_leg(gwl, n_requests, kmax, streams, small_k=6):
             "p99_s": {p: round(r["p99_s"], 4) for p, r in res.items()},
             "max_abs_dE_mixed_vs_fp64_mev": dE / MEV,
             "mixed_over_fp64_saturated_qp_per_s":
-                round(sat["bf16x3w"]["qp_per_s"] / sat["fp64"]["qp_per_s"], 3)}
+                round(sat["bf16x3w"]["qp_per_s"] / sat["fp64"]["qp_per_s"], 3),
+            "small_requests": {
+                "workload": f"the first {len(burst)} requests of the same stream with "
+                            f"k <= {small_k}, mixed form",
+                "poisson_rate_req_per_s": round(lam_b, 2),
+                "saturated": {p: pick(r) for p, r in b_sat.items()},
+                "poisson": {p: pick(r) for p, r in b_res.items()},
+                "max_abs_dE_batching_vs_not_mev": dEb / MEV}}
+
+
+def _serve_run(gwl, grid, streams, stream, inputs, small_k, prec, arrivals, window,
+               batch_max_aux):
+    """One pass of a request list through a fresh gw_server."""
+    import threading
+
+    import numpy as np
+    ks = np.array([r["k"] for r in stream])
+    srv = gwl.Server(grid, n_streams=streams, batch_max_aux=batch_max_aux, **PATHS[prec])
+    tickets, E, lat = {}, {}, {}
+    done_t, sub_t = [], []
+    lock = threading.Lock()
+    outstanding = threading.Semaphore(window) if window else None
+    t0 = time.perf_counter()
+
+    def producer():
+        for i in range(len(stream)):
+            if arrivals is not None:
+                dt = arrivals[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+            if outstanding:
+                outstanding.acquire()
+            inp = inputs[i]
+            tk = srv.submit_inputs(inp, list(inp.row_ids))
+            with lock:
+                tickets[tk] = i
+
+    failed = []
+    th = threading.Thread(target=producer, daemon=True)
+    th.start()
+    n_done = 0
+    while n_done < len(stream):
+        with lock:
+            items = list(tickets.items())
+        progressed = False
+        for tk, i in items:
+            out = srv.poll(tk)
+            if out is None:
+                continue
+            progressed = True
+            with lock:
+                del tickets[tk]
+            if outstanding:
+                outstanding.release()
+            info = out[4]
+            if info["rc"] != 0:
+                failed.append((i, info["rc"]))
+            E[i] = out[0]
+            lat[i] = info["t_done"] - info["t_submit"]
+            done_t.append(info["t_done"])
+            sub_t.append(info["t_submit"])
+            n_done += 1
+            if n_done % 16 == 0:
+                log(f"serve: {prec}: {n_done}/{len(stream)} done")
+        if not progressed:
+            time.sleep(0.002)
+    th.join()
+    st = srv.stats()
+    srv.close()
+    if failed:
+        raise RuntimeError(f"{prec}: requests failed (index, code): {failed}")
+    span = max(done_t) - min(sub_t)
+    L = np.array([lat[i] for i in range(len(stream))])
+    small = L[ks <= small_k]
+    return dict(E=E, span_s=span, req_per_s=len(stream) / span,
+                qp_per_s=sum(len(x.row_ids) for x in inputs) / span,
+                p50_s=float(np.percentile(L, 50)), p99_s=float(np.percentile(L, 99)),
+                small_p50_s=float(np.percentile(small, 50)) if small.size else None,
+                small_p99_s=float(np.percentile(small, 99)) if small.size else None,
+                peak_active=st["peak_active"], batches=st["batches"],
+                batched_requests=st["batched_requests"], graph_replays=st["graph_replays"],
+                device_mallocs=st["device_mallocs"], cache_hits=st["cache_hits"])
 
 
 def roofline_objects(h, cfg, workload, states):
