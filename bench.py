@@ -588,6 +588,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--serve-requests", type=int, default=32,
                     help="requests of the serving leg (the first ones of the stream)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving leg and print its object as the line")
     ap.add_argument("--kmax", type=int, default=24)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--crossover", default=None,
@@ -611,6 +613,12 @@ def main():
         print(json.dumps({"metric": "G0W0 wall time per call, spectral decomposition vs "
                                     "contour deformation (HOMO, LUMO)", "unit": "ms",
                           "n_gpus": 1, "data": "synthetic", "rows": crossover(gwl, ks)}))
+        return
+    if args.serve_only:
+        print(json.dumps({"metric": "serving: QP energies/s and p50/p99 request latency",
+                          "n_gpus": 1, "data": "synthetic",
+                          "serving": serve_leg(gwl, args.serve_requests, args.kmax,
+                                               args.streams)}))
         return
     if args.copy_calibration:
         x = torch.ones(2**27, dtype=torch.float64, device="cuda")     # 1 GiB
