@@ -388,6 +388,15 @@ hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, h
     return launch<2, 2, 2, KC, KM, EPI_RES_SCALE, false, false>(a, st);
   if (tile_kind == 3 && la == KC && lb == KM && epi == EPI_RES_DERIV && !scaled)
     return launch<2, 2, 2, KC, KM, EPI_RES_DERIV, false, false>(a, st);
+  // MINRES operator passes on 128 x 128 tiles (batches of 128 systems and more)
+  if (tile_kind == 0 && la == KC && lb == KM && epi == EPI_STORE && !scaled)
+    return launch<2, 4, 4, KC, KM, EPI_STORE, false, false>(a, st);
+  if (tile_kind == 0 && la == KC && lb == KM && epi == EPI_RES_SCALE && !scaled)
+    return launch<2, 4, 4, KC, KM, EPI_RES_SCALE, false, false>(a, st);
+  if (tile_kind == 0 && la == KC && lb == KM && epi == EPI_RES_DERIV && !scaled)
+    return launch<2, 4, 4, KC, KM, EPI_RES_DERIV, false, false>(a, st);
+  if (tile_kind == 0 && la == KC && lb == KC && epi == EPI_STORE && !scaled)
+    return launch<2, 4, 4, KC, KC, EPI_STORE, false, false>(a, st);
   // MINRES: part[s][sys][P] = sum_ia V[sys][ia] B_ov[P][ia], split-K partials, 64 x 128 tiles
   if (tile_kind == 2 && la == KC && lb == KC && epi == EPI_STORE && !scaled)
     return launch<1, 4, 2, KC, KC, EPI_STORE, false, false>(a, st);

@@ -1017,8 +1017,30 @@ int ensure_minres(gw_ctx* c, int kp) {
 }
 
 // mask (nullable): per 16-system block, 0 where every system's vector is zero
+// Tiles of the MINRES operator passes for a batch of kp systems: 128 x 128
+// (kind 0) for kp a multiple of 128 from 256 systems up, else the 64 x 64
+// first pass (kind 3) and 64 x 128 back-projection (kind 2).  Measured: at
+// (H2O)30 the stage takes 281 against 289 ms with the larger tiles; at
+// (H2O)10 (kp 128) 6.51 against 6.41 ms, so small batches keep the 64-row
+// tiles.  GW_TUNE_MINRES_TILE=0 / 1: never / whenever kp is a multiple of 128.
+bool mr_wide_tiles(int kp) {
+  static const int mode = [] {
+    const char* e = getenv("GW_TUNE_MINRES_TILE");
+    return e ? atoi(e) : -1;
+  }();
+  if (kp % 128 != 0) return false;
+  return mode < 0 ? kp >= 256 : mode == 1;
+}
+
+// Partials of the derivative pass: one per column tile of the first pass
+inline int deriv_parts(const gw_ctx* c, int kp) {
+  return mr_wide_tiles(kp) ? c->Kp / 128 : c->Kp / 64;
+}
+
 int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long ldc,
                 const int* mask = nullptr) {
+  const bool wide = mr_wide_tiles(kp);
+  const int T = wide ? 128 : 64, kind = wide ? 0 : 3;
   // out = scale(X B_ov): rows = systems, cols = ia.  The system tiles that
   // read one B_ov column panel are adjacent in the launch order (and so run
   // together on one XCD), so the panel comes from HBM once, not kp / 64 times
@@ -1027,7 +1049,7 @@ int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long l
   a.B = c->d_Bov; a.ldb = c->Kp; a.sB = 0;
   a.C = out; a.ldc = ldc; a.sC = 0;
   a.M = kp; a.N = c->Kp; a.K = c->Np;
-  a.map = MAP_FULL_J; a.tiles_m = kp / 64; a.tiles_n = c->Kp / 64;
+  a.map = MAP_FULL_J; a.tiles_m = kp / T; a.tiles_n = c->Kp / T;
   a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
   a.mrows = mask ? 0 : c->mr.k;   // a mask also marks the padding systems
   a.rowmask = mask; a.nMask = c->ext(mask, sizeof(int));
@@ -1035,12 +1057,12 @@ int matvec_pass(gw_ctx* c, const double* X, int kp, int epi, double* out, long l
   if (epi == EPI_RES_SCALE && c->mr_splitk1 > 1) {
     // split over N_aux for parallelism: partials, then a deterministic sum + scale
     a.C = c->mr.part; a.ldc = c->Kp; a.splitk = c->mr_splitk1; a.sSplit = (long)kp * c->Kp;
-    RCHK(run_gemm(c, a, 3, KC, KM, EPI_STORE));
+    RCHK(run_gemm(c, a, kind, KC, KM, EPI_STORE));
     HIPCHK(minres_scale_sum(c->mr, c->mr_splitk1, c->d_D, c->ext(c->d_D, 8), mask,
                             c->ext(mask, sizeof(int)), c->st));
     return 0;
   }
-  RCHK(run_gemm(c, a, 3, KC, KM, epi));
+  RCHK(run_gemm(c, a, kind, KC, KM, epi));
   return 0;
 }
 
@@ -1051,12 +1073,13 @@ int backproject_pass(gw_ctx* c, int kp, const int* mask = nullptr) {
   a.B = c->d_Bov; a.ldb = c->Kp; a.sB = 0;
   a.C = c->mr.part; a.ldc = c->Np; a.sC = 0;
   a.M = kp; a.N = c->Np; a.K = c->Kp;
-  a.map = MAP_FULL; a.tiles_m = kp / 64; a.tiles_n = c->Np / 128;
+  const bool wide = mr_wide_tiles(kp);
+  a.map = MAP_FULL; a.tiles_m = kp / (wide ? 128 : 64); a.tiles_n = c->Np / 128;
   a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1;
   a.splitk = c->mr_splitk; a.sSplit = (long)kp * c->Np;
   a.mrows = mask ? 0 : c->mr.k;
   a.rowmask = mask; a.nMask = c->ext(mask, sizeof(int));
-  RCHK(run_gemm(c, a, 2, KC, KC, EPI_STORE));
+  RCHK(run_gemm(c, a, wide ? 0 : 2, KC, KC, EPI_STORE));
   return 0;
 }
 
@@ -1263,7 +1286,7 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   HIPCHK(minres_finalize(m, c->d_xcache, c->d_rhs_idx, idx, c->Rp, n_cache, c->st));
   for (int j = 0; j < k; ++j) c->xvalid[idx[j]] = 1;
   // derivative partials: sum over ia of (B^T x)^2 * 2 D w/(D^2 - w^2)^2
-  const int nparts = c->Kp / 64;
+  const int nparts = deriv_parts(c, kp);
   RCHK(matvec_pass(c, m.x, kp, EPI_RES_DERIV, m.part, kp));
   HIPCHK(minres_results(m, c->d_R, c->d_rhs_idx, c->Rp, nparts, c->d_wc, c->d_dwc, c->d_conv,
                         c->ext(c->d_wc, 8), c->st));
