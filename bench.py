@@ -329,6 +329,15 @@ def serve_leg(gwl, n_requests, kmax, streams, small_k=6, n_burst=48):
                                 rate=1.0)
     stream = full[:n_requests]
     burst = [r for r in full if r["k"] <= small_k][:n_burst]
+    # every request's inputs are generated before the timed runs and held in
+    # host memory (generation is slower than the mixed path serves them);
+    # refuse a request list whose inputs would not fit in about 160 GB
+    held = sum(8 * r["shape"].n_aux * (r["shape"].n_ov + len(r["states"]) * r["shape"].n_mo)
+               for r in stream + burst)
+    if held > 160e9:
+        raise SystemExit(f"serving leg: the inputs of {len(stream)} requests take "
+                         f"{held / 1e9:.0f} GB of host memory; use fewer requests")
+    log(f"serve: inputs of the timed requests: {held / 1e9:.1f} GB of host memory")
     log(f"serve: generating {len(stream)} + {len(burst)} requests (seed 1000 + r each)")
     with ThreadPoolExecutor(max_workers=min(16, _cores() or 1)) as ex:
         inputs = list(ex.map(lambda r: gwgen.serving_inputs(r["k"], r["seed"]), stream))
@@ -461,7 +470,8 @@ def _serve_run(gwl, grid, streams, stream, inputs, small_k, prec, arrivals, wind
                 small_p99_s=float(np.percentile(small, 99)) if small.size else None,
                 peak_active=st["peak_active"], batches=st["batches"],
                 batched_requests=st["batched_requests"], graph_replays=st["graph_replays"],
-                device_mallocs=st["device_mallocs"], cache_hits=st["cache_hits"])
+                device_mallocs=st["device_mallocs"], cache_hits=st["cache_hits"],
+                device_frees=st["device_frees"])
 
 
 def roofline_objects(h, cfg, workload, states):

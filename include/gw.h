@@ -389,6 +389,9 @@ typedef struct gw_server_stats {
   long device_mallocs;      /* device and pinned blocks the server obtained from the
                                runtime (each later reuse of a block is a cache hit) */
   long cache_hits;
+  long device_frees;        /* cached device blocks given back to the runtime to make
+                               room (each such hipFree waits for the whole device) */
+  size_t cached_bytes;      /* device bytes held in the cache, not in use */
 } gw_server_stats;
 
 /* GW_EINVAL for bad options, GW_EDEVICE if no device or stream is usable. */

@@ -94,7 +94,8 @@ class ServerStats(ctypes.Structure):
                 ("active", ctypes.c_int), ("peak_active", ctypes.c_int),
                 ("batches", ctypes.c_long), ("batched_requests", ctypes.c_long),
                 ("graph_replays", ctypes.c_long), ("device_mallocs", ctypes.c_long),
-                ("cache_hits", ctypes.c_long)]
+                ("cache_hits", ctypes.c_long), ("device_frees", ctypes.c_long),
+                ("cached_bytes", ctypes.c_size_t)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

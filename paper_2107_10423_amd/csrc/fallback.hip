@@ -3,13 +3,17 @@
 // signed scale) and solved by Gaussian elimination with partial pivoting.
 // The paper switches to a Bunch-Kaufman factorization at this point; any
 // stable dense solve of the same symmetric indefinite system gives the same x.
-// One 1024-thread workgroup per system; rarely used.
+// One 1024-thread workgroup per system (blockIdx.x picks the system of a
+// batch), so the systems of a batch are solved side by side on the CUs.
 #include "gw_internal.h"
 
 namespace gw {
 
-__global__ __launch_bounds__(1024) void k_dense_solve(double* A, long ldA, int n, double* b,
-                                                      int* info) {
+__global__ __launch_bounds__(1024) void k_dense_solve(double* A, long ldA, long sA, int n,
+                                                      double* b, long sb, int* info) {
+  A += (long)blockIdx.x * sA;
+  b += (long)blockIdx.x * sb;
+  info += blockIdx.x;
   __shared__ double rv[1024];
   __shared__ int ri[1024];
   __shared__ double piv_inv;
@@ -89,13 +93,16 @@ __global__ __launch_bounds__(1024) void k_dense_solve(double* A, long ldA, int n
   }
 }
 
-hipError_t dense_solve(double* A, long ldA, int n, double* b, int* info, long nA, long nb,
-                       hipStream_t st) {
-  if (n <= 0) return hipSuccess;
-  GW_GUARD("dense_solve", "A", (long)(n - 1) * ldA + n - 1, nA);
-  GW_GUARD("dense_solve", "b", n - 1, nb);
+hipError_t dense_solve(double* A, long ldA, long sA, int n, double* b, long sb, int* info,
+                       int batch, long nA, long nb, long ninfo, hipStream_t st) {
+  if (n <= 0 || batch <= 0) return hipSuccess;
+  if (ldA < n || sA < (long)(n - 1) * ldA + n || sb < n)
+    return refuse("dense_solve", "shape");
+  GW_GUARD("dense_solve", "A", (long)(batch - 1) * sA + (long)(n - 1) * ldA + n - 1, nA);
+  GW_GUARD("dense_solve", "b", (long)(batch - 1) * sb + n - 1, nb);
+  GW_GUARD("dense_solve", "info", batch - 1, ninfo);
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_dense_solve, dim3(1), dim3(1024), 0, st, A, ldA, n, b, info);
+  hipLaunchKernelGGL(k_dense_solve, dim3(batch), dim3(1024), 0, st, A, ldA, sA, n, b, sb, info);
   return hipGetLastError();
 }
 

@@ -168,6 +168,10 @@ void minres_splits(int kp, int Np, int Kp, int* splitk, int* splitk1) {
 // 128, so each slab's K range is a multiple of 16)
 constexpr int PRE_SPLIT = 8;
 
+// Residue systems the dense fallback builds and solves at once (one
+// workgroup each): the fallback's workspace is FB_MAX dielectric matrices
+constexpr int FB_MAX = 32;
+
 // Elements of the MINRES partial-product buffer for a capacity of kp systems.
 // The splits follow the capacity, and a smaller capacity can need more (the
 // first pass is split over N_aux only while it has few tiles), so the buffer
@@ -232,9 +236,22 @@ struct gw_devcache {
   size_t live = 0, cached = 0;
   long n_malloc = 0, n_free = 0, n_hits = 0;
 
+  // Size classes: multiples of 256 B below 1 MiB; above, eight classes per
+  // octave (m 2^(e-3), m = 8..15: at most 12.5% over the request), so that
+  // requests of neighbouring shapes share classes and the blocks of every
+  // shape a server sees fit in the cache together.  GW_CACHE_CLASSES=fine
+  // keeps 64 KiB steps above 1 MiB instead.
   static size_t round(size_t b) {
-    const size_t q = b >= (1u << 20) ? (64u << 10) : 256;
-    return (std::max<size_t>(b, 8) + q - 1) / q * q;
+    b = std::max<size_t>(b, 8);
+    if (b < (1u << 20)) return (b + 255) / 256 * 256;
+    static const bool fine = [] {
+      const char* e = getenv("GW_CACHE_CLASSES");
+      return e && strcmp(e, "fine") == 0;
+    }();
+    if (fine) return (b + (64u << 10) - 1) / (64u << 10) * (64u << 10);
+    int e = 63 - __builtin_clzll((unsigned long long)b);   // 2^e <= b < 2^(e+1)
+    const size_t step = (size_t)1 << (e - 3);
+    return (b + step - 1) / step * step;
   }
   // a block of exactly this size class: a recurring sequence of allocations
   // (the same request shapes again) then finds every block it needs, which a
@@ -1304,40 +1321,52 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
     if (iters[j] < 0) bad.push_back(j);
   if (!bad.empty() && use_fallback) {
     tm.start(c->st);
-    const long ld = c->Np;
-    if (!c->d_dense) {
-      RCHK(c->alloc((void**)&c->d_dense, (size_t)c->Np * c->Np * sizeof(double)));
-      RCHK(c->alloc((void**)&c->d_dscale, (size_t)c->Kp * sizeof(double)));
-      RCHK(c->alloc((void**)&c->d_db, (size_t)c->Np * sizeof(double)));
-      RCHK(c->alloc((void**)&c->d_dinfo, sizeof(int)));
+    const long ld = c->Np, sq = (long)c->Np * c->Np;
+    if (!c->d_dense) {   // room for FB_MAX systems at once (counted in the footprint)
+      RCHK(c->alloc((void**)&c->d_dense, (size_t)FB_MAX * sq * sizeof(double)));
+      RCHK(c->alloc((void**)&c->d_dscale, (size_t)FB_MAX * c->Kp * sizeof(double)));
+      RCHK(c->alloc((void**)&c->d_db, (size_t)FB_MAX * c->Np * sizeof(double)));
+      RCHK(c->alloc((void**)&c->d_dinfo, FB_MAX * sizeof(int)));
     }
-    for (int j : bad) {
-      HIPCHK(make_scale_real(c->d_D, c->Kov, c->Kp, sys[j].w, c->d_dscale, c->ext(c->d_D, 8),
-                             c->ext(c->d_dscale, 8), c->st));
-      GemmArgs a{};
+    for (size_t j0 = 0; j0 < bad.size(); j0 += FB_MAX) {
+      const int nb = (int)std::min<size_t>(FB_MAX, bad.size() - j0);
+      for (int i = 0; i < nb; ++i) {
+        const System& y = sys[bad[j0 + i]];
+        double* sc = c->d_dscale + (long)i * c->Kp;
+        HIPCHK(make_scale_real(c->d_D, c->Kov, c->Kp, y.w, sc, c->ext(c->d_D, 8),
+                               c->ext(sc, 8), c->st));
+        HIPCHK(copy_vec(c->d_R + (long)y.q * c->Np, c->d_db + (long)i * c->Np, c->Np,
+                        c->ext(c->d_R + (long)y.q * c->Np, 8),
+                        c->ext(c->d_db + (long)i * c->Np, 8), c->st));
+      }
+      GemmArgs a{};   // 1 - Pi(w) of every system of the batch, full matrices
       a.A = c->d_Bov; a.lda = c->Kp;
       a.B = c->d_Bov; a.ldb = c->Kp;
-      a.scale = c->d_dscale; a.sS = 0;
-      a.C = c->d_dense; a.ldc = ld;
+      a.scale = c->d_dscale; a.sS = c->Kp;
+      a.C = c->d_dense; a.ldc = ld; a.sC = sq;
       a.M = c->Np; a.N = c->Np; a.K = c->Kp;
       a.map = MAP_FULL; a.tiles_m = c->Np / 128; a.tiles_n = c->Np / 128;
-      a.n_tiles = a.tiles_m * a.tiles_n; a.batch = 1; a.splitk = 1;
+      a.n_tiles = a.tiles_m * a.tiles_n; a.batch = nb; a.splitk = 1;
       RCHK(run_gemm(c, a, 0, KC, KC, EPI_ONE_PLUS_4));
-      HIPCHK(copy_vec(c->d_R + (long)sys[j].q * c->Np, c->d_db, c->Np,
-                      c->ext(c->d_R + (long)sys[j].q * c->Np, 8), c->ext(c->d_db, 8), c->st));
-      HIPCHK(rt_memset(c->d_dinfo, 0, sizeof(int), c->st));
-      HIPCHK(dense_solve(c->d_dense, ld, c->Np, c->d_db, c->d_dinfo, c->ext(c->d_dense, 8),
-                         c->ext(c->d_db, 8), c->st));
-      HIPCHK(copy_vec(c->d_db, m.x + (long)j * c->Np, c->Np, c->ext(c->d_db, 8),
-                      c->ext(m.x + (long)j * c->Np, 8), c->st));
-      HIPCHK(copy_vec(c->d_db, c->d_xcache + (long)sys[j].q * c->Np, c->Np, c->ext(c->d_db, 8),
-                      c->ext(c->d_xcache + (long)sys[j].q * c->Np, 8), c->st));
-      int dinfo = 0;
-      HIPCHK(rt_memcpy(&dinfo, c->d_dinfo, sizeof(int), hipMemcpyDeviceToHost, c->st));
+      HIPCHK(rt_memset(c->d_dinfo, 0, nb * sizeof(int), c->st));
+      HIPCHK(dense_solve(c->d_dense, ld, sq, c->Np, c->d_db, c->Np, c->d_dinfo, nb,
+                         c->ext(c->d_dense, 8), c->ext(c->d_db, 8), c->ext(c->d_dinfo, 4),
+                         c->st));
+      for (int i = 0; i < nb; ++i) {
+        const int j = bad[j0 + i];
+        const double* xb = c->d_db + (long)i * c->Np;
+        HIPCHK(copy_vec(xb, m.x + (long)j * c->Np, c->Np, c->ext(xb, 8),
+                        c->ext(m.x + (long)j * c->Np, 8), c->st));
+        HIPCHK(copy_vec(xb, c->d_xcache + (long)sys[j].q * c->Np, c->Np, c->ext(xb, 8),
+                        c->ext(c->d_xcache + (long)sys[j].q * c->Np, 8), c->st));
+      }
+      int dinfo[FB_MAX] = {0};
+      HIPCHK(rt_memcpy(dinfo, c->d_dinfo, nb * sizeof(int), hipMemcpyDeviceToHost, c->st));
       HIPCHK(rt_sync(c->st));
-      if (dinfo != 0)
-        return fail(GW_EDEVICE, "dense fallback: singular dielectric matrix at w = %.17g",
-                    sys[j].w);
+      for (int i = 0; i < nb; ++i)
+        if (dinfo[i] != 0)
+          return fail(GW_EDEVICE, "dense fallback: singular dielectric matrix at w = %.17g",
+                      sys[bad[j0 + i]].w);
     }
     RCHK(matvec_pass(c, m.x, kp, EPI_RES_DERIV, m.part, kp));
     HIPCHK(minres_results(m, c->d_R, c->d_rhs_idx, c->Rp, nparts, c->d_wc, c->d_dwc, c->d_conv,
@@ -1855,8 +1884,8 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
        2 * (size_t)(kp / 16) * sizeof(int);
   b += (size_t)Rp * Np * d;  // remembered residue solutions
   b += (size_t)Np * Np * d;  // preconditioner
-  // dense fallback
-  b += (size_t)Np * Np * d + (size_t)Kp * d + (size_t)Np * d + sizeof(int);
+  // dense fallback (FB_MAX systems at once)
+  b += FB_MAX * ((size_t)Np * Np * d + (size_t)Kp * d + (size_t)Np * d + sizeof(int));
   return b;
 }
 
@@ -2865,10 +2894,12 @@ gw_devcache* devcache_create(size_t cap) {
   return c;
 }
 void devcache_destroy(gw_devcache* c) { delete c; }
-void devcache_stats(gw_devcache* c, long* mallocs, long* hits, size_t* live, size_t* cached) {
+void devcache_stats(gw_devcache* c, long* mallocs, long* hits, long* frees, size_t* live,
+                    size_t* cached) {
   std::lock_guard<std::mutex> lk(c->mu);
   *mallocs = c->n_malloc;
   *hits = c->n_hits;
+  *frees = c->n_free;
   *live = c->live;
   *cached = c->cached;
 }

@@ -261,8 +261,9 @@ hipError_t minres_results(MinresBufs& m, const double* rhs_base, const int* rhs_
                           int n_rhs_rows, int n_deriv_parts, double* wc, double* dwc, int* conv,
                           long n_out, hipStream_t st);
 
-// dense fallback: solve A x = b for one system with partial pivoting (A overwritten)
-hipError_t dense_solve(double* A, long ldA, int n, double* b, int* info, long nA, long nb,
-                       hipStream_t st);
+// dense fallback: solve A_i x_i = b_i for `batch` systems (A_i = A + i sA, b_i =
+// b + i sb, info[i]) with partial pivoting, side by side (A and b overwritten)
+hipError_t dense_solve(double* A, long ldA, long sA, int n, double* b, long sb, int* info,
+                       int batch, long nA, long nb, long ninfo, hipStream_t st);
 
 }  // namespace gw

@@ -46,7 +46,8 @@ int ctx_set_stream(gw_ctx* c, hipStream_t st);
 void padded_shape(int n_mo, int n_occ, int n_aux, int n_rows, int* Np, int* Kp, int* Rp);
 gw_devcache* devcache_create(size_t cap);
 void devcache_destroy(gw_devcache* c);
-void devcache_stats(gw_devcache* c, long* mallocs, long* hits, size_t* live, size_t* cached);
+void devcache_stats(gw_devcache* c, long* mallocs, long* hits, long* frees, size_t* live,
+                    size_t* cached);
 int validate_inputs(int n_mo, int n_occ, int n_aux, const double* eps, const double* B_ov,
                     int n_rows, const int* row_ids, const double* B_rows, bool check_arrays);
 long copy_check_finite(double* dst, const double* src, long n);
@@ -549,8 +550,9 @@ int gw_server_get_stats(gw_server* s, gw_server_stats* out) {
     }
   }
   out->graph_replays = replays;
-  size_t live = 0, cached = 0;
-  devcache_stats(s->cache, &out->device_mallocs, &out->cache_hits, &live, &cached);
+  size_t live = 0;
+  devcache_stats(s->cache, &out->device_mallocs, &out->cache_hits, &out->device_frees, &live,
+                 &out->cached_bytes);
   return 0;
 }
 
