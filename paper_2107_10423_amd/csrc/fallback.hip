@@ -3,106 +3,183 @@
 // signed scale) and solved by Gaussian elimination with partial pivoting.
 // The paper switches to a Bunch-Kaufman factorization at this point; any
 // stable dense solve of the same symmetric indefinite system gives the same x.
-// One 1024-thread workgroup per system (blockIdx.x picks the system of a
-// batch), so the systems of a batch are solved side by side on the CUs.
+//
+// Blocked right-looking LU (P A = L U) over a batch of systems, all padded to
+// N_aux (a multiple of 128; the padding block of 1 - Pi is the identity, so
+// the padded solution carries the true one unchanged).  Per 128-column panel:
+//   k_lu_panel      the panel's column steps (pivot search over the rows
+//                   below, swap inside the panel, multipliers, rank-1 update
+//                   of the panel), one 1024-thread workgroup per system;
+//   k_lu_swap_trsm  the panel's row swaps on every other column, and
+//                   U12 = L11^-1 A12 right of the panel, one thread per column;
+//   gemm_f64        A22 -= L21 U12 (MFMA, every system of the batch at once);
+// then k_lu_solve applies the swaps to b and runs the two triangular solves,
+// one workgroup per system with b in LDS.
 #include "gw_internal.h"
 
 namespace gw {
 
-__global__ __launch_bounds__(1024) void k_dense_solve(double* A, long ldA, long sA, int n,
-                                                      double* b, long sb, int* info) {
-  A += (long)blockIdx.x * sA;
-  b += (long)blockIdx.x * sb;
-  info += blockIdx.x;
+constexpr int LU_NB = 128;   // panel width (the trailing GEMM's tile)
+
+__global__ __launch_bounds__(1024) void k_lu_panel(double* A, long ld, long sA, int n, int c0,
+                                                   int* piv, long sP, int* info) {
   __shared__ double rv[1024];
   __shared__ int ri[1024];
-  __shared__ double piv_inv;
-  __shared__ int piv_row;
+  __shared__ int prow;
+  A += (long)blockIdx.x * sA;
+  piv += (long)blockIdx.x * sP;
+  info += blockIdx.x;
   const int t = threadIdx.x;
-  for (int c = 0; c < n; ++c) {
-    // pivot search in column c
+  const int c1 = c0 + LU_NB;
+  for (int j = c0; j < c1; ++j) {
+    // pivot: the largest |A[r][j]| over rows r >= j (the lowest row on ties)
     double best = -1.0;
-    int bi = c;
-    for (int i = c + t; i < n; i += 1024) {
-      double v = fabs(A[(long)i * ldA + c]);
-      if (v > best) { best = v; bi = i; }
+    int bi = j;
+    for (int r = j + t; r < n; r += 1024) {
+      const double v = fabs(A[(long)r * ld + j]);
+      if (v > best) { best = v; bi = r; }
     }
     rv[t] = best;
     ri[t] = bi;
     __syncthreads();
     for (int off = 512; off > 0; off >>= 1) {
-      if (t < off) {
-        if (rv[t + off] > rv[t] || (rv[t + off] == rv[t] && ri[t + off] < ri[t])) {
-          rv[t] = rv[t + off];
-          ri[t] = ri[t + off];
-        }
+      if (t < off && (rv[t + off] > rv[t] || (rv[t + off] == rv[t] && ri[t + off] < ri[t]))) {
+        rv[t] = rv[t + off];
+        ri[t] = ri[t + off];
       }
       __syncthreads();
     }
     if (t == 0) {
-      piv_row = ri[0];
-      if (!(rv[0] > 0.0) && *info == 0) *info = c + 1;
+      prow = ri[0];
+      piv[j] = ri[0];
+      if (!(rv[0] > 0.0) && *info == 0) *info = j + 1;
     }
     __syncthreads();
-    const int p = piv_row;
-    if (p != c) {
-      for (int j = t; j < n; j += 1024) {
-        double a = A[(long)c * ldA + j];
-        A[(long)c * ldA + j] = A[(long)p * ldA + j];
-        A[(long)p * ldA + j] = a;
+    const int p = prow;
+    if (p != j && t < LU_NB) {
+      const long a = (long)j * ld + c0 + t, b = (long)p * ld + c0 + t;
+      const double x = A[a];
+      A[a] = A[b];
+      A[b] = x;
+    }
+    __syncthreads();
+    const double d = A[(long)j * ld + j];
+    const double dinv = (d != 0.0) ? 1.0 / d : 0.0;
+    for (int r = j + 1 + t; r < n; r += 1024) A[(long)r * ld + j] *= dinv;
+    __syncthreads();
+    // rank-1 update of the panel's columns right of j, rows below j
+    const int w = c1 - 1 - j;
+    if (w > 0) {
+      const long cnt = (long)(n - j - 1) * w;
+      for (long idx = t; idx < cnt; idx += 1024) {
+        const int r = j + 1 + (int)(idx / w), col = j + 1 + (int)(idx % w);
+        A[(long)r * ld + col] -= A[(long)r * ld + j] * A[(long)j * ld + col];
       }
-      if (t == 0) {
-        double a = b[c];
-        b[c] = b[p];
-        b[p] = a;
-      }
-    }
-    __syncthreads();
-    if (t == 0) {
-      double d = A[(long)c * ldA + c];
-      piv_inv = (d != 0.0) ? 1.0 / d : 0.0;
-    }
-    __syncthreads();
-    // eliminate below: multipliers first, then the trailing update
-    for (int i = c + 1 + t; i < n; i += 1024) A[(long)i * ldA + c] *= piv_inv;
-    __syncthreads();
-    const int w = n - c - 1;
-    const long cnt = (long)w * w;
-    for (long idx = t; idx < cnt; idx += 1024) {
-      int i = c + 1 + (int)(idx / w), j = c + 1 + (int)(idx % w);
-      A[(long)i * ldA + j] -= A[(long)i * ldA + c] * A[(long)c * ldA + j];
-    }
-    for (int i = c + 1 + t; i < n; i += 1024) b[i] -= A[(long)i * ldA + c] * b[c];
-    __syncthreads();
-  }
-  // back substitution, one row at a time
-  for (int i = n - 1; i >= 0; --i) {
-    double s = 0.0;
-    for (int j = i + 1 + t; j < n; j += 1024) s += A[(long)i * ldA + j] * b[j];
-    rv[t] = s;
-    __syncthreads();
-    for (int off = 512; off > 0; off >>= 1) {
-      if (t < off) rv[t] += rv[t + off];
-      __syncthreads();
-    }
-    if (t == 0) {
-      double d = A[(long)i * ldA + i];
-      b[i] = (d != 0.0) ? (b[i] - rv[0]) / d : 0.0;
     }
     __syncthreads();
   }
 }
 
-hipError_t dense_solve(double* A, long ldA, long sA, int n, double* b, long sb, int* info,
-                       int batch, long nA, long nb, long ninfo, hipStream_t st) {
+// One thread per column outside the panel: the panel's swaps in order, then
+// (right of the panel) the unit-lower triangular solve with L11.
+__global__ __launch_bounds__(256) void k_lu_swap_trsm(double* A, long ld, long sA, int n, int c0,
+                                                      const int* piv, long sP) {
+  A += (long)blockIdx.y * sA;
+  piv += (long)blockIdx.y * sP;
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  const int c1 = c0 + LU_NB;
+  if (col >= n || (col >= c0 && col < c1)) return;
+  for (int j = c0; j < c1; ++j) {
+    const int p = piv[j];
+    if (p != j) {
+      const double x = A[(long)j * ld + col];
+      A[(long)j * ld + col] = A[(long)p * ld + col];
+      A[(long)p * ld + col] = x;
+    }
+  }
+  if (col < c1) return;
+  for (int j = c0; j < c1; ++j) {
+    const double x = A[(long)j * ld + col];
+    for (int r = j + 1; r < c1; ++r) A[(long)r * ld + col] -= A[(long)r * ld + j] * x;
+  }
+}
+
+// b <- P b, then L y = b (unit lower), then U x = y; b (in LDS) ends as x.
+__global__ __launch_bounds__(1024) void k_lu_solve(const double* A, long ld, long sA, int n,
+                                                   const int* piv, long sP, double* b, long sb) {
+  extern __shared__ double xs[];
+  A += (long)blockIdx.x * sA;
+  piv += (long)blockIdx.x * sP;
+  b += (long)blockIdx.x * sb;
+  const int t = threadIdx.x;
+  for (int i = t; i < n; i += 1024) xs[i] = b[i];
+  __syncthreads();
+  if (t == 0)
+    for (int j = 0; j < n; ++j) {
+      const int p = piv[j];
+      if (p != j) {
+        const double x = xs[j];
+        xs[j] = xs[p];
+        xs[p] = x;
+      }
+    }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    const double y = xs[j];
+    for (int r = j + 1 + t; r < n; r += 1024) xs[r] -= A[(long)r * ld + j] * y;
+    __syncthreads();
+  }
+  for (int j = n - 1; j >= 0; --j) {
+    const double d = A[(long)j * ld + j];
+    const double x = (d != 0.0) ? xs[j] / d : 0.0;
+    __syncthreads();   // every thread has read xs[j]
+    if (t == 0) xs[j] = x;
+    for (int r = t; r < j; r += 1024) xs[r] -= A[(long)r * ld + j] * x;
+    __syncthreads();
+  }
+  for (int i = t; i < n; i += 1024) b[i] = xs[i];
+}
+
+hipError_t dense_solve(double* A, long ldA, long sA, int n, double* b, long sb, int* piv,
+                       long sP, int* info, int batch, long nA, long nb, long npiv, long ninfo,
+                       hipStream_t st) {
+  const char* kn = "dense_solve";
   if (n <= 0 || batch <= 0) return hipSuccess;
-  if (ldA < n || sA < (long)(n - 1) * ldA + n || sb < n)
-    return refuse("dense_solve", "shape");
-  GW_GUARD("dense_solve", "A", (long)(batch - 1) * sA + (long)(n - 1) * ldA + n - 1, nA);
-  GW_GUARD("dense_solve", "b", (long)(batch - 1) * sb + n - 1, nb);
-  GW_GUARD("dense_solve", "info", batch - 1, ninfo);
+  if (n % LU_NB != 0 || ldA < n || sA < (long)(n - 1) * ldA + n || sb < n || sP < n ||
+      (size_t)n * sizeof(double) > 64 * 1024)
+    return refuse(kn, "shape");
+  GW_GUARD(kn, "A", (long)(batch - 1) * sA + (long)(n - 1) * ldA + n - 1, nA);
+  GW_GUARD(kn, "b", (long)(batch - 1) * sb + n - 1, nb);
+  GW_GUARD(kn, "piv", (long)(batch - 1) * sP + n - 1, npiv);
+  GW_GUARD(kn, "info", batch - 1, ninfo);
+  for (int c0 = 0; c0 < n; c0 += LU_NB) {
+    if (audit_mode()) {
+      audit_note();
+      audit_note();
+    } else {
+      hipLaunchKernelGGL(k_lu_panel, dim3(batch), dim3(1024), 0, st, A, ldA, sA, n, c0, piv, sP,
+                         info);
+      hipLaunchKernelGGL(k_lu_swap_trsm, dim3((n + 255) / 256, batch), dim3(256), 0, st, A, ldA,
+                         sA, n, c0, piv, sP);
+      if (hipError_t e = hipGetLastError()) return e;
+    }
+    if (c0 + LU_NB < n) {   // A22 -= L21 U12 on 128 x 128 tiles, every system at once
+      GemmArgs a{};
+      a.A = A; a.lda = ldA; a.sA = sA;
+      a.B = A; a.ldb = ldA; a.sB = sA;
+      a.C = A; a.ldc = ldA; a.sC = sA;
+      a.M = n - c0 - LU_NB; a.N = a.M; a.K = LU_NB;
+      a.row0 = c0 + LU_NB; a.col0 = c0 + LU_NB; a.k0 = c0; a.kb0 = c0;
+      a.map = MAP_FULL; a.tiles_m = a.M / 128; a.tiles_n = a.N / 128;
+      a.n_tiles = a.tiles_m * a.tiles_n; a.batch = batch; a.splitk = 1;
+      a.alpha = -1.0; a.beta = 1.0;
+      a.nA = a.nB = a.nC = nA;
+      if (hipError_t e = gemm_f64(a, 0, KC, KM, EPI_AXPBY, st)) return e;
+    }
+  }
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_dense_solve, dim3(batch), dim3(1024), 0, st, A, ldA, sA, n, b, sb, info);
+  hipLaunchKernelGGL(k_lu_solve, dim3(batch), dim3(1024), (size_t)n * sizeof(double), st, A,
+                     ldA, sA, n, piv, sP, b, sb);
   return hipGetLastError();
 }
 

@@ -388,6 +388,9 @@ hipError_t gemm_f64(const GemmArgs& a, int tile_kind, int la, int lb, int epi, h
     return launch<2, 2, 2, KC, KM, EPI_RES_SCALE, false, false>(a, st);
   if (tile_kind == 3 && la == KC && lb == KM && epi == EPI_RES_DERIV && !scaled)
     return launch<2, 2, 2, KC, KM, EPI_RES_DERIV, false, false>(a, st);
+  // dense fallback LU: A22 -= L21 U12 (U12 rows k-major), 128 x 128 tiles, batched
+  if (tile_kind == 0 && la == KC && lb == KM && epi == EPI_AXPBY && !scaled)
+    return launch<2, 4, 4, KC, KM, EPI_AXPBY, false, false>(a, st);
   // MINRES operator passes on 128 x 128 tiles (batches of 128 systems and more)
   if (tile_kind == 0 && la == KC && lb == KM && epi == EPI_STORE && !scaled)
     return launch<2, 4, 4, KC, KM, EPI_STORE, false, false>(a, st);

@@ -506,6 +506,7 @@ struct gw_ctx {
   double* d_dscale = nullptr;
   double* d_db = nullptr;
   int* d_dinfo = nullptr;
+  int* d_dpiv = nullptr;
   gw_timing timing{};
 
   std::vector<void*> allocs;
@@ -1327,6 +1328,7 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
       RCHK(c->alloc((void**)&c->d_dscale, (size_t)FB_MAX * c->Kp * sizeof(double)));
       RCHK(c->alloc((void**)&c->d_db, (size_t)FB_MAX * c->Np * sizeof(double)));
       RCHK(c->alloc((void**)&c->d_dinfo, FB_MAX * sizeof(int)));
+      RCHK(c->alloc((void**)&c->d_dpiv, (size_t)FB_MAX * c->Np * sizeof(int)));
     }
     for (size_t j0 = 0; j0 < bad.size(); j0 += FB_MAX) {
       const int nb = (int)std::min<size_t>(FB_MAX, bad.size() - j0);
@@ -1349,9 +1351,9 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
       a.n_tiles = a.tiles_m * a.tiles_n; a.batch = nb; a.splitk = 1;
       RCHK(run_gemm(c, a, 0, KC, KC, EPI_ONE_PLUS_4));
       HIPCHK(rt_memset(c->d_dinfo, 0, nb * sizeof(int), c->st));
-      HIPCHK(dense_solve(c->d_dense, ld, sq, c->Np, c->d_db, c->Np, c->d_dinfo, nb,
-                         c->ext(c->d_dense, 8), c->ext(c->d_db, 8), c->ext(c->d_dinfo, 4),
-                         c->st));
+      HIPCHK(dense_solve(c->d_dense, ld, sq, c->Np, c->d_db, c->Np, c->d_dpiv, c->Np,
+                         c->d_dinfo, nb, c->ext(c->d_dense, 8), c->ext(c->d_db, 8),
+                         c->ext(c->d_dpiv, 4), c->ext(c->d_dinfo, 4), c->st));
       for (int i = 0; i < nb; ++i) {
         const int j = bad[j0 + i];
         const double* xb = c->d_db + (long)i * c->Np;
@@ -1885,7 +1887,8 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   b += (size_t)Rp * Np * d;  // remembered residue solutions
   b += (size_t)Np * Np * d;  // preconditioner
   // dense fallback (FB_MAX systems at once)
-  b += FB_MAX * ((size_t)Np * Np * d + (size_t)Kp * d + (size_t)Np * d + sizeof(int));
+  b += FB_MAX * ((size_t)Np * Np * d + (size_t)Kp * d + (size_t)Np * d + (size_t)Np * sizeof(int) +
+                 sizeof(int));
   return b;
 }
 
