@@ -118,6 +118,33 @@ def test_residues_match_direct_solve(fallback_only):
         assert abs(dwc[j] - dw_ref) <= 1e-9 * kappa * max(abs(dw_ref), scale)
 
 
+def test_fallback_batches_match_direct_solve():
+    """More unconverged systems than one fallback batch (32), on an N_aux of
+    five 128-column LU panels (ragged: 600 of 640): every x equals the dense
+    solve of its own 1 - Pi(w), and W^c its residue value."""
+    inp = ragged(seed=9, n_occ=6, n_virt=40, n_aux=600)
+    rng = np.random.default_rng(3)
+    k = 40
+    rows = list(inp.row_ids)
+    st = [rows[j % len(rows)] for j in range(k)]
+    ms = [int(m) for m in rng.integers(0, inp.shape.n_mo, k)]
+    D = cd.transition_energies(inp.eps, inp.n_occ)
+    ws = list(rng.uniform(-1.5, 1.5, k) * D.min())
+    with ctx(inp, minres_max_iter=1) as c:
+        x, wc, dwc, it = c.residues(st, ms, ws)
+        t = c.timing()
+    assert np.all(it < 0) and t["fallback_systems"] == k
+    n = inp.shape.n_aux
+    for j in range(k):
+        b = inp.B_rows[rows.index(st[j]), ms[j]]
+        A = np.eye(n) - cd.pi_real(inp.eps, inp.n_occ, inp.B_ov, ws[j])
+        xr = np.linalg.solve(A, b)
+        kappa = np.linalg.cond(A)
+        assert np.linalg.norm(x[j] - xr) <= 1e-11 * kappa * np.linalg.norm(xr) + 1e-15, j
+        w_ref, _ = cd.residue_value(inp.eps, inp.n_occ, inp.B_ov, b, ws[j])
+        assert abs(wc[j] - w_ref) <= 1e-10 * kappa * np.dot(b, b), j
+
+
 def test_many_residue_systems_in_one_batch():
     # more than one 64-system tile of systems
     inp = ragged()
