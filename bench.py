@@ -600,6 +600,8 @@ def main():
                     help="requests of the serving leg (the first ones of the stream)")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving leg and print its object as the line")
+    ap.add_argument("--core-only", action="store_true",
+                    help="run only the (H2O)20 core-spectrum leg and print its object as the line")
     ap.add_argument("--kmax", type=int, default=24)
     ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--crossover", default=None,
@@ -623,6 +625,11 @@ def main():
         print(json.dumps({"metric": "G0W0 wall time per call, spectral decomposition vs "
                                     "contour deformation (HOMO, LUMO)", "unit": "ms",
                           "n_gpus": 1, "data": "synthetic", "rows": crossover(gwl, ks)}))
+        return
+    if args.core_only:
+        print(json.dumps({"metric": "core spectrum: QP energies/s with the W^c table cached",
+                          "n_gpus": 1, "data": "synthetic",
+                          "core_spectrum": time_core_spectrum(gwl, "bf16x3w")}))
         return
     if args.serve_only:
         print(json.dumps({"metric": "serving: QP energies/s and p50/p99 request latency",
