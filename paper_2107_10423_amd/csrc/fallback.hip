@@ -14,7 +14,7 @@
 //                   U12 = L11^-1 A12 right of the panel, one thread per column;
 //   gemm_f64        A22 -= L21 U12 (MFMA, every system of the batch at once);
 // then k_lu_solve applies the swaps to b and runs the two triangular solves,
-// one workgroup per system with b in LDS.
+// one workgroup per system with b in LDS (up to N_aux 6144; in place beyond).
 #include "gw_internal.h"
 
 namespace gw {
@@ -104,15 +104,19 @@ __global__ __launch_bounds__(256) void k_lu_swap_trsm(double* A, long ld, long s
   }
 }
 
-// b <- P b, then L y = b (unit lower), then U x = y; b (in LDS) ends as x.
+// b <- P b, then L y = b (unit lower), then U x = y; b ends as x.  The vector
+// is worked on in LDS when it fits (in_lds), else in place in b.
 __global__ __launch_bounds__(1024) void k_lu_solve(const double* A, long ld, long sA, int n,
-                                                   const int* piv, long sP, double* b, long sb) {
-  extern __shared__ double xs[];
+                                                   const int* piv, long sP, double* b, long sb,
+                                                   int in_lds) {
+  extern __shared__ double lds_x[];
   A += (long)blockIdx.x * sA;
   piv += (long)blockIdx.x * sP;
   b += (long)blockIdx.x * sb;
   const int t = threadIdx.x;
-  for (int i = t; i < n; i += 1024) xs[i] = b[i];
+  double* xs = in_lds ? lds_x : b;
+  if (in_lds)
+    for (int i = t; i < n; i += 1024) xs[i] = b[i];
   __syncthreads();
   if (t == 0)
     for (int j = 0; j < n; ++j) {
@@ -137,7 +141,8 @@ __global__ __launch_bounds__(1024) void k_lu_solve(const double* A, long ld, lon
     for (int r = t; r < j; r += 1024) xs[r] -= A[(long)r * ld + j] * x;
     __syncthreads();
   }
-  for (int i = t; i < n; i += 1024) b[i] = xs[i];
+  if (in_lds)
+    for (int i = t; i < n; i += 1024) b[i] = xs[i];
 }
 
 hipError_t dense_solve(double* A, long ldA, long sA, int n, double* b, long sb, int* piv,
@@ -145,8 +150,7 @@ hipError_t dense_solve(double* A, long ldA, long sA, int n, double* b, long sb, 
                        hipStream_t st) {
   const char* kn = "dense_solve";
   if (n <= 0 || batch <= 0) return hipSuccess;
-  if (n % LU_NB != 0 || ldA < n || sA < (long)(n - 1) * ldA + n || sb < n || sP < n ||
-      (size_t)n * sizeof(double) > 64 * 1024)
+  if (n % LU_NB != 0 || ldA < n || sA < (long)(n - 1) * ldA + n || sb < n || sP < n)
     return refuse(kn, "shape");
   GW_GUARD(kn, "A", (long)(batch - 1) * sA + (long)(n - 1) * ldA + n - 1, nA);
   GW_GUARD(kn, "b", (long)(batch - 1) * sb + n - 1, nb);
@@ -178,8 +182,9 @@ hipError_t dense_solve(double* A, long ldA, long sA, int n, double* b, long sb, 
     }
   }
   GW_AUDIT_RETURN();
-  hipLaunchKernelGGL(k_lu_solve, dim3(batch), dim3(1024), (size_t)n * sizeof(double), st, A,
-                     ldA, sA, n, piv, sP, b, sb);
+  const int in_lds = (size_t)n * sizeof(double) <= 48 * 1024;
+  hipLaunchKernelGGL(k_lu_solve, dim3(batch), dim3(1024), in_lds ? (size_t)n * sizeof(double) : 0,
+                     st, A, ldA, sA, n, piv, sP, b, sb, in_lds);
   return hipGetLastError();
 }
 

@@ -263,7 +263,7 @@ hipError_t minres_results(MinresBufs& m, const double* rhs_base, const int* rhs_
 
 // dense fallback: solve A_i x_i = b_i for `batch` systems (A_i = A + i sA, b_i =
 // b + i sb, pivots piv + i sP, info[i]) by blocked LU with partial pivoting
-// (A, b and piv overwritten; n a multiple of 128, at most 8192)
+// (A, b and piv overwritten; n a multiple of 128)
 hipError_t dense_solve(double* A, long ldA, long sA, int n, double* b, long sb, int* piv,
                        long sP, int* info, int batch, long nA, long nb, long npiv, long ninfo,
                        hipStream_t st);

@@ -145,6 +145,23 @@ def test_fallback_batches_match_direct_solve():
         assert abs(wc[j] - w_ref) <= 1e-10 * kappa * np.dot(b, b), j
 
 
+def test_fallback_solves_past_the_lds_vector():
+    """N_aux 6200 (49 LU panels; the solve works on b in place, past the LDS
+    size it uses below 6144): the forced-fallback solutions satisfy their
+    systems to rounding."""
+    inp = ragged(seed=11, n_occ=2, n_virt=10, n_aux=6200, rows=(1, 2))
+    st, ms, ws = [1, 2, 1], [0, 5, 11], [0.05, -0.3, 0.7]
+    with ctx(inp, minres_max_iter=1) as c:
+        x, wc, dwc, it = c.residues(st, ms, ws)
+    assert np.all(it < 0)
+    rows = list(inp.row_ids)
+    n = inp.shape.n_aux
+    for j in range(3):
+        b = inp.B_rows[rows.index(st[j]), ms[j]]
+        A = np.eye(n) - cd.pi_real(inp.eps, inp.n_occ, inp.B_ov, ws[j])
+        assert np.linalg.norm(A @ x[j] - b) <= 1e-12 * np.linalg.norm(b) * np.linalg.norm(A, 1), j
+
+
 def test_many_residue_systems_in_one_batch():
     # more than one 64-system tile of systems
     inp = ragged()
