@@ -76,7 +76,7 @@ typedef struct gw_opts {
   size_t mem_budget_bytes;  /* cap on device memory of this context (0: no cap) */
   size_t work_budget_bytes; /* cap on the stage-A workspace (0: 16 GiB); grid points
                                are factored in chunks that fit */
-  int minres_batch;         /* residue systems per MINRES batch, >= 64 (0: 256); bounds
+  int minres_batch;         /* residue systems per MINRES batch, >= 64 (0: 384); bounds
                                the MINRES workspace */
   int no_graphs;            /* nonzero: launch every MINRES iteration eagerly instead of
                                replaying it from a captured HIP graph (0: graphs; they

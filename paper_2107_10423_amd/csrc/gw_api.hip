@@ -133,6 +133,12 @@ hipError_t rt_memset(void* p, int v, size_t bytes, hipStream_t st) {
 hipError_t rt_sync(hipStream_t st) { return audit_mode() ? hipSuccess : hipStreamSynchronize(st); }
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// Default residue systems per MINRES batch.  At (H2O)30 (rounds of about 400
+// systems) the stage took 262 ms with 384, 273 with 256, 290 with 320, 283
+// with 448 and 512: a batch of 384 runs on three 128-row pass tiles, and the
+// few systems left over form a second, short batch.
+constexpr int MINRES_BATCH = 384;
 inline long round_up_l(long x, long m) { return (x + m - 1) / m * m; }
 
 constexpr int PANEL = 128;  // Cholesky panel width (matches chol.hip)
@@ -385,7 +391,7 @@ struct gw_ctx {
   double qp_tol = 1e-10;
   int qp_max_iter = 100;
   double cluster_width = 0.0;  // > 0: cluster initial-guess layer
-  int minres_batch = 256;     // systems per MINRES batch (bounds the workspace)
+  int minres_batch = MINRES_BATCH;  // systems per MINRES batch (bounds the workspace)
   size_t mem_budget = 0, work_budget = 16ull << 30;
   size_t mem_used = 0;
   // host copies: eps_ks are the mean-field eigenvalues (the QP equation's
@@ -993,6 +999,14 @@ int ensure_stage(gw_ctx* c, size_t bytes) {
 }
 
 
+// Padded size of a batch of k residue systems: whole 64-row tiles, and whole
+// 128-row tiles above 256 so that large batches run the 128 x 128 pass tiles
+// (padding rows are 16-row blocks past the batch, whose MFMAs are skipped).
+inline int mr_kp(int k) {
+  const int kp = round_up(k, 64);
+  return kp > 256 ? round_up(k, 128) : kp;
+}
+
 // Staging bytes of one MINRES batch of kp systems: rhs index, warm flag,
 // frequency, tolerance in; W^c, dW^c, convergence out.
 inline size_t mr_stage_bytes(int cap) { return (size_t)cap * (4 + 4 + 4 + 8 + 8 + 8 + 8 + 4); }
@@ -1212,7 +1226,7 @@ int solve_residues_batch(gw_ctx* c, const std::vector<System>& sys, bool use_fal
   dwc.assign(k, 0.0);
   iters.assign(k, 0);
   if (k == 0) return 0;
-  const int kp = round_up(k, 64);
+  const int kp = mr_kp(k);
   RCHK(ensure_minres(c, kp));
   MinresBufs& m = c->mr;
   m.k = k; m.kp = kp; m.Np = c->Np; m.Kp = c->Kp;
@@ -1458,7 +1472,7 @@ int eval_sigma(gw_ctx* c, const std::vector<int>& states, const std::vector<doub
   const int sc = c->sig_cap;
   const size_t sig_bytes = ((size_t)sc * (3 * sizeof(double) + sizeof(int)) + 63) / 64 * 64;
   const int kmax = std::min((int)sys.size(), c->minres_batch);
-  RCHK(ensure_stage(c, sig_bytes + mr_stage_bytes(std::max(c->mr_cap, round_up(std::max(kmax, 1), 64)))));
+  RCHK(ensure_stage(c, sig_bytes + mr_stage_bytes(std::max(c->mr_cap, mr_kp(std::max(kmax, 1))))));
   {
     double* h_om = (double*)c->h_stage;
     int* h_row = (int*)(h_om + sc);
@@ -1879,7 +1893,7 @@ size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states,
   b += (size_t)round_up(std::max(n_states, 1), 8) * (sizeof(int) + 3 * d + 32 * d);
   // MINRES workspace for the largest batch
   const int kmax = std::min(std::max(n_states, 1) * n_mo, minres_batch);
-  const int kp = round_up(kmax, 64);
+  const int kp = mr_kp(kmax);
   const size_t part = minres_part_elems(kp, Np, Kp);
   b += 8 * (size_t)kp * Np * d + (size_t)kp * 16 * d + (size_t)kp * Kp * d + part * d +
        (size_t)kp * (2 * d + 2 * sizeof(int) + 2 * d + sizeof(int)) + 2 * sizeof(int) +
@@ -2258,7 +2272,7 @@ size_t gw_footprint(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, in
   gw_opts o{};
   if (opts) o = *opts;
   const size_t wb = o.work_budget_bytes ? o.work_budget_bytes : (16ull << 30);
-  const int mb = o.minres_batch > 0 ? std::max(64, o.minres_batch) : 256;
+  const int mb = o.minres_batch > 0 ? std::max(64, o.minres_batch) : MINRES_BATCH;
   if (n_mo < 2 || n_occ < 1 || n_occ >= n_mo || n_aux < 1 || n_rows < 0 || grid_n < 1) return 0;
   return footprint_bytes(n_mo, n_occ, n_aux, n_rows, n_states, grid_n, o.pi_prec, o.wc_prec, wb, mb);
 }

@@ -159,6 +159,32 @@ def run_server_case(reqs, G, prec, wc, streams):
           f"{st['batches']} batches of {st['batched_requests']} requests", flush=True)
 
 
+def run_wide_case(n_occ, n_virt, n_aux, rows, G, n_sys):
+    """One MINRES batch of n_sys > 256 systems (padded to whole 128-row pass
+    tiles)."""
+    shape = gwgen.custom_shape(n_occ, n_virt, n_aux, n_core=1)
+    inp = gwgen.make_inputs(shape, 1, rows)
+    g = gwl.Grid.gauss_legendre(G)
+    n_mo = n_occ + n_virt
+    for prec, wc in (("fp64", "fp64"), ("bf16x3", "bf16x3")):
+        with gwl.Context.from_inputs(inp, pi_prec=prec, wc_prec=wc, minres_batch=512) as c:
+            before = gwl.audit_launch_count()
+            for call in (lambda: c.cholesky([0.3, 1.0]), lambda: c.wtable(g),
+                         lambda: c.residues([rows[0]] * n_sys, [m % n_mo for m in range(n_sys)],
+                                            np.linspace(-1, 22, n_sys)),
+                         lambda: c.qp(list(rows), g)):
+                try:
+                    call()
+                except gwl.GWError as e:
+                    if e.code != gwl.GW_EAUDIT:
+                        raise
+                else:
+                    raise AssertionError("audit mode returned results")
+            n = gwl.audit_launch_count() - before
+        print(f"wide case {n_occ}/{n_virt}/{n_aux} G={G} systems={n_sys} {prec}/wc {wc}: "
+              f"{n} launches checked", flush=True)
+
+
 def main():
     gwl.audit_enable()
     small = []
@@ -177,6 +203,9 @@ def main():
     run_budget_case(40, 900, 1152, 4)
     run_uhf_case(6, 40, 150, (3, 6, 46 + 4, 46 + 5), 6)
     run_uhf_case(1, 3, 20, (0, 4, 5), 3)
+    run_wide_case(7, 45, 200, (4, 5, 6), 8, 300)
+    run_wide_case(17, 63, 129, (16, 17, 40), 7, 257)
+    run_wide_case(3, 20, 2100, (1, 2), 4, 390)
     print("audit ok")
 
 
