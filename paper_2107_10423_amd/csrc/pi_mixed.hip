@@ -438,6 +438,65 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
       }
 }
 
+// Tile set of the wide Pi build, in 128-row blocks (nb = Np / 128).  A
+// workgroup computes the four blocks (r[0..1], c[0..1]) and stores those whose
+// bit 2 rh + ch of mask is set.  Even nb: the lower 256 x 256 tiles (I, J),
+// J <= I (rows 2I, 2I + 1 against columns 2J, 2J + 1), the block above the
+// diagonal of a diagonal tile not stored.  Odd nb, where the last block row
+// L = nb - 1 would pad its tiles to 256 rows: first the strictly lower tiles of
+// the nb - 1 paired blocks; then, for each pair T, rows {2T + 1, L} against
+// columns {2T, 2T + 1} (the lower half of the diagonal tile plus two blocks
+// of row L); then the diagonal blocks left over, (2T, 2T) and (L, L), two per
+// workgroup (rows {d1, d2} against columns {d1, d2}, the two diagonal blocks
+// stored).  Each block of the lower triangle is stored by exactly one
+// workgroup; at nb = 27 ((H2O)30) that is 98 workgroups per grid point
+// against 105 tiles of 256.
+struct WideTile {
+  int r[2], c[2];
+  unsigned mask;
+};
+
+__host__ __device__ inline int wide_tile_count(int nb) {
+  const int P = nb / 2;
+  if (nb % 2 == 0) return P * (P + 1) / 2;
+  return P * (P - 1) / 2 + P + (P + 2) / 2;
+}
+
+__device__ inline WideTile wide_tile(int p, int nb) {
+  WideTile w;
+  const int P = nb / 2, L = nb - 1;
+  int I, J;
+  if (nb % 2 == 0) {
+    lower_tile(p, I, J);
+    w.r[0] = 2 * I; w.r[1] = 2 * I + 1;
+    w.c[0] = 2 * J; w.c[1] = 2 * J + 1;
+    w.mask = I == J ? 0xDu : 0xFu;   // (2I, 2I + 1) lies above the diagonal
+    return w;
+  }
+  const int n_off = P * (P - 1) / 2;
+  if (p < n_off) {
+    lower_tile(p, I, J);
+    ++I;                             // strictly lower: J < I
+    w.r[0] = 2 * I; w.r[1] = 2 * I + 1;
+    w.c[0] = 2 * J; w.c[1] = 2 * J + 1;
+    w.mask = 0xFu;
+  } else if (p < n_off + P) {
+    const int T = p - n_off;
+    w.r[0] = 2 * T + 1; w.r[1] = L;
+    w.c[0] = 2 * T; w.c[1] = 2 * T + 1;
+    w.mask = 0xFu;
+  } else {
+    const int q = p - n_off - P;     // diagonal blocks 2q and 2q + 1 of (0, 2, .., 2P - 2, L)
+    const int d1 = 2 * q < P ? 4 * q : L;
+    const bool two = 2 * q + 1 <= P;
+    const int d2 = !two ? d1 : (2 * q + 1 < P ? 4 * q + 2 : L);
+    w.r[0] = d1; w.r[1] = d2;
+    w.c[0] = d1; w.c[1] = d2;
+    w.mask = two ? 0x9u : 0x1u;      // (d1, d1) and (d2, d2)
+  }
+  return w;
+}
+
 // Wide form for large N_aux: 256 x 256 tiles per 512-thread workgroup (eight
 // wavefronts, each 128 x 64: 8 x 4 blocks of three bf16 MFMAs, the B
 // fragments of its four block columns held while the A block rows stream
@@ -447,15 +506,15 @@ __global__ __launch_bounds__(256) void k_pi_bf16x3(const uint16_t* Bhi, const ui
 // the MFMAs of step k so that the scheduler interleaves them.  Per flop it stages half of the global bytes and 7/8 of the LDS bytes
 // of a 256 x 128 tile, and half of the scaled side's split work of the
 // 128 x 128 form.  At up to 256 VGPRs one workgroup (two wavefronts per SIMD)
-// holds a CU.  Lower tiles (I, J), J <= I, of 256; the last tile row and
-// column may reach past N_aux: rows are clamped on load and not stored, and
-// a wavefront whose block lies past N_aux or wholly above the diagonal stores
-// nothing.  Same K order and products as the 128 x 128 form, so the results
-// are identical bit for bit.
+// holds a CU.  The workgroup's two 128-row halves on each side are the
+// blocks of its WideTile (above); a wavefront (128 x 64, within one block
+// pair) whose block is not in the tile's store mask still computes (which
+// keeps the K-step one basic block) but stores nothing.  Same K order and
+// products as the 128 x 128 form, so the results are identical bit for bit.
 __global__ __launch_bounds__(512) void k_pi_bf16x3_wide(const uint16_t* Bhi, const uint16_t* Blo,
                                                         long ld, const float* B32,
                                                         const float* scale, long sS, double* A,
-                                                        long ldA, long sA, int Np, int T, int Kp,
+                                                        long ldA, long sA, int Np, int Kp,
                                                         int G, OperandTabs tb) {
   __shared__ __attribute__((aligned(16))) uint16_t Ah[2][2][SLAB];   // [buffer][128-row half]
   __shared__ __attribute__((aligned(16))) uint16_t Al[2][2][SLAB];
@@ -463,19 +522,21 @@ __global__ __launch_bounds__(512) void k_pi_bf16x3_wide(const uint16_t* Bhi, con
   __shared__ __attribute__((aligned(16))) uint16_t Bl[2][2][SLAB];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 2, wn = wave & 3;
-  const int id = xcd_swizzle_m(blockIdx.x, T * (T + 1) / 2 * G);
+  const int nb = Np / 128;
+  const int id = xcd_swizzle_m(blockIdx.x, wide_tile_count(nb) * G);
   const int g = id % G;
-  int I, J;
-  lower_tile(id / G, I, J);
+  const WideTile wt = wide_tile(id / G, nb);
   const float* S = scale + (long)g * sS;
   if (tb.Bhi) {
     Bhi = tb.Bhi[g / tb.grp];
     Blo = tb.Blo[g / tb.grp];
     B32 = tb.B32[g / tb.grp];
   }
-  const int ar0 = I * 256, br0 = J * 256;
-  const int wr0 = ar0 + wm * 128, wc0 = br0 + wn * 64;
-  const bool live = wr0 < Np && wc0 < Np && wr0 + 127 >= wc0;
+  // first global row of each 128-row half (every block lies below Np)
+  const long arow[2] = {128L * wt.r[0], 128L * wt.r[1]};
+  const long brow[2] = {128L * wt.c[0], 128L * wt.c[1]};
+  const int wr0 = 128 * wt.r[wm], wc0 = 128 * wt.c[wn >> 1] + 64 * (wn & 1);
+  const bool live = (wt.mask >> (2 * wm + (wn >> 1))) & 1u;
   f4 acc[8][4];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
@@ -489,17 +550,17 @@ __global__ __launch_bounds__(512) void k_pi_bf16x3_wide(const uint16_t* Bhi, con
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       int row, ch;
-      a_item(t + 512 * u, row, ch);
-      const long gr = min(ar0 + row, Np - 1);
+      a_item(t + 512 * u, row, ch);   // row >> 7 == u
+      const long gr = arow[u] + (row & 127);
       rah[u] = *reinterpret_cast<const u32x4*>(Bhi + gr * ld + k0 + 8 * ch);
       ral[u] = *reinterpret_cast<const u32x4*>(Blo + gr * ld + k0 + 8 * ch);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       int row, ch, half;
-      b_item(t + 512 * u, row, ch, half);
+      b_item(t + 512 * u, row, ch, half);   // row >> 7 == u >> 1
       const int k = k0 + 8 * ch + 4 * half;
-      const long gr = min(br0 + row, Np - 1);
+      const long gr = brow[u >> 1] + (row & 127);
       rb[u] = *reinterpret_cast<const f32x4*>(B32 + gr * ld + k);
       rs[u] = *reinterpret_cast<const f32x4*>(S + k);
     }
@@ -581,8 +642,7 @@ __global__ __launch_bounds__(512) void k_pi_bf16x3_wide(const uint16_t* Bhi, con
       for (int r = 0; r < 4; ++r) {
         const int row = wr0 + i * 16 + mfma_row(4 * (lane >> 4) + r);
         const int col = wc0 + j * 16 + mfma_row(lane & 15);
-        if (row < Np && col < Np)
-          Ag[(long)row * ldA + col] = (row == col ? 1.0 : 0.0) + 4.0 * (double)acc[i][j][r];
+        Ag[(long)row * ldA + col] = (row == col ? 1.0 : 0.0) + 4.0 * (double)acc[i][j][r];
       }
 }
 
@@ -602,12 +662,11 @@ static hipError_t launch_pi_bf16x3(const uint16_t* Bhi, const uint16_t* Blo, con
     return refuse("pi_bf16x3", "operand table group");
   if (hipError_t e = check_pi("pi_bf16x3", ld, sS, ldA, sA, Np, Kp, G, BKB, nB, nS, nA)) return e;
   if (Np >= WIDE_FROM) {
-    const int T2 = (Np + 255) / 256;
-    const long wtotal = (long)T2 * (T2 + 1) / 2 * G;
+    const long wtotal = (long)wide_tile_count(T) * G;
     if (wtotal > 0x7fffffffL) return refuse("pi_bf16x3", "grid too large");
     GW_AUDIT_RETURN();
     hipLaunchKernelGGL(k_pi_bf16x3_wide, dim3((unsigned)wtotal), dim3(512), 0, st, Bhi, Blo, ld,
-                       B32, scale, sS, A, ldA, sA, Np, T2, Kp, G, tb);
+                       B32, scale, sS, A, ldA, sA, Np, Kp, G, tb);
     return hipGetLastError();
   }
   GW_AUDIT_RETURN();

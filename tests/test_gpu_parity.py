@@ -379,6 +379,27 @@ def test_pi_precision_h2o10_sampled_rows(prec, bound):
     assert worst < bound
 
 
+@pytest.mark.parametrize("n_aux", [2100, 2200, 3360])
+def test_pi_wide_tiles_cover_the_lower_triangle(n_aux):
+    """The wide BF16x3 Pi build (N_aux padded to 2048 and up) stores every
+    element of the lower triangle: 17, 18 and 27 blocks of 128 rows (an odd
+    count packs the last block row into the diagonal tiles' spare halves).
+    Two calls at different frequencies, so that a block left unwritten by
+    the second would still hold the first call's values."""
+    shape = gwgen.custom_shape(3, 20, n_aux, n_core=1)
+    inp = gwgen.make_inputs(shape, 5, [2])
+    D = cd.transition_energies(inp.eps, inp.n_occ)
+    low = np.tril(np.ones((n_aux, n_aux), dtype=bool))
+    with ctx(inp, pi_prec="bf16x3") as c:
+        for xis in (np.array([0.05, 3.0]), np.array([0.4, 11.0])):
+            got = c.dielectric(xis)
+            for g, x in enumerate(xis):
+                Pi = -4.0 * (inp.B_ov * (D / (D * D + x * x))) @ inp.B_ov.T
+                ref = np.eye(n_aux) - Pi
+                err = np.abs(np.where(low, got[g] - ref, 0.0)).max() / np.abs(Pi).max()
+                assert err < 1e-4, (n_aux, x, err)
+
+
 def test_setup_from_the_full_tensor():
     """gw_setup_full takes B [n_aux][n_mo][n_mo] and serves every state: the
     same energies as the row-supplied context, and states outside it."""
