@@ -880,13 +880,17 @@ __global__ __launch_bounds__(256, 4) void k_wc_bf16x3(const uint16_t* Rh, const 
 // Wide form for large N_aux: 256 x 256 tiles (256 rows of R, a 256-wide panel
 // J of F) on 512-thread workgroups, eight wavefronts of 128 x 64, with the
 // double-buffered LDS and single-block K-step of the wide Pi build (both
-// operands arrive pre-split, so the stores are plain copies); K runs over
-// k < min(256 (J + 1), N_aux).  part[g][J][q] holds the panel sums over the
-// 256-wide panels (J < ceil(N_aux / 256)).  Order: blocks of 8 grid points,
-// then the panel, then groups of 4 row tiles, grid point fastest, so the 32
-// workgroups an XCD holds share 4 R tiles and 8 F panels through its L2.
-// Rows past the padded R and columns past N_aux are clamped on load and
-// neither stored nor summed.
+// operands arrive pre-split, so the stores are plain copies).  Panel J covers
+// p in [256 J - o, 256 J - o + 256) with o = 128 when N_aux / 128 is odd (else
+// 0), so that the panels end at N_aux: the half panel an odd count leaves
+// falls at p < 0, where K is 128 long, instead of past N_aux, where K is
+// N_aux long.  K runs over k < min(256 J - o + 256, N_aux) (F is zero for
+// k > p, so each y_p has its full sum).  part[g][J][q] holds the panel sums
+// (J < ceil(N_aux / 256)).  Order: blocks of 8 grid points, then the panel,
+// then groups of 4 row tiles, grid point fastest, so the 32 workgroups an
+// XCD holds share 4 R tiles and 8 F panels through its L2.  Rows past the
+// padded R and columns outside [0, N_aux) are clamped on load and neither
+// stored nor summed.
 __global__ __launch_bounds__(512) void k_wc_bf16x3_wide(const uint16_t* Rh, const uint16_t* Rl,
                                                         long ldR, const uint16_t* Fh,
                                                         const uint16_t* Fl, long sF, int Np,
@@ -915,9 +919,9 @@ __global__ __launch_bounds__(512) void k_wc_bf16x3_wide(const uint16_t* Rh, cons
   }
   const uint16_t* Fhg = Fh + (long)g * sF;
   const uint16_t* Flg = Fl + (long)g * sF;
-  const int ar0 = I * 256, br0 = J * 256;
+  const int ar0 = I * 256, br0 = J * 256 - ((Np >> 7) & 1) * 128;
   const int nk = min(br0 + 256, Np) / BKB;
-  const bool live = br0 + wn * 64 < Np && ar0 + wm * 128 < Rp;
+  const bool live = br0 + wn * 64 >= 0 && br0 + wn * 64 < Np && ar0 + wm * 128 < Rp;
   f4 acc[8][4];
 #pragma unroll
   for (int i = 0; i < 8; ++i)
@@ -931,7 +935,7 @@ __global__ __launch_bounds__(512) void k_wc_bf16x3_wide(const uint16_t* Rh, cons
       int row, ch;
       a_item(t + 512 * u, row, ch);
       const long oa = (long)min(ar0 + row, Rp - 1) * ldR + k0 + 8 * ch;
-      const long ob = (long)min(br0 + row, Np - 1) * Np + k0 + 8 * ch;
+      const long ob = (long)min(max(br0 + row, 0), Np - 1) * Np + k0 + 8 * ch;
       rah[u] = *reinterpret_cast<const u32x4*>(Rh + oa);
       ral[u] = *reinterpret_cast<const u32x4*>(Rl + oa);
       rbh[u] = *reinterpret_cast<const u32x4*>(Fhg + ob);
@@ -995,7 +999,7 @@ __global__ __launch_bounds__(512) void k_wc_bf16x3_wide(const uint16_t* Rh, cons
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int col = br0 + wn * 64 + j * 16 + mfma_row(lane & 15);
-        if (live && col < Np) {
+        if (live && col < Np) {   // live: the wavefront's 64 columns lie in [0, Np)
           const double b = (double)bf16_to_f(Rh[ro + col]) + (double)bf16_to_f(Rl[ro + col]);
           const double y = (double)acc[i][j][r];
           sum += (2.0 * b + y) * y;

@@ -154,6 +154,8 @@ def test_serving_results_alone_and_in_the_mix():
     (3, 20, 64, (1, 2)),        # N_aux below one 128-wide panel
     (2, 3, 130, (1,)),          # N_aux just past a panel (second panel of 2 rows)
     (11, 60, 300, tuple(range(0, 71))),   # 71 x 71 rows: 40 row tiles, 5 groups of 8
+    (3, 20, 2100, (1, 2)),      # wide form, 17 blocks of 128 (panels shifted by 128)
+    (3, 20, 2200, (1, 2)),      # wide form, 18 blocks of 128
 ])
 def test_wtable_edge_shapes(n_occ, n_virt, n_aux, rows):
     """FP64 Pi, so that only the contraction's error is measured (with BF16x3
