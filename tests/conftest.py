@@ -1,7 +1,12 @@
 import os
 import sys
 
-import pytest
+# The oracle's matrices in the tests are small: a few BLAS threads are as
+# fast as many, and they avoid OpenBLAS's spin-waiting threads stalling the
+# suite when other work shares the host's cores.  Set before numpy loads.
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "4")
+
+import pytest  # noqa: E402
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
