@@ -1,12 +1,7 @@
 import os
 import sys
 
-# The oracle's matrices in the tests are small: a few BLAS threads are as
-# fast as many, and they avoid OpenBLAS's spin-waiting threads stalling the
-# suite when other work shares the host's cores.  Set before numpy loads.
-os.environ.setdefault("OPENBLAS_NUM_THREADS", "4")
-
-import pytest  # noqa: E402
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
@@ -16,3 +11,9 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+    # The CPU-only selection runs the oracle on small matrices: a few BLAS
+    # threads are as fast as many there, and they keep OpenBLAS's spinning
+    # threads from stalling the suite when other work shares the host's
+    # cores.  Set before the test modules (and numpy) are imported.
+    if "not gpu" in (config.getoption("markexpr", "") or ""):
+        os.environ.setdefault("OPENBLAS_NUM_THREADS", "4")
