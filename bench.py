@@ -463,8 +463,13 @@ def _serve_run(gwl, grid, streams, stream, inputs, small_k, prec, arrivals, wind
     span = max(done_t) - min(sub_t)
     L = np.array([lat[i] for i in range(len(stream))])
     small = L[ks <= small_k]
+    # algorithmic Pi work of every request's W^c table: N_aux (N_aux + 1) N_ov
+    # per grid point (the xi = 0 point of the preconditioner not counted)
+    pi_flop = sum(float(x.shape.n_aux) * (x.shape.n_aux + 1) * x.shape.n_ov * grid.n
+                  for x in inputs)
     return dict(E=E, span_s=span, req_per_s=len(stream) / span,
                 qp_per_s=sum(len(x.row_ids) for x in inputs) / span,
+                pi_tflops=pi_flop / span / 1e12,
                 p50_s=float(np.percentile(L, 50)), p99_s=float(np.percentile(L, 99)),
                 small_p50_s=float(np.percentile(small, 50)) if small.size else None,
                 small_p99_s=float(np.percentile(small, 99)) if small.size else None,
