@@ -38,6 +38,11 @@ PATHS = {"bf16x3w": dict(pi_prec="bf16x3", wc_prec="bf16x3"),
 DTYPES = {"bf16x3w": "bf16x3 Pi and W^c (fp32 acc) + f64", "bf16x3": "bf16x3 Pi (fp32 acc) + f64",
           "fp64": "f64", "fp32": "f32 Pi + f64"}
 MEV = 1e-3 / 27.211386245988
+# QP tolerance of the timed paths: the one the oracle fixtures were solved
+# with, so that each path's error against them measures its arithmetic and
+# not a different stopping point of the step tree (with 1e-10 Ha a Newton
+# step may stop up to ~1e-10 Ha short of the root, ~1e-10 relative)
+QP_TOL = 1e-12
 
 
 def log(msg):
@@ -70,7 +75,7 @@ def time_path(gwl, inp, states, grid, path, steps, warmup, work_budget=0):
     import torch
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
-    c = gwl.Context.from_inputs(inp, qp_tol=1e-10, work_budget_bytes=work_budget, **PATHS[path])
+    c = gwl.Context.from_inputs(inp, qp_tol=QP_TOL, work_budget_bytes=work_budget, **PATHS[path])
     torch.cuda.synchronize()
     setup_ms = 1e3 * (time.perf_counter() - t_setup)   # host -> HBM upload and setup
     with c:
@@ -114,7 +119,7 @@ def time_evgw(gwl, inp, states, grid, path, reps=2, n_cycles=3):
     import numpy as np
     import torch
     out = {}
-    with gwl.Context.from_inputs(inp, qp_tol=1e-10, **PATHS[path]) as c:
+    with gwl.Context.from_inputs(inp, qp_tol=QP_TOL, **PATHS[path]) as c:
         for mode in ("evgw0", "evgw"):
             each, rounds = [], []
             for _ in range(reps + 1):        # the first call warms up
@@ -150,7 +155,7 @@ def time_core_spectrum(gwl, path, reps=2):
                        f"n_virt={cfg.shape.n_virt}, N_aux={cfg.shape.n_aux}, "
                        f"{cfg.grid_points}-point grid, seed {cfg.seed}", "path": path}
     for width in (0.0, 0.5):
-        with gwl.Context.from_inputs(inp, qp_tol=1e-10, cluster_width=width,
+        with gwl.Context.from_inputs(inp, qp_tol=QP_TOL, cluster_width=width,
                                      **PATHS[path]) as c:
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -194,7 +199,7 @@ def crossover(gwl, ks, reps=3):
         E = {}
         for route in ("sd", "cd_fp64", "cd_bf16x3"):
             prec = "bf16x3" if route == "cd_bf16x3" else "fp64"
-            with gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=1e-10) as c:
+            with gwl.Context.from_inputs(inp, pi_prec=prec, qp_tol=QP_TOL) as c:
                 call = (lambda: c.qp_sd(states)) if route == "sd" else (lambda: c.qp(states, grid))
                 times = []
                 for rep in range(reps + 1):
@@ -672,7 +677,7 @@ def main():
                                f"(HOMO-{sh.n_occ - 1 - states[0]}..LUMO+"
                                f"{states[-1] - sh.n_occ}), seed {cfg.seed}",
                    "n_occ": sh.n_occ, "n_virt": sh.n_virt, "n_aux": sh.n_aux,
-                   "grid_points": cfg.grid_points, "states": len(states)},
+                   "grid_points": cfg.grid_points, "states": len(states), "qp_tol_ha": QP_TOL},
         "roofline": roofline_objects(h, cfg, name, states),
         # one molecule's request latency on an idle GPU (the headline path's
         # timed steps); loaded latency under a request stream: "serving"
