@@ -1865,9 +1865,10 @@ int solve_qp(gw_ctx* c, int n_states, const int* states, std::vector<QPState>& q
 // Device-memory footprint of one context over gw_setup + gw_qp, mirroring
 // every allocation above (requested bytes).  n_states bounds the number of
 // residue systems per Sigma evaluation (n_states * n_mo, in batches of at
-// most minres_batch).
+// most minres_batch; 0: a context's default batch).
 size_t footprint_bytes(int n_mo, int n_occ, int n_aux, int n_rows, int n_states, int G_in,
                        int pi_prec, int wc_prec, size_t work_budget, int minres_batch) {
+  if (minres_batch <= 0) minres_batch = MINRES_BATCH;
   const size_t d = sizeof(double);
   const int G = G_in + 1;   // the xi = 0 point of the preconditioner (on by default)
   const int Np = round_up(n_aux, 128);

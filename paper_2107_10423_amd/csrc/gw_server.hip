@@ -470,7 +470,7 @@ int gw_server_submit(gw_server* s, const gw_request* q, unsigned long long* tick
   o.work_budget_bytes = s->opts.work_budget_bytes;
   r->footprint = footprint_bytes(q->n_mo, q->n_occ, q->n_aux, q->n_rows, q->n_states,
                                  (int)s->xi.size(), s->opts.pi_prec, s->opts.wc_prec,
-                                 s->opts.work_budget_bytes, 256);
+                                 s->opts.work_budget_bytes, 0);   // the contexts' default batch
   if (r->footprint > s->budget) {
     if (r->pinned_bytes) s->pinned.release(r->B, r->pinned_bytes);
     delete r;
