@@ -149,11 +149,20 @@ def run_server_case(reqs, G, prec, wc, streams):
         ts = [srv.submit_inputs(r, list(r.row_ids)) for r in reqs]
         srv.drain()
         st = srv.stats()
-        rcs = [srv.poll(t)[4]["rc"] for t in ts]
+        infos = [srv.poll(t)[4] for t in ts]
+    rcs = [i["rc"] for i in infos]
     bad = [rc for rc in rcs if rc != gwl.GW_EAUDIT]
     if bad:
         raise AssertionError(f"server case {prec}/{wc}: request codes {rcs}: "
                              f"{gwl._lib.gw_last_error().decode()}")
+    # admission reserves what gw_footprint states for the request's context
+    # (the server's default work budget is 2 GiB)
+    for r, i in zip(reqs, infos):
+        want = gwl.footprint(r.shape.n_mo, r.n_occ, r.shape.n_aux, len(r.row_ids),
+                             len(r.row_ids), G, prec, 2 << 30, wc_prec=wc)
+        if i["footprint_bytes"] != want:
+            raise AssertionError(f"server case {prec}/{wc}: footprint {i['footprint_bytes']} "
+                                 f"against gw_footprint {want}")
     n = gwl.audit_launch_count() - before
     print(f"server case {len(reqs)} requests G={G} {prec}/wc {wc}: {n} launches checked, "
           f"{st['batches']} batches of {st['batched_requests']} requests", flush=True)
